@@ -1,0 +1,41 @@
+"""Plain FP64 CPU reference for the boundary-condition operator.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  The product
+path (``paper_2605_14780_amd``) never imports, calls or links anything here,
+and this package imports nothing from it: the two share no code.  The only
+module both sides use is ``synthinputs`` (seeded input arrays, no operator
+arithmetic).
+
+What it computes (Mat2Boundary, arXiv 2605.14780):
+
+* ``grid``          the region model: global box, blocks as full/data slices
+                    with the block id as leading coordinate, ghost = full - data
+                    (Sec. III-A; Sec. IV-A-1; Alg. 1 region lines).
+* ``operator``      assembly of the affine operator F(x) = A x + b over the
+                    ghost rows from basic sub-matrices / sub-vectors, applied
+                    in place on a full field; its vector-Jacobian product
+                    (Sec. III-B; Sec. IV-A-3/4, Tables II and III).
+* ``cubed_sphere``  the equiangular gnomonic cubed sphere: face-edge halo
+                    copy with rotated axes and 4-point Lagrange rows along the
+                    neighbour's grid line, built from 3-D geometry
+                    (Sec. II-B; Sec. III-B user-defined interpolation;
+                    Sec. V-A multi-component vectors).
+* ``hpcg``          the HPCG-shaped Cartesian case: 2x2x2 blocks with halo 1,
+                    halo copy between blocks, zero padding outside, then the
+                    27-point operator (Sec. III-B halo copying and zero
+                    padding; Sec. IV-C, BC writes feed the inner operator).
+* ``dense``         brute-force dense A on tiny grids, evaluated entry by entry
+                    from the definitions without the sparse assembly.
+
+Pins (in ``tests/test_oracle_*.py``, run with ``-m "not gpu"``) tie each part
+to something other than itself: ``numpy.pad`` for zero/circular/symmetric
+maps, the Alg. 1 rotated map, cubic reproduction and fourth-order convergence
+of the Lagrange rows, a solid-body-rotation vector field for the component
+rotation, the closed form of the 27-point operator on a constant field, and
+the dot-product identity for the adjoint.
+"""
+from .grid import Grid, Box  # noqa: F401
+from .operator import (  # noqa: F401
+    MapSub, ZeroSub, RowsSub, VectorSub, Operator, assemble, apply, vjp,
+)
