@@ -1,0 +1,290 @@
+/*
+ * hbc.h — C ABI of hipbc: boundary conditions as affine sparse operators,
+ * ghost = A * interior + b, on block-structured grids, for MI355X (gfx950).
+ *
+ * Model (Mat2Boundary, arXiv 2605.14780):
+ *  - Sec. III-A: every variable lives on a full region = data region + ghost
+ *    region.  Sec. IV-A-1: one global box [lo, hi) per dimension; each block's
+ *    full and data regions are slices (start, stop, step) of it, ghost = full -
+ *    data.  Alg. 1 puts the block id in the leading coordinate, so block full
+ *    regions are disjoint in global coordinates (checked here).
+ *  - Sec. III-B: a BC is F(x) = A x + b with x over the data region; the six
+ *    BC kinds of that section become rows of A / entries of b.
+ *  - Sec. IV-A-3 (Table II) and IV-A-4 (Table III): A is split into basic
+ *    sub-matrices, each valid on a set of rows and giving a row iterator:
+ *    a static list (here: one affine map entry, or none) or a dynamic
+ *    iterator (here: ELL or CSR tables).  A basic sub-vector gives b.
+ *
+ * Storage of a field (the device array the apply works on): cells are
+ * numbered block by block in creation order, each block's full box in
+ * row-major order (last coordinate fastest); hbc_grid_block_cells() gives each
+ * block's first cell number.  Every cell holds `inner` values (levels x fields
+ * x components).  POINT_MAJOR stores value (cell, l) at cell*inner + l;
+ * PLANE_MAJOR at l*ncells + cell.
+ *
+ * Conventions for every call:
+ *  - Return 0 (HBC_OK) or a negative HBC_E* code; hbc_last_error() then holds
+ *    a message (thread-local).  No call aborts and no C++ exception escapes.
+ *  - Host arrays passed in are copied before the call returns; the caller may
+ *    free them immediately.
+ *  - Device pointers (fields, outputs) are borrowed: the caller keeps them
+ *    alive until the stream has passed the call.  Field base pointers must be
+ *    16-byte aligned.
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  Apply
+ *    calls are asynchronous on that stream.
+ *  - Plans are immutable after creation (apart from tuning), so applies on
+ *    different streams may run concurrently on different fields.
+ *  - destroy(NULL) is a no-op.
+ */
+#ifndef HBC_H
+#define HBC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HBC_MAX_DIM 6
+
+/* status codes */
+#define HBC_OK 0
+#define HBC_EINVAL (-1)      /* bad argument, slice, size or null pointer */
+#define HBC_ERANGE (-2)      /* row outside its block's ghost region, or column outside every data region */
+#define HBC_EOVERLAP (-3)    /* overlapping sub-matrix (or sub-vector) rows without HBC_ALLOW_OVERLAP_SUM */
+#define HBC_EALIAS (-4)      /* a row written is also read as a column (in-place hazard) */
+#define HBC_EUNCOVERED (-5)  /* ghost rows covered by nothing under HBC_STRICT_COVER */
+#define HBC_ENOMEM (-6)      /* host or device allocation failed */
+#define HBC_EHIP (-7)        /* a HIP runtime error; its string is in hbc_last_error() */
+#define HBC_EUNSUPPORTED (-8)/* valid request outside what this build implements (e.g. slice step != 1) */
+
+/* element types */
+#define HBC_F64 0
+#define HBC_F32 1
+
+/* field layouts */
+#define HBC_POINT_MAJOR 0
+#define HBC_PLANE_MAJOR 1
+
+/* program flags */
+#define HBC_STRICT_COVER 1u        /* every ghost cell must be covered by a sub-matrix or sub-vector */
+#define HBC_ALLOW_OVERLAP_SUM 2u   /* overlapping rows add their contributions (default: HBC_EOVERLAP) */
+
+/* plan flags */
+#define HBC_PLAN_HOST_ONLY 1u      /* compile and validate only; no device tables (no GPU needed) */
+
+/* cubed-sphere program modes */
+#define HBC_CS_SYNC 0              /* rotated halo copy of the neighbour's cell */
+#define HBC_CS_LAGRANGE 1          /* 4-point Lagrange along the neighbour's grid line */
+
+typedef struct hbc_grid hbc_grid;
+typedef struct hbc_program hbc_program;
+typedef struct hbc_plan hbc_plan;
+typedef struct hbc_batch hbc_batch;
+
+/* One slice (start, stop, step) of a dimension, Sec. IV-A-1. */
+typedef struct {
+  int64_t start, stop, step;
+} hbc_slice;
+
+/* Half-open box of row multi-indices; the first `ndim` entries are used. */
+typedef struct {
+  int64_t lo[HBC_MAX_DIM];
+  int64_t hi[HBC_MAX_DIM];
+} hbc_box;
+
+/* Storage layout of the fields a plan is applied to.
+ * inner:      values per cell (>= 1).
+ * order:      HBC_POINT_MAJOR or HBC_PLANE_MAJOR.
+ * vec_len:    0, or the number of slots of each component of one 2-component
+ *             vector field: component 0 = slots [vec_lo, vec_lo + vec_len),
+ *             component 1 = slots [vec_lo + vec_stride, ... + vec_len).
+ *             Sub-matrices with a component rotation act on these slots
+ *             (Sec. V-A: multi-component vectors per grid point). */
+typedef struct {
+  int64_t inner;
+  int32_t order;
+  int32_t vec_len;
+  int64_t vec_lo;
+  int64_t vec_stride;
+} hbc_layout;
+
+/* Plan statistics (per apply, per field). */
+typedef struct {
+  int64_t ghost_cells;      /* all ghost cells of the grid */
+  int64_t rows_covered;     /* ghost rows written by an apply */
+  int64_t rows_uncovered;   /* ghost rows left unchanged */
+  int64_t rows_zero, rows_map, rows_ell, rows_csr, rows_vector_only;
+  int64_t rows_with_b;
+  int64_t nnz;              /* stored entries of A (ELL padding excluded) */
+  int64_t unique_sources;   /* distinct data cells read by A */
+  int64_t segments, tiles;
+  int64_t ghost_values;     /* rows_covered * inner */
+  double alg_bytes;         /* ghost writes + unique source reads + b + tables, per apply */
+  double alg_bytes_adjoint; /* ghost reads + ghost zeroing + source read-modify-write + tables */
+  int64_t table_bytes;      /* device bytes held by the plan */
+} hbc_stats;
+
+/* Launch shape of the apply kernels (chosen by the plan, changed by tuning). */
+typedef struct {
+  int32_t block;            /* threads per workgroup (64..1024, multiple of 64) */
+  int32_t lanes_per_row;    /* power of two; lanes that share one row */
+  int32_t rows_per_tile;    /* rows per work tile */
+  int32_t persistent;       /* 0: one workgroup per tile; >0: that many workgroups loop over tiles */
+} hbc_tune;
+
+/* ---- errors ---------------------------------------------------------------- */
+/* Message of the last failing call on this thread ("" if none).  Owned by the library. */
+const char* hbc_last_error(void);
+
+/* ---- grid and block layout (Sec. III-A, IV-A-1, Alg. 1) ---------------------- */
+/* Create a grid over the global box [lo[d], hi[d]), d < ndim (1 <= ndim <= 6). */
+int hbc_grid_create(int32_t ndim, const int64_t* lo, const int64_t* hi, hbc_grid** out);
+/* Add a block: full and data are ndim slices; data inside full, full inside the
+ * global box, full regions of different blocks disjoint.  Step must be 1
+ * (HBC_EUNSUPPORTED otherwise).  *block_id receives the block's index. */
+int hbc_grid_add_block(hbc_grid* g, const hbc_slice* full, const hbc_slice* data, int32_t* block_id);
+/* Total cells of all blocks' full regions (the field's cell count). */
+int64_t hbc_grid_cells(const hbc_grid* g);
+/* First cell number and cell count of block b's full region. */
+int hbc_grid_block_cells(const hbc_grid* g, int32_t b, int64_t* first_cell, int64_t* ncells);
+void hbc_grid_destroy(hbc_grid* g);
+
+/* Cubed sphere (equiangular gnomonic): 6 blocks along coordinate 0, block f has
+ * full (f, f+1) x [-h, N+h)^2 and data (f, f+1) x [0, N)^2; index (face, j, i). */
+int hbc_cs_grid_create(int64_t N, int64_t h, hbc_grid** out);
+/* Cartesian multi-block: nb[0]*nb[1]*nb[2] blocks of n[0] x n[1] x n[2] data cells
+ * with halo h, block id b = (bz*nb1 + by)*nb2 + bx along coordinate 0, then (z, y, x). */
+int hbc_cart_grid_create(const int32_t* nb, const int64_t* n, int64_t h, hbc_grid** out);
+
+/* ---- BC program: basic sub-matrices / sub-vectors (Sec. IV-A-3, Tables II, III) */
+/* The program keeps its own copy of the grid. */
+int hbc_program_create(const hbc_grid* g, hbc_program** out);
+void hbc_program_destroy(hbc_program* p);
+int hbc_program_set_flags(hbc_program* p, uint32_t flags);
+
+/* Static one-entry rows: for each row multi-index r in `rows`,
+ *   A[r, M r + offset] = weight,
+ * M an ndim x ndim integer matrix (row-major), offset ndim integers.  Covers
+ * halo copy, circular / symmetric maps and rotated copies (Sec. III-B; Alg. 1's
+ * right ghost).  `rot` is NULL or a 2x2 signed permutation (row-major) applied
+ * to the vector components of the layout.  The image of the box must lie in
+ * one block's data region (HBC_ERANGE). */
+int hbc_program_add_map(hbc_program* p, const hbc_box* rows, const int64_t* M, const int64_t* offset,
+                        double weight, const int32_t* rot, int32_t* sub_id);
+/* Rows with no entries: padding with zeros (Sec. III-B); written as +0.0. */
+int hbc_program_add_zero(hbc_program* p, const hbc_box* rows, int32_t* sub_id);
+/* Zero rows for every ghost cell of `block` that no other sub-matrix covers,
+ * resolved when the plan is compiled (the complement region of Alg. 1). */
+int hbc_program_add_zero_rest(hbc_program* p, int32_t block, int32_t* sub_id);
+/* Fixed-width rows (ELL): row k of the box (row-major) has entries
+ * (cols[k*width + m], vals[k*width + m]), m < width; cols are row-major linear
+ * indices over the global box of data cells, -1 marks padding. */
+int hbc_program_add_ell(hbc_program* p, const hbc_box* rows, int32_t width, const int64_t* cols,
+                        const double* vals, const int32_t* rot, int32_t* sub_id);
+/* Variable-width rows (CSR, Alg. 1's BoundaryCSR): row k has entries
+ * row_ptr[k] .. row_ptr[k+1]-1 of cols / vals (global linear data indices). */
+int hbc_program_add_csr(hbc_program* p, const hbc_box* rows, const int64_t* row_ptr, const int64_t* cols,
+                        const double* vals, const int32_t* rot, int32_t* sub_id);
+/* Basic sub-vector: b over `rows`, values[k*ninner + l] for row k (row-major);
+ * ninner is 1 (same b for every inner slot) or the layout's inner extent. */
+int hbc_program_add_vector(hbc_program* p, const hbc_box* rows, int64_t ninner, const double* values,
+                           int32_t* sub_id);
+
+/* Cubed-sphere programs on a grid from hbc_cs_grid_create (Sec. II-B; Sec. III-B
+ * halo copy and user-defined interpolation; Alg. 1's rotated map).  For each of
+ * the 24 face sides one sub-matrix over that side's h x N ghost strip, plus 24
+ * zero corners.  HBC_CS_SYNC: rotated copy of the neighbour's cell on the
+ * mirrored grid line.  HBC_CS_LAGRANGE: 4 entries on that line at
+ * base .. base+3 with the given weights, where base[k*N + t] and
+ * w[(k*N + t)*4 + m] describe ghost layer k, tangential index t (from
+ * hbc_cs_lagrange_weights, copied to the host); NULL for SYNC.  With
+ * `vector` != 0 each side carries its 2x2 component rotation. */
+int hbc_cs_program_add(hbc_program* p, int64_t N, int64_t h, int32_t mode, int32_t vector,
+                       const int32_t* base, const double* w);
+/* Cartesian halo program on a grid from hbc_cart_grid_create: for every block
+ * and each of its 3^3-1 ghost regions, a copy from the neighbouring block
+ * (Sec. III-B halo copying) or, outside the domain, zero rows (padding with
+ * zeros); bit d of periodic_mask wraps dimension d (z=0, y=1, x=2) instead. */
+int hbc_cart_program_add_halo(hbc_program* p, const int32_t* nb, const int64_t* n, int64_t h,
+                              int32_t periodic_mask);
+
+/* ---- plan: program compiled for a layout and element type ------------------- */
+/* Validates, partitions the rows into disjoint boxes (Sec. IV-B's
+ * non-overlapping set; Sec. IV-C's disjoint convex pieces), and builds the
+ * device tables.  dtype: HBC_F64 or HBC_F32 (weights rounded to nearest).
+ * flags: HBC_PLAN_HOST_ONLY. */
+int hbc_plan_create(const hbc_program* p, const hbc_layout* layout, int32_t dtype, uint32_t flags,
+                    hbc_plan** out);
+void hbc_plan_destroy(hbc_plan* plan);
+int hbc_plan_stats(const hbc_plan* plan, hbc_stats* out);
+/* Host evaluation of the compiled row of one ghost cell (no GPU): up to `cap`
+ * entries (column cell number, weight) and b for inner slot l (0 if none).
+ * *nnz receives the row's entry count, *kind its segment kind (-1 uncovered). */
+int hbc_plan_row(const hbc_plan* plan, int64_t ghost_cell, int64_t l, int32_t cap, int64_t* cols,
+                 double* vals, int32_t* nnz, double* b, int32_t* kind, int32_t* rot);
+int hbc_plan_get_tune(const hbc_plan* plan, hbc_tune* out);
+/* Replace the launch shape (rebuilds the tile table).  Results are identical
+ * for every valid shape. */
+int hbc_plan_set_tune(hbc_plan* plan, const hbc_tune* t);
+
+/* ---- apply (Sec. III-B: y = A x + b on the ghost rows) ------------------------ */
+/* In place on `field` (device, `nelem` values = cells * inner, else
+ * HBC_EINVAL): every covered ghost value := (A x + b); data cells and
+ * uncovered ghosts are not written. */
+int hbc_apply(const hbc_plan* plan, void* field, int64_t nelem, void* stream);
+/* Adjoint, in place on `grad` (device, a full field of output gradients):
+ * data cells += A^T * (covered ghost gradients), then covered ghost gradients
+ * := 0 (the vector-Jacobian product of hbc_apply).  Deterministic: every data
+ * value is summed by one thread in ascending ghost order. */
+int hbc_apply_adjoint(const hbc_plan* plan, void* grad, int64_t nelem, void* stream);
+/* Time `reps` applies captured in one HIP graph on `stream`; *ms receives the
+ * mean milliseconds per apply (device events around the graph launch). */
+int hbc_time_apply(const hbc_plan* plan, void* const* fields, int64_t nelem, int32_t nfields, int32_t reps,
+                   void* stream, double* ms);
+
+/* ---- 27-point consumer (BC writes feed the inner operator, Sec. IV-C) -------- */
+/* Plans from a Cartesian halo-1 program with inner == 1 and point layout.
+ * x: ghosted field; y: data-only output, block by block, each block's data box
+ * row-major.  y = 26 x_c - (sum of the 26 neighbours) per data cell. */
+/* x_nelem / y_nelem must equal the field's cells and the data cell count. */
+/* Unfused consumer: reads the ghosts already in x (run hbc_apply first). */
+int hbc_stencil27(const hbc_plan* plan, const void* x, int64_t x_nelem, void* y, int64_t y_nelem, void* stream);
+/* Fused: reads neighbours through the BC (copy from the source block or zero)
+ * and also writes x's ghost cells, in one kernel. */
+int hbc_fused_stencil27(const hbc_plan* plan, void* x, int64_t x_nelem, void* y, int64_t y_nelem, void* stream);
+
+/* ---- FP64 interpolation weights on the device (setup, not part of an apply) -- */
+/* For ghost layer k < h and tangential index t < N of any cubed-sphere face
+ * side: base_dev[k*N + t] = first node, w_dev[(k*N + t)*4 + m] = weight of node
+ * base + m, in the neighbour's tangential index counted in the direction of
+ * the ghost face's tangential index.  Device arrays of h*N and 4*h*N. */
+int hbc_cs_lagrange_weights(int64_t N, int64_t h, int32_t* base_dev, double* w_dev, void* stream);
+
+/* ---- batched persistent apply (Sec. V-C: specialise once, run many) ---------- */
+/* Concatenate the plans' work into one tile list (plans stay owned by the caller
+ * and must outlive the batch; all plans need the same dtype and layout order). */
+int hbc_batch_create(hbc_plan* const* plans, int32_t n, hbc_batch** out);
+void hbc_batch_destroy(hbc_batch* b);
+/* Bind one device field per plan (synchronous upload of the pointer table);
+ * nelem[k] must equal plan k's cells * inner. */
+int hbc_batch_bind(hbc_batch* b, void* const* fields, const int64_t* nelem);
+/* One persistent launch applying every plan to its bound field. */
+int hbc_batch_apply(hbc_batch* b, void* stream);
+/* Capture one hbc_batch_apply into a HIP graph (re-captured on each call), then
+ * hbc_batch_graph_launch replays it. */
+int hbc_batch_graph_capture(hbc_batch* b, void* stream);
+int hbc_batch_graph_launch(hbc_batch* b, void* stream);
+int hbc_batch_get_tune(const hbc_batch* b, hbc_tune* out);
+int hbc_batch_set_tune(hbc_batch* b, const hbc_tune* t);
+/* Try candidate launch shapes on the bound fields, keep the fastest; when
+ * cache_path is not NULL, read / write the choice there (JSON lines keyed by
+ * device, dtype, layout and work size).  *ms receives the best time per apply. */
+int hbc_batch_autotune(hbc_batch* b, const char* cache_path, void* stream, double* ms);
+int hbc_batch_stats(const hbc_batch* b, hbc_stats* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HBC_H */

@@ -1,0 +1,216 @@
+// Internal structures shared by the host plan compiler and the HIP launchers.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hbc.h"
+
+namespace hbc {
+
+// ---- errors -----------------------------------------------------------------
+struct Error {
+  int code;
+  std::string msg;
+};
+void set_error(const std::string& msg);
+[[noreturn]] void fail(int code, const std::string& msg);
+
+// ---- boxes ------------------------------------------------------------------
+struct Box {
+  int nd = 0;
+  int64_t lo[HBC_MAX_DIM] = {0};
+  int64_t hi[HBC_MAX_DIM] = {0};
+  int64_t extent(int d) const { return hi[d] - lo[d]; }
+  int64_t count() const {
+    int64_t n = 1;
+    for (int d = 0; d < nd; ++d) n *= (hi[d] > lo[d] ? hi[d] - lo[d] : 0);
+    return n;
+  }
+  bool empty() const { return count() == 0; }
+  bool contains(const int64_t* c) const {
+    for (int d = 0; d < nd; ++d)
+      if (c[d] < lo[d] || c[d] >= hi[d]) return false;
+    return true;
+  }
+  bool contains(const Box& b) const {
+    for (int d = 0; d < nd; ++d)
+      if (b.lo[d] < lo[d] || b.hi[d] > hi[d]) return false;
+    return true;
+  }
+};
+bool intersects(const Box& a, const Box& b);
+Box intersect(const Box& a, const Box& b);
+// a minus b as disjoint boxes (slab decomposition, at most 2*nd pieces).
+std::vector<Box> subtract(const Box& a, const Box& b);
+
+// ---- grid -------------------------------------------------------------------
+struct Block {
+  Box full, data;
+  int64_t first_cell = 0;
+  int64_t stride[HBC_MAX_DIM] = {0};  // cell strides of the full box (row-major)
+  int64_t cells = 0;
+};
+
+struct Grid {
+  int nd = 0;
+  int64_t lo[HBC_MAX_DIM] = {0}, hi[HBC_MAX_DIM] = {0};
+  std::vector<Block> blocks;
+  int64_t ncells = 0;
+  int owner(const int64_t* c) const;          // block whose full box holds c, or -1
+  int64_t cell(int b, const int64_t* c) const;  // cell number (c inside block b's full box)
+  // global linear index over [lo, hi) -> multi-index; false if out of the box
+  bool unlinear(int64_t lin, int64_t* c) const;
+  int64_t ghost_cells() const;
+};
+
+// ---- program ----------------------------------------------------------------
+enum SubKind { SUB_MAP = 0, SUB_ZERO = 1, SUB_ELL = 2, SUB_CSR = 3, SUB_VEC = 4, SUB_ZERO_REST = 5 };
+
+struct Sub {
+  int kind = SUB_ZERO;
+  Box rows;
+  int block = -1;  // owner block of the rows (ZERO_REST: the block)
+  // map
+  int64_t M[HBC_MAX_DIM * HBC_MAX_DIM] = {0};
+  int64_t off[HBC_MAX_DIM] = {0};
+  double w = 1.0;
+  int rot = 0;  // component rotation code
+  // ell
+  int width = 0;
+  std::vector<int64_t> cols;  // global linear (ELL: rows*width; CSR: nnz)
+  std::vector<double> vals;
+  std::vector<int64_t> ptr;   // CSR
+  // vector
+  int64_t ninner = 1;
+  std::vector<double> b;
+};
+
+struct Program {
+  Grid grid;
+  std::vector<Sub> subs;
+  uint32_t flags = 0;
+};
+
+// Component rotation codes.  A 2x2 signed permutation R acts on the vector
+// slots as out_a = sign_a * in_{p(a)}.  Code bits: 1 = swap (p(0) = 1),
+// 2 = sign_0 negative, 4 = sign_1 negative.  Code 0 is the identity.
+int rot_code(const int32_t* R);  // -1 if R is not a signed permutation
+int rot_inverse(int code);
+void rot_matrix(int code, int32_t* R);
+
+// ---- device-facing tables ---------------------------------------------------
+enum SegKind { SEG_ZERO = 0, SEG_MAP = 1, SEG_ELL = 2, SEG_CSR = 3, SEG_VEC = 4 };
+constexpr int SEG_MAXD = 4;
+
+struct alignas(16) DevSeg {
+  int32_t kind;
+  int32_t nd;          // box dims after dropping extent-1 dims (1..SEG_MAXD)
+  int32_t rot;         // component rotation code
+  int32_t has_b;
+  int32_t ext[SEG_MAXD];
+  int64_t dst_base;    // cell of the box origin
+  int64_t dst_stride[SEG_MAXD];
+  int64_t src_base;    // MAP: source cell of the box origin
+  int64_t src_stride[SEG_MAXD];
+  double w;            // MAP weight (stored in FP64; FP32 plans round it)
+  int64_t tab;         // ELL/CSR: first table row of this segment
+  int64_t brow;        // first row of this segment in the b table
+  int32_t width;       // ELL width
+  int32_t b_inner;     // 1 or inner
+  int64_t nrows;
+  int64_t row_base;    // first row of this segment in the plan's row numbering
+};
+
+struct alignas(16) DevTile {
+  int32_t seg;
+  int32_t nrows;
+  int64_t row0;  // first row within the segment
+};
+
+// Adjoint: one entry per (source cell, ghost row) contribution, sorted by
+// source cell then ghost cell.
+struct CscHost {
+  std::vector<int64_t> src_cell;  // distinct source cells, ascending
+  std::vector<int64_t> ptr;       // entries of src k: ptr[k] .. ptr[k+1]-1
+  std::vector<int64_t> ghost;     // ghost cell of each entry
+  std::vector<double> w;          // weight of each entry
+  std::vector<int32_t> rot;       // inverse rotation code of each entry
+};
+
+struct AdjTile {
+  int32_t first;  // first source index
+  int32_t count;
+};
+
+struct HostTables {
+  std::vector<DevSeg> segs;
+  std::vector<DevTile> tiles;
+  std::vector<int32_t> ell_col;  // cell numbers, -1 padding
+  std::vector<double> ell_val;
+  std::vector<int64_t> csr_ptr;  // per CSR table row, absolute into csr_col
+  std::vector<int32_t> csr_col;
+  std::vector<double> csr_val;
+  std::vector<double> bval;      // b table: rows * b_inner (per segment)
+  CscHost csc;
+  std::vector<AdjTile> adj_tiles;
+};
+
+struct Layout {
+  int64_t inner = 1;
+  int order = HBC_POINT_MAJOR;
+  int64_t vec_len = 0, vec_lo = 0, vec_stride = 0;
+};
+
+struct Plan {
+  Grid grid;
+  Layout layout;
+  int dtype = HBC_F64;
+  uint32_t flags = 0;
+  HostTables host;
+  hbc_stats stats{};
+  hbc_tune tune{};
+  int vec = 1;  // elements per lane access (point-major)
+  // device storage: one allocation holding every table
+  void* dev = nullptr;
+  size_t dev_bytes = 0;
+  const DevSeg* d_segs = nullptr;
+  const DevTile* d_tiles = nullptr;
+  const int32_t* d_ell_col = nullptr;
+  const void* d_ell_val = nullptr;
+  const int64_t* d_csr_ptr = nullptr;
+  const int32_t* d_csr_col = nullptr;
+  const void* d_csr_val = nullptr;
+  const void* d_bval = nullptr;
+  void* d_csc_dev = nullptr;  // allocation holding the adjoint tables
+  const int64_t* d_csc_src = nullptr;
+  const int64_t* d_csc_ptr = nullptr;
+  const int64_t* d_csc_ghost = nullptr;
+  const void* d_csc_w = nullptr;
+  const int32_t* d_csc_rot = nullptr;
+  const AdjTile* d_adj_tiles = nullptr;
+  // fused 27-point consumer: per block and direction, source block and cell delta
+  std::vector<int64_t> st_info;  // filled lazily on first use
+  const int64_t* d_st_info = nullptr;
+  void* d_st_dev = nullptr;
+  int64_t st_n[3] = {0, 0, 0};
+  int st_nblocks = 0;
+};
+
+// host plan compiler (plan.cpp)
+void compile_plan(const Program& prog, const Layout& lay, int dtype, Plan& plan);
+void build_tiles(Plan& plan, const hbc_tune& t);
+hbc_tune default_tune(const Plan& plan);
+void build_csc(Plan& plan);
+// host evaluation of a compiled row
+int plan_row(const Plan& plan, int64_t cell, int64_t l, int cap, int64_t* cols, double* vals, int32_t* nnz,
+             double* b, int32_t* kind, int32_t* rot);
+
+// cubed sphere helpers (cubed_sphere.cpp)
+void cs_add_program(Program& p, int64_t N, int64_t h, int mode, int vector, const int32_t* base,
+                    const double* w);
+// Cartesian helpers (cubed_sphere.cpp)
+void cart_add_halo(Program& p, const int32_t* nb, const int64_t* n, int64_t h, int32_t periodic);
+
+}  // namespace hbc

@@ -1,0 +1,1056 @@
+// HIP kernels for gfx950 (CDNA4, wave64) and their launchers.
+//
+// The apply is a bandwidth-bound sparse gather/scatter (Sec. III-B: every BC
+// kind is a row of y = A x + b), so there is no MFMA here: the work is laid
+// out so that every wavefront reads and writes contiguous runs of the field.
+//   point-major fields (value (cell, l) at cell*inner + l): the lanes of a
+//     row walk its inner values with 16-byte accesses, so a ghost row is one
+//     contiguous write and each source cell one contiguous read;
+//   plane-major fields (l*ncells + cell): lanes walk consecutive rows of a
+//     segment box, which are consecutive cells along the box's last dimension.
+// Each workgroup takes tiles of one segment (a disjoint box of rows of one
+// kind, Sec. IV-C), so the kind switch is uniform per workgroup.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "device.hpp"
+
+namespace hbc {
+
+#define HIP_CHECK(x)                                                                           \
+  do {                                                                                         \
+    hipError_t e_ = (x);                                                                       \
+    if (e_ != hipSuccess) fail(HBC_EHIP, std::string(#x) + ": " + hipGetErrorString(e_));      \
+  } while (0)
+
+// ---- per-launch descriptor of one plan applied to one field ---------------------------
+struct PlanDesc {
+  void* field;
+  const DevSeg* segs;
+  const int32_t* ell_col;
+  const void* ell_val;
+  const int64_t* csr_ptr;
+  const int32_t* csr_col;
+  const void* csr_val;
+  const void* bval;
+  int64_t cs, ls;  // element offset of (cell, l) = cell*cs + l*ls
+  int64_t inner;
+  int64_t vec_lo, vec_stride, vec_len;
+  int32_t lpr_shift;  // log2 lanes per row
+  int32_t vec;        // elements per lane access
+};
+
+struct AdjDesc {
+  const int64_t* src;
+  const int64_t* ptr;
+  const int64_t* ghost;
+  const void* w;
+  const int32_t* rot;
+};
+
+struct BatchTile {
+  int32_t plan;
+  int32_t seg;
+  int32_t nrows;
+  int32_t pad;
+  int64_t row0;
+};
+
+template <typename T, int V>
+struct Pack {
+  T v[V];
+};
+
+template <typename T, int V>
+__device__ __forceinline__ Pack<T, V> ldv(const T* p) {
+  Pack<T, V> r;
+  if constexpr (V == 1) {
+    r.v[0] = *p;
+  } else {
+    typedef T vt __attribute__((ext_vector_type(V)));
+    vt x = *reinterpret_cast<const vt*>(p);
+#pragma unroll
+    for (int i = 0; i < V; ++i) r.v[i] = x[i];
+  }
+  return r;
+}
+
+template <typename T, int V>
+__device__ __forceinline__ void stv(T* p, const Pack<T, V>& r) {
+  if constexpr (V == 1) {
+    *p = r.v[0];
+  } else {
+    typedef T vt __attribute__((ext_vector_type(V)));
+    vt x;
+#pragma unroll
+    for (int i = 0; i < V; ++i) x[i] = r.v[i];
+    *reinterpret_cast<vt*>(p) = x;
+  }
+}
+
+// Source inner slot of output slot l under rotation code `rot` (see rot_code):
+// component a of the vector takes sign_a * component p(a) of the source.
+template <typename T>
+__device__ __forceinline__ int64_t rot_slot(const PlanDesc& d, int rot, int64_t l, T& sign) {
+  sign = T(1);
+  if (rot == 0 || d.vec_len == 0) return l;
+  int64_t off = l - d.vec_lo;
+  int a;
+  if (off >= 0 && off < d.vec_len) {
+    a = 0;
+  } else if (off >= d.vec_stride && off < d.vec_stride + d.vec_len) {
+    a = 1;
+    off -= d.vec_stride;
+  } else {
+    return l;
+  }
+  const int p = (rot & 1) ? 1 - a : a;
+  if (rot & (2 << a)) sign = T(-1);
+  return d.vec_lo + p * d.vec_stride + off;
+}
+
+// Rows [row0, row0 + nrows) of segment s, all inner values, by `nthr` threads.
+template <typename T, int V, bool ROWFAST>
+__device__ __forceinline__ void run_tile(const PlanDesc& d, const DevSeg& s, int64_t row0, int nrows, bool zero_only,
+                                         int tid, int nthr) {
+  const int lpr = 1 << d.lpr_shift;
+  const int rp = nthr >> d.lpr_shift;  // rows per pass
+  int lane, rsub;
+  if (ROWFAST) {
+    rsub = tid % rp;
+    lane = tid / rp;
+  } else {
+    lane = tid & (lpr - 1);
+    rsub = tid >> d.lpr_shift;
+  }
+  const int64_t nvec = d.inner / V;
+  T* __restrict__ f = static_cast<T*>(d.field);
+  const int kind = zero_only ? (int)SEG_ZERO : s.kind;
+  const bool add_b = !zero_only && s.has_b;
+  for (int r = rsub; r < nrows; r += rp) {
+    const int64_t row = row0 + r;
+    uint32_t q = (uint32_t)row;
+    int64_t dst = s.dst_base, src = s.src_base;
+    for (int k = s.nd - 1; k >= 0; --k) {
+      const uint32_t e = (uint32_t)s.ext[k];
+      const uint32_t c = q % e;
+      q /= e;
+      dst += (int64_t)c * s.dst_stride[k];
+      src += (int64_t)c * s.src_stride[k];
+    }
+    const T* bp = nullptr;
+    if (add_b) bp = static_cast<const T*>(d.bval) + s.brow + row * s.b_inner;
+    for (int64_t v = lane; v < nvec; v += lpr) {
+      const int64_t l = v * V;
+      Pack<T, V> y;
+      if (kind == SEG_ZERO) {
+#pragma unroll
+        for (int i = 0; i < V; ++i) y.v[i] = T(0);
+      } else if (kind == SEG_MAP) {
+        T sign;
+        const int64_t sl = rot_slot<T>(d, s.rot, l, sign);
+        const T w = T(s.w) * sign;
+        Pack<T, V> x = ldv<T, V>(f + src * d.cs + sl * d.ls);
+#pragma unroll
+        for (int i = 0; i < V; ++i) y.v[i] = w * x.v[i];
+      } else if (kind == SEG_ELL || kind == SEG_CSR) {
+        T sign;
+        const int64_t sl = rot_slot<T>(d, s.rot, l, sign);
+        int64_t e0, e1;
+        const int32_t* cols;
+        const T* vals;
+        if (kind == SEG_ELL) {
+          e0 = s.tab + row * s.width;
+          e1 = e0 + s.width;
+          cols = d.ell_col;
+          vals = static_cast<const T*>(d.ell_val);
+        } else {
+          e0 = d.csr_ptr[s.tab + row];
+          e1 = d.csr_ptr[s.tab + row + 1];
+          cols = d.csr_col;
+          vals = static_cast<const T*>(d.csr_val);
+        }
+        Pack<T, V> acc;
+        bool first = true;
+#pragma unroll
+        for (int i = 0; i < V; ++i) acc.v[i] = T(0);
+        for (int64_t e = e0; e < e1; ++e) {
+          const int32_t c = cols[e];
+          if (c < 0) continue;
+          const T w = vals[e];
+          Pack<T, V> x = ldv<T, V>(f + (int64_t)c * d.cs + sl * d.ls);
+          if (first) {
+#pragma unroll
+            for (int i = 0; i < V; ++i) acc.v[i] = w * x.v[i];
+            first = false;
+          } else {
+#pragma unroll
+            for (int i = 0; i < V; ++i) acc.v[i] = fma(w, x.v[i], acc.v[i]);
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < V; ++i) y.v[i] = sign * acc.v[i];
+      } else {  // SEG_VEC: b only
+#pragma unroll
+        for (int i = 0; i < V; ++i) y.v[i] = T(0);
+      }
+      if (add_b) {
+        if (s.b_inner == 1) {
+          const T bb = bp[0];
+#pragma unroll
+          for (int i = 0; i < V; ++i) y.v[i] = (kind == SEG_VEC) ? bb : y.v[i] + bb;
+        } else {
+#pragma unroll
+          for (int i = 0; i < V; ++i) y.v[i] = (kind == SEG_VEC) ? bp[l + i] : y.v[i] + bp[l + i];
+        }
+      }
+      if (ROWFAST) {
+#pragma unroll
+        for (int i = 0; i < V; ++i) f[dst * d.cs + (l + i) * d.ls] = y.v[i];
+      } else {
+        stv<T, V>(f + dst * d.cs + l * d.ls, y);
+      }
+    }
+  }
+}
+
+template <typename T, int V, bool ROWFAST>
+__global__ __launch_bounds__(1024) void k_apply(PlanDesc d, const DevTile* __restrict__ tiles, int ntiles,
+                                                int zero_only) {
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const DevTile tl = tiles[t];
+    const DevSeg s = d.segs[tl.seg];
+    run_tile<T, V, ROWFAST>(d, s, tl.row0, tl.nrows, zero_only != 0, threadIdx.x, blockDim.x);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_batch(const PlanDesc* __restrict__ descs, const BatchTile* __restrict__ tiles,
+                                                int ntiles) {
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const BatchTile bt = tiles[t];
+    const PlanDesc d = descs[bt.plan];
+    const DevSeg s = d.segs[bt.seg];
+    if (sizeof(T) == 4 && d.vec == 4)
+      run_tile<T, (sizeof(T) == 4 ? 4 : 2), false>(d, s, bt.row0, bt.nrows, false, threadIdx.x, blockDim.x);
+    else if (d.vec == 2)
+      run_tile<T, 2, false>(d, s, bt.row0, bt.nrows, false, threadIdx.x, blockDim.x);
+    else
+      run_tile<T, 1, false>(d, s, bt.row0, bt.nrows, false, threadIdx.x, blockDim.x);
+  }
+}
+
+// Adjoint gather: for each source cell, in ascending ghost order,
+//   xbar[src, l] += sum_e w_e * sign_e * ybar[ghost_e, rot_e(l)]
+template <typename T, int V, bool ROWFAST>
+__global__ __launch_bounds__(1024) void k_adjoint(PlanDesc d, AdjDesc a, const AdjTile* __restrict__ tiles,
+                                                  int ntiles) {
+  const int lpr = 1 << d.lpr_shift;
+  const int rp = (int)blockDim.x >> d.lpr_shift;
+  int lane, rsub;
+  if (ROWFAST) {
+    rsub = threadIdx.x % rp;
+    lane = threadIdx.x / rp;
+  } else {
+    lane = threadIdx.x & (lpr - 1);
+    rsub = threadIdx.x >> d.lpr_shift;
+  }
+  const int64_t nvec = d.inner / V;
+  T* __restrict__ f = static_cast<T*>(d.field);
+  const T* __restrict__ W = static_cast<const T*>(a.w);
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const AdjTile tl = tiles[t];
+    for (int r = rsub; r < tl.count; r += rp) {
+      const int64_t k = tl.first + r;
+      const int64_t cell = a.src[k];
+      const int64_t e0 = a.ptr[k], e1 = a.ptr[k + 1];
+      for (int64_t v = lane; v < nvec; v += lpr) {
+        const int64_t l = v * V;
+        Pack<T, V> acc;
+#pragma unroll
+        for (int i = 0; i < V; ++i) acc.v[i] = T(0);
+        for (int64_t e = e0; e < e1; ++e) {
+          T sign;
+          const int64_t sl = rot_slot<T>(d, a.rot[e], l, sign);
+          const T w = W[e] * sign;
+          Pack<T, V> g = ldv<T, V>(f + a.ghost[e] * d.cs + sl * d.ls);
+          if (e == e0) {
+#pragma unroll
+            for (int i = 0; i < V; ++i) acc.v[i] = w * g.v[i];
+          } else {
+#pragma unroll
+            for (int i = 0; i < V; ++i) acc.v[i] = fma(w, g.v[i], acc.v[i]);
+          }
+        }
+        T* px = f + cell * d.cs + l * d.ls;
+        if (ROWFAST) {
+#pragma unroll
+          for (int i = 0; i < V; ++i) px[i * d.ls] = px[i * d.ls] + acc.v[i];
+        } else {
+          Pack<T, V> x = ldv<T, V>(px);
+#pragma unroll
+          for (int i = 0; i < V; ++i) x.v[i] = x.v[i] + acc.v[i];
+          stv<T, V>(px, x);
+        }
+      }
+    }
+  }
+}
+
+// ---- 27-point consumer on Cartesian blocks with a one-cell halo ----------------------------
+struct StDesc {
+  int32_t nblk, nz, ny, nx;
+  int64_t sz, sy;     // cell strides of a block's full box
+  int64_t bcells;     // cells per block full box
+  const int64_t* info;  // per block, 27 directions: source block, -1 zero, -2 own ghost
+};
+
+__device__ __forceinline__ int dir_index(int dz, int dy, int dx) { return (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1); }
+
+// Value of local position (z, y, x) of block b (one-cell halo) read through
+// the BC: data cells directly, ghosts from the source block or zero.
+template <typename T>
+__device__ __forceinline__ T bc_load(const T* __restrict__ x, const StDesc& st, int b, int z, int y, int xx) {
+  const int dz = z < 0 ? -1 : (z >= st.nz ? 1 : 0);
+  const int dy = y < 0 ? -1 : (y >= st.ny ? 1 : 0);
+  const int dx = xx < 0 ? -1 : (xx >= st.nx ? 1 : 0);
+  int64_t blk = b;
+  if (dz | dy | dx) {
+    blk = st.info[b * 27 + dir_index(dz, dy, dx)];
+    if (blk == -1) return T(0);
+    if (blk == -2) {
+      blk = b;
+    } else {
+      z -= dz * st.nz;
+      y -= dy * st.ny;
+      xx -= dx * st.nx;
+    }
+  }
+  return x[blk * st.bcells + (int64_t)(z + 1) * st.sz + (int64_t)(y + 1) * st.sy + (xx + 1)];
+}
+
+// One thread per (x, y) column of a 64 x 4 tile, marching over ZC planes.
+// y = 27 x_c - (box sum over 3x3x3) = 26 x_c - sum of the 26 neighbours.
+template <typename T, bool FUSED>
+__global__ __launch_bounds__(256) void k_stencil27(const T* __restrict__ x, T* __restrict__ yout, T* __restrict__ xg,
+                                                   StDesc st, int zc) {
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int ntx = (st.nx + 63) / 64, nty = (st.ny + 3) / 4;
+  int bid = blockIdx.x;
+  const int tile_x = bid % ntx;
+  bid /= ntx;
+  const int tile_y = bid % nty;
+  bid /= nty;
+  const int nzc = (st.nz + zc - 1) / zc;
+  const int tile_z = bid % nzc;
+  const int b = bid / nzc;
+  const int xx = tile_x * 64 + tx, yy = tile_y * 4 + ty;
+  if (xx >= st.nx || yy >= st.ny || b >= st.nblk) return;
+  const int z0 = tile_z * zc, z1 = min(z0 + zc, st.nz);
+  auto plane = [&](int z, T& center) -> T {
+    T s = T(0);
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        T v;
+        if (FUSED)
+          v = bc_load<T>(x, st, b, z, yy + dy, xx + dx);
+        else
+          v = x[b * st.bcells + (int64_t)(z + 1) * st.sz + (int64_t)(yy + dy + 1) * st.sy + (xx + dx + 1)];
+        if (dy == 0 && dx == 0) center = v;
+        s += v;
+      }
+    return s;
+  };
+  T c_prev, c_cur, c_next;
+  T s_prev = plane(z0 - 1, c_prev);
+  T s_cur = plane(z0, c_cur);
+  const int64_t yb = (int64_t)b * st.nz * st.ny * st.nx + (int64_t)yy * st.nx + xx;
+  for (int z = z0; z < z1; ++z) {
+    T s_next = plane(z + 1, c_next);
+    const T box = (s_prev + s_cur) + s_next;
+    yout[yb + (int64_t)z * st.ny * st.nx] = T(27) * c_cur - box;
+    s_prev = s_cur;
+    s_cur = s_next;
+    c_cur = c_next;
+  }
+  if (FUSED) {
+    // materialise the ghosts whose nearest data cell is in this column
+    const bool ex = xx == 0 || xx == st.nx - 1, ey = yy == 0 || yy == st.ny - 1;
+    for (int z = z0; z < z1; ++z) {
+      const bool ez = z == 0 || z == st.nz - 1;
+      if (!(ex || ey || ez)) continue;
+      for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dx = -1; dx <= 1; ++dx) {
+            if (!(dz | dy | dx)) continue;
+            const int gz = z + dz, gy = yy + dy, gx = xx + dx;
+            // a ghost: outside in every dimension where it moves
+            if (dz && gz >= 0 && gz < st.nz) continue;
+            if (dy && gy >= 0 && gy < st.ny) continue;
+            if (dx && gx >= 0 && gx < st.nx) continue;
+            const int64_t src = st.info[b * 27 + dir_index(dz, dy, dx)];
+            if (src == -2) continue;  // uncovered ghost: left as it is
+            const T v = bc_load<T>(x, st, b, gz, gy, gx);
+            xg[b * st.bcells + (int64_t)(gz + 1) * st.sz + (int64_t)(gy + 1) * st.sy + (gx + 1)] = v;
+          }
+    }
+  }
+}
+
+// ---- FP64 cubed-sphere interpolation weights ------------------------------------------
+// Ghost layer k beyond an edge, tangential index t: the ray through the ghost
+// meets the neighbour face on its grid line at distance k from the edge, at
+// tangential angle atan(tan(beta_t) / tan(pi/4 + (k + 1/2) D)), D = pi / 2N.
+__global__ void k_cs_weights(int N, int h, int32_t* __restrict__ base, double* __restrict__ w) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= h * N) return;
+  const int k = idx / N, t = idx % N;
+  const double q = M_PI / 4.0;
+  const double D = M_PI / (2.0 * N);
+  const double ta = tan(q + (k + 0.5) * D);
+  const double tb = tan(-q + (t + 0.5) * D);
+  double s = (atan(tb / ta) + q) / D - 0.5;
+  const double rs = rint(s);
+  if (fabs(s - rs) <= 1e-9) s = rs;
+  int b0 = (int)floor(s) - 1;
+  b0 = b0 < 0 ? 0 : (b0 > N - 4 ? N - 4 : b0);
+  const double d0 = s - b0, d1 = s - (b0 + 1), d2 = s - (b0 + 2), d3 = s - (b0 + 3);
+  base[idx] = b0;
+  w[4 * idx + 0] = -d1 * d2 * d3 / 6.0;
+  w[4 * idx + 1] = d0 * d2 * d3 / 2.0;
+  w[4 * idx + 2] = -d0 * d1 * d3 / 2.0;
+  w[4 * idx + 3] = d0 * d1 * d2 / 6.0;
+}
+
+// ---- device tables -------------------------------------------------------------------------
+namespace {
+
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+struct Packer {
+  std::vector<char> buf;
+  size_t put(const void* p, size_t n) {
+    size_t off = align256(buf.size());
+    buf.resize(off + align256(std::max<size_t>(n, 1)));
+    if (n) std::memcpy(buf.data() + off, p, n);
+    return off;
+  }
+  template <class V>
+  size_t vec(const V& v) {
+    return put(v.data(), v.size() * sizeof(typename V::value_type));
+  }
+  size_t reals(const std::vector<double>& v, int dtype) {
+    if (dtype == HBC_F64) return vec(v);
+    std::vector<float> f(v.size());
+    for (size_t k = 0; k < v.size(); ++k) f[k] = (float)v[k];  // round to nearest
+    return vec(f);
+  }
+};
+
+int ilog2(int v) {
+  int s = 0;
+  while ((1 << s) < v) ++s;
+  return s;
+}
+
+PlanDesc make_desc(const Plan& p, void* field) {
+  PlanDesc d{};
+  d.field = field;
+  d.segs = p.d_segs;
+  d.ell_col = p.d_ell_col;
+  d.ell_val = p.d_ell_val;
+  d.csr_ptr = p.d_csr_ptr;
+  d.csr_col = p.d_csr_col;
+  d.csr_val = p.d_csr_val;
+  d.bval = p.d_bval;
+  d.inner = p.layout.inner;
+  if (p.layout.order == HBC_POINT_MAJOR) {
+    d.cs = p.layout.inner;
+    d.ls = 1;
+  } else {
+    d.cs = 1;
+    d.ls = p.grid.ncells;
+  }
+  d.vec_lo = p.layout.vec_lo;
+  d.vec_stride = p.layout.vec_stride;
+  d.vec_len = p.layout.vec_len;
+  d.lpr_shift = ilog2(p.tune.lanes_per_row);
+  d.vec = p.vec;
+  return d;
+}
+
+hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace
+
+void device_free_plan(Plan& p) {
+  if (p.dev) (void)hipFree(p.dev);
+  p.dev = nullptr;
+  p.dev_bytes = 0;
+  if (p.d_st_dev) (void)hipFree(p.d_st_dev);
+  p.d_st_dev = nullptr;
+  p.d_st_info = nullptr;
+  if (p.d_adj_tiles) (void)hipFree(const_cast<AdjTile*>(p.d_adj_tiles));
+  p.d_adj_tiles = nullptr;
+  if (p.d_csc_dev) (void)hipFree(p.d_csc_dev);
+  p.d_csc_dev = nullptr;
+  p.d_csc_src = nullptr;
+  if (p.d_tiles) (void)hipFree(const_cast<DevTile*>(p.d_tiles));
+  p.d_tiles = nullptr;
+}
+
+void device_upload_plan(Plan& p) {
+  Packer pk;
+  const HostTables& T = p.host;
+  size_t o_segs = pk.vec(T.segs);
+  size_t o_ellc = pk.vec(T.ell_col);
+  size_t o_ellv = pk.reals(T.ell_val, p.dtype);
+  size_t o_csrp = pk.vec(T.csr_ptr);
+  size_t o_csrc = pk.vec(T.csr_col);
+  size_t o_csrv = pk.reals(T.csr_val, p.dtype);
+  size_t o_b = pk.reals(T.bval, p.dtype);
+  void* dev = nullptr;
+  hipError_t e = hipMalloc(&dev, pk.buf.size());
+  if (e != hipSuccess) fail(e == hipErrorOutOfMemory ? HBC_ENOMEM : HBC_EHIP, std::string("hipMalloc: ") + hipGetErrorString(e));
+  p.dev = dev;
+  p.dev_bytes = pk.buf.size();
+  HIP_CHECK(hipMemcpy(dev, pk.buf.data(), pk.buf.size(), hipMemcpyHostToDevice));
+  char* b = static_cast<char*>(dev);
+  p.d_segs = reinterpret_cast<const DevSeg*>(b + o_segs);
+  p.d_ell_col = reinterpret_cast<const int32_t*>(b + o_ellc);
+  p.d_ell_val = b + o_ellv;
+  p.d_csr_ptr = reinterpret_cast<const int64_t*>(b + o_csrp);
+  p.d_csr_col = reinterpret_cast<const int32_t*>(b + o_csrc);
+  p.d_csr_val = b + o_csrv;
+  p.d_bval = b + o_b;
+  device_upload_tiles(p);
+}
+
+void device_upload_tiles(Plan& p) {
+  if (p.d_tiles) HIP_CHECK(hipFree(const_cast<DevTile*>(p.d_tiles)));
+  p.d_tiles = nullptr;
+  void* t = nullptr;
+  size_t n = std::max<size_t>(1, p.host.tiles.size()) * sizeof(DevTile);
+  HIP_CHECK(hipMalloc(&t, n));
+  if (!p.host.tiles.empty())
+    HIP_CHECK(hipMemcpy(t, p.host.tiles.data(), p.host.tiles.size() * sizeof(DevTile), hipMemcpyHostToDevice));
+  p.d_tiles = static_cast<const DevTile*>(t);
+}
+
+void device_upload_csc(Plan& p) {
+  Packer pk;
+  const CscHost& C = p.host.csc;
+  size_t o_src = pk.vec(C.src_cell);
+  size_t o_ptr = pk.vec(C.ptr);
+  size_t o_gh = pk.vec(C.ghost);
+  size_t o_w = pk.reals(C.w, p.dtype);
+  size_t o_rot = pk.vec(C.rot);
+  void* dev = nullptr;
+  HIP_CHECK(hipMalloc(&dev, pk.buf.size()));
+  p.d_csc_dev = dev;
+  HIP_CHECK(hipMemcpy(dev, pk.buf.data(), pk.buf.size(), hipMemcpyHostToDevice));
+  char* b = static_cast<char*>(dev);
+  p.d_csc_src = reinterpret_cast<const int64_t*>(b + o_src);
+  p.d_csc_ptr = reinterpret_cast<const int64_t*>(b + o_ptr);
+  p.d_csc_ghost = reinterpret_cast<const int64_t*>(b + o_gh);
+  p.d_csc_w = b + o_w;
+  p.d_csc_rot = reinterpret_cast<const int32_t*>(b + o_rot);
+  void* t = nullptr;
+  size_t nt = std::max<size_t>(1, p.host.adj_tiles.size());
+  HIP_CHECK(hipMalloc(&t, nt * sizeof(AdjTile)));
+  if (!p.host.adj_tiles.empty())
+    HIP_CHECK(hipMemcpy(t, p.host.adj_tiles.data(), p.host.adj_tiles.size() * sizeof(AdjTile), hipMemcpyHostToDevice));
+  p.d_adj_tiles = static_cast<const AdjTile*>(t);
+}
+
+template <typename T>
+static void launch_apply_t(const Plan& p, const PlanDesc& d, hipStream_t st, bool zero_only) {
+  const int nt = (int)p.host.tiles.size();
+  if (nt == 0) return;
+  const int grid = p.tune.persistent > 0 ? std::min(p.tune.persistent, nt) : nt;
+  const int blk = p.tune.block;
+  const int z = zero_only ? 1 : 0;
+  if (p.layout.order == HBC_PLANE_MAJOR) {
+    hipLaunchKernelGGL((k_apply<T, 1, true>), dim3(grid), dim3(blk), 0, st, d, p.d_tiles, nt, z);
+  } else if (p.vec == 4) {
+    hipLaunchKernelGGL((k_apply<T, 4, false>), dim3(grid), dim3(blk), 0, st, d, p.d_tiles, nt, z);
+  } else if (p.vec == 2) {
+    hipLaunchKernelGGL((k_apply<T, 2, false>), dim3(grid), dim3(blk), 0, st, d, p.d_tiles, nt, z);
+  } else {
+    hipLaunchKernelGGL((k_apply<T, 1, false>), dim3(grid), dim3(blk), 0, st, d, p.d_tiles, nt, z);
+  }
+  HIP_CHECK(hipGetLastError());
+}
+
+void device_apply(const Plan& p, void* field, void* stream, bool zero_only) {
+  PlanDesc d = make_desc(p, field);
+  if (p.dtype == HBC_F64)
+    launch_apply_t<double>(p, d, S(stream), zero_only);
+  else
+    launch_apply_t<float>(p, d, S(stream), zero_only);
+}
+
+template <typename T>
+static void launch_adjoint_t(const Plan& p, const PlanDesc& d, hipStream_t st) {
+  AdjDesc a{p.d_csc_src, p.d_csc_ptr, p.d_csc_ghost, p.d_csc_w, p.d_csc_rot};
+  const int nt = (int)p.host.adj_tiles.size();
+  if (nt > 0) {
+    const int blk = p.tune.block;
+    if (p.layout.order == HBC_PLANE_MAJOR)
+      hipLaunchKernelGGL((k_adjoint<T, 1, true>), dim3(nt), dim3(blk), 0, st, d, a, p.d_adj_tiles, nt);
+    else if (p.vec == 4)
+      hipLaunchKernelGGL((k_adjoint<T, 4, false>), dim3(nt), dim3(blk), 0, st, d, a, p.d_adj_tiles, nt);
+    else if (p.vec == 2)
+      hipLaunchKernelGGL((k_adjoint<T, 2, false>), dim3(nt), dim3(blk), 0, st, d, a, p.d_adj_tiles, nt);
+    else
+      hipLaunchKernelGGL((k_adjoint<T, 1, false>), dim3(nt), dim3(blk), 0, st, d, a, p.d_adj_tiles, nt);
+    HIP_CHECK(hipGetLastError());
+  }
+  launch_apply_t<T>(p, d, st, true);  // covered ghost gradients := 0, after the gather
+}
+
+void device_adjoint(const Plan& p, void* grad, void* stream) {
+  PlanDesc d = make_desc(p, grad);
+  if (p.dtype == HBC_F64)
+    launch_adjoint_t<double>(p, d, S(stream));
+  else
+    launch_adjoint_t<float>(p, d, S(stream));
+}
+
+// Direction table of the 27-point consumer: for every block and each of its 26
+// ghost regions, the block the BC copies from (translation by one block), -1
+// for zero rows or -2 for uncovered ghosts; anything else cannot be fused.
+static void build_stencil_info(Plan& p) {
+  const Grid& g = p.grid;
+  if (g.nd != 4) fail(HBC_EUNSUPPORTED, "the 27-point consumer needs a Cartesian block grid (block, z, y, x)");
+  if (p.layout.inner != 1) fail(HBC_EUNSUPPORTED, "the 27-point consumer needs inner == 1");
+  const Block& B0 = g.blocks[0];
+  int64_t n[3];
+  for (int d = 0; d < 3; ++d) n[d] = B0.data.extent(d + 1);
+  for (const Block& B : g.blocks) {
+    if (B.full.extent(0) != 1) fail(HBC_EUNSUPPORTED, "blocks must have extent 1 along coordinate 0");
+    for (int d = 0; d < 3; ++d)
+      if (B.data.extent(d + 1) != n[d] || B.data.lo[d + 1] - B.full.lo[d + 1] != 1 ||
+          B.full.hi[d + 1] - B.data.hi[d + 1] != 1)
+        fail(HBC_EUNSUPPORTED, "the 27-point consumer needs equal blocks with a one-cell halo");
+  }
+  const int nb = (int)g.blocks.size();
+  std::vector<int64_t> info((size_t)nb * 27, 0);
+  int64_t cols[64];
+  double vals[64];
+  for (int b = 0; b < nb; ++b) {
+    const Block& B = g.blocks[b];
+    for (int dz = -1; dz <= 1; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int di = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+          if (!(dz | dy | dx)) {
+            info[(size_t)b * 27 + di] = b;
+            continue;
+          }
+          const int dd[3] = {dz, dy, dx};
+          int64_t lo[3], hi[3];
+          for (int d = 0; d < 3; ++d) {
+            lo[d] = dd[d] < 0 ? -1 : dd[d] == 0 ? 0 : n[d];
+            hi[d] = dd[d] < 0 ? 0 : dd[d] == 0 ? n[d] : n[d] + 1;
+          }
+          int64_t verdict = -3;  // undecided
+          for (int64_t z = lo[0]; z < hi[0]; ++z)
+            for (int64_t y = lo[1]; y < hi[1]; ++y)
+              for (int64_t x = lo[2]; x < hi[2]; ++x) {
+                int64_t c[4] = {B.full.lo[0], z, y, x};
+                const int64_t cell = g.cell(b, c);
+                int32_t nnz, kind, rot;
+                double bb;
+                plan_row(p, cell, 0, 64, cols, vals, &nnz, &bb, &kind, &rot);
+                int64_t v;
+                if (kind < 0) {
+                  v = -2;
+                } else if (kind == SEG_ZERO && bb == 0.0) {
+                  v = -1;
+                } else if (kind == SEG_MAP && nnz == 1 && vals[0] == 1.0 && rot == 0 && bb == 0.0) {
+                  // must be the translated cell (z - dz*nz, ...) of some block
+                  int64_t srcb = -1;
+                  for (int ob = 0; ob < nb; ++ob) {
+                    int64_t oc[4] = {g.blocks[ob].full.lo[0], z - dz * n[0], y - dy * n[1], x - dx * n[2]};
+                    if (g.blocks[ob].data.contains(oc) && g.cell(ob, oc) == cols[0]) srcb = ob;
+                  }
+                  if (srcb < 0) fail(HBC_EUNSUPPORTED, "a halo copy is not a translation by one block");
+                  v = srcb;
+                } else {
+                  fail(HBC_EUNSUPPORTED, "the fused consumer supports copy and zero rows only");
+                }
+                if (verdict == -3)
+                  verdict = v;
+                else if (verdict != v)
+                  fail(HBC_EUNSUPPORTED, "one ghost region mixes BC kinds or source blocks");
+              }
+          info[(size_t)b * 27 + di] = verdict;
+        }
+  }
+  p.st_info = info;
+  for (int d = 0; d < 3; ++d) p.st_n[d] = n[d];
+  p.st_nblocks = nb;
+  void* dev = nullptr;
+  HIP_CHECK(hipMalloc(&dev, info.size() * sizeof(int64_t)));
+  HIP_CHECK(hipMemcpy(dev, info.data(), info.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+  p.d_st_dev = dev;
+  p.d_st_info = static_cast<const int64_t*>(dev);
+}
+
+void device_stencil27(Plan& p, const void* x, void* y, void* stream, bool fused, void* xghost) {
+  if (!p.d_st_info) build_stencil_info(p);
+  StDesc st;
+  st.nblk = p.st_nblocks;
+  st.nz = (int32_t)p.st_n[0];
+  st.ny = (int32_t)p.st_n[1];
+  st.nx = (int32_t)p.st_n[2];
+  st.sy = st.nx + 2;
+  st.sz = (int64_t)(st.ny + 2) * st.sy;
+  st.bcells = (int64_t)(st.nz + 2) * st.sz;
+  st.info = p.d_st_info;
+  const int zc = 16;
+  const int ntx = (st.nx + 63) / 64, nty = (st.ny + 3) / 4, nzc = (st.nz + zc - 1) / zc;
+  const int64_t grid = (int64_t)ntx * nty * nzc * st.nblk;
+  if (grid >= (int64_t(1) << 31)) fail(HBC_EUNSUPPORTED, "grid too large for the 27-point consumer");
+  hipStream_t s = S(stream);
+  if (p.dtype == HBC_F64) {
+    if (fused)
+      hipLaunchKernelGGL((k_stencil27<double, true>), dim3((unsigned)grid), dim3(256), 0, s,
+                         static_cast<const double*>(x), static_cast<double*>(y), static_cast<double*>(xghost), st, zc);
+    else
+      hipLaunchKernelGGL((k_stencil27<double, false>), dim3((unsigned)grid), dim3(256), 0, s,
+                         static_cast<const double*>(x), static_cast<double*>(y), nullptr, st, zc);
+  } else {
+    if (fused)
+      hipLaunchKernelGGL((k_stencil27<float, true>), dim3((unsigned)grid), dim3(256), 0, s,
+                         static_cast<const float*>(x), static_cast<float*>(y), static_cast<float*>(xghost), st, zc);
+    else
+      hipLaunchKernelGGL((k_stencil27<float, false>), dim3((unsigned)grid), dim3(256), 0, s,
+                         static_cast<const float*>(x), static_cast<float*>(y), nullptr, st, zc);
+  }
+  HIP_CHECK(hipGetLastError());
+}
+
+void device_cs_weights(int64_t N, int64_t h, int32_t* base, double* w, void* stream) {
+  if (N * h >= (int64_t(1) << 30)) fail(HBC_EUNSUPPORTED, "grid too large");
+  const int n = (int)(N * h);
+  hipLaunchKernelGGL(k_cs_weights, dim3((n + 255) / 256), dim3(256), 0, S(stream), (int)N, (int)h, base, w);
+  HIP_CHECK(hipGetLastError());
+}
+
+// ---- timing of plain applies under a captured graph ------------------------------------
+namespace {
+struct OwnedStream {
+  hipStream_t s = nullptr;
+  bool owned = false;
+  explicit OwnedStream(void* given) {
+    if (given) {
+      s = S(given);
+    } else {
+      HIP_CHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+      owned = true;
+    }
+  }
+  ~OwnedStream() {
+    if (owned) (void)hipStreamDestroy(s);
+  }
+};
+}  // namespace
+
+double device_time_apply(const Plan& p, void* const* fields, int nfields, int reps, void* stream) {
+  OwnedStream os(stream);
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  HIP_CHECK(hipStreamBeginCapture(os.s, hipStreamCaptureModeThreadLocal));
+  try {
+    for (int r = 0; r < reps; ++r) device_apply(p, fields[r % nfields], os.s, false);
+  } catch (...) {
+    (void)hipStreamEndCapture(os.s, &graph);
+    if (graph) (void)hipGraphDestroy(graph);
+    throw;
+  }
+  HIP_CHECK(hipStreamEndCapture(os.s, &graph));
+  HIP_CHECK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  hipEvent_t e0, e1;
+  HIP_CHECK(hipEventCreate(&e0));
+  HIP_CHECK(hipEventCreate(&e1));
+  HIP_CHECK(hipGraphLaunch(exec, os.s));  // warm
+  HIP_CHECK(hipEventRecord(e0, os.s));
+  HIP_CHECK(hipGraphLaunch(exec, os.s));
+  HIP_CHECK(hipEventRecord(e1, os.s));
+  HIP_CHECK(hipEventSynchronize(e1));
+  float ms = 0;
+  HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipGraphExecDestroy(exec);
+  (void)hipGraphDestroy(graph);
+  return (double)ms / reps;
+}
+
+// ---- batched persistent apply ------------------------------------------------------------
+struct Batch {
+  std::vector<Plan*> plans;
+  int dtype = HBC_F64;
+  hbc_tune tune{};
+  std::vector<PlanDesc> descs;
+  PlanDesc* d_descs = nullptr;
+  std::vector<BatchTile> tiles;
+  BatchTile* d_tiles = nullptr;
+  bool bound = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hbc_stats stats{};
+};
+
+static void batch_tiles(Batch* b) {
+  // per plan: rows per tile so that a tile holds about tune.rows_per_tile inner values
+  std::vector<std::vector<BatchTile>> per(b->plans.size());
+  for (size_t k = 0; k < b->plans.size(); ++k) {
+    const Plan& p = *b->plans[k];
+    const int64_t I = p.layout.inner;
+    int lpr = p.tune.lanes_per_row;
+    if (b->tune.lanes_per_row > 0) lpr = std::min(lpr, b->tune.lanes_per_row);
+    b->descs[k].lpr_shift = ilog2(lpr);
+    const int64_t rp = std::max<int64_t>(1, b->tune.block / lpr);
+    int64_t rpt = std::max<int64_t>(1, (int64_t)b->tune.rows_per_tile / I);
+    rpt = ((rpt + rp - 1) / rp) * rp;
+    rpt = std::min<int64_t>(rpt, 1 << 20);
+    for (size_t s = 0; s < p.host.segs.size(); ++s) {
+      const DevSeg& sg = p.host.segs[s];
+      for (int64_t r0 = 0; r0 < sg.nrows; r0 += rpt)
+        per[k].push_back(BatchTile{(int32_t)k, (int32_t)s, (int32_t)std::min<int64_t>(rpt, sg.nrows - r0), 0, r0});
+    }
+  }
+  // interleave plans round-robin so that every part of the launch mixes grids
+  b->tiles.clear();
+  size_t more = 1;
+  for (size_t i = 0; more; ++i) {
+    more = 0;
+    for (auto& v : per)
+      if (i < v.size()) {
+        b->tiles.push_back(v[i]);
+        more = 1;
+      }
+  }
+  if (b->d_tiles) HIP_CHECK(hipFree(b->d_tiles));
+  b->d_tiles = nullptr;
+  HIP_CHECK(hipMalloc(&b->d_tiles, std::max<size_t>(1, b->tiles.size()) * sizeof(BatchTile)));
+  if (!b->tiles.empty())
+    HIP_CHECK(hipMemcpy(b->d_tiles, b->tiles.data(), b->tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice));
+  b->stats.tiles = (int64_t)b->tiles.size();
+  if (b->bound) device_batch_bind(b, nullptr);
+}
+
+Batch* device_batch_create(Plan* const* plans, int n) {
+  Batch* b = new Batch;
+  try {
+    b->plans.assign(plans, plans + n);
+    b->dtype = plans[0]->dtype;
+    b->descs.resize(n);
+    std::memset(&b->stats, 0, sizeof(b->stats));
+    for (int k = 0; k < n; ++k) {
+      b->descs[k] = make_desc(*plans[k], nullptr);
+      const hbc_stats& s = plans[k]->stats;
+      b->stats.ghost_cells += s.ghost_cells;
+      b->stats.rows_covered += s.rows_covered;
+      b->stats.rows_uncovered += s.rows_uncovered;
+      b->stats.rows_zero += s.rows_zero;
+      b->stats.rows_map += s.rows_map;
+      b->stats.rows_ell += s.rows_ell;
+      b->stats.rows_csr += s.rows_csr;
+      b->stats.rows_vector_only += s.rows_vector_only;
+      b->stats.rows_with_b += s.rows_with_b;
+      b->stats.nnz += s.nnz;
+      b->stats.unique_sources += s.unique_sources;
+      b->stats.segments += s.segments;
+      b->stats.ghost_values += s.ghost_values;
+      b->stats.alg_bytes += s.alg_bytes;
+      b->stats.alg_bytes_adjoint += s.alg_bytes_adjoint;
+      b->stats.table_bytes += (int64_t)plans[k]->dev_bytes;
+    }
+    HIP_CHECK(hipMalloc(&b->d_descs, n * sizeof(PlanDesc)));
+    b->tune.block = 256;
+    b->tune.lanes_per_row = 0;
+    b->tune.rows_per_tile = 8192;
+    int dev = 0, ncu = 256;
+    HIP_CHECK(hipGetDevice(&dev));
+    HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    b->tune.persistent = 4 * ncu;
+    batch_tiles(b);
+  } catch (...) {
+    device_batch_destroy(b);
+    throw;
+  }
+  return b;
+}
+
+void device_batch_destroy(Batch* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->d_descs) (void)hipFree(b->d_descs);
+  if (b->d_tiles) (void)hipFree(b->d_tiles);
+  delete b;
+}
+
+void device_batch_bind(Batch* b, void* const* fields) {
+  if (fields)
+    for (size_t k = 0; k < b->plans.size(); ++k) {
+      if (!fields[k] || ((uintptr_t)fields[k] & 15)) fail(HBC_EINVAL, "batch field NULL or not 16-byte aligned");
+      b->descs[k].field = fields[k];
+    }
+  HIP_CHECK(hipMemcpy(b->d_descs, b->descs.data(), b->descs.size() * sizeof(PlanDesc), hipMemcpyHostToDevice));
+  b->bound = true;
+}
+
+void device_batch_apply(Batch* b, void* stream) {
+  if (!b->bound) fail(HBC_EINVAL, "bind fields before applying a batch");
+  const int nt = (int)b->tiles.size();
+  if (nt == 0) return;
+  const int grid = b->tune.persistent > 0 ? std::min(b->tune.persistent, nt) : nt;
+  if (b->dtype == HBC_F64)
+    hipLaunchKernelGGL(k_batch<double>, dim3(grid), dim3(b->tune.block), 0, S(stream), b->d_descs, b->d_tiles, nt);
+  else
+    hipLaunchKernelGGL(k_batch<float>, dim3(grid), dim3(b->tune.block), 0, S(stream), b->d_descs, b->d_tiles, nt);
+  HIP_CHECK(hipGetLastError());
+}
+
+void device_batch_capture(Batch* b, void* stream) {
+  if (!stream) fail(HBC_EINVAL, "graph capture needs a stream");
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  HIP_CHECK(hipStreamBeginCapture(S(stream), hipStreamCaptureModeThreadLocal));
+  try {
+    device_batch_apply(b, stream);
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(S(stream), &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  HIP_CHECK(hipStreamEndCapture(S(stream), &b->graph));
+  HIP_CHECK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+}
+
+void device_batch_launch_graph(Batch* b, void* stream) {
+  if (!b->exec) fail(HBC_EINVAL, "no captured graph");
+  HIP_CHECK(hipGraphLaunch(b->exec, S(stream)));
+}
+
+hbc_tune device_batch_get_tune(const Batch* b) { return b->tune; }
+
+void device_batch_set_tune(Batch* b, const hbc_tune& t) {
+  if (t.block < 64 || t.block > 1024 || t.block % 64) fail(HBC_EINVAL, "block must be a multiple of 64 in [64, 1024]");
+  if (t.lanes_per_row < 0 || (t.lanes_per_row & (t.lanes_per_row - 1))) fail(HBC_EINVAL, "lanes_per_row: 0 or a power of two");
+  if (t.rows_per_tile < 1 || t.persistent < 0) fail(HBC_EINVAL, "bad tile size or persistent count");
+  b->tune = t;
+  batch_tiles(b);
+}
+
+void device_batch_stats(const Batch* b, hbc_stats* out) { *out = b->stats; }
+
+static std::string batch_key(const Batch* b) {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  HIP_CHECK(hipGetDevice(&dev));
+  HIP_CHECK(hipGetDeviceProperties(&prop, dev));
+  std::ostringstream k;
+  k << prop.gcnArchName << "|" << (b->dtype == HBC_F64 ? "f64" : "f32") << "|point|" << b->plans.size() << "|"
+    << b->stats.ghost_values << "|" << b->stats.rows_covered;
+  std::string s = k.str();
+  for (char& c : s)
+    if (c == '"' || c == '\\') c = '_';
+  return s;
+}
+
+static double time_batch(Batch* b, hipStream_t s, int reps) {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  for (int r = 0; r < reps; ++r) device_batch_apply(b, s);
+  HIP_CHECK(hipStreamEndCapture(s, &graph));
+  HIP_CHECK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  hipEvent_t e0, e1;
+  HIP_CHECK(hipEventCreate(&e0));
+  HIP_CHECK(hipEventCreate(&e1));
+  HIP_CHECK(hipGraphLaunch(exec, s));
+  HIP_CHECK(hipEventRecord(e0, s));
+  HIP_CHECK(hipGraphLaunch(exec, s));
+  HIP_CHECK(hipEventRecord(e1, s));
+  HIP_CHECK(hipEventSynchronize(e1));
+  float ms = 0;
+  HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipGraphExecDestroy(exec);
+  (void)hipGraphDestroy(graph);
+  return (double)ms / reps;
+}
+
+double device_batch_autotune(Batch* b, const char* cache_path, void* stream) {
+  if (!b->bound) fail(HBC_EINVAL, "bind fields before tuning a batch");
+  OwnedStream os(stream);
+  const std::string key = batch_key(b);
+  if (cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    while (std::getline(in, line)) {
+      if (line.find("\"key\": \"" + key + "\"") == std::string::npos) continue;
+      hbc_tune t{};
+      double ms = 0;
+      if (std::sscanf(line.c_str() + line.find("\"block\""), "\"block\": %d, \"lanes_per_row\": %d, \"rows_per_tile\": %d, \"persistent\": %d, \"ms\": %lf",
+                      &t.block, &t.lanes_per_row, &t.rows_per_tile, &t.persistent, &ms) == 5) {
+        device_batch_set_tune(b, t);
+        return time_batch(b, os.s, 5);
+      }
+    }
+  }
+  int dev = 0, ncu = 256;
+  HIP_CHECK(hipGetDevice(&dev));
+  HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  const hbc_tune start = b->tune;
+  hbc_tune best = start;
+  double best_ms = 1e30;
+  const int blocks[] = {256, 512};
+  const int elems[] = {4096, 8192, 16384, 32768};
+  const int pers[] = {0, 2, 4, 8};
+  const int lprs[] = {0, 32};
+  for (int bl : blocks)
+    for (int el : elems)
+      for (int pf : pers)
+        for (int lp : lprs) {
+          hbc_tune t{bl, lp, el, pf * ncu};
+          device_batch_set_tune(b, t);
+          double ms = time_batch(b, os.s, 3);
+          if (ms < best_ms) {
+            best_ms = ms;
+            best = t;
+          }
+        }
+  device_batch_set_tune(b, best);
+  best_ms = time_batch(b, os.s, 5);
+  if (cache_path) {
+    std::ofstream out(cache_path, std::ios::app);
+    out << "{\"key\": \"" << key << "\", \"block\": " << best.block << ", \"lanes_per_row\": " << best.lanes_per_row
+        << ", \"rows_per_tile\": " << best.rows_per_tile << ", \"persistent\": " << best.persistent
+        << ", \"ms\": " << best_ms << "}\n";
+  }
+  return best_ms;
+}
+
+}  // namespace hbc

@@ -1,0 +1,696 @@
+// Host plan compiler: program of basic sub-matrices -> disjoint row boxes ->
+// device segment / ELL / CSR / b / adjoint tables and a tile list.
+//
+// Sec. IV-B turns overlapping validity predicates into a non-overlapping set
+// whose members each imply or exclude every original predicate; Sec. IV-C then
+// splits the iteration space into disjoint convex pieces that run
+// independently.  Here every validity set is a box, so both steps are integer
+// box arithmetic: a box refinement yields pieces that each carry the list of
+// sub-matrices / sub-vectors covering them, and each piece becomes one
+// segment (a box with one kind of row).
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <unordered_map>
+
+#include "hbc_internal.hpp"
+
+namespace hbc {
+
+// ---- boxes --------------------------------------------------------------------
+bool intersects(const Box& a, const Box& b) {
+  for (int d = 0; d < a.nd; ++d)
+    if (std::max(a.lo[d], b.lo[d]) >= std::min(a.hi[d], b.hi[d])) return false;
+  return true;
+}
+
+Box intersect(const Box& a, const Box& b) {
+  Box r = a;
+  for (int d = 0; d < a.nd; ++d) {
+    r.lo[d] = std::max(a.lo[d], b.lo[d]);
+    r.hi[d] = std::min(a.hi[d], b.hi[d]);
+  }
+  return r;
+}
+
+std::vector<Box> subtract(const Box& a, const Box& b) {
+  std::vector<Box> out;
+  if (!intersects(a, b)) {
+    out.push_back(a);
+    return out;
+  }
+  Box cur = a;
+  for (int d = 0; d < a.nd; ++d) {
+    if (cur.lo[d] < b.lo[d]) {
+      Box p = cur;
+      p.hi[d] = b.lo[d];
+      out.push_back(p);
+      cur.lo[d] = b.lo[d];
+    }
+    if (cur.hi[d] > b.hi[d]) {
+      Box p = cur;
+      p.lo[d] = b.hi[d];
+      out.push_back(p);
+      cur.hi[d] = b.hi[d];
+    }
+  }
+  return out;
+}
+
+// ---- grid ---------------------------------------------------------------------
+int Grid::owner(const int64_t* c) const {
+  for (size_t b = 0; b < blocks.size(); ++b)
+    if (blocks[b].full.contains(c)) return (int)b;
+  return -1;
+}
+
+int64_t Grid::cell(int b, const int64_t* c) const {
+  const Block& B = blocks[b];
+  int64_t off = B.first_cell;
+  for (int d = 0; d < nd; ++d) off += (c[d] - B.full.lo[d]) * B.stride[d];
+  return off;
+}
+
+bool Grid::unlinear(int64_t lin, int64_t* c) const {
+  if (lin < 0) return false;
+  for (int d = nd - 1; d >= 0; --d) {
+    int64_t e = hi[d] - lo[d];
+    c[d] = lo[d] + lin % e;
+    lin /= e;
+  }
+  return lin == 0;
+}
+
+int64_t Grid::ghost_cells() const {
+  int64_t n = 0;
+  for (const Block& b : blocks) n += b.full.count() - b.data.count();
+  return n;
+}
+
+// ---- rotation codes ---------------------------------------------------------------
+int rot_code(const int32_t* R) {
+  if (!R) return 0;
+  int32_t a = R[0], b = R[1], c = R[2], d = R[3];
+  auto unit = [](int32_t v) { return v == 1 || v == -1; };
+  if (unit(a) && b == 0 && c == 0 && unit(d)) return (a < 0 ? 2 : 0) | (d < 0 ? 4 : 0);
+  if (a == 0 && unit(b) && unit(c) && d == 0) return 1 | (b < 0 ? 2 : 0) | (c < 0 ? 4 : 0);
+  return -1;
+}
+
+int rot_inverse(int code) {
+  if (!(code & 1)) return code;
+  int s0 = (code >> 1) & 1, s1 = (code >> 2) & 1;
+  return 1 | (s1 << 1) | (s0 << 2);
+}
+
+void rot_matrix(int code, int32_t* R) {
+  int s0 = (code & 2) ? -1 : 1, s1 = (code & 4) ? -1 : 1;
+  if (code & 1) {
+    R[0] = 0; R[1] = s0; R[2] = s1; R[3] = 0;
+  } else {
+    R[0] = s0; R[1] = 0; R[2] = 0; R[3] = s1;
+  }
+}
+
+// ---- compilation --------------------------------------------------------------------
+namespace {
+
+struct Piece {
+  Box box;
+  std::vector<int> covers;  // sub indices (matrix and vector subs)
+};
+
+// Row-major linear index of multi-index c inside box b.
+int64_t box_linear(const Box& b, const int64_t* c) {
+  int64_t k = 0;
+  for (int d = 0; d < b.nd; ++d) k = k * (b.hi[d] - b.lo[d]) + (c[d] - b.lo[d]);
+  return k;
+}
+
+// Iterate the multi-indices of a box in row-major order.
+template <class F>
+void for_box(const Box& b, F&& f) {
+  int64_t c[HBC_MAX_DIM];
+  for (int d = 0; d < b.nd; ++d) c[d] = b.lo[d];
+  int64_t n = b.count();
+  for (int64_t k = 0; k < n; ++k) {
+    f(c, k);
+    for (int d = b.nd - 1; d >= 0; --d) {
+      if (++c[d] < b.hi[d]) break;
+      c[d] = b.lo[d];
+    }
+  }
+}
+
+// Data cell of a global linear index; HBC_ERANGE if it is not a data cell.
+int64_t data_cell_of_linear(const Grid& g, int64_t lin) {
+  int64_t c[HBC_MAX_DIM];
+  if (!g.unlinear(lin, c)) fail(HBC_ERANGE, "column index " + std::to_string(lin) + " is outside the global box");
+  int b = g.owner(c);
+  if (b < 0 || !g.blocks[b].data.contains(c))
+    fail(HBC_ERANGE, "column index " + std::to_string(lin) + " is not a data cell");
+  return g.cell(b, c);
+}
+
+void map_apply(const Sub& s, int nd, const int64_t* r, int64_t* out) {
+  for (int e = 0; e < nd; ++e) {
+    int64_t v = s.off[e];
+    for (int d = 0; d < nd; ++d) v += s.M[e * nd + d] * r[d];
+    out[e] = v;
+  }
+}
+
+// Refine boxes so that pieces are disjoint and each lies fully inside or
+// outside every sub's box (the non-overlapping set of Sec. IV-B).
+std::vector<Piece> refine(const std::vector<Sub>& subs) {
+  std::vector<Piece> P;
+  for (int s = 0; s < (int)subs.size(); ++s) {
+    const Box& S = subs[s].rows;
+    std::vector<Piece> next;
+    std::vector<Box> rest{S};
+    for (Piece& p : P) {
+      if (p.box.nd == 0 || !intersects(p.box, S)) {
+        next.push_back(std::move(p));
+        continue;
+      }
+      Piece in{intersect(p.box, S), p.covers};
+      in.covers.push_back(s);
+      next.push_back(in);
+      for (const Box& o : subtract(p.box, S)) next.push_back(Piece{o, p.covers});
+      std::vector<Box> r2;
+      for (const Box& r : rest)
+        for (const Box& o : subtract(r, p.box)) r2.push_back(o);
+      rest.swap(r2);
+    }
+    for (const Box& r : rest) next.push_back(Piece{r, {s}});
+    P.swap(next);
+  }
+  return P;
+}
+
+}  // namespace
+
+void compile_plan(const Program& prog, const Layout& lay, int dtype, Plan& plan) {
+  const Grid& g = prog.grid;
+  plan.grid = g;
+  plan.layout = lay;
+  plan.dtype = dtype;
+  if (lay.inner < 1) fail(HBC_EINVAL, "layout.inner must be >= 1");
+  if (lay.order != HBC_POINT_MAJOR && lay.order != HBC_PLANE_MAJOR) fail(HBC_EINVAL, "bad layout order");
+  if (lay.vec_len < 0 || (lay.vec_len > 0 && (lay.vec_lo < 0 || lay.vec_stride < lay.vec_len ||
+                                               lay.vec_lo + lay.vec_stride + lay.vec_len > lay.inner)))
+    fail(HBC_EINVAL, "vector slots do not fit the inner extent");
+  if (g.ncells >= (int64_t(1) << 31) - 1) fail(HBC_EUNSUPPORTED, "more than 2^31-2 cells per plan");
+  if (g.blocks.empty()) fail(HBC_EINVAL, "grid has no blocks");
+
+  // 1. validate rows; expand the zero-rest subs
+  std::vector<Sub> subs;
+  std::vector<int> zero_rest_blocks;
+  for (const Sub& s0 : prog.subs) {
+    if (s0.kind == SUB_ZERO_REST) {
+      zero_rest_blocks.push_back(s0.block);
+      continue;
+    }
+    if (s0.rows.empty()) continue;
+    Sub s = s0;
+    int b = g.owner(s.rows.lo);
+    if (b < 0 || !g.blocks[b].full.contains(s.rows))
+      fail(HBC_ERANGE, "sub-matrix rows do not lie in one block's full region");
+    if (intersects(s.rows, g.blocks[b].data))
+      fail(HBC_ERANGE, "sub-matrix rows include data cells (only ghost rows are written)");
+    s.block = b;
+    subs.push_back(std::move(s));
+  }
+  for (int b : zero_rest_blocks) {
+    if (b < 0 || b >= (int)g.blocks.size()) fail(HBC_EINVAL, "zero-rest block out of range");
+    std::vector<Box> rest = subtract(g.blocks[b].full, g.blocks[b].data);
+    for (const Sub& s : subs) {
+      if (s.block != b || s.kind == SUB_VEC) continue;
+      std::vector<Box> r2;
+      for (const Box& r : rest)
+        for (const Box& o : subtract(r, s.rows)) r2.push_back(o);
+      rest.swap(r2);
+    }
+    for (const Box& r : rest) {
+      if (r.empty()) continue;
+      Sub z;
+      z.kind = SUB_ZERO;
+      z.rows = r;
+      z.block = b;
+      subs.push_back(z);
+    }
+  }
+
+  // 2. overlap rule (R2): sub-matrices are pairwise disjoint, sub-vectors too,
+  //    unless the program allows summing.
+  const bool allow_sum = prog.flags & HBC_ALLOW_OVERLAP_SUM;
+  for (size_t a = 0; a < subs.size(); ++a)
+    for (size_t c = a + 1; c < subs.size(); ++c) {
+      bool va = subs[a].kind == SUB_VEC, vc = subs[c].kind == SUB_VEC;
+      if (va != vc || subs[a].block != subs[c].block) continue;
+      if (!allow_sum && intersects(subs[a].rows, subs[c].rows))
+        fail(HBC_EOVERLAP, std::string("overlapping ") + (va ? "sub-vector" : "sub-matrix") + " rows (subs " +
+                               std::to_string(a) + " and " + std::to_string(c) + ")");
+    }
+
+  // 3. pieces
+  std::vector<Piece> pieces = refine(subs);
+  // deterministic order: by block, then by origin
+  std::sort(pieces.begin(), pieces.end(), [&](const Piece& x, const Piece& y) {
+    int bx = subs[x.covers[0]].block, by = subs[y.covers[0]].block;
+    if (bx != by) return bx < by;
+    return std::lexicographical_compare(x.box.lo, x.box.lo + x.box.nd, y.box.lo, y.box.lo + y.box.nd);
+  });
+
+  HostTables& T = plan.host;
+  hbc_stats& st = plan.stats;
+  std::memset(&st, 0, sizeof(st));
+  std::vector<int64_t> sources;
+  const int nd = g.nd;
+  int64_t row_base = 0;
+
+  for (const Piece& pc : pieces) {
+    std::vector<int> mats, vecs;
+    for (int s : pc.covers) (subs[s].kind == SUB_VEC ? vecs : mats).push_back(s);
+    const int b = subs[pc.covers[0]].block;
+    const Block& B = g.blocks[b];
+    DevSeg seg;
+    std::memset(&seg, 0, sizeof(seg));
+    seg.nrows = pc.box.count();
+    seg.row_base = row_base;
+    row_base += seg.nrows;
+    seg.w = 1.0;
+    // full-dimension strides before dropping extent-1 dims
+    int64_t dst_st[HBC_MAX_DIM], src_st[HBC_MAX_DIM] = {0};
+    for (int d = 0; d < nd; ++d) dst_st[d] = B.stride[d];
+    seg.dst_base = g.cell(b, pc.box.lo);
+    int rot = 0;
+    if (!mats.empty()) {
+      rot = subs[mats[0]].rot;
+      for (int m : mats)
+        if (subs[m].rot != rot) fail(HBC_EOVERLAP, "overlapping rows with different component rotations");
+    }
+    seg.rot = rot;
+
+    if (mats.size() == 1 && subs[mats[0]].kind == SUB_MAP) {
+      const Sub& s = subs[mats[0]];
+      seg.kind = SEG_MAP;
+      seg.w = s.w;
+      // the affine image of the piece: check its corners
+      int sb = -1;
+      for (int corner = 0; corner < (1 << nd); ++corner) {
+        int64_t r[HBC_MAX_DIM], c[HBC_MAX_DIM];
+        for (int d = 0; d < nd; ++d) r[d] = (corner >> d & 1) ? pc.box.hi[d] - 1 : pc.box.lo[d];
+        map_apply(s, nd, r, c);
+        int ob = g.owner(c);
+        if (ob < 0 || !g.blocks[ob].data.contains(c) || (sb >= 0 && ob != sb))
+          fail(HBC_ERANGE, "map sends rows outside one block's data region");
+        sb = ob;
+      }
+      int64_t c0[HBC_MAX_DIM];
+      map_apply(s, nd, pc.box.lo, c0);
+      seg.src_base = g.cell(sb, c0);
+      for (int d = 0; d < nd; ++d) {
+        int64_t v = 0;
+        for (int e = 0; e < nd; ++e) v += s.M[e * nd + d] * g.blocks[sb].stride[e];
+        src_st[d] = v;
+      }
+      st.rows_map += seg.nrows;
+      st.nnz += seg.nrows;
+      for_box(pc.box, [&](const int64_t* r, int64_t) {
+        int64_t c[HBC_MAX_DIM];
+        map_apply(s, nd, r, c);
+        sources.push_back(g.cell(sb, c));
+      });
+    } else if (mats.size() == 1 && subs[mats[0]].kind == SUB_ZERO) {
+      seg.kind = SEG_ZERO;
+      st.rows_zero += seg.nrows;
+    } else if (mats.size() == 1 && subs[mats[0]].kind == SUB_ELL) {
+      const Sub& s = subs[mats[0]];
+      seg.kind = SEG_ELL;
+      seg.width = s.width;
+      // absolute element offset: rows of this segment start here (width entries each)
+      seg.tab = (int64_t)T.ell_col.size();
+      for_box(pc.box, [&](const int64_t* r, int64_t) {
+        int64_t k = box_linear(s.rows, r);
+        for (int m = 0; m < s.width; ++m) {
+          int64_t lin = s.cols[k * s.width + m];
+          double v = s.vals[k * s.width + m];
+          if (lin < 0) {
+            T.ell_col.push_back(-1);
+            T.ell_val.push_back(0.0);
+            continue;
+          }
+          int64_t cell = data_cell_of_linear(g, lin);
+          T.ell_col.push_back((int32_t)cell);
+          T.ell_val.push_back(v);
+          sources.push_back(cell);
+          st.nnz += 1;
+        }
+      });
+      st.rows_ell += seg.nrows;
+    } else if (!mats.empty()) {
+      // one CSR sub, or several overlapping subs summed into merged CSR rows
+      seg.kind = SEG_CSR;
+      seg.tab = (int64_t)T.csr_ptr.size();
+      for_box(pc.box, [&](const int64_t* r, int64_t) {
+        std::vector<std::pair<int64_t, double>> ents;
+        for (int m : mats) {
+          const Sub& s = subs[m];
+          if (s.kind == SUB_MAP) {
+            int64_t c[HBC_MAX_DIM];
+            map_apply(s, nd, r, c);
+            int ob = g.owner(c);
+            if (ob < 0 || !g.blocks[ob].data.contains(c)) fail(HBC_ERANGE, "map sends a row outside the data region");
+            ents.emplace_back(g.cell(ob, c), s.w);
+          } else if (s.kind == SUB_ELL) {
+            int64_t k = box_linear(s.rows, r);
+            for (int q = 0; q < s.width; ++q)
+              if (s.cols[k * s.width + q] >= 0)
+                ents.emplace_back(data_cell_of_linear(g, s.cols[k * s.width + q]), s.vals[k * s.width + q]);
+          } else if (s.kind == SUB_CSR) {
+            int64_t k = box_linear(s.rows, r);
+            for (int64_t q = s.ptr[k]; q < s.ptr[k + 1]; ++q)
+              ents.emplace_back(data_cell_of_linear(g, s.cols[q]), s.vals[q]);
+          }
+        }
+        if (mats.size() > 1) {  // sum duplicate columns
+          std::stable_sort(ents.begin(), ents.end(),
+                           [](const auto& x, const auto& y) { return x.first < y.first; });
+          std::vector<std::pair<int64_t, double>> m2;
+          for (auto& e : ents) {
+            if (!m2.empty() && m2.back().first == e.first)
+              m2.back().second += e.second;
+            else
+              m2.push_back(e);
+          }
+          ents.swap(m2);
+        }
+        T.csr_ptr.push_back((int64_t)T.csr_col.size());
+        for (auto& e : ents) {
+          T.csr_col.push_back((int32_t)e.first);
+          T.csr_val.push_back(e.second);
+          sources.push_back(e.first);
+        }
+        st.nnz += (int64_t)ents.size();
+      });
+      T.csr_ptr.push_back((int64_t)T.csr_col.size());  // end of this segment's rows
+      st.rows_csr += seg.nrows;
+    } else {
+      seg.kind = SEG_VEC;
+      st.rows_vector_only += seg.nrows;
+    }
+
+    if (!vecs.empty()) {
+      int64_t bi = 1;
+      for (int v : vecs) bi = std::max(bi, subs[v].ninner);
+      for (int v : vecs)
+        if (subs[v].ninner != 1 && subs[v].ninner != lay.inner)
+          fail(HBC_EINVAL, "sub-vector inner width must be 1 or layout.inner");
+      seg.has_b = 1;
+      seg.b_inner = (int32_t)bi;
+      seg.brow = (int64_t)T.bval.size();
+      for_box(pc.box, [&](const int64_t* r, int64_t) {
+        for (int64_t l = 0; l < bi; ++l) {
+          double acc = 0.0;
+          bool first = true;
+          for (int v : vecs) {
+            const Sub& s = subs[v];
+            int64_t k = box_linear(s.rows, r);
+            double x = s.b[k * s.ninner + (s.ninner == 1 ? 0 : l)];
+            acc = first ? x : acc + x;
+            first = false;
+          }
+          T.bval.push_back(acc);
+        }
+      });
+      st.rows_with_b += seg.nrows;
+    }
+
+    // drop extent-1 dims, then merge dims contiguous in both dst and src
+    int k = 0;
+    int64_t ext[HBC_MAX_DIM], ds[HBC_MAX_DIM], ss[HBC_MAX_DIM];
+    for (int d = 0; d < nd; ++d) {
+      if (pc.box.extent(d) == 1) continue;
+      ext[k] = pc.box.extent(d);
+      ds[k] = dst_st[d];
+      ss[k] = src_st[d];
+      ++k;
+    }
+    if (k == 0) {
+      ext[0] = 1; ds[0] = 1; ss[0] = 0; k = 1;
+    }
+    int m = 0;
+    for (int d = 1; d < k; ++d) {
+      bool merge = ds[m] == ext[d] * ds[d] && (seg.kind != SEG_MAP || ss[m] == ext[d] * ss[d]);
+      if (merge) {
+        ext[m] *= ext[d];
+        ds[m] = ds[d];
+        ss[m] = ss[d];
+      } else {
+        ++m;
+        ext[m] = ext[d]; ds[m] = ds[d]; ss[m] = ss[d];
+      }
+    }
+    k = m + 1;
+    if (k > SEG_MAXD) fail(HBC_EUNSUPPORTED, "row box has more than 4 non-trivial dimensions");
+    seg.nd = k;
+    for (int d = 0; d < SEG_MAXD; ++d) {
+      seg.ext[d] = d < k ? (int32_t)ext[d] : 1;
+      seg.dst_stride[d] = d < k ? ds[d] : 0;
+      seg.src_stride[d] = d < k ? ss[d] : 0;
+      if (d < k && ext[d] >= (int64_t(1) << 31)) fail(HBC_EUNSUPPORTED, "box extent too large");
+    }
+    T.segs.push_back(seg);
+  }
+
+  // 4. statistics
+  st.ghost_cells = g.ghost_cells();
+  st.rows_covered = row_base;
+  st.rows_uncovered = st.ghost_cells - st.rows_covered;
+  if ((prog.flags & HBC_STRICT_COVER) && st.rows_uncovered > 0)
+    fail(HBC_EUNCOVERED, std::to_string(st.rows_uncovered) + " ghost cells are covered by no sub-matrix");
+  std::sort(sources.begin(), sources.end());
+  st.unique_sources = (int64_t)(std::unique(sources.begin(), sources.end()) - sources.begin());
+  st.segments = (int64_t)T.segs.size();
+  st.ghost_values = st.rows_covered * lay.inner;
+  const double es = dtype == HBC_F64 ? 8.0 : 4.0;
+  const double I = (double)lay.inner;
+  double tables = (double)T.ell_col.size() * (4.0 + es) + (double)T.csr_col.size() * (4.0 + es) +
+                  (double)T.csr_ptr.size() * 8.0 + (double)T.bval.size() * es;
+  st.alg_bytes = es * I * (double)(st.rows_covered + st.unique_sources) + tables;
+  // adjoint: read + zero the covered ghosts, read-modify-write the sources,
+  // one (ghost, weight, rotation) entry per nonzero and a pointer per source
+  st.alg_bytes_adjoint = es * I * (2.0 * (double)st.rows_covered + 2.0 * (double)st.unique_sources) +
+                         (double)st.nnz * (8.0 + es + 4.0) + (double)st.unique_sources * 16.0;
+
+  // 5. launch shape and tiles
+  plan.vec = 1;
+  if (lay.order == HBC_POINT_MAJOR) {
+    int v = dtype == HBC_F64 ? 2 : 4;
+    while (v > 1) {
+      bool ok = lay.inner % v == 0 && (lay.vec_len == 0 || (lay.vec_lo % v == 0 && lay.vec_stride % v == 0 &&
+                                                             lay.vec_len % v == 0));
+      if (ok) break;
+      v /= 2;
+    }
+    plan.vec = v;
+  }
+  plan.tune = default_tune(plan);
+  build_tiles(plan, plan.tune);
+}
+
+static int64_t pow2_ceil(int64_t v) {
+  int64_t p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+hbc_tune default_tune(const Plan& plan) {
+  hbc_tune t{};
+  t.block = 256;
+  t.persistent = 0;
+  const int64_t rows = std::max<int64_t>(1, plan.stats.rows_covered);
+  if (plan.layout.order == HBC_POINT_MAJOR) {
+    int64_t nvec = plan.layout.inner / plan.vec;
+    t.lanes_per_row = (int32_t)std::min<int64_t>(64, pow2_ceil(nvec));
+  } else {
+    t.lanes_per_row = 1;
+  }
+  const int64_t rows_per_pass = t.block / t.lanes_per_row;
+  // aim for about 2048 tiles so that all 256 CUs get several tiles
+  int64_t rpt = rows / 2048;
+  rpt = std::max<int64_t>(rpt, rows_per_pass);
+  rpt = std::min<int64_t>(rpt, 16384);
+  rpt = ((rpt + rows_per_pass - 1) / rows_per_pass) * rows_per_pass;
+  t.rows_per_tile = (int32_t)rpt;
+  return t;
+}
+
+void build_tiles(Plan& plan, const hbc_tune& t) {
+  if (t.block < 64 || t.block > 1024 || t.block % 64) fail(HBC_EINVAL, "block must be a multiple of 64 in [64, 1024]");
+  if (t.lanes_per_row < 1 || (t.lanes_per_row & (t.lanes_per_row - 1)) || t.lanes_per_row > t.block)
+    fail(HBC_EINVAL, "lanes_per_row must be a power of two <= block");
+  if (t.rows_per_tile < 1) fail(HBC_EINVAL, "rows_per_tile must be >= 1");
+  if (t.persistent < 0) fail(HBC_EINVAL, "persistent must be >= 0");
+  std::vector<DevTile> tiles;
+  for (size_t s = 0; s < plan.host.segs.size(); ++s) {
+    const DevSeg& sg = plan.host.segs[s];
+    for (int64_t r0 = 0; r0 < sg.nrows; r0 += t.rows_per_tile) {
+      DevTile tl;
+      tl.seg = (int32_t)s;
+      tl.nrows = (int32_t)std::min<int64_t>(t.rows_per_tile, sg.nrows - r0);
+      tl.row0 = r0;
+      tiles.push_back(tl);
+    }
+  }
+  // Workgroups are dealt to the 8 XCDs round-robin; interleave so that each
+  // XCD walks a contiguous run of tiles (neighbouring rows share sources).
+  const size_t n = tiles.size();
+  std::vector<DevTile> out(n);
+  const size_t X = 8;
+  if (n >= X * 2) {
+    size_t per = (n + X - 1) / X;
+    size_t i = 0;
+    for (size_t k = 0; k < per * X; ++k) {
+      size_t x = k % X, j = k / X;
+      size_t src = x * per + j;
+      if (src < n) out[i++] = tiles[src];
+    }
+  } else {
+    out = tiles;
+  }
+  plan.host.tiles.swap(out);
+  plan.stats.tiles = (int64_t)plan.host.tiles.size();
+  plan.tune = t;
+}
+
+void build_csc(Plan& plan) {
+  const HostTables& T = plan.host;
+  struct E {
+    int64_t src, ghost;
+    double w;
+    int32_t rot;
+  };
+  std::vector<E> ents;
+  ents.reserve((size_t)plan.stats.nnz);
+  for (const DevSeg& s : T.segs) {
+    const int irot = rot_inverse(s.rot);
+    int64_t c[SEG_MAXD];
+    for (int64_t r = 0; r < s.nrows; ++r) {
+      int64_t q = r;
+      for (int d = s.nd - 1; d >= 0; --d) {
+        c[d] = q % s.ext[d];
+        q /= s.ext[d];
+      }
+      int64_t dst = s.dst_base, src = s.src_base;
+      for (int d = 0; d < s.nd; ++d) {
+        dst += c[d] * s.dst_stride[d];
+        src += c[d] * s.src_stride[d];
+      }
+      if (s.kind == SEG_MAP) {
+        ents.push_back(E{src, dst, s.w, irot});
+      } else if (s.kind == SEG_ELL) {
+        for (int m = 0; m < s.width; ++m) {
+          int32_t col = T.ell_col[s.tab + r * s.width + m];
+          if (col >= 0) ents.push_back(E{col, dst, T.ell_val[s.tab + r * s.width + m], irot});
+        }
+      } else if (s.kind == SEG_CSR) {
+        for (int64_t k = T.csr_ptr[s.tab + r]; k < T.csr_ptr[s.tab + r + 1]; ++k)
+          ents.push_back(E{T.csr_col[k], dst, T.csr_val[k], irot});
+      }
+    }
+  }
+  std::sort(ents.begin(), ents.end(), [](const E& a, const E& b) {
+    return a.src != b.src ? a.src < b.src : a.ghost < b.ghost;
+  });
+  CscHost& C = plan.host.csc;
+  C = CscHost{};
+  for (size_t k = 0; k < ents.size(); ++k) {
+    if (k == 0 || ents[k].src != ents[k - 1].src) {
+      C.src_cell.push_back(ents[k].src);
+      C.ptr.push_back((int64_t)k);
+    }
+    C.ghost.push_back(ents[k].ghost);
+    C.w.push_back(ents[k].w);
+    C.rot.push_back(ents[k].rot);
+  }
+  C.ptr.push_back((int64_t)ents.size());
+  // adjoint tiles: sources grouped so that a tile holds about as many inner
+  // values as a forward tile
+  plan.host.adj_tiles.clear();
+  const int64_t ns = (int64_t)C.src_cell.size();
+  int64_t per = std::max<int64_t>(plan.tune.block / plan.tune.lanes_per_row, ns / 2048);
+  per = std::min<int64_t>(per, 16384);
+  for (int64_t s = 0; s < ns; s += per)
+    plan.host.adj_tiles.push_back(AdjTile{(int32_t)s, (int32_t)std::min<int64_t>(per, ns - s)});
+}
+
+// ---- host evaluation of compiled rows (tests without a GPU) --------------------------------
+int plan_row(const Plan& plan, int64_t cell, int64_t l, int cap, int64_t* cols, double* vals, int32_t* nnz,
+             double* b, int32_t* kind, int32_t* rot) {
+  const HostTables& T = plan.host;
+  *nnz = 0;
+  *b = 0.0;
+  *kind = -1;
+  *rot = 0;
+  for (const DevSeg& s : T.segs) {
+    // locate `cell` in the segment's box: strides are decreasing in magnitude
+    int64_t off = cell - s.dst_base;
+    int64_t c[SEG_MAXD];
+    bool in = true;
+    for (int d = 0; d < s.nd; ++d) {
+      if (s.dst_stride[d] == 0) {
+        c[d] = 0;
+        continue;
+      }
+      int64_t q = off >= 0 ? off / s.dst_stride[d] : -1;
+      if (q < 0 || q >= s.ext[d]) {
+        in = false;
+        break;
+      }
+      c[d] = q;
+      off -= q * s.dst_stride[d];
+    }
+    if (!in || off != 0) continue;
+    int64_t r = 0;
+    for (int d = 0; d < s.nd; ++d) r = r * s.ext[d] + c[d];
+    *kind = s.kind;
+    *rot = s.rot;
+    if (s.kind == SEG_MAP) {
+      int64_t src = s.src_base;
+      for (int d = 0; d < s.nd; ++d) src += c[d] * s.src_stride[d];
+      if (cap > 0) {
+        cols[0] = src;
+        vals[0] = s.w;
+      }
+      *nnz = 1;
+    } else if (s.kind == SEG_ELL) {
+      int n = 0;
+      for (int m = 0; m < s.width; ++m) {
+        int32_t col = T.ell_col[s.tab + r * s.width + m];
+        if (col < 0) continue;
+        if (n < cap) {
+          cols[n] = col;
+          vals[n] = T.ell_val[s.tab + r * s.width + m];
+        }
+        ++n;
+      }
+      *nnz = n;
+    } else if (s.kind == SEG_CSR) {
+      int n = 0;
+      for (int64_t k = T.csr_ptr[s.tab + r]; k < T.csr_ptr[s.tab + r + 1]; ++k, ++n)
+        if (n < cap) {
+          cols[n] = T.csr_col[k];
+          vals[n] = T.csr_val[k];
+        }
+      *nnz = n;
+    }
+    if (s.has_b) *b = T.bval[s.brow + r * s.b_inner + (s.b_inner == 1 ? 0 : l)];
+    return HBC_OK;
+  }
+  return HBC_OK;
+}
+
+}  // namespace hbc

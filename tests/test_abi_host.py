@@ -1,0 +1,170 @@
+"""C-ABI library checks that need no GPU (plans compiled host-only).
+
+* the library loads and exports every function ``include/hbc.h`` declares;
+* the plan compiler's rows equal the oracle's A on tiny grids (cubed-sphere
+  copy and Lagrange programs, the HPCG halo program, padding maps);
+* validation errors: rows outside the ghost region, columns outside the
+  data region, overlaps, strict cover, bad slices, bad rotations;
+* segment / row counts of the workload programs.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2605_14780_amd as hb
+from helpers import closed_form_weights
+from oracle import assemble
+from oracle import cubed_sphere as ocs
+from oracle import hpcg as ohpcg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "hbc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hbc_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = hb.lib()
+    names = declared_functions()
+    assert len(names) >= 40
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(hb.SIGNATURES), set(names) ^ set(hb.SIGNATURES)
+
+
+def compare_plan_with_oracle(plan, og, op, tol=0.0):
+    A = op.dense()
+    for r, cell in enumerate(og.ghost_cells):
+        kind, cols, vals, b, rot = plan.row(int(cell))
+        nz = np.nonzero(A[r])[0]
+        ref = {int(og.data_cells[j]): A[r, j] for j in nz}
+        got = {c: v for c, v in zip(cols, vals) if v != 0.0}
+        assert set(got) == set(ref), (cell, got, ref)
+        for c in ref:
+            assert abs(got[c] - ref[c]) <= tol, (cell, c, got[c], ref[c])
+
+
+@pytest.mark.parametrize("N,h", [(4, 1), (6, 3), (13, 3), (24, 2)])
+def test_cs_sync_plan_equals_oracle(N, h):
+    g = hb.Grid.cubed_sphere(N, h)
+    p = hb.Program(g)
+    p.cs_add(N, h, hb.CS_SYNC, vector=True)
+    plan = hb.Plan(p, inner=1, host_only=True)
+    og = ocs.grid(N, h)
+    compare_plan_with_oracle(plan, og, assemble(og, ocs.subs(N, h, "sync")))
+    # component rotation per side equals the oracle's finite-difference rotation
+    for f in range(6):
+        for side in range(4):
+            box = ocs.side_box(f, side, N, h)
+            c = og.cell((f, box[1][0], box[2][0]))
+            rot = plan.row(c)[4]
+            R = ocs.rside(f, side)
+            sw = R[0, 0] == 0
+            code = int(sw) | ((R[0, 1 if sw else 0] < 0) << 1) | ((R[1, 0 if sw else 1] < 0) << 2)
+            assert rot == code, (f, side, rot, R)
+
+
+@pytest.mark.parametrize("N,h", [(4, 1), (6, 3), (13, 3), (24, 2)])
+def test_cs_lagrange_plan_equals_oracle(N, h):
+    base, w = closed_form_weights(N, h)
+    g = hb.Grid.cubed_sphere(N, h)
+    p = hb.Program(g)
+    p.cs_add(N, h, hb.CS_LAGRANGE, vector=False, base=base, w=w)
+    plan = hb.Plan(p, inner=1, host_only=True)
+    st = plan.stats()
+    assert st["rows_ell"] == 24 * h * N and st["rows_zero"] == 24 * h * h and st["nnz"] == 4 * 24 * h * N
+    og = ocs.grid(N, h)
+    compare_plan_with_oracle(plan, og, assemble(og, ocs.subs(N, h, "lagrange")), tol=64 * N * 2.0 ** -53)
+
+
+def test_hpcg_plan_equals_oracle():
+    nb, n = 2, 4
+    g = hb.Grid.cartesian([nb] * 3, [n] * 3, 1)
+    p = hb.Program(g)
+    p.cart_add_halo([nb] * 3, [n] * 3, 1)
+    plan = hb.Plan(p, inner=1, host_only=True)
+    og = ohpcg.grid(nb, n)
+    compare_plan_with_oracle(plan, og, assemble(og, ohpcg.subs(nb, n)))
+
+
+def test_workload_program_sizes():
+    # cubed sphere C384, halo 3: 24 Lagrange strips + 24 corners
+    N, h = 384, 3
+    base, w = closed_form_weights(N, h)
+    g = hb.Grid.cubed_sphere(N, h)
+    p = hb.Program(g)
+    p.cs_add(N, h, hb.CS_LAGRANGE, True, base, w)
+    st = hb.Plan(p, inner=256, vec=(128, 64, 64), host_only=True).stats()
+    assert st["segments"] == 48 and st["rows_ell"] == 27648 and st["nnz"] == 110592
+    assert st["rows_zero"] == 216 and st["ghost_values"] == 7133184
+    assert st["unique_sources"] == 6 * (4 * h * N - 4 * h * h)
+    # HPCG-shaped: 2x2x2 blocks of 128^3, halo 1
+    g = hb.Grid.cartesian([2] * 3, [128] * 3, 1)
+    p = hb.Program(g)
+    p.cart_add_halo([2] * 3, [128] * 3, 1)
+    st = hb.Plan(p, inner=1, host_only=True).stats()
+    assert st["segments"] == 208 and st["rows_map"] == 396296 and st["rows_zero"] == 402488
+    assert st["unique_sources"] == 390152
+
+
+def one_block(n0, n1, h):
+    g = hb.Grid([0, -h, -h], [1, n0 + h, n1 + h])
+    g.add_block([(0, 1), (-h, n0 + h), (-h, n1 + h)], [(0, 1), (0, n0), (0, n1)])
+    return g
+
+
+def test_validation_errors():
+    g = one_block(4, 4, 1)
+    I3 = np.eye(3, dtype=np.int64)
+    p = hb.Program(g)
+    p.add_map([(0, 1), (0, 1), (0, 4)], I3, [0, 0, 0])  # data rows
+    with pytest.raises(hb.HbcError) as e:
+        hb.Plan(p, host_only=True)
+    assert e.value.code == hb.ERANGE
+    p = hb.Program(g)
+    p.add_map([(0, 1), (-1, 0), (0, 4)], I3, [0, 0, 0])  # copies a ghost
+    with pytest.raises(hb.HbcError) as e:
+        hb.Plan(p, host_only=True)
+    assert e.value.code == hb.ERANGE
+    p = hb.Program(g)
+    p.add_zero([(0, 1), (-1, 0), (0, 4)])
+    p.add_zero([(0, 1), (-1, 0), (3, 5)])
+    with pytest.raises(hb.HbcError) as e:
+        hb.Plan(p, host_only=True)
+    assert e.value.code == hb.EOVERLAP
+    p = hb.Program(g)
+    p.add_zero([(0, 1), (-1, 0), (0, 4)])
+    p.set_flags(hb.STRICT_COVER)
+    with pytest.raises(hb.HbcError) as e:
+        hb.Plan(p, host_only=True)
+    assert e.value.code == hb.EUNCOVERED
+    p = hb.Program(g)
+    with pytest.raises(hb.HbcError):
+        p.add_map([(0, 1), (-1, 0), (0, 4)], I3, [0, 0, 0], rot=[[1, 1], [0, 1]])
+    p = hb.Program(g)
+    p.add_ell([(0, 1), (-1, 0), (0, 1)], 2, [7, 10 ** 6], [0.5, 0.5])
+    with pytest.raises(hb.HbcError) as e:
+        hb.Plan(p, host_only=True)
+    assert e.value.code == hb.ERANGE
+    with pytest.raises(hb.HbcError) as e:
+        g.add_block([(0, 1), (0, 2, 2), (0, 2)], [(0, 1), (0, 2, 2), (0, 2)])
+    gg = hb.Grid([0], [10])
+    gg.add_block([(0, 5)], [(1, 4)])
+    with pytest.raises(hb.HbcError):
+        gg.add_block([(4, 8)], [(5, 7)])  # overlaps the first block
+
+
+def test_zero_rest_partition_covers_ghost_ring():
+    g = one_block(5, 5, 2)
+    p = hb.Program(g)
+    p.add_map([(0, 1), (0, 5), (5, 7)], np.diag([1, 1, -1]), [0, 0, 9])
+    p.add_zero_rest(0)
+    p.set_flags(hb.STRICT_COVER)
+    st = hb.Plan(p, host_only=True).stats()
+    assert st["rows_uncovered"] == 0
+    assert st["rows_map"] == 10 and st["rows_zero"] == 81 - 25 - 10
