@@ -97,6 +97,9 @@ SIGNATURES = {
     "hbc_apply": (I32, [P, P, I64, P]),
     "hbc_apply_adjoint": (I32, [P, P, I64, P]),
     "hbc_time_apply": (I32, [P, C.POINTER(P), I64, I32, I32, P, PD]),
+    "hbc_graph_create": (I32, [P, C.POINTER(P), I64, I32, I32, P, C.POINTER(P)]),
+    "hbc_graph_launch": (I32, [P, P]),
+    "hbc_graph_destroy": (None, [P]),
     "hbc_stencil27": (I32, [P, P, I64, P, I64, P]),
     "hbc_fused_stencil27": (I32, [P, P, I64, P, I64, P]),
     "hbc_cs_lagrange_weights": (I32, [I64, I64, P, P, P]),
@@ -367,6 +370,27 @@ def time_apply(plan: Plan, fields, reps, stream=None):
     ms = D()
     _check(lib().hbc_time_apply(plan._h, arr, ptrs[0][1], len(ptrs), reps, _stream(stream), C.byref(ms)))
     return ms.value
+
+
+class ApplyGraph:
+    """``reps`` applies of ``plan`` over ``fields`` (cycled) captured in one HIP graph."""
+
+    def __init__(self, plan: Plan, fields, reps, stream=None):
+        ptrs = [_field(plan, f) for f in fields]
+        arr = (P * len(ptrs))(*[p for p, _ in ptrs])
+        self._h = P()
+        self._fields = list(fields)  # keep the memory alive with the graph
+        self.reps = reps
+        _check(lib().hbc_graph_create(plan._h, arr, ptrs[0][1], len(ptrs), reps, _stream(stream),
+                                      C.byref(self._h)))
+
+    def launch(self, stream=None):
+        _check(lib().hbc_graph_launch(self._h, _stream(stream)))
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.hbc_graph_destroy(self._h)
+            self._h = None
 
 
 def stencil27(plan: Plan, x, y, stream=None):

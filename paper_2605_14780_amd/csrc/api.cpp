@@ -19,6 +19,9 @@ struct hbc_plan {
   std::mutex csc_mu;
   bool csc_ready = false;
 };
+struct hbc_graph {
+  void* g = nullptr;
+};
 struct hbc_batch {
   hbc::Batch* b = nullptr;
   std::vector<const hbc::Plan*> plans;
@@ -472,6 +475,37 @@ static void check_stencil_sizes(const hbc_plan* plan, int64_t xn, int64_t yn) {
   int64_t nd = 0;
   for (const Block& b : plan->p.grid.blocks) nd += b.data.count();
   if (yn != nd) fail(HBC_EINVAL, "y has " + std::to_string(yn) + " values, the grid has " + std::to_string(nd) + " data cells");
+}
+
+int hbc_graph_create(const hbc_plan* plan, void* const* fields, int64_t nelem, int32_t nfields, int32_t reps,
+                     void* stream, hbc_graph** out) {
+  return guard([&] {
+    check_device_plan(plan);
+    need(fields && out && nfields >= 1 && reps >= 1 && stream, "bad graph arguments");
+    check_size(plan, nelem);
+    for (int k = 0; k < nfields; ++k) check_field(fields[k]);
+    auto* g = new hbc_graph;
+    try {
+      g->g = device_graph_create(plan->p, fields, nfields, reps, stream);
+    } catch (...) {
+      delete g;
+      throw;
+    }
+    *out = g;
+  });
+}
+
+int hbc_graph_launch(hbc_graph* g, void* stream) {
+  return guard([&] {
+    need(g && g->g, "NULL graph");
+    device_graph_launch(g->g, stream);
+  });
+}
+
+void hbc_graph_destroy(hbc_graph* g) {
+  if (!g) return;
+  device_graph_destroy(g->g);
+  delete g;
 }
 
 int hbc_stencil27(const hbc_plan* plan, const void* x, int64_t x_nelem, void* y, int64_t y_nelem, void* stream) {

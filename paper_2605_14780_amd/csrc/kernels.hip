@@ -800,6 +800,50 @@ double device_time_apply(const Plan& p, void* const* fields, int nfields, int re
   return (double)ms / reps;
 }
 
+struct ApplyGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+void* device_graph_create(const Plan& p, void* const* fields, int nfields, int reps, void* stream) {
+  if (!stream) fail(HBC_EINVAL, "graph capture needs a stream");
+  auto* g = new ApplyGraph;
+  hipStream_t s = S(stream);
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    delete g;
+    fail(HBC_EHIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+  }
+  try {
+    for (int r = 0; r < reps; ++r) device_apply(p, fields[r % nfields], stream, false);
+  } catch (...) {
+    (void)hipStreamEndCapture(s, &g->graph);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    throw;
+  }
+  e = hipStreamEndCapture(s, &g->graph);
+  if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    device_graph_destroy(g);
+    fail(HBC_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+  }
+  return g;
+}
+
+void device_graph_launch(void* gp, void* stream) {
+  auto* g = static_cast<ApplyGraph*>(gp);
+  HIP_CHECK(hipGraphLaunch(g->exec, S(stream)));
+}
+
+void device_graph_destroy(void* gp) {
+  auto* g = static_cast<ApplyGraph*>(gp);
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+}
+
 // ---- batched persistent apply ------------------------------------------------------------
 struct Batch {
   std::vector<Plan*> plans;

@@ -58,3 +58,61 @@ def interp_tolerance(ref_op, X_data, key_rows, scale_floor=0.0):
 def max_rel(got, ref, bound):
     diff = np.abs(got - ref)
     return float(np.max(diff / np.maximum(bound, 1e-300)))
+
+
+U64 = 2.0 ** -53
+
+
+def _lagrange_abs_rows(N, h, which):
+    """Cubed-sphere Lagrange sub-matrices whose entries are |w_m(s)| ('w') or
+    |dw_m/ds| ('dw') at the oracle's own s (component rotations kept)."""
+    from oracle import RowsSub, ZeroSub
+    from oracle import cubed_sphere as ocs
+
+    def entries(f, j, i):
+        g, axis, L, s = ocs.neighbour_line(f, j, i, N)
+        base, w, s = ocs.lagrange_weights(s, N)
+        d = [s - (base + n) for n in range(4)]
+        if which == "w":
+            vals = [abs(v) for v in w]
+        else:
+            vals = [abs((d[1] * d[2] + d[1] * d[3] + d[2] * d[3]) / 6.0),
+                    abs((d[0] * d[2] + d[0] * d[3] + d[2] * d[3]) / 2.0),
+                    abs((d[0] * d[1] + d[0] * d[3] + d[1] * d[3]) / 2.0),
+                    abs((d[0] * d[1] + d[0] * d[2] + d[1] * d[2]) / 6.0)]
+        node = (lambda k: (g, k, L)) if axis == "i" else (lambda k: (g, L, k))
+        return [(node(base + m), vals[m]) for m in range(4)]
+
+    out = []
+    for f in range(6):
+        for side in range(4):
+            rot = tuple(int(v) for v in ocs.rside(f, side).reshape(-1))
+            out.append(RowsSub(ocs.side_box(f, side, N, h), lambda c, f=f: entries(f, c[1], c[2]), rot=rot))
+        for box in ocs.corner_boxes(f, N, h):
+            out.append(ZeroSub(box))
+    return out
+
+
+def lagrange_tolerance(N, h, full, ref, vec, rel=1e-13):
+    """Per-value bound for FP64 interpolated ghosts (ghost rows of the grid).
+
+    rel * max(|ref|, sum_m |w_m x_m|) covers the arithmetic; the ghost's
+    position s in the neighbour's index space is itself only known to a few
+    N*eps in FP64 (independent atan / tan evaluations), which moves the value by
+    ds * sum_m |dw_m/ds| |x_m|; ds = 8 N eps is allowed for that.
+    """
+    from oracle import apply as o_apply, assemble
+    from oracle import cubed_sphere as ocs
+
+    og = ocs.grid(N, h)
+    ax = np.abs(full)
+    S = np.abs(o_apply(assemble(og, _lagrange_abs_rows(N, h, "w")), ax, vec))
+    Dd = np.abs(o_apply(assemble(og, _lagrange_abs_rows(N, h, "dw")), ax, vec))
+    G = og.ghost_cells
+    return rel * np.maximum(np.abs(ref[G]), S[G]) + 8 * N * U64 * Dd[G]
+
+
+def normwise_error(got_g, ref_g, data):
+    """max over inner slots of max|got - ref| / max|data| (per slot)."""
+    scale = np.abs(data).max(axis=0)
+    return float((np.abs(got_g - ref_g).max(axis=0) / np.where(scale > 0, scale, 1.0)).max())

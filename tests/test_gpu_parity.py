@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import synthinputs
-from helpers import cs_full_field, gpu_available
+from helpers import cs_full_field, gpu_available, lagrange_tolerance, normwise_error
 from oracle import apply as o_apply, assemble, vjp as o_vjp
 from oracle import cubed_sphere as ocs
 from oracle import hpcg as ohpcg
@@ -60,11 +60,12 @@ def check_cs(N, h, nf, nl, mode, vector, seed=1, noise=0.0, order=0):
     if mode == "sync":
         assert np.array_equal(got[G], ref[G])
         return 0.0
-    bound = interp_bound(op, full[Dc])
-    bound = np.maximum(np.abs(ref[G]), bound)
-    rel = np.abs(got[G] - ref[G]) / np.where(bound > 0, bound, 1.0)
-    assert rel.max() <= 1e-13, rel.max()
-    return float(rel.max())
+    tol = lagrange_tolerance(N, h, full, ref, vec if vector else None)
+    diff = np.abs(got[G] - ref[G])
+    assert (diff <= tol).all(), float((diff / np.maximum(tol, 1e-300)).max())
+    nw = normwise_error(got[G], ref[G], full[Dc])
+    assert nw <= 1e-13, nw
+    return nw
 
 
 @pytest.mark.parametrize("N,h,nf,nl,vector", [(8, 3, 1, 1, False), (12, 3, 4, 2, True), (13, 2, 4, 3, True),
