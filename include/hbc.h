@@ -127,7 +127,7 @@ typedef struct {
 
 /* Launch shape of the apply kernels (chosen by the plan, changed by tuning). */
 typedef struct {
-  int32_t block;            /* threads per workgroup (64..1024, multiple of 64) */
+  int32_t block;            /* threads per workgroup: 64, 128, 192 or 256 */
   int32_t lanes_per_row;    /* power of two; lanes that share one row */
   int32_t rows_per_tile;    /* rows per work tile */
   int32_t persistent;       /* 0: one workgroup per tile; >0: that many workgroups loop over tiles */

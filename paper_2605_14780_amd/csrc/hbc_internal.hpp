@@ -121,12 +121,33 @@ struct alignas(16) DevSeg {
   int32_t b_inner;     // 1 or inner
   int64_t nrows;
   int64_t row_base;    // first row of this segment in the plan's row numbering
+  int32_t flags;       // SEGF_* bits
+  int32_t pad_;
 };
+constexpr int32_t SEGF_ELL_PADDED = 1;  // some ELL entry is padding (column -1)
 
 struct alignas(16) DevTile {
   int32_t seg;
   int32_t nrows;
   int64_t row0;  // first row within the segment
+};
+
+// Point-major work tile: a run of rows of one segment, described by value so
+// that the kernel reads it with scalar loads; the rows' cells come from the
+// per-row tables (row_dst, row_src) at [row_begin, row_begin + nrows).
+struct alignas(16) RowTile {
+  int32_t kind;
+  int32_t rot;
+  int32_t flags;
+  int32_t width;      // ELL width
+  int64_t row_begin;  // index into the per-row tables
+  int64_t tab;        // ELL: element offset of the first row's entries; CSR: index of its row pointer
+  int64_t brow;       // b table offset of the first row (has_b)
+  double w;           // MAP weight
+  int32_t nrows;
+  int32_t has_b;
+  int32_t b_inner;
+  int32_t pad_;
 };
 
 // Adjoint: one entry per (source cell, ghost row) contribution, sorted by
@@ -153,8 +174,14 @@ struct HostTables {
   std::vector<int32_t> csr_col;
   std::vector<double> csr_val;
   std::vector<double> bval;      // b table: rows * b_inner (per segment)
+  std::vector<Box> seg_box;      // each segment's rows in global coordinates
+  std::vector<std::vector<int>> seg_order;  // global dims of the segment rows, slowest first
   CscHost csc;
   std::vector<AdjTile> adj_tiles;
+  // point-major row tables (device order) and tiles
+  std::vector<int32_t> row_dst;  // destination cell of every covered row
+  std::vector<int32_t> row_src;  // MAP rows: source cell; other rows: 0
+  std::vector<RowTile> rtiles;
 };
 
 struct Layout {
@@ -177,6 +204,9 @@ struct Plan {
   size_t dev_bytes = 0;
   const DevSeg* d_segs = nullptr;
   const DevTile* d_tiles = nullptr;
+  const RowTile* d_rtiles = nullptr;
+  const int32_t* d_row_dst = nullptr;
+  const int32_t* d_row_src = nullptr;
   const int32_t* d_ell_col = nullptr;
   const void* d_ell_val = nullptr;
   const int64_t* d_csr_ptr = nullptr;

@@ -47,6 +47,10 @@ struct PlanDesc {
   int64_t vec_lo, vec_stride, vec_len;
   int32_t lpr_shift;  // log2 lanes per row
   int32_t vec;        // elements per lane access
+  int32_t chunked;    // point-major: each row group walks a contiguous run of rows
+  int32_t pad_;
+  const int32_t* row_dst;  // point-major row tables
+  const int32_t* row_src;
 };
 
 struct AdjDesc {
@@ -55,14 +59,6 @@ struct AdjDesc {
   const int64_t* ghost;
   const void* w;
   const int32_t* rot;
-};
-
-struct BatchTile {
-  int32_t plan;
-  int32_t seg;
-  int32_t nrows;
-  int32_t pad;
-  int64_t row0;
 };
 
 template <typename T, int V>
@@ -223,8 +219,191 @@ __device__ __forceinline__ void run_tile(const PlanDesc& d, const DevSeg& s, int
   }
 }
 
+// Point-major tile over the per-row tables: the lanes of a row group cover
+// the inner values of one row with 16-byte accesses.  A row group works
+// through its rows in batches of RB: destination cells, columns and weights
+// of the batch are read first, then every source load of the batch is issued
+// before any arithmetic or store, so a lane keeps up to 4*RB independent
+// loads in flight; repeated sources of neighbouring rows hit in L1/L2.  With
+// rows of >= 16 lanes a row group takes a contiguous run of rows, otherwise
+// rows are dealt round-robin so that neighbouring lanes write neighbouring
+// cells.
+#ifndef HBC_ROWS_PER_BATCH
+#define HBC_ROWS_PER_BATCH 4
+#endif
+constexpr int RB = HBC_ROWS_PER_BATCH;  // rows per batch of a row group
+
+template <typename T, int V>
+__device__ __forceinline__ void rt_tile(const PlanDesc& d, const RowTile& tl, bool zero_only) {
+  const int lpr = 1 << d.lpr_shift;
+  const int ngroups = (int)blockDim.x >> d.lpr_shift;
+  const int grp = (int)threadIdx.x >> d.lpr_shift;
+  const int lane = (int)threadIdx.x & (lpr - 1);
+  const int64_t nvec = d.inner / V;
+  T* __restrict__ f = static_cast<T*>(d.field);
+  const int kind = zero_only ? (int)SEG_ZERO : tl.kind;
+  const bool with_b = !zero_only && tl.has_b;
+  const int nrows = tl.nrows;
+  int rb, re, rs;
+  if (d.chunked) {
+    const int ch = (nrows + ngroups - 1) / ngroups;
+    rb = grp * ch;
+    re = min(nrows, rb + ch);
+    rs = 1;
+  } else {
+    rb = grp;
+    re = nrows;
+    rs = ngroups;
+  }
+  if (rb >= re) return;
+  const int last = rb + ((re - 1 - rb) / rs) * rs;
+  const int32_t* __restrict__ rdst = d.row_dst + tl.row_begin;
+  const int32_t* __restrict__ rsrc = d.row_src + tl.row_begin;
+  const bool ell4 = kind == SEG_ELL && tl.width == 4 && !(tl.flags & SEGF_ELL_PADDED);
+  const T* __restrict__ bt = static_cast<const T*>(d.bval) + tl.brow;
+  for (int64_t v = lane; v < nvec; v += lpr) {
+    const int64_t l = v * V;
+    T sign = T(1);
+    const int64_t sl = (kind == SEG_MAP || kind == SEG_ELL || kind == SEG_CSR) ? rot_slot<T>(d, tl.rot, l, sign) : l;
+    for (int r = rb; r < re; r += RB * rs) {
+      int rr[RB];
+      int64_t dst[RB];
+#pragma unroll
+      for (int q = 0; q < RB; ++q) {
+        rr[q] = min(r + q * rs, last);
+        dst[q] = rdst[rr[q]];
+      }
+      Pack<T, V> y[RB];
+      if (kind == SEG_MAP) {
+        const T wt = T(tl.w) * sign;
+        Pack<T, V> x[RB];
+#pragma unroll
+        for (int q = 0; q < RB; ++q) x[q] = ldv<T, V>(f + (int64_t)rsrc[rr[q]] * d.cs + sl);
+#pragma unroll
+        for (int q = 0; q < RB; ++q)
+#pragma unroll
+          for (int i = 0; i < V; ++i) y[q].v[i] = wt * x[q].v[i];
+      } else if (ell4) {
+        const int32_t* __restrict__ cb = d.ell_col + tl.tab;
+        const T* __restrict__ vb = static_cast<const T*>(d.ell_val) + tl.tab;
+        int32_t c[RB][4];
+        T wt[RB][4];
+#pragma unroll
+        for (int q = 0; q < RB; ++q)
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            c[q][m] = cb[rr[q] * 4 + m];
+            wt[q][m] = vb[rr[q] * 4 + m];
+          }
+        // Consecutive rows along a face-edge strip usually read a window
+        // that slides by one cell of the neighbour's grid line:
+        // c[q][m] = c[0][0] + (q + m) * dl.  Then the batch needs RB + 3
+        // distinct sources instead of 4 * RB.
+        const int32_t c00 = c[0][0];
+        const int32_t dl = c[0][1] - c[0][0];
+        bool slide = dl != 0;
+#pragma unroll
+        for (int q = 0; q < RB; ++q)
+#pragma unroll
+          for (int m = 0; m < 4; ++m) slide = slide && (c[q][m] == c00 + (q + m) * dl);
+        if (slide) {
+          Pack<T, V> u[RB + 3];
+#pragma unroll
+          for (int j = 0; j < RB + 3; ++j) u[j] = ldv<T, V>(f + (int64_t)(c00 + j * dl) * d.cs + sl);
+#pragma unroll
+          for (int q = 0; q < RB; ++q)
+#pragma unroll
+            for (int i = 0; i < V; ++i) {
+              T a = wt[q][0] * u[q].v[i];
+              a = fma(wt[q][1], u[q + 1].v[i], a);
+              a = fma(wt[q][2], u[q + 2].v[i], a);
+              a = fma(wt[q][3], u[q + 3].v[i], a);
+              y[q].v[i] = sign * a;
+            }
+        } else {
+          Pack<T, V> x[RB][4];
+#pragma unroll
+          for (int q = 0; q < RB; ++q)
+#pragma unroll
+            for (int m = 0; m < 4; ++m) x[q][m] = ldv<T, V>(f + (int64_t)c[q][m] * d.cs + sl);
+#pragma unroll
+          for (int q = 0; q < RB; ++q)
+#pragma unroll
+            for (int i = 0; i < V; ++i) {
+              T a = wt[q][0] * x[q][0].v[i];
+              a = fma(wt[q][1], x[q][1].v[i], a);
+              a = fma(wt[q][2], x[q][2].v[i], a);
+              a = fma(wt[q][3], x[q][3].v[i], a);
+              y[q].v[i] = sign * a;
+            }
+        }
+      } else if (kind == SEG_ELL || kind == SEG_CSR) {
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+          int64_t e0, e1;
+          const int32_t* cols;
+          const T* vals;
+          if (kind == SEG_ELL) {
+            e0 = tl.tab + (int64_t)rr[q] * tl.width;
+            e1 = e0 + tl.width;
+            cols = d.ell_col;
+            vals = static_cast<const T*>(d.ell_val);
+          } else {
+            e0 = d.csr_ptr[tl.tab + rr[q]];
+            e1 = d.csr_ptr[tl.tab + rr[q] + 1];
+            cols = d.csr_col;
+            vals = static_cast<const T*>(d.csr_val);
+          }
+          bool first = true;
+#pragma unroll
+          for (int i = 0; i < V; ++i) y[q].v[i] = T(0);
+          for (int64_t e = e0; e < e1; ++e) {
+            const int32_t cc = cols[e];
+            if (cc < 0) continue;
+            const T wt = vals[e];
+            Pack<T, V> x = ldv<T, V>(f + (int64_t)cc * d.cs + sl);
+#pragma unroll
+            for (int i = 0; i < V; ++i) y[q].v[i] = first ? wt * x.v[i] : fma(wt, x.v[i], y[q].v[i]);
+            first = false;
+          }
+#pragma unroll
+          for (int i = 0; i < V; ++i) y[q].v[i] = sign * y[q].v[i];
+        }
+      } else {  // zero rows, or b-only rows
+#pragma unroll
+        for (int q = 0; q < RB; ++q)
+#pragma unroll
+          for (int i = 0; i < V; ++i) y[q].v[i] = T(0);
+      }
+      if (with_b) {
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+          const T* bp = bt + (int64_t)rr[q] * tl.b_inner;
+#pragma unroll
+          for (int i = 0; i < V; ++i) {
+            const T bb = tl.b_inner == 1 ? bp[0] : bp[l + i];
+            y[q].v[i] = kind == SEG_VEC ? bb : y[q].v[i] + bb;
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < RB; ++q)
+        if (r + q * rs < re) stv<T, V>(f + dst[q] * d.cs + l, y[q]);
+    }
+  }
+}
+
+template <typename T, int V>
+__global__ __launch_bounds__(256) void k_apply_rows(PlanDesc d, const RowTile* __restrict__ tiles, int ntiles,
+                                                    int zero_only) {
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const RowTile tl = tiles[t];
+    rt_tile<T, V>(d, tl, zero_only != 0);
+  }
+}
+
 template <typename T, int V, bool ROWFAST>
-__global__ __launch_bounds__(1024) void k_apply(PlanDesc d, const DevTile* __restrict__ tiles, int ntiles,
+__global__ __launch_bounds__(256) void k_apply(PlanDesc d, const DevTile* __restrict__ tiles, int ntiles,
                                                 int zero_only) {
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const DevTile tl = tiles[t];
@@ -234,25 +413,24 @@ __global__ __launch_bounds__(1024) void k_apply(PlanDesc d, const DevTile* __res
 }
 
 template <typename T>
-__global__ __launch_bounds__(1024) void k_batch(const PlanDesc* __restrict__ descs, const BatchTile* __restrict__ tiles,
-                                                int ntiles) {
+__global__ __launch_bounds__(256) void k_batch(const PlanDesc* __restrict__ descs, const RowTile* __restrict__ tiles,
+                                               int ntiles) {
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const BatchTile bt = tiles[t];
-    const PlanDesc d = descs[bt.plan];
-    const DevSeg s = d.segs[bt.seg];
+    const RowTile tl = tiles[t];
+    const PlanDesc d = descs[tl.pad_];
     if (sizeof(T) == 4 && d.vec == 4)
-      run_tile<T, (sizeof(T) == 4 ? 4 : 2), false>(d, s, bt.row0, bt.nrows, false, threadIdx.x, blockDim.x);
+      rt_tile<T, (sizeof(T) == 4 ? 4 : 2)>(d, tl, false);
     else if (d.vec == 2)
-      run_tile<T, 2, false>(d, s, bt.row0, bt.nrows, false, threadIdx.x, blockDim.x);
+      rt_tile<T, 2>(d, tl, false);
     else
-      run_tile<T, 1, false>(d, s, bt.row0, bt.nrows, false, threadIdx.x, blockDim.x);
+      rt_tile<T, 1>(d, tl, false);
   }
 }
 
 // Adjoint gather: for each source cell, in ascending ghost order,
 //   xbar[src, l] += sum_e w_e * sign_e * ybar[ghost_e, rot_e(l)]
 template <typename T, int V, bool ROWFAST>
-__global__ __launch_bounds__(1024) void k_adjoint(PlanDesc d, AdjDesc a, const AdjTile* __restrict__ tiles,
+__global__ __launch_bounds__(256) void k_adjoint(PlanDesc d, AdjDesc a, const AdjTile* __restrict__ tiles,
                                                   int ntiles) {
   const int lpr = 1 << d.lpr_shift;
   const int rp = (int)blockDim.x >> d.lpr_shift;
@@ -474,6 +652,8 @@ PlanDesc make_desc(const Plan& p, void* field) {
   d.csr_col = p.d_csr_col;
   d.csr_val = p.d_csr_val;
   d.bval = p.d_bval;
+  d.row_dst = p.d_row_dst;
+  d.row_src = p.d_row_src;
   d.inner = p.layout.inner;
   if (p.layout.order == HBC_POINT_MAJOR) {
     d.cs = p.layout.inner;
@@ -487,6 +667,7 @@ PlanDesc make_desc(const Plan& p, void* field) {
   d.vec_len = p.layout.vec_len;
   d.lpr_shift = ilog2(p.tune.lanes_per_row);
   d.vec = p.vec;
+  d.chunked = p.tune.lanes_per_row >= 16 ? 1 : 0;
   return d;
 }
 
@@ -520,6 +701,8 @@ void device_upload_plan(Plan& p) {
   size_t o_csrc = pk.vec(T.csr_col);
   size_t o_csrv = pk.reals(T.csr_val, p.dtype);
   size_t o_b = pk.reals(T.bval, p.dtype);
+  size_t o_rd = pk.vec(T.row_dst);
+  size_t o_rs = pk.vec(T.row_src);
   void* dev = nullptr;
   hipError_t e = hipMalloc(&dev, pk.buf.size());
   if (e != hipSuccess) fail(e == hipErrorOutOfMemory ? HBC_ENOMEM : HBC_EHIP, std::string("hipMalloc: ") + hipGetErrorString(e));
@@ -534,18 +717,27 @@ void device_upload_plan(Plan& p) {
   p.d_csr_col = reinterpret_cast<const int32_t*>(b + o_csrc);
   p.d_csr_val = b + o_csrv;
   p.d_bval = b + o_b;
+  p.d_row_dst = reinterpret_cast<const int32_t*>(b + o_rd);
+  p.d_row_src = reinterpret_cast<const int32_t*>(b + o_rs);
   device_upload_tiles(p);
 }
 
 void device_upload_tiles(Plan& p) {
+  // one allocation: segment tiles (plane-major path), then row tiles (point-major path)
   if (p.d_tiles) HIP_CHECK(hipFree(const_cast<DevTile*>(p.d_tiles)));
   p.d_tiles = nullptr;
+  p.d_rtiles = nullptr;
+  const size_t n1 = align256(std::max<size_t>(1, p.host.tiles.size()) * sizeof(DevTile));
+  const size_t n2 = std::max<size_t>(1, p.host.rtiles.size()) * sizeof(RowTile);
   void* t = nullptr;
-  size_t n = std::max<size_t>(1, p.host.tiles.size()) * sizeof(DevTile);
-  HIP_CHECK(hipMalloc(&t, n));
+  HIP_CHECK(hipMalloc(&t, n1 + n2));
   if (!p.host.tiles.empty())
     HIP_CHECK(hipMemcpy(t, p.host.tiles.data(), p.host.tiles.size() * sizeof(DevTile), hipMemcpyHostToDevice));
+  if (!p.host.rtiles.empty())
+    HIP_CHECK(hipMemcpy(static_cast<char*>(t) + n1, p.host.rtiles.data(), p.host.rtiles.size() * sizeof(RowTile),
+                        hipMemcpyHostToDevice));
   p.d_tiles = static_cast<const DevTile*>(t);
+  p.d_rtiles = reinterpret_cast<const RowTile*>(static_cast<char*>(t) + n1);
 }
 
 void device_upload_csc(Plan& p) {
@@ -584,11 +776,11 @@ static void launch_apply_t(const Plan& p, const PlanDesc& d, hipStream_t st, boo
   if (p.layout.order == HBC_PLANE_MAJOR) {
     hipLaunchKernelGGL((k_apply<T, 1, true>), dim3(grid), dim3(blk), 0, st, d, p.d_tiles, nt, z);
   } else if (p.vec == 4) {
-    hipLaunchKernelGGL((k_apply<T, 4, false>), dim3(grid), dim3(blk), 0, st, d, p.d_tiles, nt, z);
+    hipLaunchKernelGGL((k_apply_rows<T, (sizeof(T) == 4 ? 4 : 2)>), dim3(grid), dim3(blk), 0, st, d, p.d_rtiles, nt, z);
   } else if (p.vec == 2) {
-    hipLaunchKernelGGL((k_apply<T, 2, false>), dim3(grid), dim3(blk), 0, st, d, p.d_tiles, nt, z);
+    hipLaunchKernelGGL((k_apply_rows<T, 2>), dim3(grid), dim3(blk), 0, st, d, p.d_rtiles, nt, z);
   } else {
-    hipLaunchKernelGGL((k_apply<T, 1, false>), dim3(grid), dim3(blk), 0, st, d, p.d_tiles, nt, z);
+    hipLaunchKernelGGL((k_apply_rows<T, 1>), dim3(grid), dim3(blk), 0, st, d, p.d_rtiles, nt, z);
   }
   HIP_CHECK(hipGetLastError());
 }
@@ -851,8 +1043,8 @@ struct Batch {
   hbc_tune tune{};
   std::vector<PlanDesc> descs;
   PlanDesc* d_descs = nullptr;
-  std::vector<BatchTile> tiles;
-  BatchTile* d_tiles = nullptr;
+  std::vector<RowTile> tiles;
+  RowTile* d_tiles = nullptr;
   bool bound = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -861,21 +1053,36 @@ struct Batch {
 
 static void batch_tiles(Batch* b) {
   // per plan: rows per tile so that a tile holds about tune.rows_per_tile inner values
-  std::vector<std::vector<BatchTile>> per(b->plans.size());
+  std::vector<std::vector<RowTile>> per(b->plans.size());
   for (size_t k = 0; k < b->plans.size(); ++k) {
     const Plan& p = *b->plans[k];
     const int64_t I = p.layout.inner;
     int lpr = p.tune.lanes_per_row;
     if (b->tune.lanes_per_row > 0) lpr = std::min(lpr, b->tune.lanes_per_row);
     b->descs[k].lpr_shift = ilog2(lpr);
+    b->descs[k].chunked = lpr >= 16 ? 1 : 0;
     const int64_t rp = std::max<int64_t>(1, b->tune.block / lpr);
     int64_t rpt = std::max<int64_t>(1, (int64_t)b->tune.rows_per_tile / I);
     rpt = ((rpt + rp - 1) / rp) * rp;
     rpt = std::min<int64_t>(rpt, 1 << 20);
     for (size_t s = 0; s < p.host.segs.size(); ++s) {
       const DevSeg& sg = p.host.segs[s];
-      for (int64_t r0 = 0; r0 < sg.nrows; r0 += rpt)
-        per[k].push_back(BatchTile{(int32_t)k, (int32_t)s, (int32_t)std::min<int64_t>(rpt, sg.nrows - r0), 0, r0});
+      for (int64_t r0 = 0; r0 < sg.nrows; r0 += rpt) {
+        RowTile rt{};
+        rt.kind = sg.kind;
+        rt.rot = sg.rot;
+        rt.flags = sg.flags;
+        rt.width = sg.width;
+        rt.row_begin = sg.row_base + r0;
+        rt.tab = sg.kind == SEG_ELL ? sg.tab + r0 * sg.width : sg.tab + r0;
+        rt.brow = sg.brow + r0 * sg.b_inner;
+        rt.w = sg.w;
+        rt.nrows = (int32_t)std::min<int64_t>(rpt, sg.nrows - r0);
+        rt.has_b = sg.has_b;
+        rt.b_inner = sg.b_inner;
+        rt.pad_ = (int32_t)k;  // plan index
+        per[k].push_back(rt);
+      }
     }
   }
   // interleave plans round-robin so that every part of the launch mixes grids
@@ -891,9 +1098,9 @@ static void batch_tiles(Batch* b) {
   }
   if (b->d_tiles) HIP_CHECK(hipFree(b->d_tiles));
   b->d_tiles = nullptr;
-  HIP_CHECK(hipMalloc(&b->d_tiles, std::max<size_t>(1, b->tiles.size()) * sizeof(BatchTile)));
+  HIP_CHECK(hipMalloc(&b->d_tiles, std::max<size_t>(1, b->tiles.size()) * sizeof(RowTile)));
   if (!b->tiles.empty())
-    HIP_CHECK(hipMemcpy(b->d_tiles, b->tiles.data(), b->tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice));
+    HIP_CHECK(hipMemcpy(b->d_tiles, b->tiles.data(), b->tiles.size() * sizeof(RowTile), hipMemcpyHostToDevice));
   b->stats.tiles = (int64_t)b->tiles.size();
   if (b->bound) device_batch_bind(b, nullptr);
 }
@@ -999,7 +1206,7 @@ void device_batch_launch_graph(Batch* b, void* stream) {
 hbc_tune device_batch_get_tune(const Batch* b) { return b->tune; }
 
 void device_batch_set_tune(Batch* b, const hbc_tune& t) {
-  if (t.block < 64 || t.block > 1024 || t.block % 64) fail(HBC_EINVAL, "block must be a multiple of 64 in [64, 1024]");
+  if (t.block < 64 || t.block > 256 || t.block % 64) fail(HBC_EINVAL, "block must be 64, 128, 192 or 256");
   if (t.lanes_per_row < 0 || (t.lanes_per_row & (t.lanes_per_row - 1))) fail(HBC_EINVAL, "lanes_per_row: 0 or a power of two");
   if (t.rows_per_tile < 1 || t.persistent < 0) fail(HBC_EINVAL, "bad tile size or persistent count");
   b->tune = t;
@@ -1070,7 +1277,7 @@ double device_batch_autotune(Batch* b, const char* cache_path, void* stream) {
   const hbc_tune start = b->tune;
   hbc_tune best = start;
   double best_ms = 1e30;
-  const int blocks[] = {256, 512};
+  const int blocks[] = {128, 256};
   const int elems[] = {4096, 8192, 16384, 32768};
   const int pers[] = {0, 2, 4, 8};
   const int lprs[] = {0, 32};

@@ -143,6 +143,24 @@ void for_box(const Box& b, F&& f) {
   }
 }
 
+// Iterate the multi-indices of a box with the dims in `order` (slowest first);
+// dims not listed stay at their lower bound (extent 1).
+template <class F>
+void for_box_order(const Box& b, const std::vector<int>& order, F&& f) {
+  int64_t c[HBC_MAX_DIM];
+  for (int d = 0; d < b.nd; ++d) c[d] = b.lo[d];
+  const int64_t n = b.count();
+  const int k = (int)order.size();
+  for (int64_t q = 0; q < n; ++q) {
+    f(c, q);
+    for (int j = k - 1; j >= 0; --j) {
+      const int d = order[j];
+      if (++c[d] < b.hi[d]) break;
+      c[d] = b.lo[d];
+    }
+  }
+}
+
 // Data cell of a global linear index; HBC_ERANGE if it is not a data cell.
 int64_t data_cell_of_linear(const Grid& g, int64_t lin) {
   int64_t c[HBC_MAX_DIM];
@@ -292,6 +310,21 @@ void compile_plan(const Program& prog, const Layout& lay, int dtype, Plan& plan)
         if (subs[m].rot != rot) fail(HBC_EOVERLAP, "overlapping rows with different component rotations");
     }
     seg.rot = rot;
+    // device row order: the box's non-trivial dims; for table rows of
+    // point-major fields the longest dim goes fastest, so that consecutive rows
+    // of a run share source cells (a face-edge strip walks along the edge)
+    std::vector<int> order;
+    for (int d = 0; d < nd; ++d)
+      if (pc.box.extent(d) > 1) order.push_back(d);
+    const bool table_rows = !mats.empty() && !(mats.size() == 1 && (subs[mats[0]].kind == SUB_MAP ||
+                                                                     subs[mats[0]].kind == SUB_ZERO));
+#ifndef HBC_NATURAL_ROW_ORDER
+    if (table_rows && lay.order == HBC_POINT_MAJOR)
+#else
+    if (false)
+#endif
+      std::stable_sort(order.begin(), order.end(),
+                       [&](int a, int c) { return pc.box.extent(a) < pc.box.extent(c); });
 
     if (mats.size() == 1 && subs[mats[0]].kind == SUB_MAP) {
       const Sub& s = subs[mats[0]];
@@ -318,7 +351,7 @@ void compile_plan(const Program& prog, const Layout& lay, int dtype, Plan& plan)
       }
       st.rows_map += seg.nrows;
       st.nnz += seg.nrows;
-      for_box(pc.box, [&](const int64_t* r, int64_t) {
+      for_box_order(pc.box, order, [&](const int64_t* r, int64_t) {
         int64_t c[HBC_MAX_DIM];
         map_apply(s, nd, r, c);
         sources.push_back(g.cell(sb, c));
@@ -332,7 +365,7 @@ void compile_plan(const Program& prog, const Layout& lay, int dtype, Plan& plan)
       seg.width = s.width;
       // absolute element offset: rows of this segment start here (width entries each)
       seg.tab = (int64_t)T.ell_col.size();
-      for_box(pc.box, [&](const int64_t* r, int64_t) {
+      for_box_order(pc.box, order, [&](const int64_t* r, int64_t) {
         int64_t k = box_linear(s.rows, r);
         for (int m = 0; m < s.width; ++m) {
           int64_t lin = s.cols[k * s.width + m];
@@ -340,6 +373,7 @@ void compile_plan(const Program& prog, const Layout& lay, int dtype, Plan& plan)
           if (lin < 0) {
             T.ell_col.push_back(-1);
             T.ell_val.push_back(0.0);
+            seg.flags |= SEGF_ELL_PADDED;
             continue;
           }
           int64_t cell = data_cell_of_linear(g, lin);
@@ -354,7 +388,7 @@ void compile_plan(const Program& prog, const Layout& lay, int dtype, Plan& plan)
       // one CSR sub, or several overlapping subs summed into merged CSR rows
       seg.kind = SEG_CSR;
       seg.tab = (int64_t)T.csr_ptr.size();
-      for_box(pc.box, [&](const int64_t* r, int64_t) {
+      for_box_order(pc.box, order, [&](const int64_t* r, int64_t) {
         std::vector<std::pair<int64_t, double>> ents;
         for (int m : mats) {
           const Sub& s = subs[m];
@@ -411,7 +445,7 @@ void compile_plan(const Program& prog, const Layout& lay, int dtype, Plan& plan)
       seg.has_b = 1;
       seg.b_inner = (int32_t)bi;
       seg.brow = (int64_t)T.bval.size();
-      for_box(pc.box, [&](const int64_t* r, int64_t) {
+      for_box_order(pc.box, order, [&](const int64_t* r, int64_t) {
         for (int64_t l = 0; l < bi; ++l) {
           double acc = 0.0;
           bool first = true;
@@ -431,8 +465,7 @@ void compile_plan(const Program& prog, const Layout& lay, int dtype, Plan& plan)
     // drop extent-1 dims, then merge dims contiguous in both dst and src
     int k = 0;
     int64_t ext[HBC_MAX_DIM], ds[HBC_MAX_DIM], ss[HBC_MAX_DIM];
-    for (int d = 0; d < nd; ++d) {
-      if (pc.box.extent(d) == 1) continue;
+    for (int d : order) {
       ext[k] = pc.box.extent(d);
       ds[k] = dst_st[d];
       ss[k] = src_st[d];
@@ -463,6 +496,23 @@ void compile_plan(const Program& prog, const Layout& lay, int dtype, Plan& plan)
       if (d < k && ext[d] >= (int64_t(1) << 31)) fail(HBC_EUNSUPPORTED, "box extent too large");
     }
     T.segs.push_back(seg);
+    T.seg_box.push_back(pc.box);
+    T.seg_order.push_back(order);
+    // per-row destination (and MAP source) cells in device order
+    {
+      int64_t c[SEG_MAXD] = {0};
+      for (int64_t r = 0; r < seg.nrows; ++r) {
+        int64_t q = r, dst = seg.dst_base, src = seg.src_base;
+        for (int d = seg.nd - 1; d >= 0; --d) {
+          c[d] = q % seg.ext[d];
+          q /= seg.ext[d];
+          dst += c[d] * seg.dst_stride[d];
+          src += c[d] * seg.src_stride[d];
+        }
+        T.row_dst.push_back((int32_t)dst);
+        T.row_src.push_back(seg.kind == SEG_MAP ? (int32_t)src : 0);
+      }
+    }
   }
 
   // 4. statistics
@@ -513,23 +563,30 @@ hbc_tune default_tune(const Plan& plan) {
   t.persistent = 0;
   const int64_t rows = std::max<int64_t>(1, plan.stats.rows_covered);
   if (plan.layout.order == HBC_POINT_MAJOR) {
+    // one 16-byte vector per lane: a row group covers a whole row
     int64_t nvec = plan.layout.inner / plan.vec;
-    t.lanes_per_row = (int32_t)std::min<int64_t>(64, pow2_ceil(nvec));
+    t.lanes_per_row = (int32_t)std::min<int64_t>(t.block, pow2_ceil(nvec));
   } else {
     t.lanes_per_row = 1;
   }
   const int64_t rows_per_pass = t.block / t.lanes_per_row;
-  // aim for about 2048 tiles so that all 256 CUs get several tiles
-  int64_t rpt = rows / 2048;
-  rpt = std::max<int64_t>(rpt, rows_per_pass);
+  // Short tiles keep many workgroups in flight (the apply is latency bound per
+  // row: table reads, then source loads, then stores): one batch of 4 rows per
+  // row group when a row fills >= 16 lanes, else about 4096 tiles in all.
+  int64_t rpt;
+  if (t.lanes_per_row >= 16) {
+    rpt = rows_per_pass * 4;
+  } else {
+    rpt = std::max<int64_t>(rows / 4096, rows_per_pass);
+    rpt = ((rpt + rows_per_pass - 1) / rows_per_pass) * rows_per_pass;
+  }
   rpt = std::min<int64_t>(rpt, 16384);
-  rpt = ((rpt + rows_per_pass - 1) / rows_per_pass) * rows_per_pass;
   t.rows_per_tile = (int32_t)rpt;
   return t;
 }
 
 void build_tiles(Plan& plan, const hbc_tune& t) {
-  if (t.block < 64 || t.block > 1024 || t.block % 64) fail(HBC_EINVAL, "block must be a multiple of 64 in [64, 1024]");
+  if (t.block < 64 || t.block > 256 || t.block % 64) fail(HBC_EINVAL, "block must be 64, 128, 192 or 256");
   if (t.lanes_per_row < 1 || (t.lanes_per_row & (t.lanes_per_row - 1)) || t.lanes_per_row > t.block)
     fail(HBC_EINVAL, "lanes_per_row must be a power of two <= block");
   if (t.rows_per_tile < 1) fail(HBC_EINVAL, "rows_per_tile must be >= 1");
@@ -564,6 +621,24 @@ void build_tiles(Plan& plan, const hbc_tune& t) {
   plan.host.tiles.swap(out);
   plan.stats.tiles = (int64_t)plan.host.tiles.size();
   plan.tune = t;
+  // the same cut as point-major row tiles (same XCD-aware order)
+  plan.host.rtiles.clear();
+  for (const DevTile& tl : plan.host.tiles) {
+    const DevSeg& sg = plan.host.segs[tl.seg];
+    RowTile rt{};
+    rt.kind = sg.kind;
+    rt.rot = sg.rot;
+    rt.flags = sg.flags;
+    rt.width = sg.width;
+    rt.row_begin = sg.row_base + tl.row0;
+    rt.tab = sg.kind == SEG_ELL ? sg.tab + tl.row0 * sg.width : sg.tab + tl.row0;
+    rt.brow = sg.brow + tl.row0 * sg.b_inner;
+    rt.w = sg.w;
+    rt.nrows = tl.nrows;
+    rt.has_b = sg.has_b;
+    rt.b_inner = sg.b_inner;
+    plan.host.rtiles.push_back(rt);
+  }
 }
 
 void build_csc(Plan& plan) {
@@ -631,36 +706,37 @@ void build_csc(Plan& plan) {
 int plan_row(const Plan& plan, int64_t cell, int64_t l, int cap, int64_t* cols, double* vals, int32_t* nnz,
              double* b, int32_t* kind, int32_t* rot) {
   const HostTables& T = plan.host;
+  const Grid& g = plan.grid;
   *nnz = 0;
   *b = 0.0;
   *kind = -1;
   *rot = 0;
-  for (const DevSeg& s : T.segs) {
-    // locate `cell` in the segment's box: strides are decreasing in magnitude
-    int64_t off = cell - s.dst_base;
-    int64_t c[SEG_MAXD];
-    bool in = true;
-    for (int d = 0; d < s.nd; ++d) {
-      if (s.dst_stride[d] == 0) {
-        c[d] = 0;
-        continue;
-      }
-      int64_t q = off >= 0 ? off / s.dst_stride[d] : -1;
-      if (q < 0 || q >= s.ext[d]) {
-        in = false;
-        break;
-      }
-      c[d] = q;
-      off -= q * s.dst_stride[d];
-    }
-    if (!in || off != 0) continue;
+  // global coordinates of the cell
+  int blk = -1;
+  for (size_t k = 0; k < g.blocks.size(); ++k)
+    if (cell >= g.blocks[k].first_cell && cell < g.blocks[k].first_cell + g.blocks[k].cells) blk = (int)k;
+  if (blk < 0) return HBC_OK;
+  int64_t c[HBC_MAX_DIM];
+  int64_t off = cell - g.blocks[blk].first_cell;
+  for (int d = 0; d < g.nd; ++d) {
+    c[d] = g.blocks[blk].full.lo[d] + off / g.blocks[blk].stride[d];
+    off %= g.blocks[blk].stride[d];
+  }
+  for (size_t si = 0; si < T.segs.size(); ++si) {
+    if (!T.seg_box[si].contains(c)) continue;
+    const DevSeg& s = T.segs[si];
+    const Box& bx = T.seg_box[si];
     int64_t r = 0;
-    for (int d = 0; d < s.nd; ++d) r = r * s.ext[d] + c[d];
+    for (int d : T.seg_order[si]) r = r * bx.extent(d) + (c[d] - bx.lo[d]);
     *kind = s.kind;
     *rot = s.rot;
     if (s.kind == SEG_MAP) {
-      int64_t src = s.src_base;
-      for (int d = 0; d < s.nd; ++d) src += c[d] * s.src_stride[d];
+      // row r's coordinates in the device order -> source cell
+      int64_t q = r, src = s.src_base;
+      for (int d = s.nd - 1; d >= 0; --d) {
+        src += (q % s.ext[d]) * s.src_stride[d];
+        q /= s.ext[d];
+      }
       if (cap > 0) {
         cols[0] = src;
         vals[0] = s.w;
