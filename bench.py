@@ -1,16 +1,23 @@
 #!/usr/bin/env python3
 """BC-apply benchmark on one MI355X.
 
-Workload (the headline): cubed sphere C384, halo 3, 64 levels x 4 fields
-(h, tracer scalars; u, v vector with component rotation across faces), FP64,
-point-major storage; BC = face-edge Lagrange interpolation along the
+Headline workload: cubed sphere C384, halo 3, 64 levels x 4 fields (h, tracer
+scalars; u, v vector with component rotation across faces), FP64,
+point-major storage; BC = face-edge 4-point Lagrange interpolation along the
 neighbour's grid line (weights built in FP64 on the GPU) + zero corners.
 Inputs are seeded synthetic spherical-harmonic fields + N(0, 1e-3) noise.
 
-One step = one apply of the whole BC (structured corner rows, interpolation
-rows, component rotation) to one field.  The K timed steps run as one HIP
-graph of K applies cycling over `--copies` independent fields, so the touched
-data (about 115 MB per apply) is not served from the 256 MB Infinity Cache.
+One step = one apply of the whole BC (corner zero rows, interpolation rows,
+component rotation) to one field.  The K timed steps run as one HIP graph of
+K applies cycling over `--copies` independent fields, so the touched data
+(about 115 MB per apply) is not served from the 256 MB Infinity Cache.
+
+The other workloads run after the headline and are reported under "extras":
+C48 single-field latency, the C384 workload in FP32, the HPCG-shaped 256^3
+BC + 27-point operator (BC only, unfused, fused), 64 batched grids of uneven
+sizes in FP32 (persistent launch vs 64 plain launches, autotuned), and the
+C768 forward / adjoint in FP64 and FP32.  The CPU oracle is timed on the
+host and every GPU result is checked against it in the same run.
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -20,12 +27,17 @@ import hashlib
 import json
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_source_hash():
@@ -50,34 +62,387 @@ def traffic_from_profile(name):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline_cfg2(full, got, N, h, vec, budget_s):
-    """cpu_baseline leg: the CPU oracle as it stands (assemble A once, then full
-    single-thread applies, timed), and the GPU result compared with it."""
+class Timer:
+    """Device events on the current stream around `fn` (which launches `calls` calls)."""
+
+    def __init__(self, torch):
+        self.torch = torch
+
+    def __call__(self, fn, calls, warm=1):
+        torch = self.torch
+        for _ in range(warm):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e3 / calls  # microseconds per call
+
+
+def torch_graph(torch, fn):
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    return g
+
+
+# ---------------------------------------------------------------------------------------------
+# cpu_baseline leg: the CPU oracle timed on the host, and every GPU result checked against it
+# ---------------------------------------------------------------------------------------------
+def cpu_baseline_and_checks(ctx, budget_s):
     import numpy as np
-    from oracle import apply as o_apply, assemble
+    from oracle import VectorSub, apply as o_apply, assemble
     from oracle import cubed_sphere as ocs
+    from oracle import hpcg as ohpcg
     from tests.helpers import lagrange_tolerance, normwise_error
 
+    out = {}
+    # headline: assemble once, time full single-thread applies
+    N, h, vec, full = ctx["c2_N"], ctx["c2_h"], ctx["c2_vec"], ctx["c2_full"]
     og = ocs.grid(N, h)
     op = assemble(og, ocs.subs(N, h, "lagrange", vector=True))
     reps, t0 = 0, time.perf_counter()
-    ref = None
     while True:
         ref = o_apply(op, full, vec)
         reps += 1
         if time.perf_counter() - t0 >= budget_s:
             break
     dt = time.perf_counter() - t0
-    G = og.ghost_cells
+    out["timing"] = (reps, dt)
+    G, Dc = og.ghost_cells, og.data_cells
+    got = ctx["c2_got"]
     tol = lagrange_tolerance(N, h, full, ref, vec)
     diff = np.abs(got[G] - ref[G])
-    check = {
-        "normwise_rel_err": normwise_error(got[G], ref[G], full[og.data_cells]),
+    out["c384_f64"] = {
+        "normwise_rel_err": normwise_error(got[G], ref[G], full[Dc]),
         "max_err_over_tolerance": float((diff / np.maximum(tol, 1e-300)).max()),
-        "data_cells_untouched": bool(np.array_equal(got[og.data_cells], full[og.data_cells])),
+        "data_cells_untouched": bool(np.array_equal(got[Dc], full[Dc])),
         "all_ghosts_written": bool(np.isfinite(got[G]).all()),
     }
-    return reps, dt, check
+    if "c2_got32" in ctx:
+        g32 = ctx["c2_got32"]
+        ref32in = o_apply(op, full.astype(np.float32).astype(np.float64), vec)
+        out["c384_f32"] = {
+            "normwise_err_vs_fp64_oracle": normwise_error(g32[G], ref[G], full[Dc]),
+            "normwise_err_vs_oracle_on_fp32_input": normwise_error(g32[G], ref32in[G], full[Dc]),
+            "rms_err_vs_fp64_oracle_rel": float(np.sqrt(np.mean((g32[G] - ref[G]) ** 2)) / np.abs(full[Dc]).max()),
+        }
+    del ref
+    # C48
+    if "c1" in ctx:
+        N1, h1, f1, res = ctx["c1"]
+        og1 = ocs.grid(N1, h1)
+        for mode, got1 in res.items():
+            op1 = assemble(og1, ocs.subs(N1, h1, mode))
+            r1 = o_apply(op1, f1)
+            G1 = og1.ghost_cells
+            if mode == "sync":
+                out[f"c48_{mode}_bit_exact"] = bool(np.array_equal(got1[G1], r1[G1]))
+            else:
+                t1 = lagrange_tolerance(N1, h1, f1, r1, None)
+                out[f"c48_{mode}_max_err_over_tolerance"] = float((np.abs(got1[G1] - r1[G1]) / t1).max())
+    # HPCG-shaped
+    if "c3" in ctx:
+        x, ghosted_got, y_fused, y_unfused = ctx["c3"]
+        blocks = ohpcg.ghosted_blocks(x, 2)
+        want = np.concatenate([b.reshape(-1) for b in blocks])
+        out["hpcg_ghosts_bit_exact"] = bool(np.array_equal(ghosted_got, want))
+        yref = np.concatenate([ohpcg.stencil27(b).reshape(-1) for b in blocks])
+        bound = np.concatenate([ohpcg.abs_row_sum(b).reshape(-1) for b in blocks])
+        for name, y in (("fused", y_fused), ("unfused", y_unfused)):
+            out[f"hpcg_{name}_max_err_over_bound"] = float((np.abs(y - yref) / (64 * 2.0 ** -53 * bound)).max())
+    # C768 forward with b
+    if "c5" in ctx:
+        N5, h5, f5, bvals, got5 = ctx["c5"]
+        og5 = ocs.grid(N5, h5)
+        subs = ocs.subs(N5, h5, "lagrange")
+        k = 0
+        for box in c768_b_boxes(N5, h5):
+            n = int(np.prod([b - a for a, b in box]))
+            subs.append(VectorSub(box, bvals[k:k + n]))
+            k += n
+        op5 = assemble(og5, subs)
+        r5 = o_apply(op5, f5)
+        G5 = og5.ghost_cells
+        out["c768_f64_forward_normwise_err"] = normwise_error(got5[G5], r5[G5], f5[og5.data_cells])
+    return out
+
+
+def c768_b_boxes(N, h):
+    """Ghost boxes of every face (4 strips, then 4 corners), index (face, j, i)."""
+    out = []
+    for f in range(6):
+        fb = (f, f + 1)
+        out += [[fb, (0, N), (-h, 0)], [fb, (0, N), (N, N + h)], [fb, (-h, 0), (0, N)], [fb, (N, N + h), (0, N)]]
+    for f in range(6):
+        fb = (f, f + 1)
+        out += [[fb, a, b] for a in ((-h, 0), (N, N + h)) for b in ((-h, 0), (N, N + h))]
+    return out
+
+
+# ---------------------------------------------------------------------------------------------
+def headline(ctx, args, hb, torch, tm):
+    import numpy as np
+    from tests.helpers import cs_full_field
+
+    N, h, nf, nl = 384, 3, 4, 64
+    I = nf * nl
+    vec = (2 * nl, nl, nl)
+    t0 = time.perf_counter()
+    grid, prog = hb.cs_program(N, h, hb.CS_LAGRANGE, vector=True)
+    plan = hb.Plan(prog, inner=I, vec=vec, dtype=hb.F64)
+    st = plan.stats()
+    full = cs_full_field(N, h, nf, nl, seed=2, noise=1e-3)
+    src = torch.from_numpy(full).cuda()
+    fields = [src.clone() for _ in range(args.copies)]
+    torch.cuda.synchronize()
+    log(f"C384 setup {time.perf_counter() - t0:.1f}s: {st['segments']} segments, {st['tiles']} tiles, "
+        f"tune {plan.tune}")
+    hb.apply(plan, fields[0])
+    torch.cuda.synchronize()
+    ctx.update(c2_N=N, c2_h=h, c2_vec=vec, c2_full=full, c2_got=fields[0].cpu().numpy())
+    fields[0].copy_(src)
+    del src
+
+    # timed region: K applies in one graph, cycling over the copies
+    graph = hb.ApplyGraph(plan, fields, args.steps)
+    for k in range(args.warmup):
+        hb.apply(plan, fields[k % len(fields)])
+    graph.launch()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    e0.record()
+    graph.launch()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = e0.elapsed_time(e1)
+    res = {"plan": plan, "stats": st, "ms": ms, "wall": wall}
+    # warm (cache-resident) and eager numbers for context
+    g1 = hb.ApplyGraph(plan, [fields[0]], args.steps)
+    res["warm_us"] = tm(g1.launch, args.steps)
+
+    def eager():
+        for k in range(args.steps):
+            hb.apply(plan, fields[k % len(fields)])
+
+    res["eager_us"] = tm(eager, args.steps, warm=0)
+    del g1, graph
+    # FP32 storage / accumulation on the same workload
+    plan32 = hb.Plan(prog, inner=I, vec=vec, dtype=hb.F32)
+    src32 = torch.from_numpy(full.astype(np.float32)).cuda()
+    f32 = [src32.clone() for _ in range(args.copies)]
+    hb.apply(plan32, f32[0])
+    torch.cuda.synchronize()
+    ctx["c2_got32"] = f32[0].cpu().numpy().astype(np.float64)
+    g32 = hb.ApplyGraph(plan32, f32, args.steps)
+    us32 = tm(g32.launch, args.steps)
+    st32 = plan32.stats()
+    res["f32"] = {"us_per_apply": us32, "ghost_cells_per_s": st32["ghost_values"] / us32 * 1e6,
+                  "hbm_frac": st32["alg_bytes"] / us32 / 1e3 / HBM_PEAK_GBS,
+                  "f64_over_f32_time": (ms * 1e3 / args.steps) / us32}
+    del g32, f32, src32, fields
+    torch.cuda.empty_cache()
+    return res
+
+
+def extra_c48(ctx, hb, torch, tm):
+    from tests.helpers import cs_full_field
+    N, h = 48, 3
+    full = cs_full_field(N, h, 1, 1, seed=1)
+    out, got = {}, {}
+    for mode, m in (("lagrange", hb.CS_LAGRANGE), ("sync", hb.CS_SYNC)):
+        grid, prog = hb.cs_program(N, h, m)
+        plan = hb.Plan(prog, inner=1)
+        t = torch.from_numpy(full.copy()).cuda()
+        hb.apply(plan, t)
+        torch.cuda.synchronize()
+        got[mode] = t.cpu().numpy()
+        g = hb.ApplyGraph(plan, [t], 2000)
+        us = tm(g.launch, 2000)
+        out[mode] = {"us_per_apply": us, "ghost_cells_per_s": plan.stats()["ghost_values"] / us * 1e6}
+    ctx["c1"] = (N, h, full, got)
+    return out
+
+
+def extra_hpcg(ctx, hb, torch, tm):
+    import numpy as np
+    import synthinputs
+    nb, n = 2, 128
+    x = synthinputs.uniform((nb * n,) * 3, seed=3)
+    grid = hb.Grid.cartesian([nb] * 3, [n] * 3, 1)
+    prog = hb.Program(grid)
+    prog.cart_add_halo([nb] * 3, [n] * 3, 1)
+    plan = hb.Plan(prog, inner=1)
+    st = plan.stats()
+    W = n + 2
+    full = np.full((nb ** 3, W, W, W), np.nan)
+    for bz in range(nb):
+        for by in range(nb):
+            for bx in range(nb):
+                full[(bz * nb + by) * nb + bx, 1:-1, 1:-1, 1:-1] = x[bz * n:(bz + 1) * n, by * n:(by + 1) * n,
+                                                                    bx * n:(bx + 1) * n]
+    full = full.reshape(-1)
+    src = torch.from_numpy(full).cuda()
+    C = 3
+    xs = [src.clone() for _ in range(C)]
+    ys = [torch.empty(nb ** 3 * n ** 3, dtype=torch.float64, device="cuda") for _ in range(C)]
+    hb.fused_stencil27(plan, xs[0], ys[0])
+    torch.cuda.synchronize()
+    ghosted = xs[0].cpu().numpy()
+    y_fused = ys[0].cpu().numpy()
+    xs[0].copy_(src)
+    hb.apply(plan, xs[0])
+    hb.stencil27(plan, xs[0], ys[0])
+    torch.cuda.synchronize()
+    y_unfused = ys[0].cpu().numpy()
+    ctx["c3"] = (x, ghosted, y_fused, y_unfused)
+    R = 60
+
+    def bc_only():
+        for r in range(R):
+            hb.apply(plan, xs[r % C])
+
+    def unfused():
+        for r in range(R):
+            hb.apply(plan, xs[r % C])
+            hb.stencil27(plan, xs[r % C], ys[r % C])
+
+    def fused():
+        for r in range(R):
+            hb.fused_stencil27(plan, xs[r % C], ys[r % C])
+
+    out = {}
+    data_b = nb ** 3 * n ** 3 * 8
+    ghost_b = st["rows_covered"] * 8
+    alg = {"bc_only": st["alg_bytes"],
+           "unfused": st["alg_bytes"] + (len(full) * 8 + data_b),
+           "fused": 2 * data_b + ghost_b}
+    for name, fn in (("bc_only", bc_only), ("unfused", unfused), ("fused", fused)):
+        g = torch_graph(torch, fn)
+        us = tm(g.replay, R)
+        out[name] = {"us": us, "alg_bytes": alg[name], "hbm_frac": alg[name] / us / 1e3 / HBM_PEAK_GBS}
+    out["fused_speedup_vs_unfused"] = out["unfused"]["us"] / out["fused"]["us"]
+    out["ghost_cells_per_s_bc_only"] = st["ghost_values"] / out["bc_only"]["us"] * 1e6
+    return out
+
+
+def extra_batch(ctx, hb, torch, tm):
+    import synthinputs
+    draws = synthinputs.batch_draw()
+    plans, plain, batched = [], [], []
+    t0 = time.perf_counter()
+    for k, (N, h, L) in enumerate(draws):
+        grid, prog = hb.cs_program(N, h, hb.CS_LAGRANGE)
+        plan = hb.Plan(prog, inner=L, dtype=hb.F32)
+        W = N + 2 * h
+        full = torch.full((6, W, W, L), float("nan"), dtype=torch.float32, device="cuda")
+        full[:, h:h + N, h:h + N, :] = synthinputs.cs_sh_field_torch(N, 1, L, seed=4000 + k, dtype=torch.float32)
+        full = full.reshape(-1)
+        plans.append(plan)
+        plain.append(full)
+        batched.append(full.clone())
+    torch.cuda.synchronize()
+    log(f"batch setup {time.perf_counter() - t0:.1f}s")
+    ghost_values = sum(p.stats()["ghost_values"] for p in plans)
+    alg = sum(p.stats()["alg_bytes"] for p in plans)
+
+    def plain_all():
+        for p, f in zip(plans, plain):
+            hb.apply(p, f)
+
+    gp = torch_graph(torch, plain_all)
+    us_plain = tm(gp.replay, 1)
+    batch = hb.Batch(plans)
+    batch.bind(batched)
+    s = torch.cuda.current_stream()
+    batch.graph_capture(s.cuda_stream)
+    us_default = tm(lambda: batch.graph_launch(s.cuda_stream), 1)
+    tuned_ms = batch.autotune(os.path.join(tempfile.gettempdir(), "hbc_autotune_cache.jsonl"))
+    batch.graph_capture(s.cuda_stream)
+    us_tuned = tm(lambda: batch.graph_launch(s.cuda_stream), 1)
+    # bit identity of batched vs plain (both applied once more from the same inputs)
+    for p, b in zip(plain, batched):
+        b.copy_(p)
+    gp.replay()
+    batch.graph_launch(s.cuda_stream)
+    torch.cuda.synchronize()
+    same = all(torch.equal(p, b) for p, b in zip(plain, batched))
+    out = {"grids": len(plans), "ghost_values": ghost_values, "alg_bytes": alg,
+           "plain_64_launches_us": us_plain, "batched_default_us": us_default, "batched_tuned_us": us_tuned,
+           "tune": batch.tune, "autotune_ms": tuned_ms,
+           "speedup_batched_vs_plain": us_plain / us_tuned,
+           "ghost_cells_per_s": ghost_values / us_tuned * 1e6,
+           "hbm_frac": alg / us_tuned / 1e3 / HBM_PEAK_GBS,
+           "bit_identical_to_plain": bool(same),
+           "resident_bytes": sum(f.numel() * 4 for f in plain) * 2}
+    del gp, batch, plain, batched
+    torch.cuda.empty_cache()
+    return out
+
+
+def extra_adjoint(ctx, hb, torch, tm):
+    import numpy as np
+    import synthinputs
+    N, h, L = 768, 3, 32
+    rng = np.random.default_rng(5)
+    boxes = c768_b_boxes(N, h)
+    nrows = sum(int(np.prod([b - a for a, b in box])) for box in boxes)
+    bvals = rng.normal(0.0, 1.0, size=(nrows, L))
+    W = N + 2 * h
+    data = synthinputs.cs_sh_field_torch(N, 1, L, seed=5)
+    out = {}
+    for name, dt, tdt in (("f64", hb.F64, torch.float64), ("f32", hb.F32, torch.float32)):
+        grid, prog = hb.cs_program(N, h, hb.CS_LAGRANGE)
+        k = 0
+        for box in boxes:
+            n = int(np.prod([b - a for a, b in box]))
+            prog.add_vector(box, bvals[k:k + n], ninner=L)
+            k += n
+        plan = hb.Plan(prog, inner=L, dtype=dt)
+        st = plan.stats()
+        full = torch.zeros((6, W, W, L), dtype=tdt, device="cuda")
+        full[:, h:h + N, h:h + N, :] = data.to(tdt)
+        full = full.reshape(-1)
+        C = 3
+        xs = [full.clone() for _ in range(C)]
+        if name == "f64":
+            hb.apply(plan, xs[0])
+            torch.cuda.synchronize()
+            ctx["c5"] = (N, h, full.view(-1, L).cpu().numpy(), bvals, xs[0].view(-1, L).cpu().numpy())
+            xs[0].copy_(full)
+        gf = hb.ApplyGraph(plan, xs, 60)
+        us_f = tm(gf.launch, 60)
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(7)
+        ys = [torch.randn(full.numel(), dtype=tdt, device="cuda", generator=gen) for _ in range(C)]
+        ga = hb.ApplyGraph(plan, ys, 60, op=hb.OP_ADJOINT)
+        us_a = tm(ga.launch, 60)
+        # dot-product test <A x, y> = <x, A^T y>, accumulated in FP64
+        x = full.clone()
+        z = torch.zeros_like(full)
+        Ax = x.clone()
+        hb.apply(plan, Ax)
+        hb.apply(plan, z)
+        y = torch.randn(full.numel(), dtype=tdt, device="cuda", generator=gen)
+        Aty = y.clone()
+        hb.apply_adjoint(plan, Aty)
+        torch.cuda.synchronize()
+        lhs = float(((Ax.double() - z.double()) * y.double()).sum())
+        rhs = float((x.double() * Aty.double()).sum())
+        out[name] = {"forward_us": us_f, "adjoint_us": us_a, "adjoint_over_forward": us_a / us_f,
+                     "forward_hbm_frac": st["alg_bytes"] / us_f / 1e3 / HBM_PEAK_GBS,
+                     "adjoint_hbm_frac": st["alg_bytes_adjoint"] / us_a / 1e3 / HBM_PEAK_GBS,
+                     "ghost_cells_per_s_forward": st["ghost_values"] / us_f * 1e6,
+                     "dot_product_rel": abs(lhs - rhs) / max(abs(lhs), abs(rhs))}
+        del gf, ga, xs, ys
+        torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -93,77 +458,39 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described, not built"}))
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_2605_14780_amd as hb
-    from tests.helpers import cs_full_field
 
     torch.cuda.set_device(0)
     # graph capture needs a stream other than the legacy default one
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
-    N, h, nf, nl = 384, 3, 4, 64
-    I = nf * nl
-    vec = (2 * nl, nl, nl)
-    t_setup = time.perf_counter()
-    grid, prog = hb.cs_program(N, h, hb.CS_LAGRANGE, vector=True)
-    plan = hb.Plan(prog, inner=I, vec=vec, dtype=hb.F64)
-    st = plan.stats()
-    full = cs_full_field(N, h, nf, nl, seed=2, noise=1e-3)
-    base_src = torch.from_numpy(full).cuda()
-    fields = [base_src.clone() for _ in range(args.copies)]
-    torch.cuda.synchronize()
-    print(f"[bench] setup {time.perf_counter() - t_setup:.1f}s, plan {st['segments']} segments, "
-          f"{st['tiles']} tiles, tune {plan.tune}", file=sys.stderr, flush=True)
+    tm = Timer(torch)
+    ctx = {}
+    res = headline(ctx, args, hb, torch, tm)
+    st = res["stats"]
+    log("headline done")
+    extras = {"c384_warm_cache_us_per_apply": res["warm_us"], "c384_eager_us_per_apply": res["eager_us"],
+              "c384_f32": res["f32"]}
+    if not args.no_extras:
+        for name, fn in (("c48_latency", extra_c48), ("hpcg_256cube", extra_hpcg),
+                         ("batched_64_grids_f32", extra_batch), ("c768_adjoint", extra_adjoint)):
+            t0 = time.perf_counter()
+            extras[name] = fn(ctx, hb, torch, tm)
+            log(f"{name} done in {time.perf_counter() - t0:.1f}s")
+        f64_ns = res["ms"] * 1e6 / args.steps / st["ghost_values"]
+        b32 = extras["batched_64_grids_f32"]
+        extras["ns_per_ghost_value_plain_f64_over_batched_f32"] = f64_ns / (b32["batched_tuned_us"] * 1e3 /
+                                                                            b32["ghost_values"])
 
-    # correctness of the timed configuration against the CPU oracle (also the cpu_baseline leg)
-    hb.apply(plan, fields[0])
-    torch.cuda.synchronize()
-    got = fields[0].cpu().numpy()
-    reps, dt, check = cpu_baseline_cfg2(full, got, N, h, vec, args.cpu_budget)
-    print(f"[bench] check vs oracle {check}; oracle {reps} applies in {dt:.1f}s", file=sys.stderr, flush=True)
-    fields[0].copy_(base_src)
-
-    # timed region: K applies in one graph, cycling over the copies
-    graph = hb.ApplyGraph(plan, fields, args.steps, stream=stream.cuda_stream)
-    for _ in range(args.warmup):
-        hb.apply(plan, fields[1 % len(fields)])
-    graph.launch(stream.cuda_stream)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    e0.record(stream)
-    graph.launch(stream.cuda_stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    ms = e0.elapsed_time(e1)
+    log("cpu_baseline leg: oracle timing and checks")
+    chk = cpu_baseline_and_checks(ctx, args.cpu_budget)
+    reps, dt = chk.pop("timing")
+    ms = res["ms"]
     ms_step = ms / args.steps
     value = st["ghost_values"] * args.steps / (ms / 1e3)
     achieved = st["alg_bytes"] / (ms_step / 1e3) / 1e9
-
-    extras = {}
-    # warm (cache-resident) number: same graph shape on one field
-    g1 = hb.ApplyGraph(plan, [fields[0]], args.steps, stream=stream.cuda_stream)
-    g1.launch(stream.cuda_stream)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    g1.launch(stream.cuda_stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    extras["warm_ms_per_apply"] = e0.elapsed_time(e1) / args.steps
-    # eager launches (includes launch gaps)
-    e0.record(stream)
-    for k in range(args.steps):
-        hb.apply(plan, fields[k % len(fields)])
-    e1.record(stream)
-    torch.cuda.synchronize()
-    extras["eager_ms_per_apply"] = e0.elapsed_time(e1) / args.steps
-    del g1
-
     out = {
         "metric": "BC-apply ghost cells/s + % HBM peak; batched FP32 & adjoint vs plain FP64",
         "value": value,
@@ -179,17 +506,17 @@ def main():
         "data": "synthetic (seeded spherical-harmonic fields + N(0,1e-3) noise)",
         "config": {"workload": "cubed-sphere C384, halo 3, 64 levels x 4 fields (h, tracer, u, v), "
                                "Lagrange face-edge interpolation + component rotation + zero corners, "
-                               "point-major FP64, cold cache", "N": N, "halo": h, "inner": I,
-                   "ghost_values_per_apply": st["ghost_values"], "copies": args.copies},
+                               "point-major FP64, cache-rotated over independent fields", "N": 384, "halo": 3,
+                   "inner": 256, "ghost_values_per_apply": st["ghost_values"], "copies": args.copies},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile("apply_c384_f64_pmc.json"),
-                     "alg_bytes_per_launch": st["alg_bytes"], "kernel": "k_apply<double,2,false>"},
+                     "alg_bytes_per_launch": st["alg_bytes"], "kernel": "hbc::k_apply_rows<double, 2>"},
         "cpu_baseline": {"value": st["ghost_values"] * reps / dt, "unit": "ghost cells/s", "cores": 1,
                          "kind": "oracle",
                          "sample": f"{reps} full applies of the C384 operator (scipy CSR A @ X over 256 inner "
                                    f"slots + rotation + scatter), assembly excluded"},
-        "check_vs_oracle": check,
-        "wall_s_timed": wall,
+        "checks_vs_oracle": chk,
+        "wall_s_timed": res["wall"],
         "extras": extras,
     }
     print(json.dumps(out), flush=True)

@@ -243,13 +243,16 @@ int hbc_apply_adjoint(const hbc_plan* plan, void* grad, int64_t nelem, void* str
 int hbc_time_apply(const hbc_plan* plan, void* const* fields, int64_t nelem, int32_t nfields, int32_t reps,
                    void* stream, double* ms);
 
-/* Capture `reps` applies of `plan`, cycling over the `nfields` device fields
- * (each of `nelem` values), into one HIP graph on `stream` (not NULL), for
- * replay without per-launch overhead.  The fields must stay alive while the
- * graph exists. */
+/* Capture `reps` calls of `plan` (op HBC_OP_APPLY: hbc_apply; HBC_OP_ADJOINT:
+ * hbc_apply_adjoint), cycling over the `nfields` device fields (each of
+ * `nelem` values), into one HIP graph on `stream` (not NULL), for replay
+ * without per-launch overhead.  The fields must stay alive while the graph
+ * exists. */
+#define HBC_OP_APPLY 0
+#define HBC_OP_ADJOINT 1
 typedef struct hbc_graph hbc_graph;
-int hbc_graph_create(const hbc_plan* plan, void* const* fields, int64_t nelem, int32_t nfields, int32_t reps,
-                     void* stream, hbc_graph** out);
+int hbc_graph_create(const hbc_plan* plan, int32_t op, void* const* fields, int64_t nelem, int32_t nfields,
+                     int32_t reps, void* stream, hbc_graph** out);
 int hbc_graph_launch(hbc_graph* g, void* stream);
 void hbc_graph_destroy(hbc_graph* g);
 

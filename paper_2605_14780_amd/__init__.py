@@ -22,6 +22,7 @@ POINT_MAJOR, PLANE_MAJOR = 0, 1
 STRICT_COVER, ALLOW_OVERLAP_SUM = 1, 2
 PLAN_HOST_ONLY = 1
 CS_SYNC, CS_LAGRANGE = 0, 1
+OP_APPLY, OP_ADJOINT = 0, 1
 
 SEG_ZERO, SEG_MAP, SEG_ELL, SEG_CSR, SEG_VEC = 0, 1, 2, 3, 4
 
@@ -97,7 +98,7 @@ SIGNATURES = {
     "hbc_apply": (I32, [P, P, I64, P]),
     "hbc_apply_adjoint": (I32, [P, P, I64, P]),
     "hbc_time_apply": (I32, [P, C.POINTER(P), I64, I32, I32, P, PD]),
-    "hbc_graph_create": (I32, [P, C.POINTER(P), I64, I32, I32, P, C.POINTER(P)]),
+    "hbc_graph_create": (I32, [P, I32, C.POINTER(P), I64, I32, I32, P, C.POINTER(P)]),
     "hbc_graph_launch": (I32, [P, P]),
     "hbc_graph_destroy": (None, [P]),
     "hbc_stencil27": (I32, [P, P, I64, P, I64, P]),
@@ -373,15 +374,15 @@ def time_apply(plan: Plan, fields, reps, stream=None):
 
 
 class ApplyGraph:
-    """``reps`` applies of ``plan`` over ``fields`` (cycled) captured in one HIP graph."""
+    """``reps`` applies (or adjoints) of ``plan`` over ``fields`` (cycled) captured in one HIP graph."""
 
-    def __init__(self, plan: Plan, fields, reps, stream=None):
+    def __init__(self, plan: Plan, fields, reps, stream=None, op=OP_APPLY):
         ptrs = [_field(plan, f) for f in fields]
         arr = (P * len(ptrs))(*[p for p, _ in ptrs])
         self._h = P()
         self._fields = list(fields)  # keep the memory alive with the graph
         self.reps = reps
-        _check(lib().hbc_graph_create(plan._h, arr, ptrs[0][1], len(ptrs), reps, _stream(stream),
+        _check(lib().hbc_graph_create(plan._h, op, arr, ptrs[0][1], len(ptrs), reps, _stream(stream),
                                       C.byref(self._h)))
 
     def launch(self, stream=None):

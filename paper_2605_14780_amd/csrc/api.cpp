@@ -432,6 +432,15 @@ static void check_size(const hbc_plan* plan, int64_t nelem) {
     fail(HBC_EINVAL, "field has " + std::to_string(nelem) + " values, the plan needs " + std::to_string(want));
 }
 
+static void ensure_csc(hbc_plan* plan) {
+  std::lock_guard<std::mutex> lk(plan->csc_mu);
+  if (!plan->csc_ready) {
+    build_csc(plan->p);
+    device_upload_csc(plan->p);
+    plan->csc_ready = true;
+  }
+}
+
 int hbc_apply(const hbc_plan* plan, void* field, int64_t nelem, void* stream) {
   return guard([&] {
     check_device_plan(plan);
@@ -447,14 +456,7 @@ int hbc_apply_adjoint(const hbc_plan* plan_c, void* grad, int64_t nelem, void* s
     check_field(grad);
     check_size(plan_c, nelem);
     auto* plan = const_cast<hbc_plan*>(plan_c);
-    {
-      std::lock_guard<std::mutex> lk(plan->csc_mu);
-      if (!plan->csc_ready) {
-        build_csc(plan->p);
-        device_upload_csc(plan->p);
-        plan->csc_ready = true;
-      }
-    }
+    ensure_csc(plan);
     device_adjoint(plan->p, grad, stream);
   });
 }
@@ -477,16 +479,18 @@ static void check_stencil_sizes(const hbc_plan* plan, int64_t xn, int64_t yn) {
   if (yn != nd) fail(HBC_EINVAL, "y has " + std::to_string(yn) + " values, the grid has " + std::to_string(nd) + " data cells");
 }
 
-int hbc_graph_create(const hbc_plan* plan, void* const* fields, int64_t nelem, int32_t nfields, int32_t reps,
-                     void* stream, hbc_graph** out) {
+int hbc_graph_create(const hbc_plan* plan, int32_t op, void* const* fields, int64_t nelem, int32_t nfields,
+                     int32_t reps, void* stream, hbc_graph** out) {
   return guard([&] {
     check_device_plan(plan);
     need(fields && out && nfields >= 1 && reps >= 1 && stream, "bad graph arguments");
+    need(op == HBC_OP_APPLY || op == HBC_OP_ADJOINT, "op must be HBC_OP_APPLY or HBC_OP_ADJOINT");
     check_size(plan, nelem);
     for (int k = 0; k < nfields; ++k) check_field(fields[k]);
+    if (op == HBC_OP_ADJOINT) ensure_csc(const_cast<hbc_plan*>(plan));
     auto* g = new hbc_graph;
     try {
-      g->g = device_graph_create(plan->p, fields, nfields, reps, stream);
+      g->g = device_graph_create(plan->p, op, fields, nfields, reps, stream);
     } catch (...) {
       delete g;
       throw;

@@ -429,54 +429,88 @@ __global__ __launch_bounds__(256) void k_batch(const PlanDesc* __restrict__ desc
 
 // Adjoint gather: for each source cell, in ascending ghost order,
 //   xbar[src, l] += sum_e w_e * sign_e * ybar[ghost_e, rot_e(l)]
+// One thread sums one value, so the result does not depend on scheduling.
+// The entries of a source are read in chunks of EB: their ghost cells and
+// weights first, then all ybar loads of the chunk, then the ordered sum.
+constexpr int EB = 8;
+
 template <typename T, int V, bool ROWFAST>
 __global__ __launch_bounds__(256) void k_adjoint(PlanDesc d, AdjDesc a, const AdjTile* __restrict__ tiles,
                                                   int ntiles) {
   const int lpr = 1 << d.lpr_shift;
-  const int rp = (int)blockDim.x >> d.lpr_shift;
-  int lane, rsub;
+  const int ngroups = (int)blockDim.x >> d.lpr_shift;
+  int lane, grp;
   if (ROWFAST) {
-    rsub = threadIdx.x % rp;
-    lane = threadIdx.x / rp;
+    grp = threadIdx.x % ngroups;
+    lane = threadIdx.x / ngroups;
   } else {
     lane = threadIdx.x & (lpr - 1);
-    rsub = threadIdx.x >> d.lpr_shift;
+    grp = threadIdx.x >> d.lpr_shift;
   }
   const int64_t nvec = d.inner / V;
   T* __restrict__ f = static_cast<T*>(d.field);
   const T* __restrict__ W = static_cast<const T*>(a.w);
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const AdjTile tl = tiles[t];
-    for (int r = rsub; r < tl.count; r += rp) {
+    int rb, re, rs;
+    if (!ROWFAST && d.chunked) {
+      const int ch = (tl.count + ngroups - 1) / ngroups;
+      rb = grp * ch;
+      re = min(tl.count, rb + ch);
+      rs = 1;
+    } else {
+      rb = grp;
+      re = tl.count;
+      rs = ngroups;
+    }
+    for (int r = rb; r < re; r += rs) {
       const int64_t k = tl.first + r;
       const int64_t cell = a.src[k];
       const int64_t e0 = a.ptr[k], e1 = a.ptr[k + 1];
       for (int64_t v = lane; v < nvec; v += lpr) {
         const int64_t l = v * V;
+        T* px = f + cell * d.cs + l * d.ls;
+        Pack<T, V> x;
+        if (ROWFAST) {
+#pragma unroll
+          for (int i = 0; i < V; ++i) x.v[i] = px[i * d.ls];
+        } else {
+          x = ldv<T, V>(px);
+        }
         Pack<T, V> acc;
 #pragma unroll
         for (int i = 0; i < V; ++i) acc.v[i] = T(0);
-        for (int64_t e = e0; e < e1; ++e) {
-          T sign;
-          const int64_t sl = rot_slot<T>(d, a.rot[e], l, sign);
-          const T w = W[e] * sign;
-          Pack<T, V> g = ldv<T, V>(f + a.ghost[e] * d.cs + sl * d.ls);
-          if (e == e0) {
+        bool first = true;
+        for (int64_t eb = e0; eb < e1; eb += EB) {
+          const int ne = (int)min<int64_t>(EB, e1 - eb);
+          int64_t off[EB];
+          T wt[EB];
 #pragma unroll
-            for (int i = 0; i < V; ++i) acc.v[i] = w * g.v[i];
-          } else {
+          for (int j = 0; j < EB; ++j) {
+            const int64_t e = eb + min(j, ne - 1);
+            T sign;
+            const int64_t sl = rot_slot<T>(d, a.rot[e], l, sign);
+            wt[j] = W[e] * sign;
+            off[j] = a.ghost[e] * d.cs + sl * d.ls;
+          }
+          Pack<T, V> g[EB];
 #pragma unroll
-            for (int i = 0; i < V; ++i) acc.v[i] = fma(w, g.v[i], acc.v[i]);
+          for (int j = 0; j < EB; ++j)
+            if (j < ne) g[j] = ldv<T, V>(f + off[j]);
+#pragma unroll
+          for (int j = 0; j < EB; ++j) {
+            if (j >= ne) break;
+#pragma unroll
+            for (int i = 0; i < V; ++i) acc.v[i] = first ? wt[j] * g[j].v[i] : fma(wt[j], g[j].v[i], acc.v[i]);
+            first = false;
           }
         }
-        T* px = f + cell * d.cs + l * d.ls;
+#pragma unroll
+        for (int i = 0; i < V; ++i) x.v[i] = x.v[i] + acc.v[i];
         if (ROWFAST) {
 #pragma unroll
-          for (int i = 0; i < V; ++i) px[i * d.ls] = px[i * d.ls] + acc.v[i];
+          for (int i = 0; i < V; ++i) px[i * d.ls] = x.v[i];
         } else {
-          Pack<T, V> x = ldv<T, V>(px);
-#pragma unroll
-          for (int i = 0; i < V; ++i) x.v[i] = x.v[i] + acc.v[i];
           stv<T, V>(px, x);
         }
       }
@@ -997,7 +1031,7 @@ struct ApplyGraph {
   hipGraphExec_t exec = nullptr;
 };
 
-void* device_graph_create(const Plan& p, void* const* fields, int nfields, int reps, void* stream) {
+void* device_graph_create(const Plan& p, int op, void* const* fields, int nfields, int reps, void* stream) {
   if (!stream) fail(HBC_EINVAL, "graph capture needs a stream");
   auto* g = new ApplyGraph;
   hipStream_t s = S(stream);
@@ -1007,7 +1041,12 @@ void* device_graph_create(const Plan& p, void* const* fields, int nfields, int r
     fail(HBC_EHIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
   }
   try {
-    for (int r = 0; r < reps; ++r) device_apply(p, fields[r % nfields], stream, false);
+    for (int r = 0; r < reps; ++r) {
+      if (op == HBC_OP_ADJOINT)
+        device_adjoint(p, fields[r % nfields], stream);
+      else
+        device_apply(p, fields[r % nfields], stream, false);
+    }
   } catch (...) {
     (void)hipStreamEndCapture(s, &g->graph);
     if (g->graph) (void)hipGraphDestroy(g->graph);

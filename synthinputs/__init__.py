@@ -19,6 +19,8 @@ Recipes (each seeded with ``numpy.random.default_rng(seed)``):
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 from scipy.special import sph_harm_y
 
@@ -121,4 +123,75 @@ def batch_draw(n: int = 64, seed: int = 4):
         h = int(rng.integers(2, 5))
         L = int(rng.integers(1, 129))
         out.append((N, h, L))
+    return out
+
+
+def _legendre_table(x, lmax):
+    """P[l][m] (Condon-Shortley phase) for 0 <= m <= l <= lmax, as torch tensors."""
+    import torch
+    P = {}
+    s = torch.sqrt(torch.clamp(1 - x * x, min=0.0))
+    pmm = torch.ones_like(x)
+    for m in range(lmax + 1):
+        if m > 0:
+            pmm = -pmm * (2 * m - 1) * s
+        P[(m, m)] = pmm
+        if m + 1 <= lmax:
+            P[(m + 1, m)] = x * (2 * m + 1) * pmm
+        for l in range(m + 2, lmax + 1):
+            P[(l, m)] = ((2 * l - 1) * x * P[(l - 1, m)] - (l + m - 1) * P[(l - 2, m)]) / (l - m)
+    return P
+
+
+def cs_cell_centres_torch(N, device, dtype=None):
+    """Same points as ``cs_cell_centres``, computed with torch on ``device``."""
+    import torch
+    dtype = dtype or torch.float64
+    fr = torch.tensor(_FRAMES, dtype=dtype, device=device)
+    ang = -math.pi / 4 + (torch.arange(N, dtype=dtype, device=device) + 0.5) * (math.pi / (2 * N))
+    ta = torch.tan(ang)
+    p = (fr[:, 0][:, None, None, :] + ta[None, None, :, None] * fr[:, 1][:, None, None, :]
+         + ta[None, :, None, None] * fr[:, 2][:, None, None, :])
+    return p / torch.linalg.norm(p, dim=-1, keepdim=True)
+
+
+def cs_sh_field_torch(N, nfields=1, nlevels=1, seed=1, noise=0.0, device="cuda", dtype=None):
+    """``cs_sh_field`` evaluated with torch on ``device`` (same draws, same
+    functions; values agree with the numpy version to rounding).  Noise, if
+    any, comes from torch's generator seeded with ``seed`` and so differs
+    from the numpy version's noise."""
+    import torch
+    dtype = dtype or torch.float64
+    rng = np.random.default_rng(seed)
+    pts = cs_cell_centres_torch(N, device)
+    x = pts[..., 2].clamp(-1.0, 1.0)
+    phi = torch.atan2(pts[..., 1], pts[..., 0])
+    P = _legendre_table(x, 8)
+    cache = {}
+
+    def Y(l, m):
+        key = (l, m)
+        if key not in cache:
+            am = abs(m)
+            norm = math.sqrt((2 * l + 1) / (4 * math.pi) * math.factorial(l - am) / math.factorial(l + am))
+            base = norm * P[(l, am)]
+            if m > 0:
+                cache[key] = math.sqrt(2.0) * base * torch.cos(am * phi)
+            elif m < 0:
+                cache[key] = math.sqrt(2.0) * base * torch.sin(am * phi)
+            else:
+                cache[key] = base
+        return cache[key]
+
+    nslot = nfields * nlevels
+    out = torch.empty((6, N, N, nslot), dtype=dtype, device=device)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    for k in range(nslot):
+        acc = torch.zeros((6, N, N), dtype=torch.float64, device=device)
+        for (l, m, c) in sh_terms(rng):
+            acc += c * Y(l, m)
+        if noise > 0.0:
+            acc += noise * torch.randn(acc.shape, dtype=torch.float64, device=device, generator=gen)
+        out[..., k] = acc.to(dtype)
     return out
