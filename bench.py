@@ -143,7 +143,8 @@ def cpu_baseline_and_checks(ctx, budget_s):
                 out[f"c48_{mode}_bit_exact"] = bool(np.array_equal(got1[G1], r1[G1]))
             else:
                 t1 = lagrange_tolerance(N1, h1, f1, r1, None)
-                out[f"c48_{mode}_max_err_over_tolerance"] = float((np.abs(got1[G1] - r1[G1]) / t1).max())
+                out[f"c48_{mode}_max_err_over_tolerance"] = float(
+                    (np.abs(got1[G1] - r1[G1]) / np.maximum(t1, 1e-300)).max())
     # HPCG-shaped
     if "c3" in ctx:
         x, ghosted_got, y_fused, y_unfused = ctx["c3"]
@@ -453,7 +454,18 @@ def main():
     ap.add_argument("--copies", type=int, default=9, help="independent fields cycled for cold-cache timing")
     ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of 256 MiB, 20 times (counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(20):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read": a.numel() * 8, "bytes_written": b.numel() * 8}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described, not built"}))
         sys.exit(2)
