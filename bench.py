@@ -318,17 +318,24 @@ def extra_hpcg(ctx, hb, torch, tm):
         for r in range(R):
             hb.fused_stencil27(plan, xs[r % C], ys[r % C])
 
+    def fused_no_ghost_store():
+        for r in range(R):
+            hb.fused_stencil27(plan, xs[r % C], ys[r % C], write_ghosts=False)
+
     out = {}
     data_b = nb ** 3 * n ** 3 * 8
     ghost_b = st["rows_covered"] * 8
     alg = {"bc_only": st["alg_bytes"],
            "unfused": st["alg_bytes"] + (len(full) * 8 + data_b),
-           "fused": 2 * data_b + ghost_b}
-    for name, fn in (("bc_only", bc_only), ("unfused", unfused), ("fused", fused)):
+           "fused": 2 * data_b + ghost_b,
+           "fused_no_ghost_store": 2 * data_b}
+    for name, fn in (("bc_only", bc_only), ("unfused", unfused), ("fused", fused),
+                     ("fused_no_ghost_store", fused_no_ghost_store)):
         g = torch_graph(torch, fn)
         us = tm(g.replay, R)
         out[name] = {"us": us, "alg_bytes": alg[name], "hbm_frac": alg[name] / us / 1e3 / HBM_PEAK_GBS}
     out["fused_speedup_vs_unfused"] = out["unfused"]["us"] / out["fused"]["us"]
+    out["fused_no_ghost_store_speedup_vs_unfused"] = out["unfused"]["us"] / out["fused_no_ghost_store"]["us"]
     out["ghost_cells_per_s_bc_only"] = st["ghost_values"] / out["bc_only"]["us"] * 1e6
     return out
 

@@ -264,8 +264,12 @@ void hbc_graph_destroy(hbc_graph* g);
 /* Unfused consumer: reads the ghosts already in x (run hbc_apply first). */
 int hbc_stencil27(const hbc_plan* plan, const void* x, int64_t x_nelem, void* y, int64_t y_nelem, void* stream);
 /* Fused: reads neighbours through the BC (copy from the source block or zero)
- * and also writes x's ghost cells, in one kernel. */
-int hbc_fused_stencil27(const hbc_plan* plan, void* x, int64_t x_nelem, void* y, int64_t y_nelem, void* stream);
+ * in one kernel; with write_ghosts != 0 it also writes x's covered ghost cells
+ * (as hbc_apply would), otherwise x is only read (the ghosts are consumed
+ * without being stored, Sec. IV-C's removal of BC writes no later reader
+ * needs). */
+int hbc_fused_stencil27(const hbc_plan* plan, void* x, int64_t x_nelem, void* y, int64_t y_nelem,
+                        int32_t write_ghosts, void* stream);
 
 /* ---- FP64 interpolation weights on the device (setup, not part of an apply) -- */
 /* For ghost layer k < h and tangential index t < N of any cubed-sphere face

@@ -102,7 +102,7 @@ SIGNATURES = {
     "hbc_graph_launch": (I32, [P, P]),
     "hbc_graph_destroy": (None, [P]),
     "hbc_stencil27": (I32, [P, P, I64, P, I64, P]),
-    "hbc_fused_stencil27": (I32, [P, P, I64, P, I64, P]),
+    "hbc_fused_stencil27": (I32, [P, P, I64, P, I64, I32, P]),
     "hbc_cs_lagrange_weights": (I32, [I64, I64, P, P, P]),
     "hbc_batch_create": (I32, [C.POINTER(P), I32, C.POINTER(P)]),
     "hbc_batch_destroy": (None, [P]),
@@ -403,12 +403,12 @@ def stencil27(plan: Plan, x, y, stream=None):
     return y
 
 
-def fused_stencil27(plan: Plan, x, y, stream=None):
+def fused_stencil27(plan: Plan, x, y, write_ghosts=True, stream=None):
     xp, xn = _field(plan, x)
     yp, yn = P(y.data_ptr()), int(y.numel())
     if y.dtype != x.dtype or not y.is_contiguous() or not y.is_cuda:
         raise ValueError("y must be a contiguous GPU tensor of x's dtype")
-    _check(lib().hbc_fused_stencil27(plan._h, xp, xn, yp, yn, _stream(stream)))
+    _check(lib().hbc_fused_stencil27(plan._h, xp, xn, yp, yn, int(bool(write_ghosts)), _stream(stream)))
     return y
 
 

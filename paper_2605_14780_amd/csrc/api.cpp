@@ -522,13 +522,14 @@ int hbc_stencil27(const hbc_plan* plan, const void* x, int64_t x_nelem, void* y,
   });
 }
 
-int hbc_fused_stencil27(const hbc_plan* plan, void* x, int64_t x_nelem, void* y, int64_t y_nelem, void* stream) {
+int hbc_fused_stencil27(const hbc_plan* plan, void* x, int64_t x_nelem, void* y, int64_t y_nelem,
+                        int32_t write_ghosts, void* stream) {
   return guard([&] {
     check_device_plan(plan);
     check_field(x);
     check_field(y);
     check_stencil_sizes(plan, x_nelem, y_nelem);
-    device_stencil27(const_cast<hbc_plan*>(plan)->p, x, y, stream, true, x);
+    device_stencil27(const_cast<hbc_plan*>(plan)->p, x, y, stream, true, write_ghosts ? x : nullptr);
   });
 }
 

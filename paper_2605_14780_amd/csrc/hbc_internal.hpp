@@ -220,8 +220,11 @@ struct Plan {
   const void* d_csc_w = nullptr;
   const int32_t* d_csc_rot = nullptr;
   const AdjTile* d_adj_tiles = nullptr;
-  // fused 27-point consumer: per block and direction, source block and cell delta
-  std::vector<int64_t> st_info;  // filled lazily on first use
+  // 27-point consumer: per block and neighbour direction, the block the BC
+  // copies from (-1 zero rows, -2 uncovered); computed at plan creation
+  bool st_ok = false;
+  std::string st_reason;
+  std::vector<int64_t> st_info;
   const int64_t* d_st_info = nullptr;
   void* d_st_dev = nullptr;
   int64_t st_n[3] = {0, 0, 0};
@@ -233,6 +236,7 @@ void compile_plan(const Program& prog, const Layout& lay, int dtype, Plan& plan)
 void build_tiles(Plan& plan, const hbc_tune& t);
 hbc_tune default_tune(const Plan& plan);
 void build_csc(Plan& plan);
+void compute_stencil_info(Plan& plan);
 // host evaluation of a compiled row
 int plan_row(const Plan& plan, int64_t cell, int64_t l, int cap, int64_t* cols, double* vals, int32_t* nnz,
              double* b, int32_t* kind, int32_t* rot);

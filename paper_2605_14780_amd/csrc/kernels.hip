@@ -531,13 +531,14 @@ __device__ __forceinline__ int dir_index(int dz, int dy, int dx) { return (dz + 
 // Value of local position (z, y, x) of block b (one-cell halo) read through
 // the BC: data cells directly, ghosts from the source block or zero.
 template <typename T>
-__device__ __forceinline__ T bc_load(const T* __restrict__ x, const StDesc& st, int b, int z, int y, int xx) {
+__device__ __forceinline__ T bc_load(const T* __restrict__ x, const StDesc& st, const int64_t* info, int b, int z,
+                                     int y, int xx) {
   const int dz = z < 0 ? -1 : (z >= st.nz ? 1 : 0);
   const int dy = y < 0 ? -1 : (y >= st.ny ? 1 : 0);
   const int dx = xx < 0 ? -1 : (xx >= st.nx ? 1 : 0);
   int64_t blk = b;
   if (dz | dy | dx) {
-    blk = st.info[b * 27 + dir_index(dz, dy, dx)];
+    blk = info[dir_index(dz, dy, dx)];
     if (blk == -1) return T(0);
     if (blk == -2) {
       blk = b;
@@ -550,73 +551,157 @@ __device__ __forceinline__ T bc_load(const T* __restrict__ x, const StDesc& st, 
   return x[blk * st.bcells + (int64_t)(z + 1) * st.sz + (int64_t)(y + 1) * st.sy + (xx + 1)];
 }
 
-// One thread per (x, y) column of a 64 x 4 tile, marching over ZC planes.
-// y = 27 x_c - (box sum over 3x3x3) = 26 x_c - sum of the 26 neighbours.
+// 27-point operator, LDS-tiled.  A workgroup owns a 64 (x) x 8 (y) column of
+// outputs over ZC planes and marches in z: each (x, y) plane of the tile plus
+// its one-cell halo (66 x (TY + 2) values) is staged in LDS (double buffered: the
+// next plane's global loads are in flight while the current plane is summed),
+// the 3x3 plane sums are formed separably (3 along x, then 3 along y), and
+// y = 27 x_c - (S(z-1) + S(z) + S(z+1)) = 26 x_c - (sum of the 26 neighbours).
+// FUSED: values outside a block's data box are read through the BC (the
+// source block for halo copies, zero for padding).
+#ifndef HBC_ST_TY
+#define HBC_ST_TY 8
+#endif
+#ifndef HBC_ST_ZC
+#define HBC_ST_ZC 32
+#endif
+constexpr int ST_TX = 64, ST_TY = HBC_ST_TY, ST_ZC = HBC_ST_ZC;
+constexpr int ST_RPT = ST_TY / 4;  // output rows per thread (4 wavefronts of 64 columns)
+constexpr int ST_LX = ST_TX + 2, ST_LY = ST_TY + 2, ST_PLANE = ST_LX * ST_LY;
+static_assert(ST_TY % 4 == 0, "tile rows must split over 4 wavefronts");
+
+// Value of local position (z, y, xx) of block b for the consumer (x holds the
+// ghosted blocks).  FUSED: ghost positions come through the BC.
 template <typename T, bool FUSED>
-__global__ __launch_bounds__(256) void k_stencil27(const T* __restrict__ x, T* __restrict__ yout, T* __restrict__ xg,
-                                                   StDesc st, int zc) {
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  const int ntx = (st.nx + 63) / 64, nty = (st.ny + 3) / 4;
-  int bid = blockIdx.x;
+__device__ __forceinline__ T st_value(const T* __restrict__ x, const StDesc& st, const int64_t* info, int b, int z,
+                                      int y, int xx) {
+  const int64_t off = b * st.bcells + (int64_t)(z + 1) * st.sz + (int64_t)(y + 1) * st.sy + (xx + 1);
+  if (!FUSED) return x[off];
+  const bool ghost = z < 0 || z >= st.nz || y < 0 || y >= st.ny || xx < 0 || xx >= st.nx;
+  if (!ghost) return x[off];
+  return bc_load<T>(x, st, info, b, z, y, xx);
+}
+
+// Loads of one (x, y) plane of the tile with its halo: the 64 interior columns
+// of the TY + 2 rows (one row per wavefront access, so the ghost test is
+// uniform per wavefront) and the two halo columns (2 (TY + 2) values).
+constexpr int ST_NLOAD = (ST_LY * ST_TX + 255) / 256;
+
+template <typename T, bool FUSED>
+__device__ __forceinline__ void st_fetch(const T* __restrict__ x, const StDesc& st, const int64_t* info, int b, int z,
+                                         int y0, int x0, T (&r)[ST_NLOAD], T& rh) {
+#pragma unroll
+  for (int k = 0; k < ST_NLOAD; ++k) {
+    const int e = threadIdx.x + k * 256;
+    const int ly = e >> 6, xx = x0 + (e & 63);
+    const int y = y0 + ly - 1;
+    T v = T(0);
+    // xx == nx is the right halo of a partial tile
+    if (e < ST_LY * ST_TX && y <= st.ny && xx <= st.nx)
+      v = st_value<T, FUSED>(x, st, info, b, z, y, xx);
+    r[k] = v;
+  }
+  rh = T(0);
+  if (threadIdx.x < 2 * ST_LY) {
+    const int ly = threadIdx.x >> 1, side = threadIdx.x & 1;
+    const int y = y0 + ly - 1, xx = side ? x0 + ST_TX : x0 - 1;
+    if (y <= st.ny && xx <= st.nx) rh = st_value<T, FUSED>(x, st, info, b, z, y, xx);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void st_store(T* plane, const T (&r)[ST_NLOAD], T rh) {
+#pragma unroll
+  for (int k = 0; k < ST_NLOAD; ++k) {
+    const int e = threadIdx.x + k * 256;
+    if (e < ST_LY * ST_TX) plane[(e >> 6) * ST_LX + (e & 63) + 1] = r[k];
+  }
+  if (threadIdx.x < 2 * ST_LY) {
+    const int ly = threadIdx.x >> 1, side = threadIdx.x & 1;
+    plane[ly * ST_LX + (side ? ST_LX - 1 : 0)] = rh;
+  }
+}
+
+// One launch, two kinds of workgroup.  The first nst workgroups are stencil
+// tiles; the bc_grid after them run the BC plan's row tiles (ghost
+// materialisation: they write only covered ghost cells, which the stencil
+// never reads, since it takes those values through the BC from the source
+// data cells).  bc_grid = 0 leaves x untouched.  Workgroups are dealt to the
+// 8 XCDs round-robin; stencil tiles are renumbered so that each XCD gets a
+// contiguous run of them (neighbouring tiles share halo rows in its L2).
+template <typename T, bool FUSED, int V>
+__global__ __launch_bounds__(256) void k_stencil27(const T* __restrict__ x, T* __restrict__ yout, StDesc st,
+                                                   PlanDesc d, const RowTile* __restrict__ bc_tiles, int bc_nt,
+                                                   int bc_grid) {
+  __shared__ T buf[2][ST_PLANE];
+  __shared__ int64_t info[27];  // this block's direction table, read once
+  const int ntx = (st.nx + ST_TX - 1) / ST_TX, nty = (st.ny + ST_TY - 1) / ST_TY, nzc = (st.nz + ST_ZC - 1) / ST_ZC;
+  const int nst = ntx * nty * nzc * st.nblk;
+  if ((int)blockIdx.x >= nst) {
+    for (int t = blockIdx.x - nst; t < bc_nt; t += bc_grid) rt_tile<T, V>(d, bc_tiles[t], false);
+    return;
+  }
+  int bid;
+  {
+    const int q = nst >> 3, rem = nst & 7, xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
+    bid = xcd * q + min(xcd, rem) + j;
+  }
   const int tile_x = bid % ntx;
   bid /= ntx;
   const int tile_y = bid % nty;
   bid /= nty;
-  const int nzc = (st.nz + zc - 1) / zc;
   const int tile_z = bid % nzc;
   const int b = bid / nzc;
-  const int xx = tile_x * 64 + tx, yy = tile_y * 4 + ty;
-  if (xx >= st.nx || yy >= st.ny || b >= st.nblk) return;
-  const int z0 = tile_z * zc, z1 = min(z0 + zc, st.nz);
-  auto plane = [&](int z, T& center) -> T {
-    T s = T(0);
-#pragma unroll
-    for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-      for (int dx = -1; dx <= 1; ++dx) {
-        T v;
-        if (FUSED)
-          v = bc_load<T>(x, st, b, z, yy + dy, xx + dx);
-        else
-          v = x[b * st.bcells + (int64_t)(z + 1) * st.sz + (int64_t)(yy + dy + 1) * st.sy + (xx + dx + 1)];
-        if (dy == 0 && dx == 0) center = v;
-        s += v;
-      }
-    return s;
-  };
-  T c_prev, c_cur, c_next;
-  T s_prev = plane(z0 - 1, c_prev);
-  T s_cur = plane(z0, c_cur);
-  const int64_t yb = (int64_t)b * st.nz * st.ny * st.nx + (int64_t)yy * st.nx + xx;
-  for (int z = z0; z < z1; ++z) {
-    T s_next = plane(z + 1, c_next);
-    const T box = (s_prev + s_cur) + s_next;
-    yout[yb + (int64_t)z * st.ny * st.nx] = T(27) * c_cur - box;
-    s_prev = s_cur;
-    s_cur = s_next;
-    c_cur = c_next;
-  }
+  if (b >= st.nblk) return;  // uniform per workgroup
+  const int x0 = tile_x * ST_TX, y0 = tile_y * ST_TY, z0 = tile_z * ST_ZC, z1 = min(z0 + ST_ZC, st.nz);
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // each thread: column tx, rows RPT*ty ..
   if (FUSED) {
-    // materialise the ghosts whose nearest data cell is in this column
-    const bool ex = xx == 0 || xx == st.nx - 1, ey = yy == 0 || yy == st.ny - 1;
-    for (int z = z0; z < z1; ++z) {
-      const bool ez = z == 0 || z == st.nz - 1;
-      if (!(ex || ey || ez)) continue;
-      for (int dz = -1; dz <= 1; ++dz)
-        for (int dy = -1; dy <= 1; ++dy)
-          for (int dx = -1; dx <= 1; ++dx) {
-            if (!(dz | dy | dx)) continue;
-            const int gz = z + dz, gy = yy + dy, gx = xx + dx;
-            // a ghost: outside in every dimension where it moves
-            if (dz && gz >= 0 && gz < st.nz) continue;
-            if (dy && gy >= 0 && gy < st.ny) continue;
-            if (dx && gx >= 0 && gx < st.nx) continue;
-            const int64_t src = st.info[b * 27 + dir_index(dz, dy, dx)];
-            if (src == -2) continue;  // uncovered ghost: left as it is
-            const T v = bc_load<T>(x, st, b, gz, gy, gx);
-            xg[b * st.bcells + (int64_t)(gz + 1) * st.sz + (int64_t)(gy + 1) * st.sy + (gx + 1)] = v;
-          }
+    if (threadIdx.x < 27) info[threadIdx.x] = st.info[b * 27 + threadIdx.x];
+    __syncthreads();
+  }
+  T r[ST_NLOAD], rh;
+  st_fetch<T, FUSED>(x, st, info, b, z0 - 1, y0, x0, r, rh);
+  st_store<T>(buf[0], r, rh);
+  __syncthreads();
+  T sm2[ST_RPT], sm1[ST_RPT], cm1[ST_RPT];
+#pragma unroll
+  for (int q = 0; q < ST_RPT; ++q) sm2[q] = sm1[q] = cm1[q] = T(0);
+  const int64_t plane_out = (int64_t)st.ny * st.nx;
+  const int64_t yb = (int64_t)b * st.nz * plane_out;
+  for (int p = z0 - 1; p <= z1; ++p) {
+    const int cur = (p - z0 + 1) & 1;
+    if (p + 1 <= z1) st_fetch<T, FUSED>(x, st, info, b, p + 1, y0, x0, r, rh);
+    // separable 3x3 sums of plane p for this thread's rows (LDS rows
+    // RPT*ty .. RPT*ty + RPT + 1)
+    T hsum[ST_RPT + 2];
+#pragma unroll
+    for (int q = 0; q < ST_RPT + 2; ++q) {
+      const T* row = &buf[cur][(ST_RPT * ty + q) * ST_LX + tx];
+      hsum[q] = (row[0] + row[1]) + row[2];
     }
+    T sn[ST_RPT], cn[ST_RPT];
+#pragma unroll
+    for (int q = 0; q < ST_RPT; ++q) {
+      sn[q] = (hsum[q] + hsum[q + 1]) + hsum[q + 2];
+      cn[q] = buf[cur][(ST_RPT * ty + q + 1) * ST_LX + tx + 1];
+    }
+    if (p >= z0 + 1) {
+      const int zo = p - 1;
+#pragma unroll
+      for (int q = 0; q < ST_RPT; ++q) {
+        const int yy = y0 + ST_RPT * ty + q, xx = x0 + tx;
+        if (yy < st.ny && xx < st.nx)
+          yout[yb + (int64_t)zo * plane_out + (int64_t)yy * st.nx + xx] = T(27) * cm1[q] - ((sm2[q] + sm1[q]) + sn[q]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < ST_RPT; ++q) {
+      sm2[q] = sm1[q];
+      sm1[q] = sn[q];
+      cm1[q] = cn[q];
+    }
+    if (p + 1 <= z1) st_store<T>(buf[cur ^ 1], r, rh);
+    __syncthreads();
   }
 }
 
@@ -754,6 +839,13 @@ void device_upload_plan(Plan& p) {
   p.d_row_dst = reinterpret_cast<const int32_t*>(b + o_rd);
   p.d_row_src = reinterpret_cast<const int32_t*>(b + o_rs);
   device_upload_tiles(p);
+  if (p.st_ok) {
+    void* si = nullptr;
+    HIP_CHECK(hipMalloc(&si, p.st_info.size() * sizeof(int64_t)));
+    p.d_st_dev = si;
+    HIP_CHECK(hipMemcpy(si, p.st_info.data(), p.st_info.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    p.d_st_info = static_cast<const int64_t*>(si);
+  }
 }
 
 void device_upload_tiles(Plan& p) {
@@ -854,89 +946,8 @@ void device_adjoint(const Plan& p, void* grad, void* stream) {
     launch_adjoint_t<float>(p, d, S(stream));
 }
 
-// Direction table of the 27-point consumer: for every block and each of its 26
-// ghost regions, the block the BC copies from (translation by one block), -1
-// for zero rows or -2 for uncovered ghosts; anything else cannot be fused.
-static void build_stencil_info(Plan& p) {
-  const Grid& g = p.grid;
-  if (g.nd != 4) fail(HBC_EUNSUPPORTED, "the 27-point consumer needs a Cartesian block grid (block, z, y, x)");
-  if (p.layout.inner != 1) fail(HBC_EUNSUPPORTED, "the 27-point consumer needs inner == 1");
-  const Block& B0 = g.blocks[0];
-  int64_t n[3];
-  for (int d = 0; d < 3; ++d) n[d] = B0.data.extent(d + 1);
-  for (const Block& B : g.blocks) {
-    if (B.full.extent(0) != 1) fail(HBC_EUNSUPPORTED, "blocks must have extent 1 along coordinate 0");
-    for (int d = 0; d < 3; ++d)
-      if (B.data.extent(d + 1) != n[d] || B.data.lo[d + 1] - B.full.lo[d + 1] != 1 ||
-          B.full.hi[d + 1] - B.data.hi[d + 1] != 1)
-        fail(HBC_EUNSUPPORTED, "the 27-point consumer needs equal blocks with a one-cell halo");
-  }
-  const int nb = (int)g.blocks.size();
-  std::vector<int64_t> info((size_t)nb * 27, 0);
-  int64_t cols[64];
-  double vals[64];
-  for (int b = 0; b < nb; ++b) {
-    const Block& B = g.blocks[b];
-    for (int dz = -1; dz <= 1; ++dz)
-      for (int dy = -1; dy <= 1; ++dy)
-        for (int dx = -1; dx <= 1; ++dx) {
-          const int di = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
-          if (!(dz | dy | dx)) {
-            info[(size_t)b * 27 + di] = b;
-            continue;
-          }
-          const int dd[3] = {dz, dy, dx};
-          int64_t lo[3], hi[3];
-          for (int d = 0; d < 3; ++d) {
-            lo[d] = dd[d] < 0 ? -1 : dd[d] == 0 ? 0 : n[d];
-            hi[d] = dd[d] < 0 ? 0 : dd[d] == 0 ? n[d] : n[d] + 1;
-          }
-          int64_t verdict = -3;  // undecided
-          for (int64_t z = lo[0]; z < hi[0]; ++z)
-            for (int64_t y = lo[1]; y < hi[1]; ++y)
-              for (int64_t x = lo[2]; x < hi[2]; ++x) {
-                int64_t c[4] = {B.full.lo[0], z, y, x};
-                const int64_t cell = g.cell(b, c);
-                int32_t nnz, kind, rot;
-                double bb;
-                plan_row(p, cell, 0, 64, cols, vals, &nnz, &bb, &kind, &rot);
-                int64_t v;
-                if (kind < 0) {
-                  v = -2;
-                } else if (kind == SEG_ZERO && bb == 0.0) {
-                  v = -1;
-                } else if (kind == SEG_MAP && nnz == 1 && vals[0] == 1.0 && rot == 0 && bb == 0.0) {
-                  // must be the translated cell (z - dz*nz, ...) of some block
-                  int64_t srcb = -1;
-                  for (int ob = 0; ob < nb; ++ob) {
-                    int64_t oc[4] = {g.blocks[ob].full.lo[0], z - dz * n[0], y - dy * n[1], x - dx * n[2]};
-                    if (g.blocks[ob].data.contains(oc) && g.cell(ob, oc) == cols[0]) srcb = ob;
-                  }
-                  if (srcb < 0) fail(HBC_EUNSUPPORTED, "a halo copy is not a translation by one block");
-                  v = srcb;
-                } else {
-                  fail(HBC_EUNSUPPORTED, "the fused consumer supports copy and zero rows only");
-                }
-                if (verdict == -3)
-                  verdict = v;
-                else if (verdict != v)
-                  fail(HBC_EUNSUPPORTED, "one ghost region mixes BC kinds or source blocks");
-              }
-          info[(size_t)b * 27 + di] = verdict;
-        }
-  }
-  p.st_info = info;
-  for (int d = 0; d < 3; ++d) p.st_n[d] = n[d];
-  p.st_nblocks = nb;
-  void* dev = nullptr;
-  HIP_CHECK(hipMalloc(&dev, info.size() * sizeof(int64_t)));
-  HIP_CHECK(hipMemcpy(dev, info.data(), info.size() * sizeof(int64_t), hipMemcpyHostToDevice));
-  p.d_st_dev = dev;
-  p.d_st_info = static_cast<const int64_t*>(dev);
-}
-
 void device_stencil27(Plan& p, const void* x, void* y, void* stream, bool fused, void* xghost) {
-  if (!p.d_st_info) build_stencil_info(p);
+  if (!p.st_ok || !p.d_st_info) fail(HBC_EUNSUPPORTED, p.st_reason.empty() ? "plan not usable by the 27-point consumer" : p.st_reason);
   StDesc st;
   st.nblk = p.st_nblocks;
   st.nz = (int32_t)p.st_n[0];
@@ -946,25 +957,36 @@ void device_stencil27(Plan& p, const void* x, void* y, void* stream, bool fused,
   st.sz = (int64_t)(st.ny + 2) * st.sy;
   st.bcells = (int64_t)(st.nz + 2) * st.sz;
   st.info = p.d_st_info;
-  const int zc = 16;
-  const int ntx = (st.nx + 63) / 64, nty = (st.ny + 3) / 4, nzc = (st.nz + zc - 1) / zc;
+  const int ntx = (st.nx + ST_TX - 1) / ST_TX, nty = (st.ny + ST_TY - 1) / ST_TY, nzc = (st.nz + ST_ZC - 1) / ST_ZC;
   const int64_t grid = (int64_t)ntx * nty * nzc * st.nblk;
   if (grid >= (int64_t(1) << 31)) fail(HBC_EUNSUPPORTED, "grid too large for the 27-point consumer");
   hipStream_t s = S(stream);
+  // ghost materialisation rides in the same launch as extra workgroups
+  const int bc_nt = xghost ? (int)p.host.rtiles.size() : 0;
+  const int bc_grid = bc_nt == 0 ? 0 : (p.tune.persistent > 0 ? std::min(p.tune.persistent, bc_nt) : bc_nt);
+  if ((int64_t)grid + bc_grid >= (int64_t(1) << 31)) fail(HBC_EUNSUPPORTED, "grid too large for the 27-point consumer");
+  const PlanDesc d = make_desc(p, xghost);
+  const dim3 g((unsigned)(grid + bc_grid)), blk(256);
   if (p.dtype == HBC_F64) {
-    if (fused)
-      hipLaunchKernelGGL((k_stencil27<double, true>), dim3((unsigned)grid), dim3(256), 0, s,
-                         static_cast<const double*>(x), static_cast<double*>(y), static_cast<double*>(xghost), st, zc);
+    const double* xd = static_cast<const double*>(x);
+    double* yd = static_cast<double*>(y);
+    if (!fused)
+      hipLaunchKernelGGL((k_stencil27<double, false, 1>), g, blk, 0, s, xd, yd, st, d, p.d_rtiles, 0, 0);
+    else if (p.vec >= 2)
+      hipLaunchKernelGGL((k_stencil27<double, true, 2>), g, blk, 0, s, xd, yd, st, d, p.d_rtiles, bc_nt, bc_grid);
     else
-      hipLaunchKernelGGL((k_stencil27<double, false>), dim3((unsigned)grid), dim3(256), 0, s,
-                         static_cast<const double*>(x), static_cast<double*>(y), nullptr, st, zc);
+      hipLaunchKernelGGL((k_stencil27<double, true, 1>), g, blk, 0, s, xd, yd, st, d, p.d_rtiles, bc_nt, bc_grid);
   } else {
-    if (fused)
-      hipLaunchKernelGGL((k_stencil27<float, true>), dim3((unsigned)grid), dim3(256), 0, s,
-                         static_cast<const float*>(x), static_cast<float*>(y), static_cast<float*>(xghost), st, zc);
+    const float* xf = static_cast<const float*>(x);
+    float* yf = static_cast<float*>(y);
+    if (!fused)
+      hipLaunchKernelGGL((k_stencil27<float, false, 1>), g, blk, 0, s, xf, yf, st, d, p.d_rtiles, 0, 0);
+    else if (p.vec == 4)
+      hipLaunchKernelGGL((k_stencil27<float, true, 4>), g, blk, 0, s, xf, yf, st, d, p.d_rtiles, bc_nt, bc_grid);
+    else if (p.vec == 2)
+      hipLaunchKernelGGL((k_stencil27<float, true, 2>), g, blk, 0, s, xf, yf, st, d, p.d_rtiles, bc_nt, bc_grid);
     else
-      hipLaunchKernelGGL((k_stencil27<float, false>), dim3((unsigned)grid), dim3(256), 0, s,
-                         static_cast<const float*>(x), static_cast<float*>(y), nullptr, st, zc);
+      hipLaunchKernelGGL((k_stencil27<float, true, 1>), g, blk, 0, s, xf, yf, st, d, p.d_rtiles, bc_nt, bc_grid);
   }
   HIP_CHECK(hipGetLastError());
 }

@@ -549,6 +549,7 @@ void compile_plan(const Program& prog, const Layout& lay, int dtype, Plan& plan)
   }
   plan.tune = default_tune(plan);
   build_tiles(plan, plan.tune);
+  compute_stencil_info(plan);
 }
 
 static int64_t pow2_ceil(int64_t v) {
@@ -700,6 +701,91 @@ void build_csc(Plan& plan) {
   per = std::min<int64_t>(per, 16384);
   for (int64_t s = 0; s < ns; s += per)
     plan.host.adj_tiles.push_back(AdjTile{(int32_t)s, (int32_t)std::min<int64_t>(per, ns - s)});
+}
+
+// ---- 27-point consumer: which block each one-cell ghost region copies from ------------------
+// Plays the role of the dependence analysis of Sec. IV-C for this consumer:
+// every ghost the stencil reads is traced to the BC row that writes it, and
+// the fused kernel is allowed only when each of a block's 26 ghost regions is
+// one translated copy of a neighbouring block (or zero, or left uncovered).
+void compute_stencil_info(Plan& p) {
+  p.st_ok = false;
+  const Grid& g = p.grid;
+  auto no = [&](const char* why) { p.st_reason = why; };
+  if (g.nd != 4) return no("the 27-point consumer needs a Cartesian block grid (block, z, y, x)");
+  if (p.layout.inner != 1) return no("the 27-point consumer needs inner == 1");
+  const Block& B0 = g.blocks[0];
+  int64_t n[3];
+  for (int d = 0; d < 3; ++d) n[d] = B0.data.extent(d + 1);
+  for (const Block& B : g.blocks) {
+    if (B.full.extent(0) != 1) return no("blocks must have extent 1 along coordinate 0");
+    for (int d = 0; d < 3; ++d)
+      if (B.data.extent(d + 1) != n[d] || B.data.lo[d + 1] - B.full.lo[d + 1] != 1 ||
+          B.full.hi[d + 1] - B.data.hi[d + 1] != 1)
+        return no("the 27-point consumer needs equal blocks with a one-cell halo");
+  }
+  const int nb = (int)g.blocks.size();
+  std::vector<int64_t> info((size_t)nb * 27, -3);
+  for (int b = 0; b < nb; ++b) info[(size_t)b * 27 + 13] = b;
+  std::vector<int64_t> firsts(nb);
+  for (int b = 0; b < nb; ++b) firsts[b] = g.blocks[b].first_cell;
+  const HostTables& T = p.host;
+  bool ok = true;
+  for (size_t si = 0; si < T.segs.size() && ok; ++si) {
+    const DevSeg& sg = T.segs[si];
+    const Box& bx = T.seg_box[si];
+    const int b = g.owner(bx.lo);
+    const Block& B = g.blocks[b];
+    for_box_order(bx, T.seg_order[si], [&](const int64_t* c, int64_t r) {
+      if (!ok) return;
+      int64_t pl[3];
+      int dd[3];
+      for (int d = 0; d < 3; ++d) {
+        pl[d] = c[d + 1] - B.data.lo[d + 1];
+        dd[d] = pl[d] < 0 ? -1 : (pl[d] >= n[d] ? 1 : 0);
+      }
+      const int di = (dd[0] + 1) * 9 + (dd[1] + 1) * 3 + (dd[2] + 1);
+      int64_t v;
+      if (sg.kind == SEG_ZERO && !sg.has_b) {
+        v = -1;
+      } else if (sg.kind == SEG_MAP && sg.w == 1.0 && sg.rot == 0 && !sg.has_b) {
+        const int64_t src = T.row_src[sg.row_base + r];
+        const int ob = (int)(std::upper_bound(firsts.begin(), firsts.end(), src) - firsts.begin()) - 1;
+        const Block& O = g.blocks[ob];
+        int64_t off = src - O.first_cell;
+        bool match = true;
+        for (int d = 0; d < 4; ++d) {
+          const int64_t cd = O.full.lo[d] + off / O.stride[d];
+          off %= O.stride[d];
+          if (d > 0 && cd - O.data.lo[d] != pl[d - 1] - dd[d - 1] * n[d - 1]) match = false;
+        }
+        if (!match) {
+          ok = false;
+          no("a halo copy is not a translation by one block");
+          return;
+        }
+        v = ob;
+      } else {
+        ok = false;
+        no("the fused consumer supports copy and zero rows only");
+        return;
+      }
+      int64_t& slot = info[(size_t)b * 27 + di];
+      if (slot == -3) {
+        slot = v;
+      } else if (slot != v) {
+        ok = false;
+        no("one ghost region mixes BC kinds or source blocks");
+      }
+    });
+  }
+  if (!ok) return;
+  for (int64_t& v : info)
+    if (v == -3) v = -2;
+  p.st_info.swap(info);
+  for (int d = 0; d < 3; ++d) p.st_n[d] = n[d];
+  p.st_nblocks = nb;
+  p.st_ok = true;
 }
 
 // ---- host evaluation of compiled rows (tests without a GPU) --------------------------------

@@ -151,6 +151,13 @@ def test_hpcg_bc_and_stencil(nb, n):
     xf = xt.cpu().numpy()
     want = np.concatenate([b.reshape(-1) for b in blocks])
     assert np.array_equal(xf, want), "fused ghosts differ from the oracle's halo"
+    # read-only fused: same y, x (ghosts NaN) left untouched
+    xt_ro = torch.from_numpy(full.copy()).cuda()
+    y_ro = torch.empty_like(y_f)
+    hb.fused_stencil27(plan, xt_ro, y_ro, write_ghosts=False)
+    torch.cuda.synchronize()
+    assert torch.equal(y_ro, y_f)
+    assert np.array_equal(xt_ro.cpu().numpy(), full, equal_nan=True)
     # unfused: BC apply then stencil on a fresh copy
     xt2 = torch.from_numpy(full.copy()).cuda()
     hb.apply(plan, xt2)
