@@ -48,7 +48,7 @@ struct PlanDesc {
   int32_t lpr_shift;  // log2 lanes per row
   int32_t vec;        // elements per lane access
   int32_t chunked;    // point-major: each row group walks a contiguous run of rows
-  int32_t pad_;
+  int32_t nt;         // results go out with non-temporal stores (rows of >= 128 bytes)
   const int32_t* row_dst;  // point-major row tables
   const int32_t* row_src;
 };
@@ -80,16 +80,26 @@ __device__ __forceinline__ Pack<T, V> ldv(const T* p) {
   return r;
 }
 
-template <typename T, int V>
+// Results that no later access in the same kernel reads may go out as
+// non-temporal stores (streamed past the caches rather than allocated in
+// them).  That pays for whole rows of 128 bytes or more; for short scattered
+// rows the caches merge partial lines and plain stores are faster.
+template <typename T, int V, bool NT>
 __device__ __forceinline__ void stv(T* p, const Pack<T, V>& r) {
   if constexpr (V == 1) {
-    *p = r.v[0];
+    if (NT)
+      __builtin_nontemporal_store(r.v[0], p);
+    else
+      *p = r.v[0];
   } else {
     typedef T vt __attribute__((ext_vector_type(V)));
     vt x;
 #pragma unroll
     for (int i = 0; i < V; ++i) x[i] = r.v[i];
-    *reinterpret_cast<vt*>(p) = x;
+    if (NT)
+      __builtin_nontemporal_store(x, reinterpret_cast<vt*>(p));
+    else
+      *reinterpret_cast<vt*>(p) = x;
   }
 }
 
@@ -213,7 +223,7 @@ __device__ __forceinline__ void run_tile(const PlanDesc& d, const DevSeg& s, int
 #pragma unroll
         for (int i = 0; i < V; ++i) f[dst * d.cs + (l + i) * d.ls] = y.v[i];
       } else {
-        stv<T, V>(f + dst * d.cs + l * d.ls, y);
+        stv<T, V, false>(f + dst * d.cs + l * d.ls, y);
       }
     }
   }
@@ -233,7 +243,7 @@ __device__ __forceinline__ void run_tile(const PlanDesc& d, const DevSeg& s, int
 #endif
 constexpr int RB = HBC_ROWS_PER_BATCH;  // rows per batch of a row group
 
-template <typename T, int V>
+template <typename T, int V, bool NT>
 __device__ __forceinline__ void rt_tile(const PlanDesc& d, const RowTile& tl, bool zero_only) {
   const int lpr = 1 << d.lpr_shift;
   const int ngroups = (int)blockDim.x >> d.lpr_shift;
@@ -388,17 +398,17 @@ __device__ __forceinline__ void rt_tile(const PlanDesc& d, const RowTile& tl, bo
       }
 #pragma unroll
       for (int q = 0; q < RB; ++q)
-        if (r + q * rs < re) stv<T, V>(f + dst[q] * d.cs + l, y[q]);
+        if (r + q * rs < re) stv<T, V, NT>(f + dst[q] * d.cs + l, y[q]);
     }
   }
 }
 
-template <typename T, int V>
+template <typename T, int V, bool NT>
 __global__ __launch_bounds__(256) void k_apply_rows(PlanDesc d, const RowTile* __restrict__ tiles, int ntiles,
                                                     int zero_only) {
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const RowTile tl = tiles[t];
-    rt_tile<T, V>(d, tl, zero_only != 0);
+    rt_tile<T, V, NT>(d, tl, zero_only != 0);
   }
 }
 
@@ -418,12 +428,21 @@ __global__ __launch_bounds__(256) void k_batch(const PlanDesc* __restrict__ desc
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const RowTile tl = tiles[t];
     const PlanDesc d = descs[tl.pad_];
-    if (sizeof(T) == 4 && d.vec == 4)
-      rt_tile<T, (sizeof(T) == 4 ? 4 : 2)>(d, tl, false);
-    else if (d.vec == 2)
-      rt_tile<T, 2>(d, tl, false);
-    else
-      rt_tile<T, 1>(d, tl, false);
+    if (d.nt) {
+      if (sizeof(T) == 4 && d.vec == 4)
+        rt_tile<T, (sizeof(T) == 4 ? 4 : 2), true>(d, tl, false);
+      else if (d.vec == 2)
+        rt_tile<T, 2, true>(d, tl, false);
+      else
+        rt_tile<T, 1, true>(d, tl, false);
+    } else {
+      if (sizeof(T) == 4 && d.vec == 4)
+        rt_tile<T, (sizeof(T) == 4 ? 4 : 2), false>(d, tl, false);
+      else if (d.vec == 2)
+        rt_tile<T, 2, false>(d, tl, false);
+      else
+        rt_tile<T, 1, false>(d, tl, false);
+    }
   }
 }
 
@@ -434,7 +453,7 @@ __global__ __launch_bounds__(256) void k_batch(const PlanDesc* __restrict__ desc
 // weights first, then all ybar loads of the chunk, then the ordered sum.
 constexpr int EB = 8;
 
-template <typename T, int V, bool ROWFAST>
+template <typename T, int V, bool ROWFAST, bool NT>
 __global__ __launch_bounds__(256) void k_adjoint(PlanDesc d, AdjDesc a, const AdjTile* __restrict__ tiles,
                                                   int ntiles) {
   const int lpr = 1 << d.lpr_shift;
@@ -511,7 +530,7 @@ __global__ __launch_bounds__(256) void k_adjoint(PlanDesc d, AdjDesc a, const Ad
 #pragma unroll
           for (int i = 0; i < V; ++i) px[i * d.ls] = x.v[i];
         } else {
-          stv<T, V>(px, x);
+          stv<T, V, NT>(px, x);
         }
       }
     }
@@ -638,7 +657,7 @@ __global__ __launch_bounds__(256) void k_stencil27(const T* __restrict__ x, T* _
   const int ntx = (st.nx + ST_TX - 1) / ST_TX, nty = (st.ny + ST_TY - 1) / ST_TY, nzc = (st.nz + ST_ZC - 1) / ST_ZC;
   const int nst = ntx * nty * nzc * st.nblk;
   if ((int)blockIdx.x >= nst) {
-    for (int t = blockIdx.x - nst; t < bc_nt; t += bc_grid) rt_tile<T, V>(d, bc_tiles[t], false);
+    for (int t = blockIdx.x - nst; t < bc_nt; t += bc_grid) rt_tile<T, V, false>(d, bc_tiles[t], false);
     return;
   }
   int bid;
@@ -691,7 +710,8 @@ __global__ __launch_bounds__(256) void k_stencil27(const T* __restrict__ x, T* _
       for (int q = 0; q < ST_RPT; ++q) {
         const int yy = y0 + ST_RPT * ty + q, xx = x0 + tx;
         if (yy < st.ny && xx < st.nx)
-          yout[yb + (int64_t)zo * plane_out + (int64_t)yy * st.nx + xx] = T(27) * cm1[q] - ((sm2[q] + sm1[q]) + sn[q]);
+          __builtin_nontemporal_store(T(27) * cm1[q] - ((sm2[q] + sm1[q]) + sn[q]),
+                                      &yout[yb + (int64_t)zo * plane_out + (int64_t)yy * st.nx + xx]);
       }
     }
 #pragma unroll
@@ -787,6 +807,7 @@ PlanDesc make_desc(const Plan& p, void* field) {
   d.lpr_shift = ilog2(p.tune.lanes_per_row);
   d.vec = p.vec;
   d.chunked = p.tune.lanes_per_row >= 16 ? 1 : 0;
+  d.nt = (p.layout.order == HBC_POINT_MAJOR && p.layout.inner * (p.dtype == HBC_F64 ? 8 : 4) >= 128) ? 1 : 0;
   return d;
 }
 
@@ -902,11 +923,20 @@ static void launch_apply_t(const Plan& p, const PlanDesc& d, hipStream_t st, boo
   if (p.layout.order == HBC_PLANE_MAJOR) {
     hipLaunchKernelGGL((k_apply<T, 1, true>), dim3(grid), dim3(blk), 0, st, d, p.d_tiles, nt, z);
   } else if (p.vec == 4) {
-    hipLaunchKernelGGL((k_apply_rows<T, (sizeof(T) == 4 ? 4 : 2)>), dim3(grid), dim3(blk), 0, st, d, p.d_rtiles, nt, z);
+    if (d.nt)
+      hipLaunchKernelGGL((k_apply_rows<T, (sizeof(T) == 4 ? 4 : 2), true>), dim3(grid), dim3(blk), 0, st, d, p.d_rtiles, nt, z);
+    else
+      hipLaunchKernelGGL((k_apply_rows<T, (sizeof(T) == 4 ? 4 : 2), false>), dim3(grid), dim3(blk), 0, st, d, p.d_rtiles, nt, z);
   } else if (p.vec == 2) {
-    hipLaunchKernelGGL((k_apply_rows<T, 2>), dim3(grid), dim3(blk), 0, st, d, p.d_rtiles, nt, z);
+    if (d.nt)
+      hipLaunchKernelGGL((k_apply_rows<T, 2, true>), dim3(grid), dim3(blk), 0, st, d, p.d_rtiles, nt, z);
+    else
+      hipLaunchKernelGGL((k_apply_rows<T, 2, false>), dim3(grid), dim3(blk), 0, st, d, p.d_rtiles, nt, z);
   } else {
-    hipLaunchKernelGGL((k_apply_rows<T, 1>), dim3(grid), dim3(blk), 0, st, d, p.d_rtiles, nt, z);
+    if (d.nt)
+      hipLaunchKernelGGL((k_apply_rows<T, 1, true>), dim3(grid), dim3(blk), 0, st, d, p.d_rtiles, nt, z);
+    else
+      hipLaunchKernelGGL((k_apply_rows<T, 1, false>), dim3(grid), dim3(blk), 0, st, d, p.d_rtiles, nt, z);
   }
   HIP_CHECK(hipGetLastError());
 }
@@ -926,13 +956,19 @@ static void launch_adjoint_t(const Plan& p, const PlanDesc& d, hipStream_t st) {
   if (nt > 0) {
     const int blk = p.tune.block;
     if (p.layout.order == HBC_PLANE_MAJOR)
-      hipLaunchKernelGGL((k_adjoint<T, 1, true>), dim3(nt), dim3(blk), 0, st, d, a, p.d_adj_tiles, nt);
+      hipLaunchKernelGGL((k_adjoint<T, 1, true, false>), dim3(nt), dim3(blk), 0, st, d, a, p.d_adj_tiles, nt);
+    else if (p.vec == 4 && d.nt)
+      hipLaunchKernelGGL((k_adjoint<T, 4, false, true>), dim3(nt), dim3(blk), 0, st, d, a, p.d_adj_tiles, nt);
     else if (p.vec == 4)
-      hipLaunchKernelGGL((k_adjoint<T, 4, false>), dim3(nt), dim3(blk), 0, st, d, a, p.d_adj_tiles, nt);
+      hipLaunchKernelGGL((k_adjoint<T, 4, false, false>), dim3(nt), dim3(blk), 0, st, d, a, p.d_adj_tiles, nt);
+    else if (p.vec == 2 && d.nt)
+      hipLaunchKernelGGL((k_adjoint<T, 2, false, true>), dim3(nt), dim3(blk), 0, st, d, a, p.d_adj_tiles, nt);
     else if (p.vec == 2)
-      hipLaunchKernelGGL((k_adjoint<T, 2, false>), dim3(nt), dim3(blk), 0, st, d, a, p.d_adj_tiles, nt);
+      hipLaunchKernelGGL((k_adjoint<T, 2, false, false>), dim3(nt), dim3(blk), 0, st, d, a, p.d_adj_tiles, nt);
+    else if (d.nt)
+      hipLaunchKernelGGL((k_adjoint<T, 1, false, true>), dim3(nt), dim3(blk), 0, st, d, a, p.d_adj_tiles, nt);
     else
-      hipLaunchKernelGGL((k_adjoint<T, 1, false>), dim3(nt), dim3(blk), 0, st, d, a, p.d_adj_tiles, nt);
+      hipLaunchKernelGGL((k_adjoint<T, 1, false, false>), dim3(nt), dim3(blk), 0, st, d, a, p.d_adj_tiles, nt);
     HIP_CHECK(hipGetLastError());
   }
   launch_apply_t<T>(p, d, st, true);  // covered ghost gradients := 0, after the gather
