@@ -158,6 +158,45 @@ struct CscHost {
   std::vector<int64_t> ghost;     // ghost cell of each entry
   std::vector<double> w;          // weight of each entry
   std::vector<int32_t> rot;       // inverse rotation code of each entry
+  // Fixed-width copy (width aw = largest entry count, at most ADJ_MAXW): the
+  // entries of source k at k*aw + m, m < cnt[k], so that a source's entries
+  // are addressed without reading ptr first.  Sources with cnt > aw use the
+  // CSR form above.
+  int32_t aw = 0;
+  std::vector<int32_t> cnt;
+  std::vector<int32_t> fghost;
+  std::vector<double> fw;
+  std::vector<int8_t> frot;
+};
+constexpr int ADJ_MAXW = 8;
+// Row groups of at least this many lanes (rows of >= 128 bytes) take
+// contiguous runs of rows (neighbouring rows share sources); narrower groups
+// take rows round-robin (neighbouring lanes write neighbouring cells).
+constexpr int CHUNK_LPR = 8;
+
+// LDS-staged adjoint (point-major plans).  A tile is a run of consecutive
+// sources; the distinct ghost rows its entries read (at most ADJ_LDS_ROWS,
+// and at most the LDS budget) are loaded once into LDS, and each entry holds
+// the LDS slot of its ghost.  A ghost row read by one tile only is zeroed by
+// that tile once loaded; one read by several tiles has a counter of reader
+// tiles, and the tile whose decrement empties it zeroes the row and restores
+// the counter for the next call.  Covered ghost rows no source reads are
+// zeroed by extra workgroups of the same launch.
+constexpr int ADJ_LDS_ROWS = 64;
+constexpr int ADJ_LDS_BYTES = 40 * 1024;
+constexpr int ADJ_ZERO_ROWS = 64;  // rows per zeroing workgroup
+struct AdjLdsTile {
+  int32_t first_src, nsrc, first_u, nu;
+};
+struct AdjLdsHost {
+  bool ok = false;
+  int32_t brows = 0;                // LDS rows per tile
+  std::vector<AdjLdsTile> tiles;
+  std::vector<int32_t> u_cell;      // distinct ghost rows of each tile
+  std::vector<int32_t> u_ctr;       // counter of a row several tiles read, else -1
+  std::vector<int32_t> ctr_init;    // reader tiles per counter
+  std::vector<uint16_t> slot;       // per source k, entry m < cnt[k]: LDS slot, at k*aw + m
+  std::vector<int32_t> zero_rows;   // covered ghost rows that no source reads
 };
 
 struct AdjTile {
@@ -178,6 +217,7 @@ struct HostTables {
   std::vector<std::vector<int>> seg_order;  // global dims of the segment rows, slowest first
   CscHost csc;
   std::vector<AdjTile> adj_tiles;
+  AdjLdsHost adj_lds;
   // point-major row tables (device order) and tiles
   std::vector<int32_t> row_dst;  // destination cell of every covered row
   std::vector<int32_t> row_src;  // MAP rows: source cell; other rows: 0
@@ -219,6 +259,18 @@ struct Plan {
   const int64_t* d_csc_ghost = nullptr;
   const void* d_csc_w = nullptr;
   const int32_t* d_csc_rot = nullptr;
+  const int32_t* d_adj_cnt = nullptr;
+  const int32_t* d_adj_fg = nullptr;
+  const void* d_adj_fw = nullptr;
+  const int8_t* d_adj_frot = nullptr;
+  void* d_al_dev = nullptr;  // allocation holding the LDS-staged adjoint tables
+  const AdjLdsTile* d_al_tiles = nullptr;
+  const int32_t* d_al_ucell = nullptr;
+  const int32_t* d_al_uctr = nullptr;
+  const int32_t* d_al_ctrinit = nullptr;
+  int32_t* d_al_ctr = nullptr;  // reader counters (restored by every adjoint call)
+  const uint16_t* d_al_slot = nullptr;
+  const int32_t* d_al_zero = nullptr;
   const AdjTile* d_adj_tiles = nullptr;
   // 27-point consumer: per block and neighbour direction, the block the BC
   // copies from (-1 zero rows, -2 uncovered); computed at plan creation

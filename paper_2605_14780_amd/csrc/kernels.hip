@@ -59,6 +59,11 @@ struct AdjDesc {
   const int64_t* ghost;
   const void* w;
   const int32_t* rot;
+  const int32_t* cnt;  // entries per source
+  const int32_t* fg;   // fixed-width entries: ghost cell, weight, rotation at k*aw + m
+  const void* fw;
+  const int8_t* frot;
+  int32_t aw;
 };
 
 template <typename T, int V>
@@ -235,9 +240,9 @@ __device__ __forceinline__ void run_tile(const PlanDesc& d, const DevSeg& s, int
 // of the batch are read first, then every source load of the batch is issued
 // before any arithmetic or store, so a lane keeps up to 4*RB independent
 // loads in flight; repeated sources of neighbouring rows hit in L1/L2.  With
-// rows of >= 16 lanes a row group takes a contiguous run of rows, otherwise
-// rows are dealt round-robin so that neighbouring lanes write neighbouring
-// cells.
+// groups of >= CHUNK_LPR lanes a row group takes a contiguous run of rows,
+// otherwise rows are dealt round-robin so that neighbouring lanes write
+// neighbouring cells.
 #ifndef HBC_ROWS_PER_BATCH
 #define HBC_ROWS_PER_BATCH 4
 #endif
@@ -449,8 +454,10 @@ __global__ __launch_bounds__(256) void k_batch(const PlanDesc* __restrict__ desc
 // Adjoint gather: for each source cell, in ascending ghost order,
 //   xbar[src, l] += sum_e w_e * sign_e * ybar[ghost_e, rot_e(l)]
 // One thread sums one value, so the result does not depend on scheduling.
-// The entries of a source are read in chunks of EB: their ghost cells and
-// weights first, then all ybar loads of the chunk, then the ordered sum.
+// A source's entries come from the fixed-width table (no pointer to chase:
+// the source index, its count and its entries are read together, then all
+// its ybar loads are issued, then the ordered sum); sources with more than aw
+// entries walk the CSR form in chunks of EB.
 constexpr int EB = 8;
 
 template <typename T, int V, bool ROWFAST, bool NT>
@@ -469,6 +476,8 @@ __global__ __launch_bounds__(256) void k_adjoint(PlanDesc d, AdjDesc a, const Ad
   const int64_t nvec = d.inner / V;
   T* __restrict__ f = static_cast<T*>(d.field);
   const T* __restrict__ W = static_cast<const T*>(a.w);
+  const T* __restrict__ FW = static_cast<const T*>(a.fw);
+  const int aw = a.aw;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const AdjTile tl = tiles[t];
     int rb, re, rs;
@@ -485,7 +494,21 @@ __global__ __launch_bounds__(256) void k_adjoint(PlanDesc d, AdjDesc a, const Ad
     for (int r = rb; r < re; r += rs) {
       const int64_t k = tl.first + r;
       const int64_t cell = a.src[k];
-      const int64_t e0 = a.ptr[k], e1 = a.ptr[k + 1];
+      const int cnt = a.cnt[k];
+      int32_t fg[ADJ_MAXW];
+      T fwt[ADJ_MAXW];
+      int fr[ADJ_MAXW];
+#pragma unroll
+      for (int m = 0; m < ADJ_MAXW; ++m) {
+        fg[m] = 0;
+        fwt[m] = T(0);
+        fr[m] = 0;
+        if (m < aw) {
+          fg[m] = a.fg[k * aw + m];
+          fwt[m] = FW[k * aw + m];
+          fr[m] = a.frot[k * aw + m];
+        }
+      }
       for (int64_t v = lane; v < nvec; v += lpr) {
         const int64_t l = v * V;
         T* px = f + cell * d.cs + l * d.ls;
@@ -497,31 +520,54 @@ __global__ __launch_bounds__(256) void k_adjoint(PlanDesc d, AdjDesc a, const Ad
           x = ldv<T, V>(px);
         }
         Pack<T, V> acc;
+        if (cnt <= aw) {
+          Pack<T, V> g[ADJ_MAXW];
+          T wt[ADJ_MAXW];
 #pragma unroll
-        for (int i = 0; i < V; ++i) acc.v[i] = T(0);
-        bool first = true;
-        for (int64_t eb = e0; eb < e1; eb += EB) {
-          const int ne = (int)min<int64_t>(EB, e1 - eb);
-          int64_t off[EB];
-          T wt[EB];
-#pragma unroll
-          for (int j = 0; j < EB; ++j) {
-            const int64_t e = eb + min(j, ne - 1);
-            T sign;
-            const int64_t sl = rot_slot<T>(d, a.rot[e], l, sign);
-            wt[j] = W[e] * sign;
-            off[j] = a.ghost[e] * d.cs + sl * d.ls;
+          for (int m = 0; m < ADJ_MAXW; ++m) {
+            if (m < cnt) {
+              T sign;
+              const int64_t sl = rot_slot<T>(d, fr[m], l, sign);
+              wt[m] = fwt[m] * sign;
+              g[m] = ldv<T, V>(f + (int64_t)fg[m] * d.cs + sl * d.ls);
+            }
           }
-          Pack<T, V> g[EB];
 #pragma unroll
-          for (int j = 0; j < EB; ++j)
-            if (j < ne) g[j] = ldv<T, V>(f + off[j]);
+          for (int i = 0; i < V; ++i) acc.v[i] = wt[0] * g[0].v[i];
 #pragma unroll
-          for (int j = 0; j < EB; ++j) {
-            if (j >= ne) break;
+          for (int m = 1; m < ADJ_MAXW; ++m)
+            if (m < cnt) {
 #pragma unroll
-            for (int i = 0; i < V; ++i) acc.v[i] = first ? wt[j] * g[j].v[i] : fma(wt[j], g[j].v[i], acc.v[i]);
-            first = false;
+              for (int i = 0; i < V; ++i) acc.v[i] = fma(wt[m], g[m].v[i], acc.v[i]);
+            }
+        } else {
+          const int64_t e0 = a.ptr[k], e1 = a.ptr[k + 1];
+#pragma unroll
+          for (int i = 0; i < V; ++i) acc.v[i] = T(0);
+          bool first = true;
+          for (int64_t eb = e0; eb < e1; eb += EB) {
+            const int ne = (int)min<int64_t>(EB, e1 - eb);
+            int64_t off[EB];
+            T wt[EB];
+#pragma unroll
+            for (int j = 0; j < EB; ++j) {
+              const int64_t e = eb + min(j, ne - 1);
+              T sign;
+              const int64_t sl = rot_slot<T>(d, a.rot[e], l, sign);
+              wt[j] = W[e] * sign;
+              off[j] = a.ghost[e] * d.cs + sl * d.ls;
+            }
+            Pack<T, V> g[EB];
+#pragma unroll
+            for (int j = 0; j < EB; ++j)
+              if (j < ne) g[j] = ldv<T, V>(f + off[j]);
+#pragma unroll
+            for (int j = 0; j < EB; ++j) {
+              if (j >= ne) break;
+#pragma unroll
+              for (int i = 0; i < V; ++i) acc.v[i] = first ? wt[j] * g[j].v[i] : fma(wt[j], g[j].v[i], acc.v[i]);
+              first = false;
+            }
           }
         }
 #pragma unroll
@@ -533,6 +579,117 @@ __global__ __launch_bounds__(256) void k_adjoint(PlanDesc d, AdjDesc a, const Ad
           stv<T, V, NT>(px, x);
         }
       }
+    }
+  }
+}
+
+// LDS-staged adjoint (point-major).  Per tile: the distinct ghost rows its
+// sources read are loaded into LDS once; each row is then retired (zeroed by
+// this tile if it is the row's only reader tile, or the last one to
+// decrement the row's reader counter, which it then restores); then each
+// source sums its entries from LDS in ascending ghost order, exactly as the
+// CSR-walking kernel does, so both give the same bits.  Workgroups past the
+// tiles zero the covered ghost rows that no source reads.
+struct AdjLdsDesc {
+  const AdjLdsTile* tiles;
+  const int32_t* ucell;
+  const int32_t* uctr;
+  const int32_t* ctrinit;
+  int32_t* ctr;
+  const uint16_t* slot;
+  const int32_t* zero;
+  int32_t ntiles;
+  int32_t nzero;
+};
+
+template <typename T, int V, bool NT>
+__global__ __launch_bounds__(256) void k_adjoint_lds(PlanDesc d, AdjDesc a, AdjLdsDesc q) {
+  extern __shared__ __align__(16) unsigned char adj_smem[];
+  T* rows = reinterpret_cast<T*>(adj_smem);
+  __shared__ int zflag[ADJ_LDS_ROWS];
+  typedef T vt __attribute__((ext_vector_type(V)));
+  T* __restrict__ f = static_cast<T*>(d.field);
+  const int64_t inner = d.inner;
+  const int nvec = (int)(inner / V);
+  Pack<T, V> zero;
+#pragma unroll
+  for (int i = 0; i < V; ++i) zero.v[i] = T(0);
+  if ((int)blockIdx.x >= q.ntiles) {
+    const int r0 = ((int)blockIdx.x - q.ntiles) * ADJ_ZERO_ROWS;
+    const int nr = min(ADJ_ZERO_ROWS, q.nzero - r0);
+    for (int e = threadIdx.x; e < nr * nvec; e += blockDim.x) {
+      const int r = e / nvec, v = e - r * nvec;
+      stv<T, V, NT>(f + (int64_t)q.zero[r0 + r] * d.cs + (int64_t)v * V, zero);
+    }
+    return;
+  }
+  const AdjLdsTile tl = q.tiles[blockIdx.x];
+  const int nu = tl.nu;
+  for (int e = threadIdx.x; e < nu * nvec; e += blockDim.x) {
+    const int u = e / nvec, v = e - u * nvec;
+    const Pack<T, V> g = ldv<T, V>(f + (int64_t)q.ucell[tl.first_u + u] * d.cs + (int64_t)v * V);
+    vt w;
+#pragma unroll
+    for (int i = 0; i < V; ++i) w[i] = g.v[i];
+    *reinterpret_cast<vt*>(&rows[(int64_t)u * inner + (int64_t)v * V]) = w;
+  }
+  __syncthreads();  // every load of this tile's ghost rows has returned
+  if ((int)threadIdx.x < nu) {
+    const int c = q.uctr[tl.first_u + threadIdx.x];
+    int z = 1;
+    if (c >= 0) {
+      z = atomicSub(&q.ctr[c], 1) == 1 ? 1 : 0;
+      if (z) atomicExch(&q.ctr[c], q.ctrinit[c]);
+    }
+    zflag[threadIdx.x] = z;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < nu * nvec; e += blockDim.x) {
+    const int u = e / nvec, v = e - u * nvec;
+    if (zflag[u]) stv<T, V, NT>(f + (int64_t)q.ucell[tl.first_u + u] * d.cs + (int64_t)v * V, zero);
+  }
+  const int lpr = 1 << d.lpr_shift;
+  const int ngroups = (int)blockDim.x >> d.lpr_shift;
+  const int lane = threadIdx.x & (lpr - 1), grp = threadIdx.x >> d.lpr_shift;
+  const T* __restrict__ FW = static_cast<const T*>(a.fw);
+  const int aw = a.aw;
+  for (int r = grp; r < tl.nsrc; r += ngroups) {
+    const int64_t k = tl.first_src + r;
+    const int64_t cell = a.src[k];
+    const int cnt = a.cnt[k];
+    int sl_[ADJ_MAXW];
+    T fwt[ADJ_MAXW];
+    int fr[ADJ_MAXW];
+#pragma unroll
+    for (int m = 0; m < ADJ_MAXW; ++m) {
+      sl_[m] = 0;
+      fwt[m] = T(0);
+      fr[m] = 0;
+      if (m < aw) {
+        sl_[m] = q.slot[k * aw + m];
+        fwt[m] = FW[k * aw + m];
+        fr[m] = a.frot[k * aw + m];
+      }
+    }
+    for (int v = lane; v < nvec; v += lpr) {
+      const int64_t l = (int64_t)v * V;
+      T* px = f + cell * d.cs + l;
+      Pack<T, V> x = ldv<T, V>(px);
+      Pack<T, V> acc;
+#pragma unroll
+      for (int m = 0; m < ADJ_MAXW; ++m) {
+        if (m < cnt) {
+          T sign;
+          const int64_t sl = rot_slot<T>(d, fr[m], l, sign);
+          const T wt = fwt[m] * sign;
+          const vt g = *reinterpret_cast<const vt*>(&rows[(int64_t)sl_[m] * inner + sl]);
+#pragma unroll
+          for (int i = 0; i < V; ++i) acc.v[i] = m == 0 ? wt * g[i] : fma(wt, g[i], acc.v[i]);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < V; ++i) x.v[i] = x.v[i] + acc.v[i];
+      stv<T, V, NT>(px, x);
     }
   }
 }
@@ -806,7 +963,7 @@ PlanDesc make_desc(const Plan& p, void* field) {
   d.vec_len = p.layout.vec_len;
   d.lpr_shift = ilog2(p.tune.lanes_per_row);
   d.vec = p.vec;
-  d.chunked = p.tune.lanes_per_row >= 16 ? 1 : 0;
+  d.chunked = p.tune.lanes_per_row >= CHUNK_LPR ? 1 : 0;
   d.nt = (p.layout.order == HBC_POINT_MAJOR && p.layout.inner * (p.dtype == HBC_F64 ? 8 : 4) >= 128) ? 1 : 0;
   return d;
 }
@@ -826,6 +983,8 @@ void device_free_plan(Plan& p) {
   p.d_adj_tiles = nullptr;
   if (p.d_csc_dev) (void)hipFree(p.d_csc_dev);
   p.d_csc_dev = nullptr;
+  if (p.d_al_dev) (void)hipFree(p.d_al_dev);
+  p.d_al_dev = nullptr;
   p.d_csc_src = nullptr;
   if (p.d_tiles) (void)hipFree(const_cast<DevTile*>(p.d_tiles));
   p.d_tiles = nullptr;
@@ -895,6 +1054,10 @@ void device_upload_csc(Plan& p) {
   size_t o_gh = pk.vec(C.ghost);
   size_t o_w = pk.reals(C.w, p.dtype);
   size_t o_rot = pk.vec(C.rot);
+  size_t o_cnt = pk.vec(C.cnt);
+  size_t o_fg = pk.vec(C.fghost);
+  size_t o_fw = pk.reals(C.fw, p.dtype);
+  size_t o_frot = pk.vec(C.frot);
   void* dev = nullptr;
   HIP_CHECK(hipMalloc(&dev, pk.buf.size()));
   p.d_csc_dev = dev;
@@ -905,6 +1068,33 @@ void device_upload_csc(Plan& p) {
   p.d_csc_ghost = reinterpret_cast<const int64_t*>(b + o_gh);
   p.d_csc_w = b + o_w;
   p.d_csc_rot = reinterpret_cast<const int32_t*>(b + o_rot);
+  p.d_adj_cnt = reinterpret_cast<const int32_t*>(b + o_cnt);
+  p.d_adj_fg = reinterpret_cast<const int32_t*>(b + o_fg);
+  p.d_adj_fw = b + o_fw;
+  p.d_adj_frot = reinterpret_cast<const int8_t*>(b + o_frot);
+  const AdjLdsHost& A = p.host.adj_lds;
+  if (A.ok) {
+    Packer q;
+    size_t o_t = q.vec(A.tiles);
+    size_t o_uc = q.vec(A.u_cell);
+    size_t o_uk = q.vec(A.u_ctr);
+    size_t o_ci = q.vec(A.ctr_init);
+    size_t o_ct = q.vec(A.ctr_init);  // counters start at their reader counts
+    size_t o_sl = q.vec(A.slot);
+    size_t o_z = q.vec(A.zero_rows);
+    void* dv = nullptr;
+    HIP_CHECK(hipMalloc(&dv, q.buf.size()));
+    p.d_al_dev = dv;
+    HIP_CHECK(hipMemcpy(dv, q.buf.data(), q.buf.size(), hipMemcpyHostToDevice));
+    char* c = static_cast<char*>(dv);
+    p.d_al_tiles = reinterpret_cast<const AdjLdsTile*>(c + o_t);
+    p.d_al_ucell = reinterpret_cast<const int32_t*>(c + o_uc);
+    p.d_al_uctr = reinterpret_cast<const int32_t*>(c + o_uk);
+    p.d_al_ctrinit = reinterpret_cast<const int32_t*>(c + o_ci);
+    p.d_al_ctr = reinterpret_cast<int32_t*>(c + o_ct);
+    p.d_al_slot = reinterpret_cast<const uint16_t*>(c + o_sl);
+    p.d_al_zero = reinterpret_cast<const int32_t*>(c + o_z);
+  }
   void* t = nullptr;
   size_t nt = std::max<size_t>(1, p.host.adj_tiles.size());
   HIP_CHECK(hipMalloc(&t, nt * sizeof(AdjTile)));
@@ -949,9 +1139,34 @@ void device_apply(const Plan& p, void* field, void* stream, bool zero_only) {
     launch_apply_t<float>(p, d, S(stream), zero_only);
 }
 
+template <typename T, int V>
+static void launch_adjoint_lds(const Plan& p, const PlanDesc& d, const AdjDesc& a, hipStream_t st) {
+  const AdjLdsHost& A = p.host.adj_lds;
+  AdjLdsDesc q{p.d_al_tiles, p.d_al_ucell, p.d_al_uctr, p.d_al_ctrinit, p.d_al_ctr, p.d_al_slot, p.d_al_zero,
+               (int32_t)A.tiles.size(), (int32_t)A.zero_rows.size()};
+  const int grid = q.ntiles + (q.nzero + ADJ_ZERO_ROWS - 1) / ADJ_ZERO_ROWS;
+  if (grid == 0) return;
+  const size_t lds = (size_t)A.brows * p.layout.inner * sizeof(T);
+  if (d.nt)
+    hipLaunchKernelGGL((k_adjoint_lds<T, V, true>), dim3(grid), dim3(p.tune.block), lds, st, d, a, q);
+  else
+    hipLaunchKernelGGL((k_adjoint_lds<T, V, false>), dim3(grid), dim3(p.tune.block), lds, st, d, a, q);
+  HIP_CHECK(hipGetLastError());
+}
+
 template <typename T>
 static void launch_adjoint_t(const Plan& p, const PlanDesc& d, hipStream_t st) {
-  AdjDesc a{p.d_csc_src, p.d_csc_ptr, p.d_csc_ghost, p.d_csc_w, p.d_csc_rot};
+  AdjDesc a{p.d_csc_src, p.d_csc_ptr,  p.d_csc_ghost, p.d_csc_w,          p.d_csc_rot,
+            p.d_adj_cnt, p.d_adj_fg, p.d_adj_fw,    p.d_adj_frot, p.host.csc.aw};
+  if (p.host.adj_lds.ok && p.layout.order == HBC_POINT_MAJOR) {
+    if (sizeof(T) == 4 && p.vec == 4)
+      launch_adjoint_lds<T, (sizeof(T) == 4 ? 4 : 2)>(p, d, a, st);
+    else if (p.vec >= 2)
+      launch_adjoint_lds<T, 2>(p, d, a, st);
+    else
+      launch_adjoint_lds<T, 1>(p, d, a, st);
+    return;
+  }
   const int nt = (int)p.host.adj_tiles.size();
   if (nt > 0) {
     const int blk = p.tune.block;
@@ -1157,7 +1372,7 @@ static void batch_tiles(Batch* b) {
     int lpr = p.tune.lanes_per_row;
     if (b->tune.lanes_per_row > 0) lpr = std::min(lpr, b->tune.lanes_per_row);
     b->descs[k].lpr_shift = ilog2(lpr);
-    b->descs[k].chunked = lpr >= 16 ? 1 : 0;
+    b->descs[k].chunked = lpr >= CHUNK_LPR ? 1 : 0;
     const int64_t rp = std::max<int64_t>(1, b->tune.block / lpr);
     int64_t rpt = std::max<int64_t>(1, (int64_t)b->tune.rows_per_tile / I);
     rpt = ((rpt + rp - 1) / rp) * rp;

@@ -573,9 +573,10 @@ hbc_tune default_tune(const Plan& plan) {
   const int64_t rows_per_pass = t.block / t.lanes_per_row;
   // Short tiles keep many workgroups in flight (the apply is latency bound per
   // row: table reads, then source loads, then stores): one batch of 4 rows per
-  // row group when a row fills >= 16 lanes, else about 4096 tiles in all.
+  // row group when groups take contiguous runs of rows, else about 4096 tiles
+  // in all.
   int64_t rpt;
-  if (t.lanes_per_row >= 16) {
+  if (t.lanes_per_row >= CHUNK_LPR) {
     rpt = rows_per_pass * 4;
   } else {
     rpt = std::max<int64_t>(rows / 4096, rows_per_pass);
@@ -642,6 +643,75 @@ void build_tiles(Plan& plan, const hbc_tune& t) {
   }
 }
 
+// Tiles of the LDS-staged adjoint: consecutive sources, greedily, while the
+// distinct ghost rows of the tile fit the LDS rows and the tile stays short
+// enough to leave many workgroups in flight.
+static void build_adj_lds(Plan& plan) {
+  const CscHost& C = plan.host.csc;
+  AdjLdsHost& A = plan.host.adj_lds;
+  A = AdjLdsHost{};
+  if (plan.layout.order != HBC_POINT_MAJOR) return;
+  const int64_t row_bytes = plan.layout.inner * (plan.dtype == HBC_F64 ? 8 : 4);
+  const int64_t brows = std::min<int64_t>(ADJ_LDS_ROWS, ADJ_LDS_BYTES / std::max<int64_t>(1, row_bytes));
+  const int64_t nsrc = (int64_t)C.src_cell.size();
+  int64_t maxc = 0;
+  for (int64_t k = 0; k < nsrc; ++k) maxc = std::max<int64_t>(maxc, C.cnt[k]);
+  if (maxc > C.aw || maxc > brows || brows < 1) return;  // the CSR-walking kernel serves such plans
+  A.brows = (int32_t)brows;
+  // sources per tile: about 4 per row group of the launch shape
+  const int64_t groups = std::max<int64_t>(1, plan.tune.block / plan.tune.lanes_per_row);
+  const int64_t smax = std::max<int64_t>(1, std::min<int64_t>(4 * groups, 256));
+  A.slot.assign((size_t)nsrc * C.aw, 0);
+  std::unordered_map<int64_t, int32_t> local;
+  std::unordered_map<int64_t, int32_t> readers;  // ghost -> reader tiles
+  int64_t k = 0;
+  while (k < nsrc) {
+    AdjLdsTile t{(int32_t)k, 0, (int32_t)A.u_cell.size(), 0};
+    local.clear();
+    while (k < nsrc && t.nsrc < smax) {
+      int add = 0;
+      for (int32_t m = 0; m < C.cnt[k]; ++m)
+        if (!local.count(C.fghost[k * C.aw + m])) ++add;
+      // (a ghost repeated within one source is counted twice: conservative)
+      if (t.nu + add > brows) break;
+      for (int32_t m = 0; m < C.cnt[k]; ++m) {
+        const int64_t g = C.fghost[k * C.aw + m];
+        auto it = local.find(g);
+        int32_t sl;
+        if (it == local.end()) {
+          sl = t.nu++;
+          local.emplace(g, sl);
+          A.u_cell.push_back((int32_t)g);
+          ++readers[g];
+        } else {
+          sl = it->second;
+        }
+        A.slot[k * C.aw + m] = (uint16_t)sl;
+      }
+      ++t.nsrc;
+      ++k;
+    }
+    if (t.nsrc == 0) return;  // cannot happen: every source fits an empty tile
+    A.tiles.push_back(t);
+  }
+  std::unordered_map<int64_t, int32_t> ctr_of;
+  A.u_ctr.assign(A.u_cell.size(), -1);
+  for (size_t u = 0; u < A.u_cell.size(); ++u) {
+    const int64_t g = A.u_cell[u];
+    const int32_t n = readers[g];
+    if (n < 2) continue;
+    auto it = ctr_of.find(g);
+    if (it == ctr_of.end()) {
+      it = ctr_of.emplace(g, (int32_t)A.ctr_init.size()).first;
+      A.ctr_init.push_back(n);
+    }
+    A.u_ctr[u] = it->second;
+  }
+  for (int32_t r : plan.host.row_dst)
+    if (!readers.count(r)) A.zero_rows.push_back(r);
+  A.ok = true;
+}
+
 void build_csc(Plan& plan) {
   const HostTables& T = plan.host;
   struct E {
@@ -693,6 +763,25 @@ void build_csc(Plan& plan) {
     C.rot.push_back(ents[k].rot);
   }
   C.ptr.push_back((int64_t)ents.size());
+  const int64_t nsrc = (int64_t)C.src_cell.size();
+  int64_t maxc = 0;
+  for (int64_t k = 0; k < nsrc; ++k) maxc = std::max(maxc, C.ptr[k + 1] - C.ptr[k]);
+  C.aw = (int32_t)std::max<int64_t>(1, std::min<int64_t>(maxc, ADJ_MAXW));
+  C.cnt.assign(nsrc, 0);
+  C.fghost.assign(nsrc * C.aw, 0);
+  C.fw.assign(nsrc * C.aw, 0.0);
+  C.frot.assign(nsrc * C.aw, 0);
+  for (int64_t k = 0; k < nsrc; ++k) {
+    const int64_t n = C.ptr[k + 1] - C.ptr[k];
+    C.cnt[k] = (int32_t)n;
+    for (int64_t m = 0; m < std::min<int64_t>(n, C.aw); ++m) {
+      const int64_t e = C.ptr[k] + m;
+      C.fghost[k * C.aw + m] = (int32_t)C.ghost[e];
+      C.fw[k * C.aw + m] = C.w[e];
+      C.frot[k * C.aw + m] = (int8_t)C.rot[e];
+    }
+  }
+  build_adj_lds(plan);
   // adjoint tiles: sources grouped so that a tile holds about as many inner
   // values as a forward tile
   plan.host.adj_tiles.clear();
