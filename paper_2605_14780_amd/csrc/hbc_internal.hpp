@@ -238,7 +238,8 @@ struct Plan {
   HostTables host;
   hbc_stats stats{};
   hbc_tune tune{};
-  int vec = 1;  // elements per lane access (point-major)
+  int vec = 1;     // elements per lane access (point-major)
+  int unroll = 1;  // accesses per lane and row: vec * unroll elements make 16 bytes where the row allows
   // device storage: one allocation holding every table
   void* dev = nullptr;
   size_t dev_bytes = 0;

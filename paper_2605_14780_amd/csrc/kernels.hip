@@ -49,6 +49,8 @@ struct PlanDesc {
   int32_t vec;        // elements per lane access
   int32_t chunked;    // point-major: each row group walks a contiguous run of rows
   int32_t nt;         // results go out with non-temporal stores (rows of >= 128 bytes)
+  int32_t unroll;     // accesses of vec elements per lane and row (point-major)
+  int32_t pad_;
   const int32_t* row_dst;  // point-major row tables
   const int32_t* row_src;
 };
@@ -248,7 +250,10 @@ __device__ __forceinline__ void run_tile(const PlanDesc& d, const DevSeg& s, int
 #endif
 constexpr int RB = HBC_ROWS_PER_BATCH;  // rows per batch of a row group
 
-template <typename T, int V, bool NT>
+// U > 1: a lane carries U accesses of V elements per row, lpr apart (rows
+// whose length is not a multiple of a 16-byte vector still keep 16 bytes of
+// loads per lane and source in flight, and every access stays coalesced).
+template <typename T, int V, int U, bool NT>
 __device__ __forceinline__ void rt_tile(const PlanDesc& d, const RowTile& tl, bool zero_only) {
   const int lpr = 1 << d.lpr_shift;
   const int ngroups = (int)blockDim.x >> d.lpr_shift;
@@ -276,10 +281,19 @@ __device__ __forceinline__ void rt_tile(const PlanDesc& d, const RowTile& tl, bo
   const int32_t* __restrict__ rsrc = d.row_src + tl.row_begin;
   const bool ell4 = kind == SEG_ELL && tl.width == 4 && !(tl.flags & SEGF_ELL_PADDED);
   const T* __restrict__ bt = static_cast<const T*>(d.bval) + tl.brow;
-  for (int64_t v = lane; v < nvec; v += lpr) {
-    const int64_t l = v * V;
-    T sign = T(1);
-    const int64_t sl = (kind == SEG_MAP || kind == SEG_ELL || kind == SEG_CSR) ? rot_slot<T>(d, tl.rot, l, sign) : l;
+  const bool rotates = kind == SEG_MAP || kind == SEG_ELL || kind == SEG_CSR;
+  for (int64_t v0 = lane; v0 < nvec; v0 += (int64_t)lpr * U) {
+    int64_t l[U], sl[U];
+    T sign[U];
+    bool ok[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t v = v0 + (int64_t)u * lpr;
+      ok[u] = v < nvec;
+      l[u] = (ok[u] ? v : v0) * V;  // a spare access repeats a valid one and is not stored
+      sign[u] = T(1);
+      sl[u] = rotates ? rot_slot<T>(d, tl.rot, l[u], sign[u]) : l[u];
+    }
     for (int r = rb; r < re; r += RB * rs) {
       int rr[RB];
       int64_t dst[RB];
@@ -288,16 +302,23 @@ __device__ __forceinline__ void rt_tile(const PlanDesc& d, const RowTile& tl, bo
         rr[q] = min(r + q * rs, last);
         dst[q] = rdst[rr[q]];
       }
-      Pack<T, V> y[RB];
+      Pack<T, V> y[RB][U];
       if (kind == SEG_MAP) {
-        const T wt = T(tl.w) * sign;
-        Pack<T, V> x[RB];
+        Pack<T, V> x[RB][U];
 #pragma unroll
-        for (int q = 0; q < RB; ++q) x[q] = ldv<T, V>(f + (int64_t)rsrc[rr[q]] * d.cs + sl);
+        for (int q = 0; q < RB; ++q) {
+          const T* src = f + (int64_t)rsrc[rr[q]] * d.cs;
 #pragma unroll
-        for (int q = 0; q < RB; ++q)
+          for (int u = 0; u < U; ++u) x[q][u] = ldv<T, V>(src + sl[u]);
+        }
 #pragma unroll
-          for (int i = 0; i < V; ++i) y[q].v[i] = wt * x[q].v[i];
+        for (int u = 0; u < U; ++u) {
+          const T wt = T(tl.w) * sign[u];
+#pragma unroll
+          for (int q = 0; q < RB; ++q)
+#pragma unroll
+            for (int i = 0; i < V; ++i) y[q][u].v[i] = wt * x[q][u].v[i];
+        }
       } else if (ell4) {
         const int32_t* __restrict__ cb = d.ell_col + tl.tab;
         const T* __restrict__ vb = static_cast<const T*>(d.ell_val) + tl.tab;
@@ -322,35 +343,47 @@ __device__ __forceinline__ void rt_tile(const PlanDesc& d, const RowTile& tl, bo
 #pragma unroll
           for (int m = 0; m < 4; ++m) slide = slide && (c[q][m] == c00 + (q + m) * dl);
         if (slide) {
-          Pack<T, V> u[RB + 3];
+          Pack<T, V> w[RB + 3][U];
 #pragma unroll
-          for (int j = 0; j < RB + 3; ++j) u[j] = ldv<T, V>(f + (int64_t)(c00 + j * dl) * d.cs + sl);
+          for (int j = 0; j < RB + 3; ++j) {
+            const T* src = f + (int64_t)(c00 + j * dl) * d.cs;
+#pragma unroll
+            for (int u = 0; u < U; ++u) w[j][u] = ldv<T, V>(src + sl[u]);
+          }
 #pragma unroll
           for (int q = 0; q < RB; ++q)
 #pragma unroll
-            for (int i = 0; i < V; ++i) {
-              T a = wt[q][0] * u[q].v[i];
-              a = fma(wt[q][1], u[q + 1].v[i], a);
-              a = fma(wt[q][2], u[q + 2].v[i], a);
-              a = fma(wt[q][3], u[q + 3].v[i], a);
-              y[q].v[i] = sign * a;
-            }
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+              for (int i = 0; i < V; ++i) {
+                T a = wt[q][0] * w[q][u].v[i];
+                a = fma(wt[q][1], w[q + 1][u].v[i], a);
+                a = fma(wt[q][2], w[q + 2][u].v[i], a);
+                a = fma(wt[q][3], w[q + 3][u].v[i], a);
+                y[q][u].v[i] = sign[u] * a;
+              }
         } else {
-          Pack<T, V> x[RB][4];
+          Pack<T, V> x[RB][4][U];
 #pragma unroll
           for (int q = 0; q < RB; ++q)
 #pragma unroll
-            for (int m = 0; m < 4; ++m) x[q][m] = ldv<T, V>(f + (int64_t)c[q][m] * d.cs + sl);
+            for (int m = 0; m < 4; ++m) {
+              const T* src = f + (int64_t)c[q][m] * d.cs;
 #pragma unroll
-          for (int q = 0; q < RB; ++q)
-#pragma unroll
-            for (int i = 0; i < V; ++i) {
-              T a = wt[q][0] * x[q][0].v[i];
-              a = fma(wt[q][1], x[q][1].v[i], a);
-              a = fma(wt[q][2], x[q][2].v[i], a);
-              a = fma(wt[q][3], x[q][3].v[i], a);
-              y[q].v[i] = sign * a;
+              for (int u = 0; u < U; ++u) x[q][m][u] = ldv<T, V>(src + sl[u]);
             }
+#pragma unroll
+          for (int q = 0; q < RB; ++q)
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+              for (int i = 0; i < V; ++i) {
+                T a = wt[q][0] * x[q][0][u].v[i];
+                a = fma(wt[q][1], x[q][1][u].v[i], a);
+                a = fma(wt[q][2], x[q][2][u].v[i], a);
+                a = fma(wt[q][3], x[q][3][u].v[i], a);
+                y[q][u].v[i] = sign[u] * a;
+              }
         }
       } else if (kind == SEG_ELL || kind == SEG_CSR) {
 #pragma unroll
@@ -371,49 +404,64 @@ __device__ __forceinline__ void rt_tile(const PlanDesc& d, const RowTile& tl, bo
           }
           bool first = true;
 #pragma unroll
-          for (int i = 0; i < V; ++i) y[q].v[i] = T(0);
+          for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int i = 0; i < V; ++i) y[q][u].v[i] = T(0);
           for (int64_t e = e0; e < e1; ++e) {
             const int32_t cc = cols[e];
             if (cc < 0) continue;
             const T wt = vals[e];
-            Pack<T, V> x = ldv<T, V>(f + (int64_t)cc * d.cs + sl);
+            const T* src = f + (int64_t)cc * d.cs;
+            Pack<T, V> x[U];
 #pragma unroll
-            for (int i = 0; i < V; ++i) y[q].v[i] = first ? wt * x.v[i] : fma(wt, x.v[i], y[q].v[i]);
+            for (int u = 0; u < U; ++u) x[u] = ldv<T, V>(src + sl[u]);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+              for (int i = 0; i < V; ++i) y[q][u].v[i] = first ? wt * x[u].v[i] : fma(wt, x[u].v[i], y[q][u].v[i]);
             first = false;
           }
 #pragma unroll
-          for (int i = 0; i < V; ++i) y[q].v[i] = sign * y[q].v[i];
+          for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int i = 0; i < V; ++i) y[q][u].v[i] = sign[u] * y[q][u].v[i];
         }
       } else {  // zero rows, or b-only rows
 #pragma unroll
         for (int q = 0; q < RB; ++q)
 #pragma unroll
-          for (int i = 0; i < V; ++i) y[q].v[i] = T(0);
+          for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int i = 0; i < V; ++i) y[q][u].v[i] = T(0);
       }
       if (with_b) {
 #pragma unroll
         for (int q = 0; q < RB; ++q) {
           const T* bp = bt + (int64_t)rr[q] * tl.b_inner;
 #pragma unroll
-          for (int i = 0; i < V; ++i) {
-            const T bb = tl.b_inner == 1 ? bp[0] : bp[l + i];
-            y[q].v[i] = kind == SEG_VEC ? bb : y[q].v[i] + bb;
-          }
+          for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int i = 0; i < V; ++i) {
+              const T bb = tl.b_inner == 1 ? bp[0] : bp[l[u] + i];
+              y[q][u].v[i] = kind == SEG_VEC ? bb : y[q][u].v[i] + bb;
+            }
         }
       }
 #pragma unroll
       for (int q = 0; q < RB; ++q)
-        if (r + q * rs < re) stv<T, V, NT>(f + dst[q] * d.cs + l, y[q]);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (r + q * rs < re && ok[u]) stv<T, V, NT>(f + dst[q] * d.cs + l[u], y[q][u]);
     }
   }
 }
 
-template <typename T, int V, bool NT>
+template <typename T, int V, int U, bool NT>
 __global__ __launch_bounds__(256) void k_apply_rows(PlanDesc d, const RowTile* __restrict__ tiles, int ntiles,
                                                     int zero_only) {
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const RowTile tl = tiles[t];
-    rt_tile<T, V, NT>(d, tl, zero_only != 0);
+    rt_tile<T, V, U, NT>(d, tl, zero_only != 0);
   }
 }
 
@@ -427,27 +475,36 @@ __global__ __launch_bounds__(256) void k_apply(PlanDesc d, const DevTile* __rest
   }
 }
 
+// Batch tiles of different plans: (vec, unroll) chosen per tile at run time.
+template <typename T, bool NT>
+__device__ __forceinline__ void rt_tile_any(const PlanDesc& d, const RowTile& tl) {
+  if (sizeof(T) == 4) {
+    if (d.vec == 4)
+      rt_tile<T, (sizeof(T) == 4 ? 4 : 2), 1, NT>(d, tl, false);
+    else if (d.vec == 2)
+      d.unroll >= 2 ? rt_tile<T, 2, 2, NT>(d, tl, false) : rt_tile<T, 2, 1, NT>(d, tl, false);
+    else if (d.unroll >= 4)
+      rt_tile<T, 1, 4, NT>(d, tl, false);
+    else
+      d.unroll >= 2 ? rt_tile<T, 1, 2, NT>(d, tl, false) : rt_tile<T, 1, 1, NT>(d, tl, false);
+  } else {
+    if (d.vec >= 2)
+      rt_tile<T, 2, 1, NT>(d, tl, false);
+    else
+      d.unroll >= 2 ? rt_tile<T, 1, 2, NT>(d, tl, false) : rt_tile<T, 1, 1, NT>(d, tl, false);
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_batch(const PlanDesc* __restrict__ descs, const RowTile* __restrict__ tiles,
                                                int ntiles) {
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const RowTile tl = tiles[t];
     const PlanDesc d = descs[tl.pad_];
-    if (d.nt) {
-      if (sizeof(T) == 4 && d.vec == 4)
-        rt_tile<T, (sizeof(T) == 4 ? 4 : 2), true>(d, tl, false);
-      else if (d.vec == 2)
-        rt_tile<T, 2, true>(d, tl, false);
-      else
-        rt_tile<T, 1, true>(d, tl, false);
-    } else {
-      if (sizeof(T) == 4 && d.vec == 4)
-        rt_tile<T, (sizeof(T) == 4 ? 4 : 2), false>(d, tl, false);
-      else if (d.vec == 2)
-        rt_tile<T, 2, false>(d, tl, false);
-      else
-        rt_tile<T, 1, false>(d, tl, false);
-    }
+    if (d.nt)
+      rt_tile_any<T, true>(d, tl);
+    else
+      rt_tile_any<T, false>(d, tl);
   }
 }
 
@@ -814,7 +871,7 @@ __global__ __launch_bounds__(256) void k_stencil27(const T* __restrict__ x, T* _
   const int ntx = (st.nx + ST_TX - 1) / ST_TX, nty = (st.ny + ST_TY - 1) / ST_TY, nzc = (st.nz + ST_ZC - 1) / ST_ZC;
   const int nst = ntx * nty * nzc * st.nblk;
   if ((int)blockIdx.x >= nst) {
-    for (int t = blockIdx.x - nst; t < bc_nt; t += bc_grid) rt_tile<T, V, false>(d, bc_tiles[t], false);
+    for (int t = blockIdx.x - nst; t < bc_nt; t += bc_grid) rt_tile<T, V, 1, false>(d, bc_tiles[t], false);
     return;
   }
   int bid;
@@ -965,6 +1022,7 @@ PlanDesc make_desc(const Plan& p, void* field) {
   d.vec = p.vec;
   d.chunked = p.tune.lanes_per_row >= CHUNK_LPR ? 1 : 0;
   d.nt = (p.layout.order == HBC_POINT_MAJOR && p.layout.inner * (p.dtype == HBC_F64 ? 8 : 4) >= 128) ? 1 : 0;
+  d.unroll = p.unroll;
   return d;
 }
 
@@ -1103,6 +1161,37 @@ void device_upload_csc(Plan& p) {
   p.d_adj_tiles = static_cast<const AdjTile*>(t);
 }
 
+template <typename T, int V, int U>
+static void launch_rows_vu(const PlanDesc& d, hipStream_t st, int grid, int blk, const RowTile* tiles, int nt, int z) {
+  if (d.nt)
+    hipLaunchKernelGGL((k_apply_rows<T, V, U, true>), dim3(grid), dim3(blk), 0, st, d, tiles, nt, z);
+  else
+    hipLaunchKernelGGL((k_apply_rows<T, V, U, false>), dim3(grid), dim3(blk), 0, st, d, tiles, nt, z);
+}
+
+// point-major row tiles: one instance per (vec, unroll) a plan can select
+template <typename T>
+static void launch_rows(const PlanDesc& d, hipStream_t st, int grid, int blk, const RowTile* tiles, int nt, int z) {
+  if (sizeof(T) == 4) {
+    if (d.vec == 4)
+      launch_rows_vu<T, (sizeof(T) == 4 ? 4 : 2), 1>(d, st, grid, blk, tiles, nt, z);
+    else if (d.vec == 2)
+      d.unroll >= 2 ? launch_rows_vu<T, 2, 2>(d, st, grid, blk, tiles, nt, z)
+                    : launch_rows_vu<T, 2, 1>(d, st, grid, blk, tiles, nt, z);
+    else if (d.unroll >= 4)
+      launch_rows_vu<T, 1, 4>(d, st, grid, blk, tiles, nt, z);
+    else
+      d.unroll >= 2 ? launch_rows_vu<T, 1, 2>(d, st, grid, blk, tiles, nt, z)
+                    : launch_rows_vu<T, 1, 1>(d, st, grid, blk, tiles, nt, z);
+  } else {
+    if (d.vec >= 2)
+      launch_rows_vu<T, 2, 1>(d, st, grid, blk, tiles, nt, z);
+    else
+      d.unroll >= 2 ? launch_rows_vu<T, 1, 2>(d, st, grid, blk, tiles, nt, z)
+                    : launch_rows_vu<T, 1, 1>(d, st, grid, blk, tiles, nt, z);
+  }
+}
+
 template <typename T>
 static void launch_apply_t(const Plan& p, const PlanDesc& d, hipStream_t st, bool zero_only) {
   const int nt = (int)p.host.tiles.size();
@@ -1112,21 +1201,8 @@ static void launch_apply_t(const Plan& p, const PlanDesc& d, hipStream_t st, boo
   const int z = zero_only ? 1 : 0;
   if (p.layout.order == HBC_PLANE_MAJOR) {
     hipLaunchKernelGGL((k_apply<T, 1, true>), dim3(grid), dim3(blk), 0, st, d, p.d_tiles, nt, z);
-  } else if (p.vec == 4) {
-    if (d.nt)
-      hipLaunchKernelGGL((k_apply_rows<T, (sizeof(T) == 4 ? 4 : 2), true>), dim3(grid), dim3(blk), 0, st, d, p.d_rtiles, nt, z);
-    else
-      hipLaunchKernelGGL((k_apply_rows<T, (sizeof(T) == 4 ? 4 : 2), false>), dim3(grid), dim3(blk), 0, st, d, p.d_rtiles, nt, z);
-  } else if (p.vec == 2) {
-    if (d.nt)
-      hipLaunchKernelGGL((k_apply_rows<T, 2, true>), dim3(grid), dim3(blk), 0, st, d, p.d_rtiles, nt, z);
-    else
-      hipLaunchKernelGGL((k_apply_rows<T, 2, false>), dim3(grid), dim3(blk), 0, st, d, p.d_rtiles, nt, z);
   } else {
-    if (d.nt)
-      hipLaunchKernelGGL((k_apply_rows<T, 1, true>), dim3(grid), dim3(blk), 0, st, d, p.d_rtiles, nt, z);
-    else
-      hipLaunchKernelGGL((k_apply_rows<T, 1, false>), dim3(grid), dim3(blk), 0, st, d, p.d_rtiles, nt, z);
+    launch_rows<T>(d, st, grid, blk, p.d_rtiles, nt, z);
   }
   HIP_CHECK(hipGetLastError());
 }

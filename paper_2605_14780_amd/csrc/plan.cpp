@@ -546,6 +546,10 @@ void compile_plan(const Program& prog, const Layout& lay, int dtype, Plan& plan)
       v /= 2;
     }
     plan.vec = v;
+    const int64_t nvec = lay.inner / v;
+    int u = 16 / (v * (int)es);
+    while (u > 1 && u > nvec) u /= 2;
+    plan.unroll = u;
   }
   plan.tune = default_tune(plan);
   build_tiles(plan, plan.tune);
@@ -564,9 +568,10 @@ hbc_tune default_tune(const Plan& plan) {
   t.persistent = 0;
   const int64_t rows = std::max<int64_t>(1, plan.stats.rows_covered);
   if (plan.layout.order == HBC_POINT_MAJOR) {
-    // one 16-byte vector per lane: a row group covers a whole row
+    // 16 bytes per lane (vec elements, unroll times): a row group covers a whole row
     int64_t nvec = plan.layout.inner / plan.vec;
-    t.lanes_per_row = (int32_t)std::min<int64_t>(t.block, pow2_ceil(nvec));
+    int64_t nacc = (nvec + plan.unroll - 1) / plan.unroll;
+    t.lanes_per_row = (int32_t)std::min<int64_t>(t.block, pow2_ceil(nacc));
   } else {
     t.lanes_per_row = 1;
   }
