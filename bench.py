@@ -252,6 +252,26 @@ def headline(ctx, args, hb, torch, tm):
     return res
 
 
+def extra_c384_plane_major(ctx, hb, torch, tm):
+    """The headline operator on the plane-major layout (value l of every cell contiguous)."""
+    N, h, nf, nl = 384, 3, 4, 64
+    I = nf * nl
+    vec = (2 * nl, nl, nl)
+    grid, prog = hb.cs_program(N, h, hb.CS_LAGRANGE, vector=True)
+    plan = hb.Plan(prog, inner=I, vec=vec, dtype=hb.F64, order=hb.PLANE_MAJOR)
+    st = plan.stats()
+    src = torch.from_numpy(ctx["c2_full"]).cuda().t().contiguous().reshape(-1)
+    fields = [src.clone() for _ in range(3)]
+    del src
+    g = hb.ApplyGraph(plan, fields, 90)
+    us = tm(g.launch, 90)
+    out = {"us_per_apply": us, "ghost_cells_per_s": st["ghost_values"] / us * 1e6,
+           "hbm_frac": st["alg_bytes"] / us / 1e3 / HBM_PEAK_GBS, "copies": 3}
+    del g, fields
+    torch.cuda.empty_cache()
+    return out
+
+
 def extra_c48(ctx, hb, torch, tm):
     from tests.helpers import cs_full_field
     N, h = 48, 3
@@ -461,6 +481,9 @@ def main():
     ap.add_argument("--copies", type=int, default=9, help="independent fields cycled for cold-cache timing")
     ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--extras", default="all",
+                    help="comma-separated subset of: c384_plane_major, c48_latency, hpcg_256cube, "
+                         "batched_64_grids_f32, c768_adjoint")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 256 MiB, 20 times (counter calibration)")
     args = ap.parse_args()
@@ -493,15 +516,24 @@ def main():
     extras = {"c384_warm_cache_us_per_apply": res["warm_us"], "c384_eager_us_per_apply": res["eager_us"],
               "c384_f32": res["f32"]}
     if not args.no_extras:
-        for name, fn in (("c48_latency", extra_c48), ("hpcg_256cube", extra_hpcg),
-                         ("batched_64_grids_f32", extra_batch), ("c768_adjoint", extra_adjoint)):
+        table = (("c384_plane_major", extra_c384_plane_major), ("c48_latency", extra_c48),
+                 ("hpcg_256cube", extra_hpcg), ("batched_64_grids_f32", extra_batch),
+                 ("c768_adjoint", extra_adjoint))
+        want = {n for n, _ in table} if args.extras == "all" else set(args.extras.split(","))
+        unknown = want - {n for n, _ in table}
+        if unknown:
+            raise SystemExit(f"unknown extras: {sorted(unknown)}")
+        for name, fn in table:
+            if name not in want:
+                continue
             t0 = time.perf_counter()
             extras[name] = fn(ctx, hb, torch, tm)
             log(f"{name} done in {time.perf_counter() - t0:.1f}s")
-        f64_ns = res["ms"] * 1e6 / args.steps / st["ghost_values"]
-        b32 = extras["batched_64_grids_f32"]
-        extras["ns_per_ghost_value_plain_f64_over_batched_f32"] = f64_ns / (b32["batched_tuned_us"] * 1e3 /
-                                                                            b32["ghost_values"])
+        if "batched_64_grids_f32" in extras:
+            f64_ns = res["ms"] * 1e6 / args.steps / st["ghost_values"]
+            b32 = extras["batched_64_grids_f32"]
+            extras["ns_per_ghost_value_plain_f64_over_batched_f32"] = f64_ns / (b32["batched_tuned_us"] * 1e3 /
+                                                                                b32["ghost_values"])
 
     log("cpu_baseline leg: oracle timing and checks")
     chk = cpu_baseline_and_checks(ctx, args.cpu_budget)

@@ -131,24 +131,25 @@ __device__ __forceinline__ int64_t rot_slot(const PlanDesc& d, int rot, int64_t 
   return d.vec_lo + p * d.vec_stride + off;
 }
 
-// Rows [row0, row0 + nrows) of segment s, all inner values, by `nthr` threads.
-template <typename T, int V, bool ROWFAST>
-__device__ __forceinline__ void run_tile(const PlanDesc& d, const DevSeg& s, int64_t row0, int nrows, bool zero_only,
-                                         int tid, int nthr) {
+// Plane-major tile: rows [row0, row0 + nrows) of segment s, all inner values.
+// Consecutive threads take consecutive rows (neighbouring ghost cells are
+// neighbours in every plane), the lpr thread sets of a workgroup take planes
+// l = lane, lane + lpr, ...; a thread reads its row's columns and weights
+// once and then works through its planes PB at a time, all loads of the PB
+// planes issued before any arithmetic or store.
+constexpr int PB = 8;
+
+template <typename T>
+__device__ __forceinline__ void run_tile_pm(const PlanDesc& d, const DevSeg& s, int64_t row0, int nrows,
+                                            bool zero_only, int tid, int nthr) {
   const int lpr = 1 << d.lpr_shift;
   const int rp = nthr >> d.lpr_shift;  // rows per pass
-  int lane, rsub;
-  if (ROWFAST) {
-    rsub = tid % rp;
-    lane = tid / rp;
-  } else {
-    lane = tid & (lpr - 1);
-    rsub = tid >> d.lpr_shift;
-  }
-  const int64_t nvec = d.inner / V;
+  const int rsub = tid % rp, lane = tid / rp;
+  const int64_t nvec = d.inner;
   T* __restrict__ f = static_cast<T*>(d.field);
   const int kind = zero_only ? (int)SEG_ZERO : s.kind;
   const bool add_b = !zero_only && s.has_b;
+  const bool narrow = kind == SEG_ELL && s.width <= 4;
   for (int r = rsub; r < nrows; r += rp) {
     const int64_t row = row0 + r;
     uint32_t q = (uint32_t)row;
@@ -162,22 +163,55 @@ __device__ __forceinline__ void run_tile(const PlanDesc& d, const DevSeg& s, int
     }
     const T* bp = nullptr;
     if (add_b) bp = static_cast<const T*>(d.bval) + s.brow + row * s.b_inner;
-    for (int64_t v = lane; v < nvec; v += lpr) {
-      const int64_t l = v * V;
-      Pack<T, V> y;
-      if (kind == SEG_ZERO) {
+    int32_t col[4] = {-1, -1, -1, -1};
+    T wt[4] = {T(0), T(0), T(0), T(0)};
+    if (narrow) {
+      const int64_t e0 = s.tab + row * s.width;
 #pragma unroll
-        for (int i = 0; i < V; ++i) y.v[i] = T(0);
-      } else if (kind == SEG_MAP) {
-        T sign;
-        const int64_t sl = rot_slot<T>(d, s.rot, l, sign);
-        const T w = T(s.w) * sign;
-        Pack<T, V> x = ldv<T, V>(f + src * d.cs + sl * d.ls);
+      for (int m = 0; m < 4; ++m)
+        if (m < s.width) {
+          col[m] = d.ell_col[e0 + m];
+          wt[m] = static_cast<const T*>(d.ell_val)[e0 + m];
+        }
+    }
+    for (int64_t v0 = lane; v0 < nvec; v0 += (int64_t)lpr * PB) {
+      int64_t l[PB], sl[PB];
+      T sign[PB];
+      bool ok[PB];
 #pragma unroll
-        for (int i = 0; i < V; ++i) y.v[i] = w * x.v[i];
+      for (int u = 0; u < PB; ++u) {
+        const int64_t v = v0 + (int64_t)u * lpr;
+        ok[u] = v < nvec;
+        l[u] = ok[u] ? v : v0;
+        sign[u] = T(1);
+        sl[u] = (kind == SEG_MAP || kind == SEG_ELL || kind == SEG_CSR) ? rot_slot<T>(d, s.rot, l[u], sign[u]) : l[u];
+      }
+      T y[PB];
+      if (kind == SEG_MAP) {
+        T x[PB];
+#pragma unroll
+        for (int u = 0; u < PB; ++u) x[u] = f[src * d.cs + sl[u] * d.ls];
+#pragma unroll
+        for (int u = 0; u < PB; ++u) y[u] = (T(s.w) * sign[u]) * x[u];
+      } else if (narrow) {
+        T x[PB][4];
+#pragma unroll
+        for (int u = 0; u < PB; ++u)
+#pragma unroll
+          for (int m = 0; m < 4; ++m) x[u][m] = col[m] >= 0 ? f[(int64_t)col[m] * d.cs + sl[u] * d.ls] : T(0);
+#pragma unroll
+        for (int u = 0; u < PB; ++u) {
+          T acc = T(0);
+          bool first = true;
+#pragma unroll
+          for (int m = 0; m < 4; ++m)
+            if (col[m] >= 0) {
+              acc = first ? wt[m] * x[u][m] : fma(wt[m], x[u][m], acc);
+              first = false;
+            }
+          y[u] = sign[u] * acc;
+        }
       } else if (kind == SEG_ELL || kind == SEG_CSR) {
-        T sign;
-        const int64_t sl = rot_slot<T>(d, s.rot, l, sign);
         int64_t e0, e1;
         const int32_t* cols;
         const T* vals;
@@ -192,46 +226,37 @@ __device__ __forceinline__ void run_tile(const PlanDesc& d, const DevSeg& s, int
           cols = d.csr_col;
           vals = static_cast<const T*>(d.csr_val);
         }
-        Pack<T, V> acc;
-        bool first = true;
+        T acc[PB];
 #pragma unroll
-        for (int i = 0; i < V; ++i) acc.v[i] = T(0);
+        for (int u = 0; u < PB; ++u) acc[u] = T(0);
+        bool first = true;
         for (int64_t e = e0; e < e1; ++e) {
           const int32_t c = cols[e];
           if (c < 0) continue;
           const T w = vals[e];
-          Pack<T, V> x = ldv<T, V>(f + (int64_t)c * d.cs + sl * d.ls);
-          if (first) {
+          T x[PB];
 #pragma unroll
-            for (int i = 0; i < V; ++i) acc.v[i] = w * x.v[i];
-            first = false;
-          } else {
+          for (int u = 0; u < PB; ++u) x[u] = f[(int64_t)c * d.cs + sl[u] * d.ls];
 #pragma unroll
-            for (int i = 0; i < V; ++i) acc.v[i] = fma(w, x.v[i], acc.v[i]);
-          }
+          for (int u = 0; u < PB; ++u) acc[u] = first ? w * x[u] : fma(w, x[u], acc[u]);
+          first = false;
         }
 #pragma unroll
-        for (int i = 0; i < V; ++i) y.v[i] = sign * acc.v[i];
-      } else {  // SEG_VEC: b only
+        for (int u = 0; u < PB; ++u) y[u] = sign[u] * acc[u];
+      } else {  // zero rows, or b-only rows
 #pragma unroll
-        for (int i = 0; i < V; ++i) y.v[i] = T(0);
+        for (int u = 0; u < PB; ++u) y[u] = T(0);
       }
       if (add_b) {
-        if (s.b_inner == 1) {
-          const T bb = bp[0];
 #pragma unroll
-          for (int i = 0; i < V; ++i) y.v[i] = (kind == SEG_VEC) ? bb : y.v[i] + bb;
-        } else {
-#pragma unroll
-          for (int i = 0; i < V; ++i) y.v[i] = (kind == SEG_VEC) ? bp[l + i] : y.v[i] + bp[l + i];
+        for (int u = 0; u < PB; ++u) {
+          const T bb = s.b_inner == 1 ? bp[0] : bp[l[u]];
+          y[u] = (kind == SEG_VEC) ? bb : y[u] + bb;
         }
       }
-      if (ROWFAST) {
 #pragma unroll
-        for (int i = 0; i < V; ++i) f[dst * d.cs + (l + i) * d.ls] = y.v[i];
-      } else {
-        stv<T, V, false>(f + dst * d.cs + l * d.ls, y);
-      }
+      for (int u = 0; u < PB; ++u)
+        if (ok[u]) f[dst * d.cs + l[u] * d.ls] = y[u];
     }
   }
 }
@@ -465,13 +490,13 @@ __global__ __launch_bounds__(256) void k_apply_rows(PlanDesc d, const RowTile* _
   }
 }
 
-template <typename T, int V, bool ROWFAST>
-__global__ __launch_bounds__(256) void k_apply(PlanDesc d, const DevTile* __restrict__ tiles, int ntiles,
-                                                int zero_only) {
+template <typename T>
+__global__ __launch_bounds__(256) void k_apply_pm(PlanDesc d, const DevTile* __restrict__ tiles, int ntiles,
+                                                   int zero_only) {
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const DevTile tl = tiles[t];
     const DevSeg s = d.segs[tl.seg];
-    run_tile<T, V, ROWFAST>(d, s, tl.row0, tl.nrows, zero_only != 0, threadIdx.x, blockDim.x);
+    run_tile_pm<T>(d, s, tl.row0, tl.nrows, zero_only != 0, threadIdx.x, blockDim.x);
   }
 }
 
@@ -1200,7 +1225,7 @@ static void launch_apply_t(const Plan& p, const PlanDesc& d, hipStream_t st, boo
   const int blk = p.tune.block;
   const int z = zero_only ? 1 : 0;
   if (p.layout.order == HBC_PLANE_MAJOR) {
-    hipLaunchKernelGGL((k_apply<T, 1, true>), dim3(grid), dim3(blk), 0, st, d, p.d_tiles, nt, z);
+    hipLaunchKernelGGL((k_apply_pm<T>), dim3(grid), dim3(blk), 0, st, d, p.d_tiles, nt, z);
   } else {
     launch_rows<T>(d, st, grid, blk, p.d_rtiles, nt, z);
   }

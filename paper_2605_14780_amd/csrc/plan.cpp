@@ -573,7 +573,10 @@ hbc_tune default_tune(const Plan& plan) {
     int64_t nacc = (nvec + plan.unroll - 1) / plan.unroll;
     t.lanes_per_row = (int32_t)std::min<int64_t>(t.block, pow2_ceil(nacc));
   } else {
-    t.lanes_per_row = 1;
+    // plane-major: 8 planes per thread and batch, up to 16 thread sets over
+    // the planes (16 consecutive rows per wavefront and plane)
+    const int64_t sets = (plan.layout.inner + 7) / 8;
+    t.lanes_per_row = (int32_t)std::min<int64_t>(16, pow2_ceil(sets));
   }
   const int64_t rows_per_pass = t.block / t.lanes_per_row;
   // Short tiles keep many workgroups in flight (the apply is latency bound per
@@ -581,7 +584,9 @@ hbc_tune default_tune(const Plan& plan) {
   // row group when groups take contiguous runs of rows, else about 4096 tiles
   // in all.
   int64_t rpt;
-  if (t.lanes_per_row >= CHUNK_LPR) {
+  if (plan.layout.order != HBC_POINT_MAJOR && t.lanes_per_row > 1) {
+    rpt = rows_per_pass;  // one pass of rows over all planes per tile
+  } else if (t.lanes_per_row >= CHUNK_LPR) {
     rpt = rows_per_pass * 4;
   } else {
     rpt = std::max<int64_t>(rows / 4096, rows_per_pass);
