@@ -33,7 +33,9 @@
  *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  Apply
  *    calls are asynchronous on that stream.
  *  - Plans are immutable after creation (apart from tuning), so applies on
- *    different streams may run concurrently on different fields.
+ *    different streams may run concurrently on different fields.  The one
+ *    exception is the adjoint: calls of hbc_apply_adjoint on one plan must not
+ *    overlap in time (see there).
  *  - destroy(NULL) is a no-op.
  */
 #ifndef HBC_H
@@ -235,8 +237,14 @@ int hbc_plan_set_tune(hbc_plan* plan, const hbc_tune* t);
 int hbc_apply(const hbc_plan* plan, void* field, int64_t nelem, void* stream);
 /* Adjoint, in place on `grad` (device, a full field of output gradients):
  * data cells += A^T * (covered ghost gradients), then covered ghost gradients
- * := 0 (the vector-Jacobian product of hbc_apply).  Deterministic: every data
- * value is summed by one thread in ascending ghost order. */
+ * := 0 (the vector-Jacobian product of hbc_apply; Sec. III-B's F is affine, so
+ * its Jacobian is A).  Deterministic: every data value is summed by one thread
+ * in ascending ghost order.  One launch: a ghost row that several workgroups
+ * read is zeroed by the last of them, found with a per-row counter of reader
+ * workgroups that the plan owns and every call restores; adjoint calls on one
+ * plan must therefore not overlap in time (serialise them on one stream).
+ * The first call builds the transposed tables (allocates; not inside graph
+ * capture: hbc_graph_create with HBC_OP_ADJOINT builds them first). */
 int hbc_apply_adjoint(const hbc_plan* plan, void* grad, int64_t nelem, void* stream);
 /* Time `reps` applies captured in one HIP graph on `stream`; *ms receives the
  * mean milliseconds per apply (device events around the graph launch). */
