@@ -27,13 +27,18 @@ What it computes (Mat2Boundary, arXiv 2605.14780):
                     padding; Sec. IV-C, BC writes feed the inner operator).
 * ``dense``         brute-force dense A on tiny grids, evaluated entry by entry
                     from the definitions without the sparse assembly.
+* ``averaging``     block-edge averaging of co-located points (data rows,
+                    Sec. III-B), on a vertex-centred cubed sphere, sets found
+                    by 3-D position; applied together with the ghost rows, all
+                    rows reading the input field.
 
 Pins (in ``tests/test_oracle_*.py``, run with ``-m "not gpu"``) tie each part
 to something other than itself: ``numpy.pad`` for zero/circular/symmetric
 maps, the Alg. 1 rotated map, cubic reproduction and fourth-order convergence
 of the Lagrange rows, a solid-body-rotation vector field for the component
-rotation, the closed form of the 27-point operator on a constant field, and
-the dot-product identity for the adjoint.
+rotation, the closed form of the 27-point operator on a constant field, the
+dot-product identity for the adjoint, and the cube's vertex count and
+edge/corner sharing for the averaging sets.
 """
 from .grid import Grid, Box  # noqa: F401
 from .operator import (  # noqa: F401
