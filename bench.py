@@ -272,6 +272,38 @@ def extra_c384_plane_major(ctx, hb, torch, tm):
     return out
 
 
+def extra_edge_average(ctx, hb, torch, tm):
+    """Vertex-centred C384 (385 points per side), h 3, 256 values per point, FP64:
+    rotated ghost copies plus block-edge averaging of the co-located boundary
+    points (data rows, staged through scratch) vs the ghost copies alone."""
+    import synthinputs
+    Np, h, I = 385, 3, 256
+    W = Np + 2 * h
+    data = synthinputs.cs_sh_field_torch(Np, 4, 64, seed=6)  # point values at cell-centre angles of Np
+    full = torch.zeros((6, W, W, I), dtype=torch.float64, device="cuda")
+    full[:, h:h + Np, h:h + Np, :] = data
+    full = full.reshape(-1)
+    del data
+    out = {}
+    for name, avg in (("ghosts_only", False), ("ghosts_and_edge_average", True)):
+        g = hb.Grid.cubed_sphere(Np, h)
+        p = hb.Program(g)
+        p.cs_add(Np, h, hb.CS_SYNC)
+        if avg:
+            p.cs_add_edge_average(Np)
+        plan = hb.Plan(p, inner=I, dtype=hb.F64)
+        st = plan.stats()
+        fields = [full.clone() for _ in range(3)]
+        gr = hb.ApplyGraph(plan, fields, 60)
+        us = tm(gr.launch, 60)
+        out[name] = {"us_per_apply": us, "rows_data": st["rows_data"], "rows_covered": st["rows_covered"],
+                     "alg_bytes": st["alg_bytes"], "hbm_frac": st["alg_bytes"] / us / 1e3 / HBM_PEAK_GBS}
+        del gr, fields
+        torch.cuda.empty_cache()
+    out["data_rows_extra_us"] = out["ghosts_and_edge_average"]["us_per_apply"] - out["ghosts_only"]["us_per_apply"]
+    return out
+
+
 def extra_c48(ctx, hb, torch, tm):
     from tests.helpers import cs_full_field
     N, h = 48, 3
@@ -482,7 +514,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extras", default="all",
-                    help="comma-separated subset of: c384_plane_major, c48_latency, hpcg_256cube, "
+                    help="comma-separated subset of: c384_plane_major, edge_average_np385, c48_latency, hpcg_256cube, "
                          "batched_64_grids_f32, c768_adjoint")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 256 MiB, 20 times (counter calibration)")
@@ -516,7 +548,8 @@ def main():
     extras = {"c384_warm_cache_us_per_apply": res["warm_us"], "c384_eager_us_per_apply": res["eager_us"],
               "c384_f32": res["f32"]}
     if not args.no_extras:
-        table = (("c384_plane_major", extra_c384_plane_major), ("c48_latency", extra_c48),
+        table = (("c384_plane_major", extra_c384_plane_major), ("edge_average_np385", extra_edge_average),
+                 ("c48_latency", extra_c48),
                  ("hpcg_256cube", extra_hpcg), ("batched_64_grids_f32", extra_batch),
                  ("c768_adjoint", extra_adjoint))
         want = {n for n, _ in table} if args.extras == "all" else set(args.extras.split(","))

@@ -125,6 +125,7 @@ typedef struct {
   double alg_bytes;         /* ghost writes + unique source reads + b + tables, per apply */
   double alg_bytes_adjoint; /* ghost reads + ghost zeroing + source read-modify-write + tables */
   int64_t table_bytes;      /* device bytes held by the plan */
+  int64_t rows_data;        /* data rows written (block-edge averaging), staged through scratch */
 } hbc_stats;
 
 /* Launch shape of the apply kernels (chosen by the plan, changed by tuning). */
@@ -193,6 +194,26 @@ int hbc_program_add_csr(hbc_program* p, const hbc_box* rows, const int64_t* row_
 int hbc_program_add_vector(hbc_program* p, const hbc_box* rows, int64_t ninner, const double* values,
                            int32_t* sub_id);
 
+/* Rows on data cells (Sec. III-B block-edge averaging: where points of
+ * different blocks share one physical location, a sparse Sync sub-matrix with
+ * a few entries per row rewrites those data values).  `rows` lies in one
+ * block's data region; row k has entries row_ptr[k] .. row_ptr[k+1]-1 of
+ * cols (global linear data indices) / vals.  Every row of an apply, ghost or
+ * data, reads the input values: data rows are computed into a plan-owned
+ * scratch buffer and written after the ghost rows have read their sources
+ * (so applies of one such plan must not overlap in time).  Point-major
+ * layouts only; such plans have no adjoint, batch or 27-point consumer
+ * (HBC_EUNSUPPORTED).  Data-row boxes may not overlap each other (HBC_EOVERLAP). */
+int hbc_program_add_data_csr(hbc_program* p, const hbc_box* rows, const int64_t* row_ptr, const int64_t* cols,
+                             const double* vals, int32_t* sub_id);
+/* Block-edge averaging on a vertex-centred cubed sphere (grid from
+ * hbc_cs_grid_create(Np, h): Np points per face side, the boundary points of a
+ * face coincide with its neighbours'): every face-boundary point becomes the
+ * mean of its 2 (cube edge) or 3 (cube corner) co-located copies, entries in
+ * ascending cell order with weight 1/k.  Connectivity from the integer face
+ * frames. */
+int hbc_cs_program_add_edge_average(hbc_program* p, int64_t Np);
+
 /* Cubed-sphere programs on a grid from hbc_cs_grid_create (Sec. II-B; Sec. III-B
  * halo copy and user-defined interpolation; Alg. 1's rotated map).  For each of
  * the 24 face sides one sub-matrix over that side's h x N ghost strip, plus 24
@@ -222,7 +243,9 @@ void hbc_plan_destroy(hbc_plan* plan);
 int hbc_plan_stats(const hbc_plan* plan, hbc_stats* out);
 /* Host evaluation of the compiled row of one ghost cell (no GPU): up to `cap`
  * entries (column cell number, weight) and b for inner slot l (0 if none).
- * *nnz receives the row's entry count, *kind its segment kind (-1 uncovered). */
+ * *nnz receives the row's entry count, *kind its segment kind (0 zero, 1 map,
+ * 2 ELL, 3 CSR, 4 b only, 5 data row (hbc_program_add_data_csr; ghost_cell
+ * may then name a data cell), -1 uncovered). */
 int hbc_plan_row(const hbc_plan* plan, int64_t ghost_cell, int64_t l, int32_t cap, int64_t* cols,
                  double* vals, int32_t* nnz, double* b, int32_t* kind, int32_t* rot);
 int hbc_plan_get_tune(const hbc_plan* plan, hbc_tune* out);

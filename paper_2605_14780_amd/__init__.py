@@ -24,7 +24,7 @@ PLAN_HOST_ONLY = 1
 CS_SYNC, CS_LAGRANGE = 0, 1
 OP_APPLY, OP_ADJOINT = 0, 1
 
-SEG_ZERO, SEG_MAP, SEG_ELL, SEG_CSR, SEG_VEC = 0, 1, 2, 3, 4
+SEG_ZERO, SEG_MAP, SEG_ELL, SEG_CSR, SEG_VEC, SEG_DATA_ROW = 0, 1, 2, 3, 4, 5
 
 
 class HbcError(RuntimeError):
@@ -50,7 +50,8 @@ class StatsT(C.Structure):
     _fields_ = [(n, C.c_int64) for n in (
         "ghost_cells", "rows_covered", "rows_uncovered", "rows_zero", "rows_map", "rows_ell", "rows_csr",
         "rows_vector_only", "rows_with_b", "nnz", "unique_sources", "segments", "tiles", "ghost_values")] + [
-        ("alg_bytes", C.c_double), ("alg_bytes_adjoint", C.c_double), ("table_bytes", C.c_int64)]
+        ("alg_bytes", C.c_double), ("alg_bytes_adjoint", C.c_double), ("table_bytes", C.c_int64),
+        ("rows_data", C.c_int64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -87,6 +88,8 @@ SIGNATURES = {
     "hbc_program_add_ell": (I32, [P, C.POINTER(BoxT), I32, PI64, PD, PI32, PI32]),
     "hbc_program_add_csr": (I32, [P, C.POINTER(BoxT), PI64, PI64, PD, PI32, PI32]),
     "hbc_program_add_vector": (I32, [P, C.POINTER(BoxT), I64, PD, PI32]),
+    "hbc_program_add_data_csr": (I32, [P, C.POINTER(BoxT), PI64, PI64, PD, PI32]),
+    "hbc_cs_program_add_edge_average": (I32, [P, I64]),
     "hbc_cs_program_add": (I32, [P, I64, I64, I32, I32, PI32, PD]),
     "hbc_cart_program_add_halo": (I32, [P, PI32, PI64, I64, I32]),
     "hbc_plan_create": (I32, [P, C.POINTER(LayoutT), I32, U32, C.POINTER(P)]),
@@ -271,6 +274,19 @@ class Program:
         sid = I32()
         _check(lib().hbc_program_add_vector(self._h, C.byref(_box(rows)), ninner, v_p, C.byref(sid)))
         return sid.value
+
+    def add_data_csr(self, rows, row_ptr, cols, vals):
+        """Rows on data cells (block-edge averaging); every row reads the input field."""
+        p_a, p_p = _i64(row_ptr)
+        c_a, c_p = _i64(np.asarray(cols).reshape(-1))
+        v_a, v_p = _f64(np.asarray(vals).reshape(-1))
+        sid = I32()
+        _check(lib().hbc_program_add_data_csr(self._h, C.byref(_box(rows)), p_p, c_p, v_p, C.byref(sid)))
+        return sid.value
+
+    def cs_add_edge_average(self, Np):
+        """Averaging of co-located face-boundary points of a vertex-centred cubed sphere."""
+        _check(lib().hbc_cs_program_add_edge_average(self._h, Np))
 
     def cs_add(self, N, h, mode, vector=False, base=None, w=None):
         if base is None:

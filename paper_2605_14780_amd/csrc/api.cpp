@@ -333,6 +333,32 @@ int hbc_program_add_vector(hbc_program* p, const hbc_box* rows, int64_t ninner, 
   });
 }
 
+int hbc_program_add_data_csr(hbc_program* p, const hbc_box* rows, const int64_t* row_ptr, const int64_t* cols,
+                             const double* vals, int32_t* sub_id) {
+  return guard([&] {
+    need(p && row_ptr, "NULL argument");
+    DataSub s;
+    s.rows = to_box(p->p.grid, rows);
+    const int64_t nr = s.rows.count();
+    need(row_ptr[0] == 0, "row_ptr[0] must be 0");
+    for (int64_t k = 0; k < nr; ++k) need(row_ptr[k + 1] >= row_ptr[k], "row_ptr must be non-decreasing");
+    const int64_t nnz = row_ptr[nr];
+    need(nnz == 0 || (cols && vals), "NULL cols / vals");
+    s.ptr.assign(row_ptr, row_ptr + nr + 1);
+    s.cols.assign(cols, cols + nnz);
+    s.vals.assign(vals, vals + nnz);
+    p->p.dsubs.push_back(std::move(s));
+    if (sub_id) *sub_id = (int32_t)(p->p.dsubs.size() - 1);
+  });
+}
+
+int hbc_cs_program_add_edge_average(hbc_program* p, int64_t Np) {
+  return guard([&] {
+    need(p != nullptr, "NULL argument");
+    cs_add_edge_average(p->p, Np);
+  });
+}
+
 int hbc_cs_program_add(hbc_program* p, int64_t N, int64_t h, int32_t mode, int32_t vector, const int32_t* base,
                        const double* w) {
   return guard([&] {
@@ -455,6 +481,7 @@ int hbc_apply_adjoint(const hbc_plan* plan_c, void* grad, int64_t nelem, void* s
     check_device_plan(plan_c);
     check_field(grad);
     check_size(plan_c, nelem);
+    if (plan_c->p.stats.rows_data > 0) fail(HBC_EUNSUPPORTED, "no adjoint for plans with data rows");
     auto* plan = const_cast<hbc_plan*>(plan_c);
     ensure_csc(plan);
     device_adjoint(plan->p, grad, stream);
@@ -487,7 +514,10 @@ int hbc_graph_create(const hbc_plan* plan, int32_t op, void* const* fields, int6
     need(op == HBC_OP_APPLY || op == HBC_OP_ADJOINT, "op must be HBC_OP_APPLY or HBC_OP_ADJOINT");
     check_size(plan, nelem);
     for (int k = 0; k < nfields; ++k) check_field(fields[k]);
-    if (op == HBC_OP_ADJOINT) ensure_csc(const_cast<hbc_plan*>(plan));
+    if (op == HBC_OP_ADJOINT) {
+      if (plan->p.stats.rows_data > 0) fail(HBC_EUNSUPPORTED, "no adjoint for plans with data rows");
+      ensure_csc(const_cast<hbc_plan*>(plan));
+    }
     auto* g = new hbc_graph;
     try {
       g->g = device_graph_create(plan->p, op, fields, nfields, reps, stream);
@@ -551,6 +581,7 @@ int hbc_batch_create(hbc_plan* const* plans, int32_t n, hbc_batch** out) {
       ps.push_back(&plans[k]->p);
       need(plans[k]->p.dtype == plans[0]->p.dtype, "all plans of a batch need the same dtype");
       need(plans[k]->p.layout.order == HBC_POINT_MAJOR, "batches take point-major plans");
+      if (plans[k]->p.stats.rows_data > 0) fail(HBC_EUNSUPPORTED, "batches do not take plans with data rows");
     }
     auto* b = new hbc_batch;
     b->plans.assign(ps.begin(), ps.end());

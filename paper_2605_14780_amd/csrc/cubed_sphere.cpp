@@ -6,7 +6,10 @@
 // direction of the tangential index are derived here exactly, from integer
 // frame vectors (centre c, tangents e1, e2 with c x e1 = e2), so no floating
 // point decides an index.
+#include <algorithm>
 #include <cstring>
+#include <numeric>
+#include <vector>
 
 #include "hbc_internal.hpp"
 
@@ -227,6 +230,83 @@ void cart_add_halo(Program& p, const int32_t* nb, const int64_t* n, int64_t h, i
               p.subs.push_back(std::move(s));
             }
       }
+}
+
+// Block-edge averaging on a vertex-centred cubed sphere (Np points per face
+// side).  The boundary point at tangential index t of side `side` of face f
+// coincides with the point at t (or Np-1-t when the tangential index runs
+// backwards) of the facing side of the neighbour: the same integer links as
+// the ghost programs.  Co-located points are merged by union-find; every
+// member of a set of k points gets a row with the k members, weight 1/k.
+void cs_add_edge_average(Program& p, int64_t Np) {
+  const Grid& g = p.grid;
+  if (Np < 3) fail(HBC_EINVAL, "edge averaging needs at least 3 points per face side");
+  if (g.nd != 3 || g.blocks.size() != 6 || g.blocks[0].data.extent(1) != Np || g.blocks[0].data.extent(2) != Np)
+    fail(HBC_EINVAL, "program grid is not the cubed-sphere grid of this Np");
+  const int64_t h = -g.blocks[0].full.lo[1];
+  const int64_t W = Np + 2 * h;
+  const int64_t n = 6 * Np * Np;
+  std::vector<int64_t> parent(n);
+  std::iota(parent.begin(), parent.end(), 0);
+  auto find = [&](int64_t a) {
+    while (parent[a] != a) a = parent[a] = parent[parent[a]];
+    return a;
+  };
+  auto point = [&](int f, int side, int64_t t) {
+    int64_t j = 0, i = 0;
+    if (side == LEFT) { j = t; i = 0; }
+    if (side == RIGHT) { j = t; i = Np - 1; }
+    if (side == BOTTOM) { j = 0; i = t; }
+    if (side == TOP) { j = Np - 1; i = t; }
+    return (f * Np + j) * Np + i;
+  };
+  for (int f = 0; f < 6; ++f)
+    for (int side = 0; side < 4; ++side) {
+      SideLink L = link(f, side);
+      for (int64_t t = 0; t < Np; ++t) {
+        const int64_t a = find(point(f, side, t)), b = find(point(L.g, L.gside, L.rev ? Np - 1 - t : t));
+        if (a != b) parent[std::max(a, b)] = std::min(a, b);
+      }
+    }
+  std::vector<std::vector<int64_t>> members(n);
+  for (int64_t q = 0; q < n; ++q) {
+    const int64_t f = q / (Np * Np), j = (q / Np) % Np, i = q % Np;
+    if (i != 0 && i != Np - 1 && j != 0 && j != Np - 1) continue;
+    members[find(q)].push_back(q);
+  }
+  // global linear data index of point q over the box [0,6) x [-h, Np+h)^2
+  auto lin = [&](int64_t q) {
+    const int64_t f = q / (Np * Np), j = (q / Np) % Np, i = q % Np;
+    return (f * W + (j + h)) * W + (i + h);
+  };
+  for (int f = 0; f < 6; ++f) {
+    // the face boundary as 4 disjoint boxes: bottom and top rows, then the
+    // left and right columns without their ends
+    const int64_t boxes[4][4] = {{0, 1, 0, Np}, {Np - 1, Np, 0, Np}, {1, Np - 1, 0, 1}, {1, Np - 1, Np - 1, Np}};
+    for (const auto& bx : boxes) {
+      DataSub ds;
+      ds.rows.nd = 3;
+      ds.rows.lo[0] = f;
+      ds.rows.hi[0] = f + 1;
+      ds.rows.lo[1] = bx[0];
+      ds.rows.hi[1] = bx[1];
+      ds.rows.lo[2] = bx[2];
+      ds.rows.hi[2] = bx[3];
+      ds.ptr.push_back(0);
+      for (int64_t j = bx[0]; j < bx[1]; ++j)
+        for (int64_t i = bx[2]; i < bx[3]; ++i) {
+          const int64_t q = (f * Np + j) * Np + i;
+          const std::vector<int64_t>& m = members[find(q)];
+          if (m.size() < 2) fail(HBC_EINVAL, "internal: a face-boundary point has no co-located copy");
+          for (int64_t c : m) {  // members are in ascending point (= cell) order
+            ds.cols.push_back(lin(c));
+            ds.vals.push_back(1.0 / (double)m.size());
+          }
+          ds.ptr.push_back((int64_t)ds.cols.size());
+        }
+      p.dsubs.push_back(std::move(ds));
+    }
+  }
 }
 
 }  // namespace hbc

@@ -87,9 +87,18 @@ struct Sub {
   std::vector<double> b;
 };
 
+// Rows on data cells (block-edge averaging): CSR over a box of one block's
+// data region, columns as global linear data indices.
+struct DataSub {
+  Box rows;
+  std::vector<int64_t> ptr, cols;
+  std::vector<double> vals;
+};
+
 struct Program {
   Grid grid;
   std::vector<Sub> subs;
+  std::vector<DataSub> dsubs;
   uint32_t flags = 0;
 };
 
@@ -101,7 +110,7 @@ int rot_inverse(int code);
 void rot_matrix(int code, int32_t* R);
 
 // ---- device-facing tables ---------------------------------------------------
-enum SegKind { SEG_ZERO = 0, SEG_MAP = 1, SEG_ELL = 2, SEG_CSR = 3, SEG_VEC = 4 };
+enum SegKind { SEG_ZERO = 0, SEG_MAP = 1, SEG_ELL = 2, SEG_CSR = 3, SEG_VEC = 4, SEG_DATA_ROW = 5 };
 constexpr int SEG_MAXD = 4;
 
 struct alignas(16) DevSeg {
@@ -222,6 +231,11 @@ struct HostTables {
   std::vector<int32_t> row_dst;  // destination cell of every covered row
   std::vector<int32_t> row_src;  // MAP rows: source cell; other rows: 0
   std::vector<RowTile> rtiles;
+  // data rows: destination cells, CSR over data cells (absolute pointers)
+  std::vector<int32_t> dr_cell;
+  std::vector<int64_t> dr_ptr;
+  std::vector<int32_t> dr_col;
+  std::vector<double> dr_val;
 };
 
 struct Layout {
@@ -254,6 +268,11 @@ struct Plan {
   const int32_t* d_csr_col = nullptr;
   const void* d_csr_val = nullptr;
   const void* d_bval = nullptr;
+  const int32_t* d_dr_cell = nullptr;
+  const int64_t* d_dr_ptr = nullptr;
+  const int32_t* d_dr_col = nullptr;
+  const void* d_dr_val = nullptr;
+  void* d_dr_scratch = nullptr;  // rows_data * inner values (own allocation)
   void* d_csc_dev = nullptr;  // allocation holding the adjoint tables
   const int64_t* d_csc_src = nullptr;
   const int64_t* d_csc_ptr = nullptr;
@@ -299,5 +318,6 @@ void cs_add_program(Program& p, int64_t N, int64_t h, int mode, int vector, cons
                     const double* w);
 // Cartesian helpers (cubed_sphere.cpp)
 void cart_add_halo(Program& p, const int32_t* nb, const int64_t* n, int64_t h, int32_t periodic);
+void cs_add_edge_average(Program& p, int64_t Np);
 
 }  // namespace hbc

@@ -481,10 +481,73 @@ __device__ __forceinline__ void rt_tile(const PlanDesc& d, const RowTile& tl, bo
   }
 }
 
+// Data rows (block-edge averaging).  Every row of an apply reads the input
+// field, so data rows are first computed into scratch by extra workgroups of
+// the ghost-row launch (they only read data cells and write scratch), and
+// written by k_data_scatter after it.  A row's entries are read 4 at a time,
+// all loads issued before the ordered sum.  A row group of lpr lanes takes one
+// row; entries are summed in table order (first product, then FMAs), one
+// thread per value.
+struct DataDesc {
+  const int64_t* ptr;
+  const int32_t* col;
+  const void* val;
+  void* scratch;
+  int32_t nrows;
+  int32_t grid;  // workgroups of the launch that gather data rows (0: none)
+};
+
+template <typename T, int V>
+__device__ __forceinline__ void data_gather_rows(const PlanDesc& d, const DataDesc& dd, int wg, int nwg) {
+  const int lpr = 1 << d.lpr_shift;
+  const int ngroups = (int)blockDim.x >> d.lpr_shift;
+  const int lane = threadIdx.x & (lpr - 1), grp = threadIdx.x >> d.lpr_shift;
+  const T* __restrict__ f = static_cast<const T*>(d.field);
+  const T* __restrict__ val = static_cast<const T*>(dd.val);
+  T* __restrict__ scratch = static_cast<T*>(dd.scratch);
+  const int64_t nvec = d.inner / V;
+  for (int r = wg * ngroups + grp; r < dd.nrows; r += nwg * ngroups) {
+    const int64_t e0 = dd.ptr[r], e1 = dd.ptr[r + 1];
+    for (int64_t v = lane; v < nvec; v += lpr) {
+      const int64_t l = v * V;
+      Pack<T, V> acc;
+#pragma unroll
+      for (int i = 0; i < V; ++i) acc.v[i] = T(0);
+      bool first = true;
+      for (int64_t eb = e0; eb < e1; eb += 4) {  // 4 entries' loads in flight, then the ordered sum
+        const int ne = (int)min<int64_t>(4, e1 - eb);
+        T w[4];
+        Pack<T, V> x[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (j < ne) {
+            w[j] = val[eb + j];
+            x[j] = ldv<T, V>(f + (int64_t)dd.col[eb + j] * d.cs + l);
+          }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (j < ne) {
+#pragma unroll
+            for (int i = 0; i < V; ++i) acc.v[i] = first ? w[j] * x[j].v[i] : fma(w[j], x[j].v[i], acc.v[i]);
+            first = false;
+          }
+      }
+      stv<T, V, false>(scratch + (int64_t)r * d.inner + l, acc);
+    }
+  }
+}
+
 template <typename T, int V, int U, bool NT>
 __global__ __launch_bounds__(256) void k_apply_rows(PlanDesc d, const RowTile* __restrict__ tiles, int ntiles,
-                                                    int zero_only) {
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+                                                    int zero_only, DataDesc dd) {
+  // the first dd.grid workgroups gather data rows (dispatched first, they
+  // overlap the ghost-row tiles)
+  if ((int)blockIdx.x < dd.grid) {
+    data_gather_rows<T, V>(d, dd, (int)blockIdx.x, dd.grid);
+    return;
+  }
+  const int main = (int)gridDim.x - dd.grid;
+  for (int t = (int)blockIdx.x - dd.grid; t < ntiles; t += main) {
     const RowTile tl = tiles[t];
     rt_tile<T, V, U, NT>(d, tl, zero_only != 0);
   }
@@ -661,6 +724,27 @@ __global__ __launch_bounds__(256) void k_adjoint(PlanDesc d, AdjDesc a, const Ad
           stv<T, V, NT>(px, x);
         }
       }
+    }
+  }
+}
+
+template <typename T, int V>
+__global__ __launch_bounds__(256) void k_data_scatter(PlanDesc d, const int32_t* __restrict__ cell,
+                                                      const T* __restrict__ scratch, int nrows) {
+  const int lpr = 1 << d.lpr_shift;
+  const int ngroups = (int)blockDim.x >> d.lpr_shift;
+  const int lane = threadIdx.x & (lpr - 1), grp = threadIdx.x >> d.lpr_shift;
+  T* __restrict__ f = static_cast<T*>(d.field);
+  const int64_t nvec = d.inner / V;
+  for (int r = blockIdx.x * ngroups + grp; r < nrows; r += gridDim.x * ngroups) {
+    const int64_t dst = cell[r];
+    for (int64_t v = lane; v < nvec; v += lpr) {
+      const int64_t l = v * V;
+      const Pack<T, V> x = ldv<T, V>(scratch + (int64_t)r * d.inner + l);
+      if (d.nt)
+        stv<T, V, true>(f + dst * d.cs + l, x);
+      else
+        stv<T, V, false>(f + dst * d.cs + l, x);
     }
   }
 }
@@ -1068,6 +1152,8 @@ void device_free_plan(Plan& p) {
   p.d_csc_dev = nullptr;
   if (p.d_al_dev) (void)hipFree(p.d_al_dev);
   p.d_al_dev = nullptr;
+  if (p.d_dr_scratch) (void)hipFree(p.d_dr_scratch);
+  p.d_dr_scratch = nullptr;
   p.d_csc_src = nullptr;
   if (p.d_tiles) (void)hipFree(const_cast<DevTile*>(p.d_tiles));
   p.d_tiles = nullptr;
@@ -1085,6 +1171,10 @@ void device_upload_plan(Plan& p) {
   size_t o_b = pk.reals(T.bval, p.dtype);
   size_t o_rd = pk.vec(T.row_dst);
   size_t o_rs = pk.vec(T.row_src);
+  size_t o_drc = pk.vec(T.dr_cell);
+  size_t o_drp = pk.vec(T.dr_ptr);
+  size_t o_drk = pk.vec(T.dr_col);
+  size_t o_drv = pk.reals(T.dr_val, p.dtype);
   void* dev = nullptr;
   hipError_t e = hipMalloc(&dev, pk.buf.size());
   if (e != hipSuccess) fail(e == hipErrorOutOfMemory ? HBC_ENOMEM : HBC_EHIP, std::string("hipMalloc: ") + hipGetErrorString(e));
@@ -1101,6 +1191,17 @@ void device_upload_plan(Plan& p) {
   p.d_bval = b + o_b;
   p.d_row_dst = reinterpret_cast<const int32_t*>(b + o_rd);
   p.d_row_src = reinterpret_cast<const int32_t*>(b + o_rs);
+  p.d_dr_cell = reinterpret_cast<const int32_t*>(b + o_drc);
+  p.d_dr_ptr = reinterpret_cast<const int64_t*>(b + o_drp);
+  p.d_dr_col = reinterpret_cast<const int32_t*>(b + o_drk);
+  p.d_dr_val = b + o_drv;
+  if (p.stats.rows_data > 0) {
+    void* sc = nullptr;
+    const size_t n = (size_t)p.stats.rows_data * (size_t)p.layout.inner * (p.dtype == HBC_F64 ? 8 : 4);
+    e = hipMalloc(&sc, n);
+    if (e != hipSuccess) fail(e == hipErrorOutOfMemory ? HBC_ENOMEM : HBC_EHIP, std::string("hipMalloc: ") + hipGetErrorString(e));
+    p.d_dr_scratch = sc;
+  }
   device_upload_tiles(p);
   if (p.st_ok) {
     void* si = nullptr;
@@ -1187,57 +1288,91 @@ void device_upload_csc(Plan& p) {
 }
 
 template <typename T, int V, int U>
-static void launch_rows_vu(const PlanDesc& d, hipStream_t st, int grid, int blk, const RowTile* tiles, int nt, int z) {
+static void launch_rows_vu(const PlanDesc& d, hipStream_t st, int grid, int blk, const RowTile* tiles, int nt, int z,
+                           const DataDesc& dd) {
   if (d.nt)
-    hipLaunchKernelGGL((k_apply_rows<T, V, U, true>), dim3(grid), dim3(blk), 0, st, d, tiles, nt, z);
+    hipLaunchKernelGGL((k_apply_rows<T, V, U, true>), dim3(grid + dd.grid), dim3(blk), 0, st, d, tiles, nt, z, dd);
   else
-    hipLaunchKernelGGL((k_apply_rows<T, V, U, false>), dim3(grid), dim3(blk), 0, st, d, tiles, nt, z);
+    hipLaunchKernelGGL((k_apply_rows<T, V, U, false>), dim3(grid + dd.grid), dim3(blk), 0, st, d, tiles, nt, z, dd);
 }
 
 // point-major row tiles: one instance per (vec, unroll) a plan can select
 template <typename T>
-static void launch_rows(const PlanDesc& d, hipStream_t st, int grid, int blk, const RowTile* tiles, int nt, int z) {
+static void launch_rows(const PlanDesc& d, hipStream_t st, int grid, int blk, const RowTile* tiles, int nt, int z,
+                        const DataDesc& dd) {
   if (sizeof(T) == 4) {
     if (d.vec == 4)
-      launch_rows_vu<T, (sizeof(T) == 4 ? 4 : 2), 1>(d, st, grid, blk, tiles, nt, z);
+      launch_rows_vu<T, (sizeof(T) == 4 ? 4 : 2), 1>(d, st, grid, blk, tiles, nt, z, dd);
     else if (d.vec == 2)
-      d.unroll >= 2 ? launch_rows_vu<T, 2, 2>(d, st, grid, blk, tiles, nt, z)
-                    : launch_rows_vu<T, 2, 1>(d, st, grid, blk, tiles, nt, z);
+      d.unroll >= 2 ? launch_rows_vu<T, 2, 2>(d, st, grid, blk, tiles, nt, z, dd)
+                    : launch_rows_vu<T, 2, 1>(d, st, grid, blk, tiles, nt, z, dd);
     else if (d.unroll >= 4)
-      launch_rows_vu<T, 1, 4>(d, st, grid, blk, tiles, nt, z);
+      launch_rows_vu<T, 1, 4>(d, st, grid, blk, tiles, nt, z, dd);
     else
-      d.unroll >= 2 ? launch_rows_vu<T, 1, 2>(d, st, grid, blk, tiles, nt, z)
-                    : launch_rows_vu<T, 1, 1>(d, st, grid, blk, tiles, nt, z);
+      d.unroll >= 2 ? launch_rows_vu<T, 1, 2>(d, st, grid, blk, tiles, nt, z, dd)
+                    : launch_rows_vu<T, 1, 1>(d, st, grid, blk, tiles, nt, z, dd);
   } else {
     if (d.vec >= 2)
-      launch_rows_vu<T, 2, 1>(d, st, grid, blk, tiles, nt, z);
+      launch_rows_vu<T, 2, 1>(d, st, grid, blk, tiles, nt, z, dd);
     else
-      d.unroll >= 2 ? launch_rows_vu<T, 1, 2>(d, st, grid, blk, tiles, nt, z)
-                    : launch_rows_vu<T, 1, 1>(d, st, grid, blk, tiles, nt, z);
+      d.unroll >= 2 ? launch_rows_vu<T, 1, 2>(d, st, grid, blk, tiles, nt, z, dd)
+                    : launch_rows_vu<T, 1, 1>(d, st, grid, blk, tiles, nt, z, dd);
   }
 }
 
 template <typename T>
 static void launch_apply_t(const Plan& p, const PlanDesc& d, hipStream_t st, bool zero_only) {
   const int nt = (int)p.host.tiles.size();
-  if (nt == 0) return;
   const int grid = p.tune.persistent > 0 ? std::min(p.tune.persistent, nt) : nt;
   const int blk = p.tune.block;
   const int z = zero_only ? 1 : 0;
+  DataDesc dd{p.d_dr_ptr, p.d_dr_col, p.d_dr_val, p.d_dr_scratch, 0, 0};
+  if (!zero_only && p.stats.rows_data > 0) {
+    // data rows gather into scratch in extra workgroups of this launch
+    const int groups = blk / p.tune.lanes_per_row;
+    dd.nrows = (int32_t)p.stats.rows_data;
+    dd.grid = (int32_t)std::min<int64_t>((p.stats.rows_data + groups - 1) / groups, 4096);
+  }
+  if (grid + dd.grid == 0) return;
   if (p.layout.order == HBC_PLANE_MAJOR) {
-    hipLaunchKernelGGL((k_apply_pm<T>), dim3(grid), dim3(blk), 0, st, d, p.d_tiles, nt, z);
+    if (grid > 0) hipLaunchKernelGGL((k_apply_pm<T>), dim3(grid), dim3(blk), 0, st, d, p.d_tiles, nt, z);
   } else {
-    launch_rows<T>(d, st, grid, blk, p.d_rtiles, nt, z);
+    launch_rows<T>(d, st, grid, blk, p.d_rtiles, nt, z, dd);
   }
   HIP_CHECK(hipGetLastError());
 }
 
+template <typename T, int V>
+static void launch_data_scatter(const Plan& p, const PlanDesc& d, hipStream_t st) {
+  const int n = (int)p.stats.rows_data;
+  const int blk = p.tune.block;
+  const int groups = blk >> d.lpr_shift;
+  const int grid = (int)std::min<int64_t>((n + groups - 1) / groups, 4096);
+  hipLaunchKernelGGL((k_data_scatter<T, V>), dim3(grid), dim3(blk), 0, st, d, p.d_dr_cell,
+                     static_cast<const T*>(p.d_dr_scratch), n);
+  HIP_CHECK(hipGetLastError());
+}
+
+template <typename T>
+static void launch_data_scatter_v(const Plan& p, const PlanDesc& d, hipStream_t st) {
+  if (sizeof(T) == 4 && p.vec == 4)
+    launch_data_scatter<T, (sizeof(T) == 4 ? 4 : 2)>(p, d, st);
+  else if (p.vec >= 2)
+    launch_data_scatter<T, 2>(p, d, st);
+  else
+    launch_data_scatter<T, 1>(p, d, st);
+}
+
 void device_apply(const Plan& p, void* field, void* stream, bool zero_only) {
   PlanDesc d = make_desc(p, field);
-  if (p.dtype == HBC_F64)
+  const bool data_rows = !zero_only && p.stats.rows_data > 0;
+  if (p.dtype == HBC_F64) {
     launch_apply_t<double>(p, d, S(stream), zero_only);
-  else
+    if (data_rows) launch_data_scatter_v<double>(p, d, S(stream));
+  } else {
     launch_apply_t<float>(p, d, S(stream), zero_only);
+    if (data_rows) launch_data_scatter_v<float>(p, d, S(stream));
+  }
 }
 
 template <typename T, int V>

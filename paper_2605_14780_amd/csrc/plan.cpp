@@ -515,6 +515,33 @@ void compile_plan(const Program& prog, const Layout& lay, int dtype, Plan& plan)
     }
   }
 
+  // 3b. data rows (block-edge averaging): validated like the ghost rows, but
+  //     inside a data region; staged through scratch by the apply
+  for (size_t a = 0; a < prog.dsubs.size(); ++a) {
+    const DataSub& ds = prog.dsubs[a];
+    if (ds.rows.empty()) continue;
+    int b = g.owner(ds.rows.lo);
+    if (b < 0 || !g.blocks[b].data.contains(ds.rows))
+      fail(HBC_ERANGE, "data-row box does not lie in one block's data region");
+    for (size_t c = a + 1; c < prog.dsubs.size(); ++c)
+      if (intersects(ds.rows, prog.dsubs[c].rows)) fail(HBC_EOVERLAP, "overlapping data-row boxes");
+    for_box(ds.rows, [&](const int64_t* r, int64_t k) {
+      T.dr_cell.push_back((int32_t)g.cell(b, r));
+      T.dr_ptr.push_back((int64_t)T.dr_col.size());
+      for (int64_t e = ds.ptr[k]; e < ds.ptr[k + 1]; ++e) {
+        const int64_t cell = data_cell_of_linear(g, ds.cols[e]);
+        T.dr_col.push_back((int32_t)cell);
+        T.dr_val.push_back(ds.vals[e]);
+        sources.push_back(cell);
+        st.nnz++;
+      }
+    });
+  }
+  T.dr_ptr.push_back((int64_t)T.dr_col.size());
+  st.rows_data = (int64_t)T.dr_cell.size();
+  if (st.rows_data > 0 && lay.order != HBC_POINT_MAJOR)
+    fail(HBC_EUNSUPPORTED, "data rows need the point-major layout");
+
   // 4. statistics
   st.ghost_cells = g.ghost_cells();
   st.rows_covered = row_base;
@@ -528,8 +555,9 @@ void compile_plan(const Program& prog, const Layout& lay, int dtype, Plan& plan)
   const double es = dtype == HBC_F64 ? 8.0 : 4.0;
   const double I = (double)lay.inner;
   double tables = (double)T.ell_col.size() * (4.0 + es) + (double)T.csr_col.size() * (4.0 + es) +
-                  (double)T.csr_ptr.size() * 8.0 + (double)T.bval.size() * es;
-  st.alg_bytes = es * I * (double)(st.rows_covered + st.unique_sources) + tables;
+                  (double)T.csr_ptr.size() * 8.0 + (double)T.bval.size() * es +
+                  (double)T.dr_col.size() * (4.0 + es) + (double)T.dr_cell.size() * 12.0;
+  st.alg_bytes = es * I * (double)(st.rows_covered + st.rows_data + st.unique_sources) + tables;
   // adjoint: read + zero the covered ghosts, read-modify-write the sources,
   // one (ghost, weight, rotation) entry per nonzero and a pointer per source
   st.alg_bytes_adjoint = es * I * (2.0 * (double)st.rows_covered + 2.0 * (double)st.unique_sources) +
@@ -813,6 +841,7 @@ void compute_stencil_info(Plan& p) {
   auto no = [&](const char* why) { p.st_reason = why; };
   if (g.nd != 4) return no("the 27-point consumer needs a Cartesian block grid (block, z, y, x)");
   if (p.layout.inner != 1) return no("the 27-point consumer needs inner == 1");
+  if (p.stats.rows_data > 0) return no("the 27-point consumer does not take data rows");
   const Block& B0 = g.blocks[0];
   int64_t n[3];
   for (int d = 0; d < 3; ++d) n[d] = B0.data.extent(d + 1);
@@ -901,6 +930,18 @@ int plan_row(const Plan& plan, int64_t cell, int64_t l, int cap, int64_t* cols, 
   for (size_t k = 0; k < g.blocks.size(); ++k)
     if (cell >= g.blocks[k].first_cell && cell < g.blocks[k].first_cell + g.blocks[k].cells) blk = (int)k;
   if (blk < 0) return HBC_OK;
+  for (size_t k = 0; k < T.dr_cell.size(); ++k) {
+    if (T.dr_cell[k] != cell) continue;  // a data row (kind SEG_DATA_ROW)
+    *kind = SEG_DATA_ROW;
+    int n = 0;
+    for (int64_t e = T.dr_ptr[k]; e < T.dr_ptr[k + 1]; ++e, ++n)
+      if (n < cap) {
+        cols[n] = T.dr_col[e];
+        vals[n] = T.dr_val[e];
+      }
+    *nnz = n;
+    return HBC_OK;
+  }
   int64_t c[HBC_MAX_DIM];
   int64_t off = cell - g.blocks[blk].first_cell;
   for (int d = 0; d < g.nd; ++d) {

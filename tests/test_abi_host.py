@@ -168,3 +168,61 @@ def test_zero_rest_partition_covers_ghost_ring():
     st = hb.Plan(p, host_only=True).stats()
     assert st["rows_uncovered"] == 0
     assert st["rows_map"] == 10 and st["rows_zero"] == 81 - 25 - 10
+
+
+# ---- data rows: block-edge averaging -------------------------------------------------------
+@pytest.mark.parametrize("Np,h", [(4, 1), (6, 2), (11, 3)])
+def test_edge_average_plan_equals_oracle(Np, h):
+    from oracle import averaging as oav
+    g = hb.Grid.cubed_sphere(Np, h)
+    p = hb.Program(g)
+    p.cs_add_edge_average(Np)
+    plan = hb.Plan(p, inner=3, host_only=True)
+    st = plan.stats()
+    assert st["rows_data"] == 24 * Np - 24
+    og = ocs.grid(Np, h)
+    dop = oav.assemble_data(og, oav.edge_average_subs(Np))
+    S = dop.S.toarray()
+    for r in np.nonzero(dop.rows)[0]:
+        cell = int(og.data_cells[r])
+        kind, cols, vals, b, rot = plan.row(cell)
+        assert kind == hb.SEG_DATA_ROW
+        ref = {int(og.data_cells[j]): S[r, j] for j in np.nonzero(S[r])[0]}
+        assert dict(zip(cols, vals)) == ref, (cell, cols, vals, ref)
+    # interior points are no rows
+    inner = og.data_cells[~dop.rows][0]
+    assert plan.row(int(inner))[0] == -1
+
+
+def test_data_rows_validation():
+    Np, h = 5, 1
+    g = hb.Grid.cubed_sphere(Np, h)
+    W = Np + 2 * h
+
+    def lin(f, j, i):
+        return (f * W + (j + h)) * W + (i + h)
+
+    p = hb.Program(g)
+    p.add_data_csr([(0, 1), (0, 1), (0, 2)], [0, 1, 2], [lin(0, 1, 1), lin(0, 1, 1)], [1.0, 1.0])
+    p.add_data_csr([(0, 1), (0, 1), (1, 3)], [0, 1, 2], [lin(0, 1, 1), lin(0, 1, 1)], [1.0, 1.0])
+    with pytest.raises(hb.HbcError) as e:
+        hb.Plan(p, inner=1, host_only=True)
+    assert e.value.code == hb.EOVERLAP
+    p = hb.Program(g)
+    p.add_data_csr([(0, 1), (-1, 0), (0, 1)], [0, 1], [lin(0, 1, 1)], [1.0])  # a ghost row
+    with pytest.raises(hb.HbcError) as e:
+        hb.Plan(p, inner=1, host_only=True)
+    assert e.value.code == hb.ERANGE
+    p = hb.Program(g)
+    p.add_data_csr([(0, 1), (0, 1), (0, 1)], [0, 1], [lin(0, -1, 0)], [1.0])  # a ghost column
+    with pytest.raises(hb.HbcError) as e:
+        hb.Plan(p, inner=1, host_only=True)
+    assert e.value.code == hb.ERANGE
+    p = hb.Program(g)
+    p.cs_add_edge_average(Np)
+    with pytest.raises(hb.HbcError) as e:
+        hb.Plan(p, inner=2, order=hb.PLANE_MAJOR, host_only=True)
+    assert e.value.code == hb.EUNSUPPORTED
+    with pytest.raises(hb.HbcError) as e:
+        hb.Program(hb.Grid.cubed_sphere(Np + 1, h)).cs_add_edge_average(Np)
+    assert e.value.code == hb.EINVAL
