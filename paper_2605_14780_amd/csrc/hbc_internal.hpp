@@ -182,6 +182,8 @@ constexpr int ADJ_MAXW = 8;
 // contiguous runs of rows (neighbouring rows share sources); narrower groups
 // take rows round-robin (neighbouring lanes write neighbouring cells).
 constexpr int CHUNK_LPR = 8;
+// Rows a row group handles per batch (all their loads issued together).
+inline int rows_per_batch(int lanes_per_row) { return lanes_per_row >= 128 ? 2 : 4; }
 
 // LDS-staged adjoint (point-major plans).  A tile is a run of consecutive
 // sources; the distinct ghost rows its entries read (at most ADJ_LDS_ROWS,

@@ -270,15 +270,14 @@ __device__ __forceinline__ void run_tile_pm(const PlanDesc& d, const DevSeg& s, 
 // groups of >= CHUNK_LPR lanes a row group takes a contiguous run of rows,
 // otherwise rows are dealt round-robin so that neighbouring lanes write
 // neighbouring cells.
-#ifndef HBC_ROWS_PER_BATCH
-#define HBC_ROWS_PER_BATCH 4
-#endif
-constexpr int RB = HBC_ROWS_PER_BATCH;  // rows per batch of a row group
+// RB (rows per batch of a row group) is rows_per_batch(lanes per row): 2 for
+// rows of >= 128 lanes (>= 2 KiB: the batch is already many loads, and short
+// tiles keep more workgroups in flight), else 4.
 
 // U > 1: a lane carries U accesses of V elements per row, lpr apart (rows
 // whose length is not a multiple of a 16-byte vector still keep 16 bytes of
 // loads per lane and source in flight, and every access stays coalesced).
-template <typename T, int V, int U, bool NT>
+template <typename T, int V, int U, bool NT, int RB>
 __device__ __forceinline__ void rt_tile(const PlanDesc& d, const RowTile& tl, bool zero_only) {
   const int lpr = 1 << d.lpr_shift;
   const int ngroups = (int)blockDim.x >> d.lpr_shift;
@@ -537,7 +536,7 @@ __device__ __forceinline__ void data_gather_rows(const PlanDesc& d, const DataDe
   }
 }
 
-template <typename T, int V, int U, bool NT>
+template <typename T, int V, int U, bool NT, int RB>
 __global__ __launch_bounds__(256) void k_apply_rows(PlanDesc d, const RowTile* __restrict__ tiles, int ntiles,
                                                     int zero_only, DataDesc dd) {
   // the first dd.grid workgroups gather data rows (dispatched first, they
@@ -549,7 +548,7 @@ __global__ __launch_bounds__(256) void k_apply_rows(PlanDesc d, const RowTile* _
   const int main = (int)gridDim.x - dd.grid;
   for (int t = (int)blockIdx.x - dd.grid; t < ntiles; t += main) {
     const RowTile tl = tiles[t];
-    rt_tile<T, V, U, NT>(d, tl, zero_only != 0);
+    rt_tile<T, V, U, NT, RB>(d, tl, zero_only != 0);
   }
 }
 
@@ -568,18 +567,18 @@ template <typename T, bool NT>
 __device__ __forceinline__ void rt_tile_any(const PlanDesc& d, const RowTile& tl) {
   if (sizeof(T) == 4) {
     if (d.vec == 4)
-      rt_tile<T, (sizeof(T) == 4 ? 4 : 2), 1, NT>(d, tl, false);
+      rt_tile<T, (sizeof(T) == 4 ? 4 : 2), 1, NT, 4>(d, tl, false);
     else if (d.vec == 2)
-      d.unroll >= 2 ? rt_tile<T, 2, 2, NT>(d, tl, false) : rt_tile<T, 2, 1, NT>(d, tl, false);
+      d.unroll >= 2 ? rt_tile<T, 2, 2, NT, 4>(d, tl, false) : rt_tile<T, 2, 1, NT, 4>(d, tl, false);
     else if (d.unroll >= 4)
-      rt_tile<T, 1, 4, NT>(d, tl, false);
+      rt_tile<T, 1, 4, NT, 4>(d, tl, false);
     else
-      d.unroll >= 2 ? rt_tile<T, 1, 2, NT>(d, tl, false) : rt_tile<T, 1, 1, NT>(d, tl, false);
+      d.unroll >= 2 ? rt_tile<T, 1, 2, NT, 4>(d, tl, false) : rt_tile<T, 1, 1, NT, 4>(d, tl, false);
   } else {
     if (d.vec >= 2)
-      rt_tile<T, 2, 1, NT>(d, tl, false);
+      rt_tile<T, 2, 1, NT, 4>(d, tl, false);
     else
-      d.unroll >= 2 ? rt_tile<T, 1, 2, NT>(d, tl, false) : rt_tile<T, 1, 1, NT>(d, tl, false);
+      d.unroll >= 2 ? rt_tile<T, 1, 2, NT, 4>(d, tl, false) : rt_tile<T, 1, 1, NT, 4>(d, tl, false);
   }
 }
 
@@ -980,7 +979,7 @@ __global__ __launch_bounds__(256) void k_stencil27(const T* __restrict__ x, T* _
   const int ntx = (st.nx + ST_TX - 1) / ST_TX, nty = (st.ny + ST_TY - 1) / ST_TY, nzc = (st.nz + ST_ZC - 1) / ST_ZC;
   const int nst = ntx * nty * nzc * st.nblk;
   if ((int)blockIdx.x >= nst) {
-    for (int t = blockIdx.x - nst; t < bc_nt; t += bc_grid) rt_tile<T, V, 1, false>(d, bc_tiles[t], false);
+    for (int t = blockIdx.x - nst; t < bc_nt; t += bc_grid) rt_tile<T, V, 1, false, 4>(d, bc_tiles[t], false);
     return;
   }
   int bid;
@@ -1290,10 +1289,15 @@ void device_upload_csc(Plan& p) {
 template <typename T, int V, int U>
 static void launch_rows_vu(const PlanDesc& d, hipStream_t st, int grid, int blk, const RowTile* tiles, int nt, int z,
                            const DataDesc& dd) {
-  if (d.nt)
-    hipLaunchKernelGGL((k_apply_rows<T, V, U, true>), dim3(grid + dd.grid), dim3(blk), 0, st, d, tiles, nt, z, dd);
+  const bool rb2 = rows_per_batch(1 << d.lpr_shift) == 2;
+  if (d.nt && rb2)
+    hipLaunchKernelGGL((k_apply_rows<T, V, U, true, 2>), dim3(grid + dd.grid), dim3(blk), 0, st, d, tiles, nt, z, dd);
+  else if (d.nt)
+    hipLaunchKernelGGL((k_apply_rows<T, V, U, true, 4>), dim3(grid + dd.grid), dim3(blk), 0, st, d, tiles, nt, z, dd);
+  else if (rb2)
+    hipLaunchKernelGGL((k_apply_rows<T, V, U, false, 2>), dim3(grid + dd.grid), dim3(blk), 0, st, d, tiles, nt, z, dd);
   else
-    hipLaunchKernelGGL((k_apply_rows<T, V, U, false>), dim3(grid + dd.grid), dim3(blk), 0, st, d, tiles, nt, z, dd);
+    hipLaunchKernelGGL((k_apply_rows<T, V, U, false, 4>), dim3(grid + dd.grid), dim3(blk), 0, st, d, tiles, nt, z, dd);
 }
 
 // point-major row tiles: one instance per (vec, unroll) a plan can select

@@ -608,14 +608,14 @@ hbc_tune default_tune(const Plan& plan) {
   }
   const int64_t rows_per_pass = t.block / t.lanes_per_row;
   // Short tiles keep many workgroups in flight (the apply is latency bound per
-  // row: table reads, then source loads, then stores): one batch of 4 rows per
+  // row: table reads, then source loads, then stores): one batch of rows per
   // row group when groups take contiguous runs of rows, else about 4096 tiles
   // in all.
   int64_t rpt;
   if (plan.layout.order != HBC_POINT_MAJOR && t.lanes_per_row > 1) {
     rpt = rows_per_pass;  // one pass of rows over all planes per tile
   } else if (t.lanes_per_row >= CHUNK_LPR) {
-    rpt = rows_per_pass * 4;
+    rpt = rows_per_pass * rows_per_batch(t.lanes_per_row);
   } else {
     rpt = std::max<int64_t>(rows / 4096, rows_per_pass);
     rpt = ((rpt + rows_per_pass - 1) / rows_per_pass) * rows_per_pass;
