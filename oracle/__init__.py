@@ -27,6 +27,9 @@ What it computes (Mat2Boundary, arXiv 2605.14780):
                     padding; Sec. IV-C, BC writes feed the inner operator).
 * ``dense``         brute-force dense A on tiny grids, evaluated entry by entry
                     from the definitions without the sparse assembly.
+* ``footprint``     the consumer footprint of Sec. IV-C: ghost rows that no
+                    read of the consuming operator reaches, and the operator
+                    restricted to the others.
 * ``averaging``     block-edge averaging of co-located points (data rows,
                     Sec. III-B), on a vertex-centred cubed sphere, sets found
                     by 3-D position; applied together with the ghost rows, all
