@@ -304,6 +304,30 @@ def extra_edge_average(ctx, hb, torch, tm):
     return out
 
 
+def extra_footprint(ctx, hb, torch, tm):
+    """The headline operator with a consumer footprint declared: a radius-1
+    cross stencil reads one ghost layer of the three (Sec. IV-C removes the
+    other rows), against the full halo."""
+    N, h, nf, nl = 384, 3, 4, 64
+    I = nf * nl
+    vec = (2 * nl, nl, nl)
+    offs = [(0, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]
+    grid, prog = hb.cs_program(N, h, hb.CS_LAGRANGE, vector=True)
+    prog.set_consumer(offs)
+    plan = hb.Plan(prog, inner=I, vec=vec, dtype=hb.F64)
+    st = plan.stats()
+    src = torch.from_numpy(ctx["c2_full"]).cuda()
+    fields = [src.clone() for _ in range(9)]
+    del src
+    g = hb.ApplyGraph(plan, fields, 90)
+    us = tm(g.launch, 90)
+    out = {"consumer": "cross radius 1", "rows_covered": st["rows_covered"], "rows_dead": st["rows_dead"],
+           "us_per_apply": us, "alg_bytes": st["alg_bytes"], "hbm_frac": st["alg_bytes"] / us / 1e3 / HBM_PEAK_GBS}
+    del g, fields
+    torch.cuda.empty_cache()
+    return out
+
+
 def extra_c48(ctx, hb, torch, tm):
     from tests.helpers import cs_full_field
     N, h = 48, 3
@@ -514,7 +538,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extras", default="all",
-                    help="comma-separated subset of: c384_plane_major, edge_average_np385, c48_latency, hpcg_256cube, "
+                    help="comma-separated subset of: c384_plane_major, c384_cross_footprint, edge_average_np385, "
+                         "c48_latency, hpcg_256cube, "
                          "batched_64_grids_f32, c768_adjoint")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 256 MiB, 20 times (counter calibration)")
@@ -548,7 +573,8 @@ def main():
     extras = {"c384_warm_cache_us_per_apply": res["warm_us"], "c384_eager_us_per_apply": res["eager_us"],
               "c384_f32": res["f32"]}
     if not args.no_extras:
-        table = (("c384_plane_major", extra_c384_plane_major), ("edge_average_np385", extra_edge_average),
+        table = (("c384_plane_major", extra_c384_plane_major), ("c384_cross_footprint", extra_footprint),
+                 ("edge_average_np385", extra_edge_average),
                  ("c48_latency", extra_c48),
                  ("hpcg_256cube", extra_hpcg), ("batched_64_grids_f32", extra_batch),
                  ("c768_adjoint", extra_adjoint))

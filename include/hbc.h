@@ -126,6 +126,8 @@ typedef struct {
   double alg_bytes_adjoint; /* ghost reads + ghost zeroing + source read-modify-write + tables */
   int64_t table_bytes;      /* device bytes held by the plan */
   int64_t rows_data;        /* data rows written (block-edge averaging), staged through scratch */
+  int64_t rows_dead;        /* ghost rows of sub-matrices / sub-vectors dropped: no consumer read reaches them */
+  int64_t ghost_cells_live; /* ghost cells some consumer read reaches (all ghost cells without a consumer) */
 } hbc_stats;
 
 /* Launch shape of the apply kernels (chosen by the plan, changed by tuning). */
@@ -193,6 +195,17 @@ int hbc_program_add_csr(hbc_program* p, const hbc_box* rows, const int64_t* row_
  * ninner is 1 (same b for every inner slot) or the layout's inner extent. */
 int hbc_program_add_vector(hbc_program* p, const hbc_box* rows, int64_t ninner, const double* values,
                            int32_t* sub_id);
+
+/* Consumer footprint (Sec. IV-C: boundary writes that no later read depends
+ * on are removed, and the rest is split into disjoint boxes).  `offsets`
+ * (noffsets x ndim, row-major) are the relative positions at which the
+ * operator consuming the field reads around each data cell.  A ghost cell is
+ * live if a data cell of its block plus some offset lands on it; rows of
+ * sub-matrices and sub-vectors at other ghost cells are dropped (not written,
+ * counted in rows_dead), and HBC_STRICT_COVER then asks only for the live
+ * ghosts to be covered.  noffsets = 0 restores the default (every row kept).
+ * Block grids keep offset 0 in the block coordinate. */
+int hbc_program_set_consumer(hbc_program* p, int32_t noffsets, const int64_t* offsets);
 
 /* Rows on data cells (Sec. III-B block-edge averaging: where points of
  * different blocks share one physical location, a sparse Sync sub-matrix with

@@ -51,7 +51,7 @@ class StatsT(C.Structure):
         "ghost_cells", "rows_covered", "rows_uncovered", "rows_zero", "rows_map", "rows_ell", "rows_csr",
         "rows_vector_only", "rows_with_b", "nnz", "unique_sources", "segments", "tiles", "ghost_values")] + [
         ("alg_bytes", C.c_double), ("alg_bytes_adjoint", C.c_double), ("table_bytes", C.c_int64),
-        ("rows_data", C.c_int64)]
+        ("rows_data", C.c_int64), ("rows_dead", C.c_int64), ("ghost_cells_live", C.c_int64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -88,6 +88,7 @@ SIGNATURES = {
     "hbc_program_add_ell": (I32, [P, C.POINTER(BoxT), I32, PI64, PD, PI32, PI32]),
     "hbc_program_add_csr": (I32, [P, C.POINTER(BoxT), PI64, PI64, PD, PI32, PI32]),
     "hbc_program_add_vector": (I32, [P, C.POINTER(BoxT), I64, PD, PI32]),
+    "hbc_program_set_consumer": (I32, [P, I32, PI64]),
     "hbc_program_add_data_csr": (I32, [P, C.POINTER(BoxT), PI64, PI64, PD, PI32]),
     "hbc_cs_program_add_edge_average": (I32, [P, I64]),
     "hbc_cs_program_add": (I32, [P, I64, I64, I32, I32, PI32, PD]),
@@ -274,6 +275,13 @@ class Program:
         sid = I32()
         _check(lib().hbc_program_add_vector(self._h, C.byref(_box(rows)), ninner, v_p, C.byref(sid)))
         return sid.value
+
+    def set_consumer(self, offsets):
+        """Read offsets of the consuming operator (n x ndim); ghost rows no read reaches are dropped."""
+        o = np.asarray(offsets, dtype=np.int64).reshape(-1)
+        o_a, o_p = _i64(o)
+        n = 0 if o.size == 0 else len(offsets)
+        _check(lib().hbc_program_set_consumer(self._h, n, o_p if n else None))
 
     def add_data_csr(self, rows, row_ptr, cols, vals):
         """Rows on data cells (block-edge averaging); every row reads the input field."""

@@ -238,6 +238,15 @@ int hbc_program_set_flags(hbc_program* p, uint32_t flags) {
   });
 }
 
+int hbc_program_set_consumer(hbc_program* p, int32_t noffsets, const int64_t* offsets) {
+  return guard([&] {
+    need(p != nullptr, "NULL argument");
+    need(noffsets >= 0, "noffsets must be >= 0");
+    need(noffsets == 0 || offsets != nullptr, "NULL offsets");
+    p->p.consumer.assign(offsets, offsets + (size_t)noffsets * p->p.grid.nd);
+  });
+}
+
 int hbc_program_add_map(hbc_program* p, const hbc_box* rows, const int64_t* M, const int64_t* offset, double weight,
                         const int32_t* rot, int32_t* sub_id) {
   return guard([&] {

@@ -100,6 +100,7 @@ struct Program {
   std::vector<Sub> subs;
   std::vector<DataSub> dsubs;
   uint32_t flags = 0;
+  std::vector<int64_t> consumer;  // consumer read offsets, noffsets x nd (empty: keep every row)
 };
 
 // Component rotation codes.  A 2x2 signed permutation R acts on the vector

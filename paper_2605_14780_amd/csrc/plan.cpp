@@ -274,6 +274,52 @@ void compile_plan(const Program& prog, const Layout& lay, int dtype, Plan& plan)
 
   // 3. pieces
   std::vector<Piece> pieces = refine(subs);
+  // 3a. consumer footprint (Sec. IV-C): keep only the parts of the pieces that
+  //     some consumer read reaches; live ghost region of a block = union over
+  //     offsets of (data + offset) inside the full box, minus the data box
+  int64_t dead = 0, live_ghosts = 0;
+  if (!prog.consumer.empty()) {
+    const size_t no = prog.consumer.size() / g.nd;
+    std::vector<std::vector<Box>> live(g.blocks.size());
+    for (size_t b = 0; b < g.blocks.size(); ++b) {
+      const Block& B = g.blocks[b];
+      std::vector<Box> L;  // disjoint
+      for (size_t o = 0; o < no; ++o) {
+        Box sh = B.data;
+        for (int d = 0; d < g.nd; ++d) {
+          sh.lo[d] += prog.consumer[o * g.nd + d];
+          sh.hi[d] += prog.consumer[o * g.nd + d];
+        }
+        if (!intersects(sh, B.full)) continue;
+        std::vector<Box> add = subtract(intersect(sh, B.full), B.data);
+        for (const Box& have : L) {  // keep L disjoint
+          std::vector<Box> a2;
+          for (const Box& a : add)
+            for (const Box& x : subtract(a, have)) a2.push_back(x);
+          add.swap(a2);
+        }
+        for (const Box& a : add)
+          if (!a.empty()) L.push_back(a);
+      }
+      for (const Box& a : L) live_ghosts += a.count();
+      live[b].swap(L);
+    }
+    std::vector<Piece> kept;
+    for (const Piece& pc : pieces) {
+      const int b = subs[pc.covers[0]].block;
+      int64_t in = 0;
+      for (const Box& a : live[b]) {
+        if (!intersects(pc.box, a)) continue;
+        Piece q{intersect(pc.box, a), pc.covers};
+        in += q.box.count();
+        kept.push_back(std::move(q));
+      }
+      dead += pc.box.count() - in;
+    }
+    pieces.swap(kept);
+  } else {
+    live_ghosts = g.ghost_cells();
+  }
   // deterministic order: by block, then by origin
   std::sort(pieces.begin(), pieces.end(), [&](const Piece& x, const Piece& y) {
     int bx = subs[x.covers[0]].block, by = subs[y.covers[0]].block;
@@ -546,8 +592,10 @@ void compile_plan(const Program& prog, const Layout& lay, int dtype, Plan& plan)
   st.ghost_cells = g.ghost_cells();
   st.rows_covered = row_base;
   st.rows_uncovered = st.ghost_cells - st.rows_covered;
-  if ((prog.flags & HBC_STRICT_COVER) && st.rows_uncovered > 0)
-    fail(HBC_EUNCOVERED, std::to_string(st.rows_uncovered) + " ghost cells are covered by no sub-matrix");
+  st.rows_dead = dead;
+  st.ghost_cells_live = live_ghosts;
+  if ((prog.flags & HBC_STRICT_COVER) && live_ghosts - st.rows_covered > 0)
+    fail(HBC_EUNCOVERED, std::to_string(live_ghosts - st.rows_covered) + " ghost cells are covered by no sub-matrix");
   std::sort(sources.begin(), sources.end());
   st.unique_sources = (int64_t)(std::unique(sources.begin(), sources.end()) - sources.begin());
   st.segments = (int64_t)T.segs.size();

@@ -226,3 +226,40 @@ def test_data_rows_validation():
     with pytest.raises(hb.HbcError) as e:
         hb.Program(hb.Grid.cubed_sphere(Np + 1, h)).cs_add_edge_average(Np)
     assert e.value.code == hb.EINVAL
+
+
+# ---- consumer footprint ------------------------------------------------------------------
+@pytest.mark.parametrize("N,h,r,mode", [(8, 3, 1, "sync"), (9, 3, 2, "lagrange"), (6, 2, 2, "sync")])
+def test_consumer_footprint_plan_equals_oracle(N, h, r, mode):
+    from oracle import footprint as ofp
+    offs = [(0, 0, 0)] + [o for k in range(1, r + 1) for o in ((0, k, 0), (0, -k, 0), (0, 0, k), (0, 0, -k))]
+    g = hb.Grid.cubed_sphere(N, h)
+    p = hb.Program(g)
+    if mode == "sync":
+        p.cs_add(N, h, hb.CS_SYNC)
+    else:
+        base, w = closed_form_weights(N, h)
+        p.cs_add(N, h, hb.CS_LAGRANGE, False, base, w)
+    p.set_consumer(offs)
+    plan = hb.Plan(p, inner=1, host_only=True)
+    st = plan.stats()
+    og = ocs.grid(N, h)
+    live = ofp.live_ghost_mask(og, offs)
+    assert st["ghost_cells_live"] == live.sum() == 6 * 4 * r * N
+    assert st["rows_covered"] == live.sum()
+    assert st["rows_dead"] == 6 * (4 * h * N + 4 * h * h) - live.sum()
+    A = assemble(og, ocs.subs(N, h, mode)).dense()
+    for row, cell in enumerate(og.ghost_cells):
+        kind, cols, vals, b, rot = plan.row(int(cell))
+        assert (kind >= 0) == bool(live[row]), cell
+        if not live[row]:
+            continue
+        ref = {int(og.data_cells[j]): A[row, j] for j in np.nonzero(A[row])[0]}
+        got = {c: v for c, v in zip(cols, vals) if v != 0.0}
+        assert set(got) == set(ref), (cell, got, ref)
+        assert max(abs(got[c] - ref[c]) for c in ref) <= 1e-13
+    # strict cover asks only for the live ghosts
+    p.set_flags(hb.STRICT_COVER)
+    hb.Plan(p, inner=1, host_only=True)
+    p.set_consumer([])
+    assert hb.Plan(p, inner=1, host_only=True).stats()["rows_dead"] == 0
