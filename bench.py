@@ -208,6 +208,12 @@ def headline(ctx, args, hb, torch, tm):
     fields[0].copy_(src)
     del src
 
+    # the default launch shape, then the autotuned one (specialise once, run many)
+    g0 = hb.ApplyGraph(plan, fields, args.steps)
+    default_us = tm(g0.launch, args.steps)
+    default_tune = plan.tune
+    del g0
+    tune_ms = plan.autotune(fields, os.path.join(tempfile.gettempdir(), "hbc_plan_tune.jsonl"))
     # timed region: K applies in one graph, cycling over the copies
     graph = hb.ApplyGraph(plan, fields, args.steps)
     for k in range(args.warmup):
@@ -223,7 +229,9 @@ def headline(ctx, args, hb, torch, tm):
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     ms = e0.elapsed_time(e1)
-    res = {"plan": plan, "stats": st, "ms": ms, "wall": wall}
+    res = {"plan": plan, "stats": st, "ms": ms, "wall": wall,
+           "tuning": {"default_tune": default_tune, "default_us_per_apply": default_us, "tuned": plan.tune,
+                      "tuned_ms_in_autotune": tune_ms}}
     # warm (cache-resident) and eager numbers for context
     g1 = hb.ApplyGraph(plan, [fields[0]], args.steps)
     res["warm_us"] = tm(g1.launch, args.steps)
@@ -571,7 +579,7 @@ def main():
     st = res["stats"]
     log("headline done")
     extras = {"c384_warm_cache_us_per_apply": res["warm_us"], "c384_eager_us_per_apply": res["eager_us"],
-              "c384_f32": res["f32"]}
+              "c384_f32": res["f32"], "c384_launch_shape": res["tuning"]}
     if not args.no_extras:
         table = (("c384_plane_major", extra_c384_plane_major), ("c384_cross_footprint", extra_footprint),
                  ("edge_average_np385", extra_edge_average),

@@ -266,6 +266,16 @@ int hbc_plan_get_tune(const hbc_plan* plan, hbc_tune* out);
  * for every valid shape. */
 int hbc_plan_set_tune(hbc_plan* plan, const hbc_tune* t);
 
+/* Try candidate launch shapes (workgroup size, lanes per row, rows per tile,
+ * persistent workgroups), timing HIP-graph applies cycled over the `nfields`
+ * device fields (`nelem` values each; their ghost values are overwritten,
+ * data cells are not), and keep the fastest.  With cache_path (JSON lines
+ * keyed by device, dtype, layout and the plan's sizes) a stored choice is
+ * reused.  *ms receives the chosen shape's time per apply.  Results do not
+ * depend on the shape (Sec. V-C: specialise once, run many). */
+int hbc_plan_autotune(hbc_plan* plan, void* const* fields, int64_t nelem, int32_t nfields, const char* cache_path,
+                      void* stream, double* ms);
+
 /* ---- apply (Sec. III-B: y = A x + b on the ghost rows) ------------------------ */
 /* In place on `field` (device, `nelem` values = cells * inner, else
  * HBC_EINVAL): every covered ghost value := (A x + b); data cells and

@@ -99,6 +99,7 @@ SIGNATURES = {
     "hbc_plan_row": (I32, [P, I64, I64, I32, PI64, PD, PI32, PD, PI32, PI32]),
     "hbc_plan_get_tune": (I32, [P, C.POINTER(TuneT)]),
     "hbc_plan_set_tune": (I32, [P, C.POINTER(TuneT)]),
+    "hbc_plan_autotune": (I32, [P, C.POINTER(P), I64, I32, C.c_char_p, P, PD]),
     "hbc_apply": (I32, [P, P, I64, P]),
     "hbc_apply_adjoint": (I32, [P, P, I64, P]),
     "hbc_time_apply": (I32, [P, C.POINTER(P), I64, I32, I32, P, PD]),
@@ -359,6 +360,15 @@ class Plan:
     def tune(self, d):
         t = TuneT(**d)
         _check(lib().hbc_plan_set_tune(self._h, C.byref(t)))
+
+    def autotune(self, fields, cache_path=None, stream=None):
+        """Pick the fastest launch shape on ``fields`` (ghosts overwritten); returns ms per apply."""
+        ptrs = [_field(self, f) for f in fields]
+        arr = (P * len(ptrs))(*[p for p, _ in ptrs])
+        ms = D()
+        _check(lib().hbc_plan_autotune(self._h, arr, ptrs[0][1], len(ptrs),
+                                       cache_path.encode() if cache_path else None, _stream(stream), C.byref(ms)))
+        return ms.value
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:

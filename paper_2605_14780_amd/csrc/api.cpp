@@ -508,6 +508,17 @@ int hbc_time_apply(const hbc_plan* plan, void* const* fields, int64_t nelem, int
   });
 }
 
+int hbc_plan_autotune(hbc_plan* plan, void* const* fields, int64_t nelem, int32_t nfields, const char* cache_path,
+                      void* stream, double* ms) {
+  return guard([&] {
+    check_device_plan(plan);
+    need(fields && ms && nfields >= 1, "bad tuning arguments");
+    check_size(plan, nelem);
+    for (int k = 0; k < nfields; ++k) check_field(fields[k]);
+    *ms = device_plan_autotune(plan->p, fields, nfields, cache_path, stream);
+  });
+}
+
 static void check_stencil_sizes(const hbc_plan* plan, int64_t xn, int64_t yn) {
   check_size(plan, xn);
   int64_t nd = 0;

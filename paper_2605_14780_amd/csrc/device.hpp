@@ -14,6 +14,7 @@ void device_adjoint(const Plan& p, void* grad, void* stream);
 void device_stencil27(Plan& p, const void* x, void* y, void* stream, bool fused, void* xghost);
 void device_cs_weights(int64_t N, int64_t h, int32_t* base, double* w, void* stream);
 double device_time_apply(const Plan& p, void* const* fields, int nfields, int reps, void* stream);
+double device_plan_autotune(Plan& p, void* const* fields, int nfields, const char* cache_path, void* stream);
 void* device_graph_create(const Plan& p, int op, void* const* fields, int nfields, int reps, void* stream);
 void device_graph_launch(void* g, void* stream);
 void device_graph_destroy(void* g);

@@ -1805,6 +1805,80 @@ static double time_batch(Batch* b, hipStream_t s, int reps) {
   return (double)ms / reps;
 }
 
+// ---- plan autotuner ------------------------------------------------------------------------
+static std::string plan_key(const Plan& p) {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  HIP_CHECK(hipGetDevice(&dev));
+  HIP_CHECK(hipGetDeviceProperties(&prop, dev));
+  std::ostringstream k;
+  k << prop.gcnArchName << "|plan|" << (p.dtype == HBC_F64 ? "f64" : "f32") << "|"
+    << (p.layout.order == HBC_POINT_MAJOR ? "point" : "plane") << "|" << p.layout.inner << "|" << p.vec << "|"
+    << p.stats.rows_covered << "|" << p.stats.segments << "|" << p.stats.nnz << "|" << p.stats.rows_data;
+  std::string s = k.str();
+  for (char& c : s)
+    if (c == '"' || c == '\\') c = '_';
+  return s;
+}
+
+// Try launch shapes on the given fields (cycled, so the timing sees cold
+// caches when the fields are many), keep the fastest.  Results do not depend
+// on the shape; only the tile table changes.
+double device_plan_autotune(Plan& p, void* const* fields, int nfields, const char* cache_path, void* stream) {
+  const std::string key = plan_key(p);
+  const int reps = std::max(2 * nfields, 12);
+  if (cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    while (std::getline(in, line)) {
+      if (line.find("\"key\": \"" + key + "\"") == std::string::npos) continue;
+      hbc_tune t{};
+      double ms = 0;
+      if (std::sscanf(line.c_str() + line.find("\"block\""),
+                      "\"block\": %d, \"lanes_per_row\": %d, \"rows_per_tile\": %d, \"persistent\": %d, \"ms\": %lf",
+                      &t.block, &t.lanes_per_row, &t.rows_per_tile, &t.persistent, &ms) == 5) {
+        build_tiles(p, t);
+        device_upload_tiles(p);
+        return device_time_apply(p, fields, nfields, reps, stream);
+      }
+    }
+  }
+  int dev = 0, ncu = 256;
+  HIP_CHECK(hipGetDevice(&dev));
+  HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  const hbc_tune def = default_tune(p);
+  std::vector<hbc_tune> cand;
+  for (int bl : {128, 256})
+    for (int lf : {1, 2}) {
+      const int lpr = std::max(1, std::min(bl, def.lanes_per_row / lf));
+      const int rp = bl / lpr;
+      for (int m : {1, 2, 4, 8})
+        for (int pf : {0, 4}) cand.push_back(hbc_tune{bl, lpr, rp * m, pf * ncu});
+    }
+  cand.push_back(def);
+  hbc_tune best = def;
+  double best_ms = 1e30;
+  for (const hbc_tune& t : cand) {
+    build_tiles(p, t);
+    device_upload_tiles(p);
+    const double ms = device_time_apply(p, fields, nfields, reps, stream);
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = t;
+    }
+  }
+  build_tiles(p, best);
+  device_upload_tiles(p);
+  best_ms = device_time_apply(p, fields, nfields, reps, stream);
+  if (cache_path) {
+    std::ofstream out(cache_path, std::ios::app);
+    out << "{\"key\": \"" << key << "\", \"block\": " << best.block << ", \"lanes_per_row\": " << best.lanes_per_row
+        << ", \"rows_per_tile\": " << best.rows_per_tile << ", \"persistent\": " << best.persistent
+        << ", \"ms\": " << best_ms << "}\n";
+  }
+  return best_ms;
+}
+
 double device_batch_autotune(Batch* b, const char* cache_path, void* stream) {
   if (!b->bound) fail(HBC_EINVAL, "bind fields before tuning a batch");
   OwnedStream os(stream);

@@ -270,3 +270,22 @@ def test_fp32_against_fp64_oracle(mode):
     ref32 = o_apply(op, full.astype(np.float32).astype(np.float64), vec)
     err32 = normwise_error(got[G], ref32[G], full[og.data_cells])
     assert err32 <= 2e-6, err32
+
+
+def test_plan_autotune_is_value_neutral(tmp_path):
+    N, h, nf, nl = 24, 3, 4, 3
+    grid, plan, vec = cs_plan(N, h, nf, nl)
+    full = torch.from_numpy(cs_full_field(N, h, nf, nl, seed=70)).cuda()
+    want = full.clone()
+    hb.apply(plan, want)
+    scratch = [full.clone() for _ in range(3)]
+    cache = str(tmp_path / "plan_tune.jsonl")
+    ms = plan.autotune(scratch, cache)
+    assert ms > 0 and open(cache).read().count("key") == 1
+    tuned = plan.tune
+    ms2 = plan.autotune(scratch, cache)  # read back from the cache
+    assert ms2 > 0 and plan.tune == tuned and open(cache).read().count("key") == 1
+    got = full.clone()
+    hb.apply(plan, got)
+    torch.cuda.synchronize()
+    assert torch.equal(got, want)
