@@ -212,9 +212,11 @@ int hbc_program_set_consumer(hbc_program* p, int32_t noffsets, const int64_t* of
  * a few entries per row rewrites those data values).  `rows` lies in one
  * block's data region; row k has entries row_ptr[k] .. row_ptr[k+1]-1 of
  * cols (global linear data indices) / vals.  Every row of an apply, ghost or
- * data, reads the input values: data rows are computed into a plan-owned
- * scratch buffer and written after the ghost rows have read their sources
- * (so applies of one such plan must not overlap in time).  Point-major
+ * data, reads the input values: data rows that read each other's cells form
+ * closed components, each read whole into registers and written after the
+ * ghost rows (components of up to 8 rows, columns and entries per row);
+ * otherwise the data rows are staged through a plan-owned scratch buffer, and
+ * applies of such a plan must not overlap in time.  Point-major
  * layouts only; such plans have no adjoint, batch or 27-point consumer
  * (HBC_EUNSUPPORTED).  Data-row boxes may not overlap each other (HBC_EOVERLAP). */
 int hbc_program_add_data_csr(hbc_program* p, const hbc_box* rows, const int64_t* row_ptr, const int64_t* cols,

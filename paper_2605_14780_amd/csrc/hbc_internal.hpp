@@ -87,6 +87,15 @@ struct Sub {
   std::vector<double> b;
 };
 
+// A closed component of data rows (block-edge averaging: one co-located set):
+// its distinct columns (cells) and its rows [first_row, first_row + nrow) of
+// the component row tables.
+constexpr int DC_MAX = 8;
+struct alignas(16) DataComp {
+  int32_t ncol, nrow, first_row, pad_;
+  int32_t col[DC_MAX];
+};
+
 // Rows on data cells (block-edge averaging): CSR over a box of one block's
 // data region, columns as global linear data indices.
 struct DataSub {
@@ -239,6 +248,13 @@ struct HostTables {
   std::vector<int64_t> dr_ptr;
   std::vector<int32_t> dr_col;
   std::vector<double> dr_val;
+  // the data rows split into closed components (rows that read each other's
+  // cells), each small enough to be read into registers whole, then written
+  bool dc_ok = false;
+  std::vector<DataComp> dc_comp;
+  std::vector<int32_t> dc_row_dst, dc_row_ent, dc_row_n;  // per component row
+  std::vector<int32_t> dc_slot;                           // per entry: column slot in its component
+  std::vector<double> dc_w;
 };
 
 struct Layout {
@@ -276,6 +292,12 @@ struct Plan {
   const int32_t* d_dr_col = nullptr;
   const void* d_dr_val = nullptr;
   void* d_dr_scratch = nullptr;  // rows_data * inner values (own allocation)
+  const DataComp* d_dc_comp = nullptr;
+  const int32_t* d_dc_row_dst = nullptr;
+  const int32_t* d_dc_row_ent = nullptr;
+  const int32_t* d_dc_row_n = nullptr;
+  const int32_t* d_dc_slot = nullptr;
+  const void* d_dc_w = nullptr;
   void* d_csc_dev = nullptr;  // allocation holding the adjoint tables
   const int64_t* d_csc_src = nullptr;
   const int64_t* d_csc_ptr = nullptr;

@@ -727,6 +727,55 @@ __global__ __launch_bounds__(256) void k_adjoint(PlanDesc d, AdjDesc a, const Ad
   }
 }
 
+// Data rows in closed components (block-edge averaging: a component is one
+// co-located set): a row group reads all of a component's columns into
+// registers, then computes and writes its rows, so no scratch is needed; it
+// runs after the ghost rows, which read the input values.  Sums in table
+// order, as k_data_scatter's rows.
+template <typename T, int V, bool NT>
+__global__ __launch_bounds__(256) void k_data_components(PlanDesc d, const DataComp* __restrict__ comps,
+                                                         const int32_t* __restrict__ row_dst,
+                                                         const int32_t* __restrict__ row_ent,
+                                                         const int32_t* __restrict__ row_n,
+                                                         const int32_t* __restrict__ slot, const T* __restrict__ w,
+                                                         int ncomp) {
+  const int lpr = 1 << d.lpr_shift;
+  const int ngroups = (int)blockDim.x >> d.lpr_shift;
+  const int lane = threadIdx.x & (lpr - 1), grp = threadIdx.x >> d.lpr_shift;
+  T* __restrict__ f = static_cast<T*>(d.field);
+  const int64_t nvec = d.inner / V;
+  for (int c = blockIdx.x * ngroups + grp; c < ncomp; c += gridDim.x * ngroups) {
+    const DataComp cp = comps[c];
+    for (int64_t v = lane; v < nvec; v += lpr) {
+      const int64_t l = v * V;
+      Pack<T, V> x[DC_MAX];
+#pragma unroll
+      for (int m = 0; m < DC_MAX; ++m)
+        if (m < cp.ncol) x[m] = ldv<T, V>(f + (int64_t)cp.col[m] * d.cs + l);
+      for (int k = 0; k < cp.nrow; ++k) {
+        const int r = cp.first_row + k;
+        const int e0 = row_ent[r], ne = row_n[r];
+        Pack<T, V> acc;
+#pragma unroll
+        for (int i = 0; i < V; ++i) acc.v[i] = T(0);
+#pragma unroll
+        for (int j = 0; j < DC_MAX; ++j) {
+          if (j >= ne) break;
+          const int sj = slot[e0 + j];
+          const T wj = w[e0 + j];
+          Pack<T, V> xs = x[0];
+#pragma unroll
+          for (int m = 1; m < DC_MAX; ++m)
+            if (m == sj) xs = x[m];
+#pragma unroll
+          for (int i = 0; i < V; ++i) acc.v[i] = j == 0 ? wj * xs.v[i] : fma(wj, xs.v[i], acc.v[i]);
+        }
+        stv<T, V, NT>(f + (int64_t)row_dst[r] * d.cs + l, acc);
+      }
+    }
+  }
+}
+
 template <typename T, int V>
 __global__ __launch_bounds__(256) void k_data_scatter(PlanDesc d, const int32_t* __restrict__ cell,
                                                       const T* __restrict__ scratch, int nrows) {
@@ -1174,6 +1223,12 @@ void device_upload_plan(Plan& p) {
   size_t o_drp = pk.vec(T.dr_ptr);
   size_t o_drk = pk.vec(T.dr_col);
   size_t o_drv = pk.reals(T.dr_val, p.dtype);
+  size_t o_dcc = pk.vec(T.dc_comp);
+  size_t o_dcd = pk.vec(T.dc_row_dst);
+  size_t o_dce = pk.vec(T.dc_row_ent);
+  size_t o_dcn = pk.vec(T.dc_row_n);
+  size_t o_dcs = pk.vec(T.dc_slot);
+  size_t o_dcw = pk.reals(T.dc_w, p.dtype);
   void* dev = nullptr;
   hipError_t e = hipMalloc(&dev, pk.buf.size());
   if (e != hipSuccess) fail(e == hipErrorOutOfMemory ? HBC_ENOMEM : HBC_EHIP, std::string("hipMalloc: ") + hipGetErrorString(e));
@@ -1194,7 +1249,13 @@ void device_upload_plan(Plan& p) {
   p.d_dr_ptr = reinterpret_cast<const int64_t*>(b + o_drp);
   p.d_dr_col = reinterpret_cast<const int32_t*>(b + o_drk);
   p.d_dr_val = b + o_drv;
-  if (p.stats.rows_data > 0) {
+  p.d_dc_comp = reinterpret_cast<const DataComp*>(b + o_dcc);
+  p.d_dc_row_dst = reinterpret_cast<const int32_t*>(b + o_dcd);
+  p.d_dc_row_ent = reinterpret_cast<const int32_t*>(b + o_dce);
+  p.d_dc_row_n = reinterpret_cast<const int32_t*>(b + o_dcn);
+  p.d_dc_slot = reinterpret_cast<const int32_t*>(b + o_dcs);
+  p.d_dc_w = b + o_dcw;
+  if (p.stats.rows_data > 0 && !T.dc_ok) {
     void* sc = nullptr;
     const size_t n = (size_t)p.stats.rows_data * (size_t)p.layout.inner * (p.dtype == HBC_F64 ? 8 : 4);
     e = hipMalloc(&sc, n);
@@ -1331,7 +1392,7 @@ static void launch_apply_t(const Plan& p, const PlanDesc& d, hipStream_t st, boo
   const int blk = p.tune.block;
   const int z = zero_only ? 1 : 0;
   DataDesc dd{p.d_dr_ptr, p.d_dr_col, p.d_dr_val, p.d_dr_scratch, 0, 0};
-  if (!zero_only && p.stats.rows_data > 0) {
+  if (!zero_only && p.stats.rows_data > 0 && !p.host.dc_ok) {
     // data rows gather into scratch in extra workgroups of this launch
     const int groups = blk / p.tune.lanes_per_row;
     dd.nrows = (int32_t)p.stats.rows_data;
@@ -1357,8 +1418,32 @@ static void launch_data_scatter(const Plan& p, const PlanDesc& d, hipStream_t st
   HIP_CHECK(hipGetLastError());
 }
 
+template <typename T, int V>
+static void launch_data_components(const Plan& p, const PlanDesc& d, hipStream_t st) {
+  const int n = (int)p.host.dc_comp.size();
+  const int blk = p.tune.block;
+  const int groups = blk >> d.lpr_shift;
+  const int grid = (int)std::min<int64_t>((n + groups - 1) / groups, 4096);
+  if (d.nt)
+    hipLaunchKernelGGL((k_data_components<T, V, true>), dim3(grid), dim3(blk), 0, st, d, p.d_dc_comp, p.d_dc_row_dst,
+                       p.d_dc_row_ent, p.d_dc_row_n, p.d_dc_slot, static_cast<const T*>(p.d_dc_w), n);
+  else
+    hipLaunchKernelGGL((k_data_components<T, V, false>), dim3(grid), dim3(blk), 0, st, d, p.d_dc_comp, p.d_dc_row_dst,
+                       p.d_dc_row_ent, p.d_dc_row_n, p.d_dc_slot, static_cast<const T*>(p.d_dc_w), n);
+  HIP_CHECK(hipGetLastError());
+}
+
 template <typename T>
 static void launch_data_scatter_v(const Plan& p, const PlanDesc& d, hipStream_t st) {
+  if (p.host.dc_ok) {
+    if (sizeof(T) == 4 && p.vec == 4)
+      launch_data_components<T, (sizeof(T) == 4 ? 4 : 2)>(p, d, st);
+    else if (p.vec >= 2)
+      launch_data_components<T, 2>(p, d, st);
+    else
+      launch_data_components<T, 1>(p, d, st);
+    return;
+  }
   if (sizeof(T) == 4 && p.vec == 4)
     launch_data_scatter<T, (sizeof(T) == 4 ? 4 : 2)>(p, d, st);
   else if (p.vec >= 2)

@@ -209,6 +209,67 @@ std::vector<Piece> refine(const std::vector<Sub>& subs) {
 
 }  // namespace
 
+// Closed components of the data rows: rows are joined when one reads a cell
+// another writes.  Every written cell a component reads is then written by
+// that component, so reading all its columns first and writing its rows after
+// gives the input-field semantics without scratch.  Used when every
+// component has at most DC_MAX rows, columns and entries per row.
+static void build_data_components(HostTables& T) {
+  T.dc_ok = false;
+  T.dc_comp.clear();
+  T.dc_row_dst.clear();
+  T.dc_row_ent.clear();
+  T.dc_row_n.clear();
+  T.dc_slot.clear();
+  T.dc_w.clear();
+  const int64_t n = (int64_t)T.dr_cell.size();
+  if (n == 0) return;
+  std::unordered_map<int32_t, int64_t> row_of;
+  for (int64_t r = 0; r < n; ++r) row_of[T.dr_cell[r]] = r;
+  std::vector<int64_t> parent(n);
+  std::iota(parent.begin(), parent.end(), 0);
+  auto find = [&](int64_t a) {
+    while (parent[a] != a) a = parent[a] = parent[parent[a]];
+    return a;
+  };
+  for (int64_t r = 0; r < n; ++r)
+    for (int64_t e = T.dr_ptr[r]; e < T.dr_ptr[r + 1]; ++e) {
+      auto it = row_of.find(T.dr_col[e]);
+      if (it == row_of.end()) continue;
+      const int64_t a = find(r), b = find(it->second);
+      if (a != b) parent[std::max(a, b)] = std::min(a, b);
+    }
+  std::map<int64_t, std::vector<int64_t>> comps;  // root -> rows (ascending)
+  for (int64_t r = 0; r < n; ++r) comps[find(r)].push_back(r);
+  for (const auto& kv : comps) {
+    const std::vector<int64_t>& rows = kv.second;
+    DataComp c{};
+    c.first_row = (int32_t)T.dc_row_dst.size();
+    c.nrow = (int32_t)rows.size();
+    if (c.nrow > DC_MAX) return;
+    for (int64_t r : rows) {
+      if (T.dr_ptr[r + 1] - T.dr_ptr[r] > DC_MAX) return;
+      T.dc_row_dst.push_back(T.dr_cell[r]);
+      T.dc_row_ent.push_back((int32_t)T.dc_slot.size());
+      T.dc_row_n.push_back((int32_t)(T.dr_ptr[r + 1] - T.dr_ptr[r]));
+      for (int64_t e = T.dr_ptr[r]; e < T.dr_ptr[r + 1]; ++e) {
+        int slot = -1;
+        for (int m = 0; m < c.ncol; ++m)
+          if (c.col[m] == T.dr_col[e]) slot = m;
+        if (slot < 0) {
+          if (c.ncol == DC_MAX) return;
+          slot = c.ncol++;
+          c.col[slot] = T.dr_col[e];
+        }
+        T.dc_slot.push_back(slot);
+        T.dc_w.push_back(T.dr_val[e]);
+      }
+    }
+    T.dc_comp.push_back(c);
+  }
+  T.dc_ok = true;
+}
+
 void compile_plan(const Program& prog, const Layout& lay, int dtype, Plan& plan) {
   const Grid& g = prog.grid;
   plan.grid = g;
@@ -585,6 +646,7 @@ void compile_plan(const Program& prog, const Layout& lay, int dtype, Plan& plan)
   }
   T.dr_ptr.push_back((int64_t)T.dr_col.size());
   st.rows_data = (int64_t)T.dr_cell.size();
+  build_data_components(T);
   if (st.rows_data > 0 && lay.order != HBC_POINT_MAJOR)
     fail(HBC_EUNSUPPORTED, "data rows need the point-major layout");
 

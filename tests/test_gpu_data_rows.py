@@ -104,3 +104,41 @@ def test_data_rows_refuse_adjoint_and_batch():
     with pytest.raises(hb.HbcError) as e:
         hb.Batch([plan])
     assert e.value.code == hb.EUNSUPPORTED
+
+
+@pytest.mark.parametrize("length", [5, 12])
+def test_custom_data_rows_chain(length):
+    """A cyclic chain of rows (each the mean of itself and its right
+    neighbour) forms one component: registers for <= 8 rows, scratch above."""
+    Np, h, I = 16, 2, 3
+    W = Np + 2 * h
+    g = hb.Grid.cubed_sphere(Np, h)
+    p = hb.Program(g)
+    p.cs_add(Np, h, hb.CS_SYNC)
+
+    def lin(f, j, i):
+        return (f * W + (j + h)) * W + (i + h)
+
+    f, j = 2, 5
+    cols, ptr, subs_rows, subs_ents = [], [0], [], []
+    for i in range(length):
+        nxt = (i + 1) % length
+        cols += [lin(f, j, 1 + i), lin(f, j, 1 + nxt)]
+        ptr.append(len(cols))
+        subs_rows.append((f, j, 1 + i))
+        subs_ents.append([((f, j, 1 + i), 0.5), ((f, j, 1 + nxt), 0.5)])
+    p.add_data_csr([(f, f + 1), (j, j + 1), (1, 1 + length)], ptr, cols, [0.5] * len(cols))
+    # a row that reads only cells no data row writes
+    p.add_data_csr([(f, f + 1), (j + 2, j + 3), (3, 4)], [0, 2], [lin(f, 0, 0), lin(f, 9, 9)], [0.25, 0.5])
+    subs_rows.append((f, j + 2, 3))
+    subs_ents.append([((f, 0, 0), 0.25), ((f, 9, 9), 0.5)])
+    plan = hb.Plan(p, inner=I)
+    og = ocs.grid(Np, h)
+    op = assemble(og, ocs.subs(Np, h, "sync"))
+    dop = oav.assemble_data(og, [oav.DataRowsSub(subs_rows, subs_ents)])
+    u = field(og, I, 21)
+    t = torch.from_numpy(u.copy()).cuda()
+    hb.apply(plan, t)
+    torch.cuda.synchronize()
+    ref = oav.apply_with_data_rows(op, dop, u)
+    assert np.array_equal(t.cpu().numpy(), ref, equal_nan=True)
