@@ -27,6 +27,9 @@ What it computes (Mat2Boundary, arXiv 2605.14780):
                     padding; Sec. IV-C, BC writes feed the inner operator).
 * ``dense``         brute-force dense A on tiny grids, evaluated entry by entry
                     from the definitions without the sparse assembly.
+* ``quadrature``    wide interpolation rows, Sec. III-B's Agg . Recons: a
+                    Gauss rule over each ghost cell of tensor-product cubic
+                    reconstructions on the neighbour face.
 * ``footprint``     the consumer footprint of Sec. IV-C: ghost rows that no
                     read of the consuming operator reaches, and the operator
                     restricted to the others.
