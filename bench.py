@@ -336,6 +336,46 @@ def extra_footprint(ctx, hb, torch, tm):
     return out
 
 
+def extra_wide_rows(ctx, hb, torch, tm):
+    """Wide interpolation rows (Gauss average over each ghost cell of cubic
+    tensor-product reconstructions, 16..25 entries per row, CSR): the
+    headline's C384 fields (I = 256, FP64, 9 cold copies) and the paper's
+    6 x 90 x 90 shallow-water grid with (h, u, v) per cell."""
+    import numpy as np
+    out = {}
+    N, h, nf, nl = 384, 3, 4, 64
+    I = nf * nl
+    vec = (2 * nl, nl, nl)
+    g = hb.Grid.cubed_sphere(N, h)
+    p = hb.Program(g)
+    p.cs_add_quadrature(N, h, 2, vector=True)
+    plan = hb.Plan(p, inner=I, vec=vec, dtype=hb.F64)
+    st = plan.stats()
+    src = torch.from_numpy(ctx["c2_full"]).cuda()
+    fields = [src.clone() for _ in range(9)]
+    del src
+    gr = hb.ApplyGraph(plan, fields, 90)
+    us = tm(gr.launch, 90)
+    out["c384_i256_f64"] = {"us_per_apply": us, "nnz_per_row": st["nnz"] / st["rows_csr"],
+                            "ghost_cells_per_s": st["ghost_values"] / us * 1e6, "alg_bytes": st["alg_bytes"],
+                            "hbm_frac": st["alg_bytes"] / us / 1e3 / HBM_PEAK_GBS}
+    del gr, fields
+    torch.cuda.empty_cache()
+    N, h, L = 90, 3, 1
+    from tests.helpers import cs_full_field
+    g = hb.Grid.cubed_sphere(N, h)
+    p = hb.Program(g)
+    p.cs_add_quadrature(N, h, 2, vector=True)
+    plan = hb.Plan(p, inner=3, vec=(1, 1, 1), dtype=hb.F64)
+    st = plan.stats()
+    full = torch.from_numpy(cs_full_field(N, h, 3, L, seed=9)).cuda()
+    gr = hb.ApplyGraph(plan, [full], 2000)
+    us = tm(gr.launch, 2000)
+    out["c90_hUV_f64"] = {"us_per_apply": us, "ghost_cells_per_s": st["ghost_values"] / us * 1e6,
+                          "nnz_per_row": st["nnz"] / st["rows_csr"]}
+    return out
+
+
 def extra_c48(ctx, hb, torch, tm):
     from tests.helpers import cs_full_field
     N, h = 48, 3
@@ -546,7 +586,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extras", default="all",
-                    help="comma-separated subset of: c384_plane_major, c384_cross_footprint, edge_average_np385, "
+                    help="comma-separated subset of: c384_plane_major, c384_cross_footprint, wide_rows, edge_average_np385, "
                          "c48_latency, hpcg_256cube, "
                          "batched_64_grids_f32, c768_adjoint")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -582,6 +622,7 @@ def main():
               "c384_f32": res["f32"], "c384_launch_shape": res["tuning"]}
     if not args.no_extras:
         table = (("c384_plane_major", extra_c384_plane_major), ("c384_cross_footprint", extra_footprint),
+                 ("wide_rows", extra_wide_rows),
                  ("edge_average_np385", extra_edge_average),
                  ("c48_latency", extra_c48),
                  ("hpcg_256cube", extra_hpcg), ("batched_64_grids_f32", extra_batch),

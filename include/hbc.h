@@ -240,6 +240,16 @@ int hbc_cs_program_add_edge_average(hbc_program* p, int64_t Np);
  * `vector` != 0 each side carries its 2x2 component rotation. */
 int hbc_cs_program_add(hbc_program* p, int64_t N, int64_t h, int32_t mode, int32_t vector,
                        const int32_t* base, const double* w);
+/* Wide interpolation rows on a grid from hbc_cs_grid_create (Sec. III-B:
+ * HOPE's ghost values as Itp = Agg . Recons, user-preprocessed into sparse
+ * rows): each edge ghost cell is the q x q Gauss-Legendre average (q = 1, 2,
+ * 3) over its square in its face's angles of cubic tensor-product Lagrange
+ * reconstructions (4 x 4 nodes in the neighbour's index space, base
+ * clamp(floor(s) - 1, 0, N - 4) per direction); the row is the union of the
+ * stencils with weights summed (16..25 entries for q = 2), in ascending cell
+ * order, stored as CSR.  Corners are zero rows; `vector` adds the side's
+ * component rotation.  Weights from FP64 geometry on the host. */
+int hbc_cs_program_add_quadrature(hbc_program* p, int64_t N, int64_t h, int32_t q, int32_t vector);
 /* Cartesian halo program on a grid from hbc_cart_grid_create: for every block
  * and each of its 3^3-1 ghost regions, a copy from the neighbouring block
  * (Sec. III-B halo copying) or, outside the domain, zero rows (padding with

@@ -91,6 +91,7 @@ SIGNATURES = {
     "hbc_program_set_consumer": (I32, [P, I32, PI64]),
     "hbc_program_add_data_csr": (I32, [P, C.POINTER(BoxT), PI64, PI64, PD, PI32]),
     "hbc_cs_program_add_edge_average": (I32, [P, I64]),
+    "hbc_cs_program_add_quadrature": (I32, [P, I64, I64, I32, I32]),
     "hbc_cs_program_add": (I32, [P, I64, I64, I32, I32, PI32, PD]),
     "hbc_cart_program_add_halo": (I32, [P, PI32, PI64, I64, I32]),
     "hbc_plan_create": (I32, [P, C.POINTER(LayoutT), I32, U32, C.POINTER(P)]),
@@ -292,6 +293,10 @@ class Program:
         sid = I32()
         _check(lib().hbc_program_add_data_csr(self._h, C.byref(_box(rows)), p_p, c_p, v_p, C.byref(sid)))
         return sid.value
+
+    def cs_add_quadrature(self, N, h, q=2, vector=False):
+        """Wide rows: Gauss average over each ghost cell of cubic tensor-product reconstructions."""
+        _check(lib().hbc_cs_program_add_quadrature(self._h, N, h, q, int(bool(vector))))
 
     def cs_add_edge_average(self, Np):
         """Averaging of co-located face-boundary points of a vertex-centred cubed sphere."""

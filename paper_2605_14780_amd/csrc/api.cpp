@@ -361,6 +361,13 @@ int hbc_program_add_data_csr(hbc_program* p, const hbc_box* rows, const int64_t*
   });
 }
 
+int hbc_cs_program_add_quadrature(hbc_program* p, int64_t N, int64_t h, int32_t q, int32_t vector) {
+  return guard([&] {
+    need(p != nullptr, "NULL argument");
+    cs_add_quadrature(p->p, N, h, q, vector);
+  });
+}
+
 int hbc_cs_program_add_edge_average(hbc_program* p, int64_t Np) {
   return guard([&] {
     need(p != nullptr, "NULL argument");

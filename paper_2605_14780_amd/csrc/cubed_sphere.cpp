@@ -7,6 +7,8 @@
 // frame vectors (centre c, tangents e1, e2 with c x e1 = e2), so no floating
 // point decides an index.
 #include <algorithm>
+#include <cmath>
+#include <map>
 #include <cstring>
 #include <numeric>
 #include <vector>
@@ -306,6 +308,112 @@ void cs_add_edge_average(Program& p, int64_t Np) {
         }
       p.dsubs.push_back(std::move(ds));
     }
+  }
+}
+
+// Wide interpolation rows (Sec. III-B, HOPE's Itp = Agg . Recons): the value
+// of edge ghost cell (f, j, i) is a q x q Gauss-Legendre average over the
+// cell's square in f's angles of cubic tensor-product Lagrange
+// reconstructions on the neighbour face g (4 x 4 nodes per point in g's index
+// space, base clamp(floor(s) - 1, 0, N - 4) per direction).  The row is the
+// union of the stencils, weights summed, in ascending cell order.  Corner
+// ghosts are zero rows.  FP64 geometry on the host, from the integer frames.
+void cs_add_quadrature(Program& p, int64_t N, int64_t h, int q, int vector) {
+  const Grid& g = p.grid;
+  if (N < 4 || h < 1 || h > N) fail(HBC_EINVAL, "cubed sphere needs N >= 4 and 1 <= h <= N");
+  if (g.nd != 3 || g.blocks.size() != 6 || g.blocks[0].data.extent(1) != N ||
+      g.blocks[0].full.lo[1] != -h || g.blocks[0].full.hi[1] != N + h)
+    fail(HBC_EINVAL, "program grid is not the cubed-sphere grid of this N and h");
+  // Gauss-Legendre nodes (in cell widths, on [-1/2, 1/2]) and weights (sum 1)
+  std::vector<double> xn, wn;
+  if (q == 1) {
+    xn = {0.0};
+    wn = {1.0};
+  } else if (q == 2) {
+    const double a = 0.5 / std::sqrt(3.0);
+    xn = {-a, a};
+    wn = {0.5, 0.5};
+  } else if (q == 3) {
+    const double a = 0.5 * std::sqrt(0.6);
+    xn = {-a, 0.0, a};
+    wn = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+  } else {
+    fail(HBC_EINVAL, "quadrature order must be 1, 2 or 3");
+  }
+  const double D = M_PI / (2.0 * (double)N);
+  const double Q = M_PI / 4.0;
+  const int64_t W = N + 2 * h;
+  auto lin = [&](int64_t f, int64_t j, int64_t i) { return (f * W + (j + h)) * W + (i + h); };
+  auto lag4 = [&](double s, int64_t& base, double* w) {
+    base = (int64_t)std::floor(s) - 1;
+    base = base < 0 ? 0 : (base > N - 4 ? N - 4 : base);
+    const double d0 = s - base, d1 = s - (base + 1), d2 = s - (base + 2), d3 = s - (base + 3);
+    w[0] = -d1 * d2 * d3 / 6.0;
+    w[1] = d0 * d2 * d3 / 2.0;
+    w[2] = -d0 * d1 * d3 / 2.0;
+    w[3] = d0 * d1 * d2 / 6.0;
+  };
+  for (int f = 0; f < 6; ++f) {
+    for (int side = 0; side < 4; ++side) {
+      SideLink L = link(f, side);
+      Sub s;
+      s.kind = SUB_CSR;
+      s.rows.nd = 3;
+      s.rows.lo[0] = f;
+      s.rows.hi[0] = f + 1;
+      if (side == LEFT) { s.rows.lo[1] = 0; s.rows.hi[1] = N; s.rows.lo[2] = -h; s.rows.hi[2] = 0; }
+      if (side == RIGHT) { s.rows.lo[1] = 0; s.rows.hi[1] = N; s.rows.lo[2] = N; s.rows.hi[2] = N + h; }
+      if (side == BOTTOM) { s.rows.lo[1] = -h; s.rows.hi[1] = 0; s.rows.lo[2] = 0; s.rows.hi[2] = N; }
+      if (side == TOP) { s.rows.lo[1] = N; s.rows.hi[1] = N + h; s.rows.lo[2] = 0; s.rows.hi[2] = N; }
+      s.rot = vector ? rot_code(L.rot) : 0;
+      if (s.rot < 0) fail(HBC_EINVAL, "internal: face rotation is not a signed permutation");
+      const V3 cf = FR[f][0], e1f = FR[f][1], e2f = FR[f][2];
+      const V3 cg = FR[L.g][0], e1g = FR[L.g][1], e2g = FR[L.g][2];
+      s.ptr.push_back(0);
+      for (int64_t j = s.rows.lo[1]; j < s.rows.hi[1]; ++j)
+        for (int64_t i = s.rows.lo[2]; i < s.rows.hi[2]; ++i) {
+          std::map<int64_t, double> acc;
+          for (size_t b = 0; b < xn.size(); ++b)
+            for (size_t a = 0; a < xn.size(); ++a) {
+              const double ta = std::tan(-Q + ((double)i + 0.5 + xn[a]) * D);
+              const double tb = std::tan(-Q + ((double)j + 0.5 + xn[b]) * D);
+              // P = c_f + ta e1_f + tb e2_f, seen from g
+              const double Px = cf.x + ta * e1f.x + tb * e2f.x, Py = cf.y + ta * e1f.y + tb * e2f.y,
+                           Pz = cf.z + ta * e1f.z + tb * e2f.z;
+              const double pc = Px * cg.x + Py * cg.y + Pz * cg.z;
+              const double ag = std::atan((Px * e1g.x + Py * e1g.y + Pz * e1g.z) / pc);
+              const double bg = std::atan((Px * e2g.x + Py * e2g.y + Pz * e2g.z) / pc);
+              const double si = (ag + Q) / D - 0.5, sj = (bg + Q) / D - 0.5;
+              int64_t bj, bi;
+              double wj[4], wi[4];
+              lag4(sj, bj, wj);
+              lag4(si, bi, wi);
+              const double wq = wn[a] * wn[b];
+              for (int u = 0; u < 4; ++u)
+                for (int v = 0; v < 4; ++v) acc[lin(L.g, bj + u, bi + v)] += wq * wj[u] * wi[v];
+            }
+          for (const auto& kv : acc) {
+            s.cols.push_back(kv.first);
+            s.vals.push_back(kv.second);
+          }
+          s.ptr.push_back((int64_t)s.cols.size());
+        }
+      p.subs.push_back(std::move(s));
+    }
+    const int64_t lo[2] = {-h, N}, hi[2] = {0, N + h};
+    for (int a = 0; a < 2; ++a)
+      for (int c = 0; c < 2; ++c) {
+        Sub z;
+        z.kind = SUB_ZERO;
+        z.rows.nd = 3;
+        z.rows.lo[0] = f;
+        z.rows.hi[0] = f + 1;
+        z.rows.lo[1] = lo[a];
+        z.rows.hi[1] = hi[a];
+        z.rows.lo[2] = lo[c];
+        z.rows.hi[2] = hi[c];
+        p.subs.push_back(z);
+      }
   }
 }
 

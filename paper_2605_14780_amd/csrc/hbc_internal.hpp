@@ -344,5 +344,6 @@ void cs_add_program(Program& p, int64_t N, int64_t h, int mode, int vector, cons
 // Cartesian helpers (cubed_sphere.cpp)
 void cart_add_halo(Program& p, const int32_t* nb, const int64_t* n, int64_t h, int32_t periodic);
 void cs_add_edge_average(Program& p, int64_t Np);
+void cs_add_quadrature(Program& p, int64_t N, int64_t h, int q, int vector);
 
 }  // namespace hbc

@@ -263,3 +263,17 @@ def test_consumer_footprint_plan_equals_oracle(N, h, r, mode):
     hb.Plan(p, inner=1, host_only=True)
     p.set_consumer([])
     assert hb.Plan(p, inner=1, host_only=True).stats()["rows_dead"] == 0
+
+
+# ---- wide rows: quadrature of tensor-product reconstructions --------------------------------
+@pytest.mark.parametrize("N,h,q", [(8, 2, 2), (12, 3, 2), (9, 1, 3), (6, 2, 1)])
+def test_quadrature_plan_equals_oracle(N, h, q):
+    from oracle import quadrature as oq
+    g = hb.Grid.cubed_sphere(N, h)
+    p = hb.Program(g)
+    p.cs_add_quadrature(N, h, q)
+    plan = hb.Plan(p, inner=1, host_only=True)
+    og = ocs.grid(N, h)
+    st = plan.stats()
+    assert st["rows_csr"] == 24 * h * N and st["rows_zero"] == 24 * h * h
+    compare_plan_with_oracle(plan, og, assemble(og, oq.subs(N, h, q)), tol=1e-13)
