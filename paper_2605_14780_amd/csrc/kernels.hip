@@ -410,8 +410,17 @@ __device__ __forceinline__ void rt_tile(const PlanDesc& d, const RowTile& tl, bo
               }
         }
       } else if (kind == SEG_ELL || kind == SEG_CSR) {
+        // general rows (any width): entries in chunks of EC, each chunk's
+        // columns and weights read together, then all its source loads, then
+        // the sum in entry order (first product, then FMAs)
+        constexpr int EC = 8;
 #pragma unroll
         for (int q = 0; q < RB; ++q) {
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int i = 0; i < V; ++i) y[q][u].v[i] = T(0);
+          if (r + q * rs >= re) continue;  // a batch slot past the group's rows
           int64_t e0, e1;
           const int32_t* cols;
           const T* vals;
@@ -427,23 +436,37 @@ __device__ __forceinline__ void rt_tile(const PlanDesc& d, const RowTile& tl, bo
             vals = static_cast<const T*>(d.csr_val);
           }
           bool first = true;
+          for (int64_t eb = e0; eb < e1; eb += EC) {
+            const int ne = (int)min<int64_t>(EC, e1 - eb);
+            int32_t cc[EC];
+            T wv[EC];
 #pragma unroll
-          for (int u = 0; u < U; ++u)
+            for (int k = 0; k < EC; ++k) {
+              cc[k] = -1;
+              wv[k] = T(0);
+              if (k < ne) {
+                cc[k] = cols[eb + k];
+                wv[k] = vals[eb + k];
+              }
+            }
+            Pack<T, V> x[EC][U];
 #pragma unroll
-            for (int i = 0; i < V; ++i) y[q][u].v[i] = T(0);
-          for (int64_t e = e0; e < e1; ++e) {
-            const int32_t cc = cols[e];
-            if (cc < 0) continue;
-            const T wt = vals[e];
-            const T* src = f + (int64_t)cc * d.cs;
-            Pack<T, V> x[U];
+            for (int k = 0; k < EC; ++k)
+              if (cc[k] >= 0) {
+                const T* src = f + (int64_t)cc[k] * d.cs;
 #pragma unroll
-            for (int u = 0; u < U; ++u) x[u] = ldv<T, V>(src + sl[u]);
+                for (int u = 0; u < U; ++u) x[k][u] = ldv<T, V>(src + sl[u]);
+              }
 #pragma unroll
-            for (int u = 0; u < U; ++u)
+            for (int k = 0; k < EC; ++k)
+              if (cc[k] >= 0) {
 #pragma unroll
-              for (int i = 0; i < V; ++i) y[q][u].v[i] = first ? wt * x[u].v[i] : fma(wt, x[u].v[i], y[q][u].v[i]);
-            first = false;
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                  for (int i = 0; i < V; ++i)
+                    y[q][u].v[i] = first ? wv[k] * x[k][u].v[i] : fma(wv[k], x[k][u].v[i], y[q][u].v[i]);
+                first = false;
+              }
           }
 #pragma unroll
           for (int u = 0; u < U; ++u)
