@@ -169,6 +169,23 @@ struct alignas(16) RowTile {
   int32_t pad_;
 };
 
+// Wide rows (CSR segments averaging >= WIDE_NNZ entries per row, rows of
+// >= WIDE_ROW_BYTES, point-major): cut into tiles of consecutive rows whose
+// distinct source cells (at most WIDE_UCAP) are staged in LDS one slice of
+// WIDE_ROW_BYTES of their inner values at a time; each entry carries the LDS
+// slot of its source.
+// The tile's entries (at most WIDE_ECAP) and row pointers are staged too.
+constexpr int WIDE_NNZ = 8, WIDE_UCAP = 128, WIDE_ROWS = 32, WIDE_ROW_BYTES = 128, WIDE_ECAP = 512;
+struct alignas(16) WideTile {
+  int32_t rot, has_b, b_inner, nrows;
+  int64_t row_begin;  // index into the per-row tables
+  int64_t tab;        // index of the first row's CSR pointer
+  int64_t brow;       // b table offset of the first row
+  int32_t first_u, nu;
+  int64_t e0;         // first entry (csr_ptr[tab])
+  int32_t ne, pad_;   // entries of the tile's rows
+};
+
 // Adjoint: one entry per (source cell, ghost row) contribution, sorted by
 // source cell then ghost cell.
 struct CscHost {
@@ -243,6 +260,11 @@ struct HostTables {
   std::vector<int32_t> row_dst;  // destination cell of every covered row
   std::vector<int32_t> row_src;  // MAP rows: source cell; other rows: 0
   std::vector<RowTile> rtiles;
+  // wide rows (see WideTile); seg_wide marks the segments they take
+  std::vector<char> seg_wide;
+  std::vector<WideTile> wtiles;
+  std::vector<int32_t> w_ucell;
+  std::vector<uint16_t> w_slot;  // parallel to csr_col (0 outside wide segments)
   // data rows: destination cells, CSR over data cells (absolute pointers)
   std::vector<int32_t> dr_cell;
   std::vector<int64_t> dr_ptr;
@@ -287,6 +309,9 @@ struct Plan {
   const int32_t* d_csr_col = nullptr;
   const void* d_csr_val = nullptr;
   const void* d_bval = nullptr;
+  const WideTile* d_wtiles = nullptr;
+  const int32_t* d_w_ucell = nullptr;
+  const uint16_t* d_w_slot = nullptr;
   const int32_t* d_dr_cell = nullptr;
   const int64_t* d_dr_ptr = nullptr;
   const int32_t* d_dr_col = nullptr;

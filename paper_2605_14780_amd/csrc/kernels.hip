@@ -503,6 +503,110 @@ __device__ __forceinline__ void rt_tile(const PlanDesc& d, const RowTile& tl, bo
   }
 }
 
+// Wide rows (WideTile).  Workgroup (tile, slice): the tile's distinct
+// source cells are staged in LDS, WIDE_ROW_BYTES of inner values each (the
+// slots this slice's outputs read, through the component rotation); then a
+// group of lanes per row sums the row's entries from LDS in entry order
+// (first product, then FMAs: the same bits as the general row path).
+// zero_only writes +0 to the tile's rows (the adjoint's ghost reset).
+template <typename T, int V, bool NT>
+__global__ __launch_bounds__(256) void k_apply_wide(PlanDesc d, const WideTile* __restrict__ tiles,
+                                                    const int32_t* __restrict__ ucell,
+                                                    const uint16_t* __restrict__ slot, int nslices, int zero_only) {
+  extern __shared__ __align__(16) unsigned char wide_smem[];
+  constexpr int S = WIDE_ROW_BYTES / (int)sizeof(T);  // values per cell and slice
+  constexpr int LPR = S / V;                          // lanes per row
+  T* lds = reinterpret_cast<T*>(wide_smem);                                    // WIDE_UCAP x S values
+  T* lw = reinterpret_cast<T*>(wide_smem + WIDE_UCAP * WIDE_ROW_BYTES);        // WIDE_ECAP weights
+  uint16_t* ls = reinterpret_cast<uint16_t*>(lw + WIDE_ECAP);                  // WIDE_ECAP slots
+  int32_t* lp = reinterpret_cast<int32_t*>(ls + WIDE_ECAP);                    // WIDE_ROWS + 1 row starts
+  const WideTile tl = tiles[blockIdx.x / nslices];
+  const int64_t l0 = (int64_t)(blockIdx.x % nslices) * S;
+  const int nv = (int)min<int64_t>(S, d.inner - l0) / V;  // vectors of this slice
+  T* __restrict__ f = static_cast<T*>(d.field);
+  const T* __restrict__ vals = static_cast<const T*>(d.csr_val);
+  typedef T vt __attribute__((ext_vector_type(V)));
+  if (!zero_only) {
+    // every staging load of this thread (source slices, entries, row starts)
+    // is issued before the first LDS store
+    constexpr int NIT = (WIDE_UCAP * LPR + 255) / 256;  // launched with 256 threads
+    constexpr int NE = (WIDE_ECAP + 255) / 256;
+    Pack<T, V> g[NIT];
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) {
+      const int e = threadIdx.x + k * 256;
+      const int u = e / LPR, v = e - u * LPR;
+      if (u < tl.nu && v < nv) {
+        T sign;
+        const int64_t sl = rot_slot<T>(d, tl.rot, l0 + (int64_t)v * V, sign);
+        g[k] = ldv<T, V>(f + (int64_t)ucell[tl.first_u + u] * d.cs + sl);
+      }
+    }
+    T ew[NE];
+    uint16_t es[NE];
+#pragma unroll
+    for (int k = 0; k < NE; ++k) {
+      const int e = threadIdx.x + k * 256;
+      if (e < tl.ne) {
+        ew[k] = vals[tl.e0 + e];
+        es[k] = slot[tl.e0 + e];
+      }
+    }
+    int32_t rp = 0;
+    if ((int)threadIdx.x <= tl.nrows) rp = (int32_t)(d.csr_ptr[tl.tab + threadIdx.x] - tl.e0);
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) {
+      const int e = threadIdx.x + k * 256;
+      const int u = e / LPR, v = e - u * LPR;
+      if (u < tl.nu && v < nv) {
+        vt w;
+#pragma unroll
+        for (int i = 0; i < V; ++i) w[i] = g[k].v[i];
+        *reinterpret_cast<vt*>(&lds[u * S + v * V]) = w;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NE; ++k) {
+      const int e = threadIdx.x + k * 256;
+      if (e < tl.ne) {
+        lw[e] = ew[k];
+        ls[e] = es[k];
+      }
+    }
+    if ((int)threadIdx.x <= tl.nrows) lp[threadIdx.x] = rp;
+    __syncthreads();
+  }
+  const int lane = threadIdx.x % LPR, grp = threadIdx.x / LPR, ngrp = blockDim.x / LPR;
+  if (lane >= nv) return;
+  const int64_t l = l0 + (int64_t)lane * V;
+  T sign;
+  (void)rot_slot<T>(d, tl.rot, l, sign);
+  const T* __restrict__ bt = static_cast<const T*>(d.bval) + tl.brow;
+  for (int r = grp; r < tl.nrows; r += ngrp) {
+    const int64_t dst = d.row_dst[tl.row_begin + r];
+    Pack<T, V> y;
+#pragma unroll
+    for (int i = 0; i < V; ++i) y.v[i] = T(0);
+    if (!zero_only) {
+      const int e0 = lp[r], e1 = lp[r + 1];
+      for (int e = e0; e < e1; ++e) {
+        const T w = lw[e];
+        const vt x = *reinterpret_cast<const vt*>(&lds[(int)ls[e] * S + lane * V]);
+#pragma unroll
+        for (int i = 0; i < V; ++i) y.v[i] = e == e0 ? w * x[i] : fma(w, x[i], y.v[i]);
+      }
+#pragma unroll
+      for (int i = 0; i < V; ++i) y.v[i] = sign * y.v[i];
+      if (tl.has_b) {
+        const T* bp = bt + (int64_t)r * tl.b_inner;
+#pragma unroll
+        for (int i = 0; i < V; ++i) y.v[i] += tl.b_inner == 1 ? bp[0] : bp[l + i];
+      }
+    }
+    stv<T, V, NT>(f + dst * d.cs + l, y);
+  }
+}
+
 // Data rows (block-edge averaging).  Every row of an apply reads the input
 // field, so data rows are first computed into scratch by extra workgroups of
 // the ghost-row launch (they only read data cells and write scratch), and
@@ -1242,6 +1346,9 @@ void device_upload_plan(Plan& p) {
   size_t o_b = pk.reals(T.bval, p.dtype);
   size_t o_rd = pk.vec(T.row_dst);
   size_t o_rs = pk.vec(T.row_src);
+  size_t o_wt = pk.vec(T.wtiles);
+  size_t o_wu = pk.vec(T.w_ucell);
+  size_t o_ws = pk.vec(T.w_slot);
   size_t o_drc = pk.vec(T.dr_cell);
   size_t o_drp = pk.vec(T.dr_ptr);
   size_t o_drk = pk.vec(T.dr_col);
@@ -1268,6 +1375,9 @@ void device_upload_plan(Plan& p) {
   p.d_bval = b + o_b;
   p.d_row_dst = reinterpret_cast<const int32_t*>(b + o_rd);
   p.d_row_src = reinterpret_cast<const int32_t*>(b + o_rs);
+  p.d_wtiles = reinterpret_cast<const WideTile*>(b + o_wt);
+  p.d_w_ucell = reinterpret_cast<const int32_t*>(b + o_wu);
+  p.d_w_slot = reinterpret_cast<const uint16_t*>(b + o_ws);
   p.d_dr_cell = reinterpret_cast<const int32_t*>(b + o_drc);
   p.d_dr_ptr = reinterpret_cast<const int64_t*>(b + o_drp);
   p.d_dr_col = reinterpret_cast<const int32_t*>(b + o_drk);
@@ -1408,9 +1518,34 @@ static void launch_rows(const PlanDesc& d, hipStream_t st, int grid, int blk, co
   }
 }
 
+template <typename T, int V>
+static void launch_wide(const Plan& p, const PlanDesc& d, hipStream_t st, bool zero_only) {
+  constexpr int S = WIDE_ROW_BYTES / (int)sizeof(T);
+  const int nslices = (int)((p.layout.inner + S - 1) / S);
+  const int grid = (int)p.host.wtiles.size() * nslices;
+  const size_t lds = zero_only ? 0
+                              : (size_t)WIDE_UCAP * WIDE_ROW_BYTES + (size_t)WIDE_ECAP * (sizeof(T) + 2) +
+                                    (size_t)(WIDE_ROWS + 1) * 4;
+  if (d.nt)
+    hipLaunchKernelGGL((k_apply_wide<T, V, true>), dim3(grid), dim3(256), lds, st, d, p.d_wtiles, p.d_w_ucell,
+                       p.d_w_slot, nslices, zero_only ? 1 : 0);
+  else
+    hipLaunchKernelGGL((k_apply_wide<T, V, false>), dim3(grid), dim3(256), lds, st, d, p.d_wtiles, p.d_w_ucell,
+                       p.d_w_slot, nslices, zero_only ? 1 : 0);
+  HIP_CHECK(hipGetLastError());
+}
+
 template <typename T>
 static void launch_apply_t(const Plan& p, const PlanDesc& d, hipStream_t st, bool zero_only) {
-  const int nt = (int)p.host.tiles.size();
+  if (p.layout.order == HBC_POINT_MAJOR && !p.host.wtiles.empty()) {
+    if (sizeof(T) == 4 && p.vec == 4)
+      launch_wide<T, (sizeof(T) == 4 ? 4 : 2)>(p, d, st, zero_only);
+    else if (p.vec >= 2)
+      launch_wide<T, 2>(p, d, st, zero_only);
+    else
+      launch_wide<T, 1>(p, d, st, zero_only);
+  }
+  const int nt = (int)(p.layout.order == HBC_POINT_MAJOR ? p.host.rtiles.size() : p.host.tiles.size());
   const int grid = p.tune.persistent > 0 ? std::min(p.tune.persistent, nt) : nt;
   const int blk = p.tune.block;
   const int z = zero_only ? 1 : 0;

@@ -735,6 +735,66 @@ hbc_tune default_tune(const Plan& plan) {
   return t;
 }
 
+// Wide-row tiles (see WideTile): consecutive rows of a wide CSR segment, in
+// device order, greedily while their distinct source cells fit WIDE_UCAP.
+static void build_wide(Plan& plan) {
+  HostTables& T = plan.host;
+  T.seg_wide.assign(T.segs.size(), 0);
+  T.wtiles.clear();
+  T.w_ucell.clear();
+  T.w_slot.assign(T.csr_col.size(), 0);
+  if (plan.layout.order != HBC_POINT_MAJOR) return;
+  const int64_t es = plan.dtype == HBC_F64 ? 8 : 4;
+  if (plan.layout.inner * es < WIDE_ROW_BYTES) return;
+  std::unordered_map<int32_t, int32_t> local;
+  for (size_t si = 0; si < T.segs.size(); ++si) {
+    const DevSeg& sg = T.segs[si];
+    if (sg.kind != SEG_CSR || sg.nrows == 0) continue;
+    const int64_t nnz = T.csr_ptr[sg.tab + sg.nrows] - T.csr_ptr[sg.tab];
+    if (nnz < WIDE_NNZ * sg.nrows) continue;
+    bool fits = true;
+    for (int64_t r = 0; r < sg.nrows && fits; ++r) {
+      local.clear();
+      for (int64_t e = T.csr_ptr[sg.tab + r]; e < T.csr_ptr[sg.tab + r + 1]; ++e) local[T.csr_col[e]] = 0;
+      fits = (int64_t)local.size() <= WIDE_UCAP && T.csr_ptr[sg.tab + r + 1] - T.csr_ptr[sg.tab + r] <= WIDE_ECAP;
+    }
+    if (!fits) continue;
+    T.seg_wide[si] = 1;
+    int64_t r = 0;
+    while (r < sg.nrows) {
+      WideTile w{};
+      w.rot = sg.rot;
+      w.has_b = sg.has_b;
+      w.b_inner = sg.b_inner;
+      w.row_begin = sg.row_base + r;
+      w.tab = sg.tab + r;
+      w.brow = sg.brow + r * sg.b_inner;
+      w.first_u = (int32_t)T.w_ucell.size();
+      w.e0 = T.csr_ptr[sg.tab + r];
+      local.clear();
+      while (r < sg.nrows && w.nrows < WIDE_ROWS) {
+        int add = 0;
+        for (int64_t e = T.csr_ptr[sg.tab + r]; e < T.csr_ptr[sg.tab + r + 1]; ++e)
+          if (!local.count(T.csr_col[e])) ++add;  // repeats within the row count twice: conservative
+        const int64_t ne = T.csr_ptr[sg.tab + r + 1] - w.e0;
+        if (w.nu + add > WIDE_UCAP || ne > WIDE_ECAP) break;
+        for (int64_t e = T.csr_ptr[sg.tab + r]; e < T.csr_ptr[sg.tab + r + 1]; ++e) {
+          auto it = local.find(T.csr_col[e]);
+          if (it == local.end()) {
+            it = local.emplace(T.csr_col[e], w.nu++).first;
+            T.w_ucell.push_back(T.csr_col[e]);
+          }
+          T.w_slot[e] = (uint16_t)it->second;
+        }
+        ++w.nrows;
+        ++r;
+      }
+      w.ne = (int32_t)(T.csr_ptr[sg.tab + r] - w.e0);
+      T.wtiles.push_back(w);
+    }
+  }
+}
+
 void build_tiles(Plan& plan, const hbc_tune& t) {
   if (t.block < 64 || t.block > 256 || t.block % 64) fail(HBC_EINVAL, "block must be 64, 128, 192 or 256");
   if (t.lanes_per_row < 1 || (t.lanes_per_row & (t.lanes_per_row - 1)) || t.lanes_per_row > t.block)
@@ -773,8 +833,10 @@ void build_tiles(Plan& plan, const hbc_tune& t) {
   plan.tune = t;
   // the same cut as point-major row tiles (same XCD-aware order)
   plan.host.rtiles.clear();
+  if (plan.host.seg_wide.size() != plan.host.segs.size()) build_wide(plan);
   for (const DevTile& tl : plan.host.tiles) {
     const DevSeg& sg = plan.host.segs[tl.seg];
+    if (plan.host.seg_wide[tl.seg]) continue;  // served by the wide-row tiles
     RowTile rt{};
     rt.kind = sg.kind;
     rt.rot = sg.rot;

@@ -58,3 +58,46 @@ def test_quadrature_rows(N, h, nf, nl, q, dtype):
     assert (d <= tol).all(), float((d / np.maximum(tol, 1e-300)).max())
     corners = np.isin(G, np.concatenate([og.cells_of_box(f, b) for f in range(6) for b in ocs.corner_boxes(f, N, h)]))
     assert (got[G][corners] == 0).all()
+
+
+@pytest.mark.parametrize("nl,dtype", [(8, "f64"), (16, "f32"), (12, "f64")])
+def test_quadrature_rows_staged(nl, dtype):
+    """Rows of >= 256 bytes take the LDS-staged wide-row kernel (several
+    inner-value slices per tile, partial last slice for nl = 12)."""
+    N, h, nf, q = 10, 3, 4, 2
+    I = nf * nl
+    vec = (2 * nl, nl, nl)
+    dt = hb.F64 if dtype == "f64" else hb.F32
+    g = hb.Grid.cubed_sphere(N, h)
+    p = hb.Program(g)
+    p.cs_add_quadrature(N, h, q, vector=True)
+    rng = np.random.default_rng(nl)
+    b = rng.standard_normal((N * h, I))
+    p.add_vector(ocs.side_box(3, ocs.RIGHT, N, h), b, ninner=I)
+    plan = hb.Plan(p, inner=I, vec=vec, dtype=dt)
+    full = cs_full_field(N, h, nf, nl, seed=30 + nl)
+    t = torch.from_numpy(full.astype(np.float64 if dt == hb.F64 else np.float32)).cuda()
+    hb.apply(plan, t)
+    torch.cuda.synchronize()
+    got = t.cpu().numpy().astype(np.float64)
+    og = ocs.grid(N, h)
+    from oracle import VectorSub
+    op = assemble(og, oq.subs(N, h, q, vector=True) + [VectorSub(ocs.side_box(3, ocs.RIGHT, N, h), b)])
+    ref = o_apply(op, full, vec)
+    G = og.ghost_cells
+    pat, mag = wide_bounds(op, full, og, vec)
+    ulp = 2.0 ** -53 if dt == hb.F64 else 2.0 ** -24
+    tol = 1e-13 * pat + 64 * ulp * (mag + np.abs(ref[G]))
+    d = np.abs(got[G] - ref[G])
+    assert (d <= tol).all(), float((d / np.maximum(tol, 1e-300)).max())
+    # the adjoint through the same plan: dot-product identity
+    y = torch.randn(g.cells, I, dtype=t.dtype, device="cuda", generator=torch.Generator("cuda").manual_seed(3))
+    x = torch.from_numpy(np.nan_to_num(full, nan=0.0).astype(np.float64 if dt == hb.F64 else np.float32)).cuda()
+    Ax, z, Aty = x.clone(), torch.zeros_like(x), y.clone()
+    hb.apply(plan, Ax)
+    hb.apply(plan, z)
+    hb.apply_adjoint(plan, Aty)
+    torch.cuda.synchronize()
+    lhs = float(((Ax.double() - z.double()) * y.double()).sum())
+    rhs = float((x.double() * Aty.double()).sum())
+    assert abs(lhs - rhs) <= (1e-12 if dt == hb.F64 else 1e-5) * max(abs(lhs), abs(rhs))
