@@ -50,7 +50,7 @@ struct PlanDesc {
   int32_t chunked;    // point-major: each row group walks a contiguous run of rows
   int32_t nt;         // results go out with non-temporal stores (rows of >= 128 bytes)
   int32_t unroll;     // accesses of vec elements per lane and row (point-major)
-  int32_t pad_;
+  int32_t general;    // the row tiles hold general ELL/CSR rows
   const int32_t* row_dst;  // point-major row tables
   const int32_t* row_src;
 };
@@ -277,7 +277,10 @@ __device__ __forceinline__ void run_tile_pm(const PlanDesc& d, const DevSeg& s, 
 // U > 1: a lane carries U accesses of V elements per row, lpr apart (rows
 // whose length is not a multiple of a 16-byte vector still keep 16 bytes of
 // loads per lane and source in flight, and every access stays coalesced).
-template <typename T, int V, int U, bool NT, int RB>
+// GEN: the tile list may hold general ELL/CSR rows (other than the 4-wide
+// Lagrange rows); without it that path is compiled out (its registers would
+// lower the occupancy of every other kind).
+template <typename T, int V, int U, bool NT, int RB, bool GEN>
 __device__ __forceinline__ void rt_tile(const PlanDesc& d, const RowTile& tl, bool zero_only) {
   const int lpr = 1 << d.lpr_shift;
   const int ngroups = (int)blockDim.x >> d.lpr_shift;
@@ -409,7 +412,7 @@ __device__ __forceinline__ void rt_tile(const PlanDesc& d, const RowTile& tl, bo
                 y[q][u].v[i] = sign[u] * a;
               }
         }
-      } else if (kind == SEG_ELL || kind == SEG_CSR) {
+      } else if (GEN && (kind == SEG_ELL || kind == SEG_CSR)) {
         // general rows (any width): entries in chunks of EC, each chunk's
         // columns and weights read together, then all its source loads, then
         // the sum in entry order (first product, then FMAs)
@@ -663,7 +666,7 @@ __device__ __forceinline__ void data_gather_rows(const PlanDesc& d, const DataDe
   }
 }
 
-template <typename T, int V, int U, bool NT, int RB>
+template <typename T, int V, int U, bool NT, int RB, bool GEN>
 __global__ __launch_bounds__(256) void k_apply_rows(PlanDesc d, const RowTile* __restrict__ tiles, int ntiles,
                                                     int zero_only, DataDesc dd) {
   // the first dd.grid workgroups gather data rows (dispatched first, they
@@ -675,7 +678,7 @@ __global__ __launch_bounds__(256) void k_apply_rows(PlanDesc d, const RowTile* _
   const int main = (int)gridDim.x - dd.grid;
   for (int t = (int)blockIdx.x - dd.grid; t < ntiles; t += main) {
     const RowTile tl = tiles[t];
-    rt_tile<T, V, U, NT, RB>(d, tl, zero_only != 0);
+    rt_tile<T, V, U, NT, RB, GEN>(d, tl, zero_only != 0);
   }
 }
 
@@ -694,18 +697,18 @@ template <typename T, bool NT>
 __device__ __forceinline__ void rt_tile_any(const PlanDesc& d, const RowTile& tl) {
   if (sizeof(T) == 4) {
     if (d.vec == 4)
-      rt_tile<T, (sizeof(T) == 4 ? 4 : 2), 1, NT, 4>(d, tl, false);
+      rt_tile<T, (sizeof(T) == 4 ? 4 : 2), 1, NT, 4, true>(d, tl, false);
     else if (d.vec == 2)
-      d.unroll >= 2 ? rt_tile<T, 2, 2, NT, 4>(d, tl, false) : rt_tile<T, 2, 1, NT, 4>(d, tl, false);
+      d.unroll >= 2 ? rt_tile<T, 2, 2, NT, 4, true>(d, tl, false) : rt_tile<T, 2, 1, NT, 4, true>(d, tl, false);
     else if (d.unroll >= 4)
-      rt_tile<T, 1, 4, NT, 4>(d, tl, false);
+      rt_tile<T, 1, 4, NT, 4, true>(d, tl, false);
     else
-      d.unroll >= 2 ? rt_tile<T, 1, 2, NT, 4>(d, tl, false) : rt_tile<T, 1, 1, NT, 4>(d, tl, false);
+      d.unroll >= 2 ? rt_tile<T, 1, 2, NT, 4, true>(d, tl, false) : rt_tile<T, 1, 1, NT, 4, true>(d, tl, false);
   } else {
     if (d.vec >= 2)
-      rt_tile<T, 2, 1, NT, 4>(d, tl, false);
+      rt_tile<T, 2, 1, NT, 4, true>(d, tl, false);
     else
-      d.unroll >= 2 ? rt_tile<T, 1, 2, NT, 4>(d, tl, false) : rt_tile<T, 1, 1, NT, 4>(d, tl, false);
+      d.unroll >= 2 ? rt_tile<T, 1, 2, NT, 4, true>(d, tl, false) : rt_tile<T, 1, 1, NT, 4, true>(d, tl, false);
   }
 }
 
@@ -1076,13 +1079,7 @@ __device__ __forceinline__ T bc_load(const T* __restrict__ x, const StDesc& st, 
 // y = 27 x_c - (S(z-1) + S(z) + S(z+1)) = 26 x_c - (sum of the 26 neighbours).
 // FUSED: values outside a block's data box are read through the BC (the
 // source block for halo copies, zero for padding).
-#ifndef HBC_ST_TY
-#define HBC_ST_TY 8
-#endif
-#ifndef HBC_ST_ZC
-#define HBC_ST_ZC 32
-#endif
-constexpr int ST_TX = 64, ST_TY = HBC_ST_TY, ST_ZC = HBC_ST_ZC;
+constexpr int ST_TX = 64, ST_TY = 8, ST_ZC = 32;  // 64 x 16 and 16..64 planes measured: no gain
 constexpr int ST_RPT = ST_TY / 4;  // output rows per thread (4 wavefronts of 64 columns)
 constexpr int ST_LX = ST_TX + 2, ST_LY = ST_TY + 2, ST_PLANE = ST_LX * ST_LY;
 static_assert(ST_TY % 4 == 0, "tile rows must split over 4 wavefronts");
@@ -1155,7 +1152,7 @@ __global__ __launch_bounds__(256) void k_stencil27(const T* __restrict__ x, T* _
   const int ntx = (st.nx + ST_TX - 1) / ST_TX, nty = (st.ny + ST_TY - 1) / ST_TY, nzc = (st.nz + ST_ZC - 1) / ST_ZC;
   const int nst = ntx * nty * nzc * st.nblk;
   if ((int)blockIdx.x >= nst) {
-    for (int t = blockIdx.x - nst; t < bc_nt; t += bc_grid) rt_tile<T, V, 1, false, 4>(d, bc_tiles[t], false);
+    for (int t = blockIdx.x - nst; t < bc_nt; t += bc_grid) rt_tile<T, V, 1, false, 4, true>(d, bc_tiles[t], false);
     return;
   }
   int bid;
@@ -1307,6 +1304,9 @@ PlanDesc make_desc(const Plan& p, void* field) {
   d.chunked = p.tune.lanes_per_row >= CHUNK_LPR ? 1 : 0;
   d.nt = (p.layout.order == HBC_POINT_MAJOR && p.layout.inner * (p.dtype == HBC_F64 ? 8 : 4) >= 128) ? 1 : 0;
   d.unroll = p.unroll;
+  d.general = 0;
+  for (const RowTile& t : p.host.rtiles)
+    if (t.kind == SEG_CSR || (t.kind == SEG_ELL && (t.width != 4 || (t.flags & SEGF_ELL_PADDED)))) d.general = 1;
   return d;
 }
 
@@ -1484,14 +1484,26 @@ template <typename T, int V, int U>
 static void launch_rows_vu(const PlanDesc& d, hipStream_t st, int grid, int blk, const RowTile* tiles, int nt, int z,
                            const DataDesc& dd) {
   const bool rb2 = rows_per_batch(1 << d.lpr_shift) == 2;
-  if (d.nt && rb2)
-    hipLaunchKernelGGL((k_apply_rows<T, V, U, true, 2>), dim3(grid + dd.grid), dim3(blk), 0, st, d, tiles, nt, z, dd);
-  else if (d.nt)
-    hipLaunchKernelGGL((k_apply_rows<T, V, U, true, 4>), dim3(grid + dd.grid), dim3(blk), 0, st, d, tiles, nt, z, dd);
-  else if (rb2)
-    hipLaunchKernelGGL((k_apply_rows<T, V, U, false, 2>), dim3(grid + dd.grid), dim3(blk), 0, st, d, tiles, nt, z, dd);
-  else
-    hipLaunchKernelGGL((k_apply_rows<T, V, U, false, 4>), dim3(grid + dd.grid), dim3(blk), 0, st, d, tiles, nt, z, dd);
+  const dim3 g(grid + dd.grid), b(blk);
+  if (d.general) {
+    if (d.nt && rb2)
+      hipLaunchKernelGGL((k_apply_rows<T, V, U, true, 2, true>), g, b, 0, st, d, tiles, nt, z, dd);
+    else if (d.nt)
+      hipLaunchKernelGGL((k_apply_rows<T, V, U, true, 4, true>), g, b, 0, st, d, tiles, nt, z, dd);
+    else if (rb2)
+      hipLaunchKernelGGL((k_apply_rows<T, V, U, false, 2, true>), g, b, 0, st, d, tiles, nt, z, dd);
+    else
+      hipLaunchKernelGGL((k_apply_rows<T, V, U, false, 4, true>), g, b, 0, st, d, tiles, nt, z, dd);
+  } else {
+    if (d.nt && rb2)
+      hipLaunchKernelGGL((k_apply_rows<T, V, U, true, 2, false>), g, b, 0, st, d, tiles, nt, z, dd);
+    else if (d.nt)
+      hipLaunchKernelGGL((k_apply_rows<T, V, U, true, 4, false>), g, b, 0, st, d, tiles, nt, z, dd);
+    else if (rb2)
+      hipLaunchKernelGGL((k_apply_rows<T, V, U, false, 2, false>), g, b, 0, st, d, tiles, nt, z, dd);
+    else
+      hipLaunchKernelGGL((k_apply_rows<T, V, U, false, 4, false>), g, b, 0, st, d, tiles, nt, z, dd);
+  }
 }
 
 // point-major row tiles: one instance per (vec, unroll) a plan can select
