@@ -277,10 +277,12 @@ __device__ __forceinline__ void run_tile_pm(const PlanDesc& d, const DevSeg& s, 
 // U > 1: a lane carries U accesses of V elements per row, lpr apart (rows
 // whose length is not a multiple of a 16-byte vector still keep 16 bytes of
 // loads per lane and source in flight, and every access stays coalesced).
-// GEN: the tile list may hold general ELL/CSR rows (other than the 4-wide
-// Lagrange rows); without it that path is compiled out (its registers would
-// lower the occupancy of every other kind).
-template <typename T, int V, int U, bool NT, int RB, bool GEN>
+// KM: the row kinds the tile list may hold besides copies, zero and b rows:
+// bit 0 the 4-wide Lagrange rows, bit 1 general ELL/CSR rows.  Paths of
+// absent kinds are compiled out (their registers would lower the occupancy of
+// every other kind).
+constexpr int KM_ELL4 = 1, KM_GENERAL = 2;
+template <typename T, int V, int U, bool NT, int RB, int KM>
 __device__ __forceinline__ void rt_tile(const PlanDesc& d, const RowTile& tl, bool zero_only) {
   const int lpr = 1 << d.lpr_shift;
   const int ngroups = (int)blockDim.x >> d.lpr_shift;
@@ -306,7 +308,7 @@ __device__ __forceinline__ void rt_tile(const PlanDesc& d, const RowTile& tl, bo
   const int last = rb + ((re - 1 - rb) / rs) * rs;
   const int32_t* __restrict__ rdst = d.row_dst + tl.row_begin;
   const int32_t* __restrict__ rsrc = d.row_src + tl.row_begin;
-  const bool ell4 = kind == SEG_ELL && tl.width == 4 && !(tl.flags & SEGF_ELL_PADDED);
+  const bool ell4 = (KM & KM_ELL4) && kind == SEG_ELL && tl.width == 4 && !(tl.flags & SEGF_ELL_PADDED);
   const T* __restrict__ bt = static_cast<const T*>(d.bval) + tl.brow;
   const bool rotates = kind == SEG_MAP || kind == SEG_ELL || kind == SEG_CSR;
   for (int64_t v0 = lane; v0 < nvec; v0 += (int64_t)lpr * U) {
@@ -412,7 +414,7 @@ __device__ __forceinline__ void rt_tile(const PlanDesc& d, const RowTile& tl, bo
                 y[q][u].v[i] = sign[u] * a;
               }
         }
-      } else if (GEN && (kind == SEG_ELL || kind == SEG_CSR)) {
+      } else if ((KM & KM_GENERAL) && (kind == SEG_ELL || kind == SEG_CSR)) {
         // general rows (any width): entries in chunks of EC, each chunk's
         // columns and weights read together, then all its source loads, then
         // the sum in entry order (first product, then FMAs)
@@ -666,7 +668,7 @@ __device__ __forceinline__ void data_gather_rows(const PlanDesc& d, const DataDe
   }
 }
 
-template <typename T, int V, int U, bool NT, int RB, bool GEN>
+template <typename T, int V, int U, bool NT, int RB, int KM>
 __global__ __launch_bounds__(256) void k_apply_rows(PlanDesc d, const RowTile* __restrict__ tiles, int ntiles,
                                                     int zero_only, DataDesc dd) {
   // the first dd.grid workgroups gather data rows (dispatched first, they
@@ -678,7 +680,7 @@ __global__ __launch_bounds__(256) void k_apply_rows(PlanDesc d, const RowTile* _
   const int main = (int)gridDim.x - dd.grid;
   for (int t = (int)blockIdx.x - dd.grid; t < ntiles; t += main) {
     const RowTile tl = tiles[t];
-    rt_tile<T, V, U, NT, RB, GEN>(d, tl, zero_only != 0);
+    rt_tile<T, V, U, NT, RB, KM>(d, tl, zero_only != 0);
   }
 }
 
@@ -693,35 +695,35 @@ __global__ __launch_bounds__(256) void k_apply_pm(PlanDesc d, const DevTile* __r
 }
 
 // Batch tiles of different plans: (vec, unroll) chosen per tile at run time.
-template <typename T, bool NT>
+template <typename T, bool NT, int KM>
 __device__ __forceinline__ void rt_tile_any(const PlanDesc& d, const RowTile& tl) {
   if (sizeof(T) == 4) {
     if (d.vec == 4)
-      rt_tile<T, (sizeof(T) == 4 ? 4 : 2), 1, NT, 4, true>(d, tl, false);
-    else if (d.vec == 2)
-      d.unroll >= 2 ? rt_tile<T, 2, 2, NT, 4, true>(d, tl, false) : rt_tile<T, 2, 1, NT, 4, true>(d, tl, false);
+      rt_tile<T, (sizeof(T) == 4 ? 4 : 2), 1, NT, 4, KM>(d, tl, false);
+    else if (d.vec == 2)  // unrolled rows take batches of 2 (registers of the whole batch kernel)
+      d.unroll >= 2 ? rt_tile<T, 2, 2, NT, 2, KM>(d, tl, false) : rt_tile<T, 2, 1, NT, 4, KM>(d, tl, false);
     else if (d.unroll >= 4)
-      rt_tile<T, 1, 4, NT, 4, true>(d, tl, false);
+      rt_tile<T, 1, 4, NT, 2, KM>(d, tl, false);
     else
-      d.unroll >= 2 ? rt_tile<T, 1, 2, NT, 4, true>(d, tl, false) : rt_tile<T, 1, 1, NT, 4, true>(d, tl, false);
+      d.unroll >= 2 ? rt_tile<T, 1, 2, NT, 2, KM>(d, tl, false) : rt_tile<T, 1, 1, NT, 4, KM>(d, tl, false);
   } else {
     if (d.vec >= 2)
-      rt_tile<T, 2, 1, NT, 4, true>(d, tl, false);
+      rt_tile<T, 2, 1, NT, 4, KM>(d, tl, false);
     else
-      d.unroll >= 2 ? rt_tile<T, 1, 2, NT, 4, true>(d, tl, false) : rt_tile<T, 1, 1, NT, 4, true>(d, tl, false);
+      d.unroll >= 2 ? rt_tile<T, 1, 2, NT, 2, KM>(d, tl, false) : rt_tile<T, 1, 1, NT, 4, KM>(d, tl, false);
   }
 }
 
-template <typename T>
+template <typename T, int KM>
 __global__ __launch_bounds__(256) void k_batch(const PlanDesc* __restrict__ descs, const RowTile* __restrict__ tiles,
                                                int ntiles) {
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const RowTile tl = tiles[t];
     const PlanDesc d = descs[tl.pad_];
     if (d.nt)
-      rt_tile_any<T, true>(d, tl);
+      rt_tile_any<T, true, KM>(d, tl);
     else
-      rt_tile_any<T, false>(d, tl);
+      rt_tile_any<T, false, KM>(d, tl);
   }
 }
 
@@ -1151,9 +1153,12 @@ __global__ __launch_bounds__(256) void k_stencil27(const T* __restrict__ x, T* _
   __shared__ int64_t info[27];  // this block's direction table, read once
   const int ntx = (st.nx + ST_TX - 1) / ST_TX, nty = (st.ny + ST_TY - 1) / ST_TY, nzc = (st.nz + ST_ZC - 1) / ST_ZC;
   const int nst = ntx * nty * nzc * st.nblk;
-  if ((int)blockIdx.x >= nst) {
-    for (int t = blockIdx.x - nst; t < bc_nt; t += bc_grid) rt_tile<T, V, 1, false, 4, true>(d, bc_tiles[t], false);
-    return;
+  if constexpr (FUSED) {
+    // halo programs the consumer accepts hold copies and zero rows only
+    if ((int)blockIdx.x >= nst) {
+      for (int t = blockIdx.x - nst; t < bc_nt; t += bc_grid) rt_tile<T, V, 1, false, 4, 0>(d, bc_tiles[t], false);
+      return;
+    }
   }
   int bid;
   {
@@ -1487,22 +1492,22 @@ static void launch_rows_vu(const PlanDesc& d, hipStream_t st, int grid, int blk,
   const dim3 g(grid + dd.grid), b(blk);
   if (d.general) {
     if (d.nt && rb2)
-      hipLaunchKernelGGL((k_apply_rows<T, V, U, true, 2, true>), g, b, 0, st, d, tiles, nt, z, dd);
+      hipLaunchKernelGGL((k_apply_rows<T, V, U, true, 2, 3>), g, b, 0, st, d, tiles, nt, z, dd);
     else if (d.nt)
-      hipLaunchKernelGGL((k_apply_rows<T, V, U, true, 4, true>), g, b, 0, st, d, tiles, nt, z, dd);
+      hipLaunchKernelGGL((k_apply_rows<T, V, U, true, 4, 3>), g, b, 0, st, d, tiles, nt, z, dd);
     else if (rb2)
-      hipLaunchKernelGGL((k_apply_rows<T, V, U, false, 2, true>), g, b, 0, st, d, tiles, nt, z, dd);
+      hipLaunchKernelGGL((k_apply_rows<T, V, U, false, 2, 3>), g, b, 0, st, d, tiles, nt, z, dd);
     else
-      hipLaunchKernelGGL((k_apply_rows<T, V, U, false, 4, true>), g, b, 0, st, d, tiles, nt, z, dd);
+      hipLaunchKernelGGL((k_apply_rows<T, V, U, false, 4, 3>), g, b, 0, st, d, tiles, nt, z, dd);
   } else {
     if (d.nt && rb2)
-      hipLaunchKernelGGL((k_apply_rows<T, V, U, true, 2, false>), g, b, 0, st, d, tiles, nt, z, dd);
+      hipLaunchKernelGGL((k_apply_rows<T, V, U, true, 2, 1>), g, b, 0, st, d, tiles, nt, z, dd);
     else if (d.nt)
-      hipLaunchKernelGGL((k_apply_rows<T, V, U, true, 4, false>), g, b, 0, st, d, tiles, nt, z, dd);
+      hipLaunchKernelGGL((k_apply_rows<T, V, U, true, 4, 1>), g, b, 0, st, d, tiles, nt, z, dd);
     else if (rb2)
-      hipLaunchKernelGGL((k_apply_rows<T, V, U, false, 2, false>), g, b, 0, st, d, tiles, nt, z, dd);
+      hipLaunchKernelGGL((k_apply_rows<T, V, U, false, 2, 1>), g, b, 0, st, d, tiles, nt, z, dd);
     else
-      hipLaunchKernelGGL((k_apply_rows<T, V, U, false, 4, false>), g, b, 0, st, d, tiles, nt, z, dd);
+      hipLaunchKernelGGL((k_apply_rows<T, V, U, false, 4, 1>), g, b, 0, st, d, tiles, nt, z, dd);
   }
 }
 
@@ -1979,10 +1984,21 @@ void device_batch_apply(Batch* b, void* stream) {
   const int nt = (int)b->tiles.size();
   if (nt == 0) return;
   const int grid = b->tune.persistent > 0 ? std::min(b->tune.persistent, nt) : nt;
-  if (b->dtype == HBC_F64)
-    hipLaunchKernelGGL(k_batch<double>, dim3(grid), dim3(b->tune.block), 0, S(stream), b->d_descs, b->d_tiles, nt);
-  else
-    hipLaunchKernelGGL(k_batch<float>, dim3(grid), dim3(b->tune.block), 0, S(stream), b->d_descs, b->d_tiles, nt);
+  bool gen = false;  // any general ELL/CSR rows among the tiles
+  for (const RowTile& t : b->tiles)
+    if (t.kind == SEG_CSR || (t.kind == SEG_ELL && (t.width != 4 || (t.flags & SEGF_ELL_PADDED)))) gen = true;
+  const dim3 g(grid), blk(b->tune.block);
+  if (b->dtype == HBC_F64) {
+    if (gen)
+      hipLaunchKernelGGL((k_batch<double, 3>), g, blk, 0, S(stream), b->d_descs, b->d_tiles, nt);
+    else
+      hipLaunchKernelGGL((k_batch<double, 1>), g, blk, 0, S(stream), b->d_descs, b->d_tiles, nt);
+  } else {
+    if (gen)
+      hipLaunchKernelGGL((k_batch<float, 3>), g, blk, 0, S(stream), b->d_descs, b->d_tiles, nt);
+    else
+      hipLaunchKernelGGL((k_batch<float, 1>), g, blk, 0, S(stream), b->d_descs, b->d_tiles, nt);
+  }
   HIP_CHECK(hipGetLastError());
 }
 
