@@ -669,7 +669,7 @@ def main():
                    "inner": 256, "ghost_values_per_apply": st["ghost_values"], "copies": args.copies},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile("apply_c384_f64_pmc.json"),
-                     "alg_bytes_per_launch": st["alg_bytes"], "kernel": "hbc::k_apply_rows<double, 2, 1, true, 2>"},
+                     "alg_bytes_per_launch": st["alg_bytes"], "kernel": "hbc::k_apply_rows<double, 2, 1, true, 2, 1>"},
         "cpu_baseline": {"value": st["ghost_values"] * reps / dt, "unit": "ghost cells/s", "cores": 1,
                          "kind": "oracle",
                          "sample": f"{reps} full applies of the C384 operator (scipy CSR A @ X over 256 inner "
