@@ -1,0 +1,110 @@
+"""Full-size GPU checks in the launch configurations the bench times.
+
+* C384, halo 3, 256 inner values (4 fields x 64 levels, (u, v) rotated),
+  FP64, after the autotuner has picked the launch shape: sampled ghost rows
+  (all 256 values of each; edge strips and corners) against the rows the
+  oracle evaluates one by one from the geometry;
+* C768, halo 3, 32 levels, with a sub-vector b on every side: the adjoint
+  against the forward through the dot-product identity.
+"""
+import numpy as np
+import pytest
+
+import synthinputs
+from helpers import gpu_available
+from oracle import cubed_sphere as ocs
+
+pytestmark = [pytest.mark.gpu]
+
+U64 = 2.0 ** -53
+
+if gpu_available():
+    import torch
+
+    import paper_2605_14780_amd as hb
+
+
+def test_c384_sampled_rows_tuned_shape(tmp_path):
+    N, h, nf, nl = 384, 3, 4, 64
+    I = nf * nl
+    vec = (2 * nl, nl, nl)
+    W = N + 2 * h
+    grid, prog = hb.cs_program(N, h, hb.CS_LAGRANGE, vector=True)
+    plan = hb.Plan(prog, inner=I, vec=vec, dtype=hb.F64)
+    data = synthinputs.cs_sh_field_torch(N, nf, nl, seed=2, device="cuda")
+    full = torch.full((6, W, W, I), float("nan"), dtype=torch.float64, device="cuda")
+    full[:, h:h + N, h:h + N] = data
+    full = full.reshape(-1, I)
+    del data
+    plan.autotune([full.clone() for _ in range(2)], str(tmp_path / "tune.jsonl"))
+    out = full.clone()
+    hb.apply(plan, out)
+    torch.cuda.synchronize()
+    assert torch.isfinite(out).all(), "a ghost was left unwritten"
+    rng = np.random.default_rng(0)
+    u_sl = np.arange(vec[0], vec[0] + vec[2])
+    v_sl = u_sl + vec[1]
+    rows = corners = 0
+    while rows < 1500:
+        f = int(rng.integers(6))
+        j, i = (int(v) for v in rng.integers(-h, N + h, size=2))
+        if 0 <= j < N and 0 <= i < N:
+            continue
+        got = out[(f * W + (j + h)) * W + (i + h)].cpu().numpy()
+        if ocs.is_corner(j, i, N):
+            assert (got == 0).all() and not np.signbit(got).any(), (f, j, i)
+            corners += 1
+            continue
+        ents = ocs.lagrange_entries(f, j, i, N)
+        src = [(g * W + (jj + h)) * W + (ii + h) for (g, jj, ii), _ in ents]
+        w = np.array([wv for _, wv in ents])
+        X = full[torch.tensor(src, device="cuda")].cpu().numpy()
+        y = w @ X
+        R = ocs.rside(f, ocs.side_of(j, i, N))
+        ref = y.copy()
+        ref[u_sl] = R[0, 0] * y[u_sl] + R[0, 1] * y[v_sl]
+        ref[v_sl] = R[1, 0] * y[u_sl] + R[1, 1] * y[v_sl]
+        # arithmetic: 1e-13 of sum |w x|; position: the fractional index is
+        # known to ~8 N eps and the weights' slopes stay below 4
+        ax = np.abs(X).sum(axis=0)
+        wx = np.abs(w) @ np.abs(X)
+        bnd = 1e-13 * np.maximum(wx, 1e-300) + 8 * N * U64 * 4 * ax
+        bnd_rot = bnd.copy()
+        bnd_rot[u_sl] = np.maximum(bnd[u_sl], bnd[v_sl])
+        bnd_rot[v_sl] = bnd_rot[u_sl]
+        assert (np.abs(got - ref) <= bnd_rot).all(), (f, j, i)
+        rows += 1
+    assert corners > 0
+
+
+def test_c768_adjoint_dot_product():
+    N, h, L = 768, 3, 32
+    W = N + 2 * h
+    grid, prog = hb.cs_program(N, h, hb.CS_LAGRANGE)
+    rng = np.random.default_rng(5)
+    for f in range(6):
+        for side in (ocs.LEFT, ocs.RIGHT, ocs.BOTTOM, ocs.TOP):
+            prog.add_vector(ocs.side_box(f, side, N, h), rng.normal(size=(N * h, L)), ninner=L)
+    plan = hb.Plan(prog, inner=L, dtype=hb.F64)
+    x = torch.zeros((6, W, W, L), dtype=torch.float64, device="cuda")
+    x[:, h:h + N, h:h + N] = synthinputs.cs_sh_field_torch(N, 1, L, seed=5, device="cuda")
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    y = torch.randn(x.shape, dtype=torch.float64, device="cuda", generator=gen)
+    y[:, h:h + N, h:h + N] = 0.0      # only the BC part enters the identity
+    x, y = x.reshape(-1), y.reshape(-1)
+    Ax, b = x.clone(), torch.zeros_like(x)
+    hb.apply(plan, Ax)
+    hb.apply(plan, b)
+    Aty = y.clone()
+    hb.apply_adjoint(plan, Aty)
+    torch.cuda.synchronize()
+    Ax -= b
+    lhs_t, rhs_t = Ax * y, x * Aty
+    lhs, rhs = float(lhs_t.sum()), float(rhs_t.sum())
+    scale = float(lhs_t.abs().sum() + rhs_t.abs().sum())
+    assert abs(lhs - rhs) <= 1e-12 * scale, (lhs, rhs, scale)
+    assert abs(lhs) > 1e-6 * scale
+    # covered ghosts of the adjoint are cleared
+    G = torch.ones((6, W, W), dtype=torch.bool, device="cuda")
+    G[:, h:h + N, h:h + N] = False
+    assert (Aty.reshape(6, W, W, L)[G] == 0).all()
