@@ -170,20 +170,22 @@ struct alignas(16) RowTile {
 };
 
 // Wide rows (CSR segments averaging >= WIDE_NNZ entries per row, rows of
-// >= WIDE_ROW_BYTES, point-major): cut into tiles of consecutive rows whose
-// distinct source cells (at most WIDE_UCAP) are staged in LDS one slice of
-// WIDE_ROW_BYTES of their inner values at a time; each entry carries the LDS
-// slot of its source.
-// The tile's entries (at most WIDE_ECAP) and row pointers are staged too.
+// >= WIDE_ROW_BYTES, point-major).  A segment's rows are visited with its
+// thinnest box dimension innermost (for a halo strip: every ghost layer at one
+// tangential position, then the next position), and cut greedily into tiles
+// of at most WIDE_ROWS rows whose distinct source cells (at most WIDE_UCAP)
+// and entries (at most WIDE_ECAP) fit.  The kernel stages a tile's source
+// cells in LDS one slice of WIDE_ROW_BYTES of inner values at a time; each
+// tile has its own copy of its rows' entries (weight, LDS slot of the source)
+// and row starts, in tile order.
 constexpr int WIDE_NNZ = 8, WIDE_UCAP = 128, WIDE_ROWS = 32, WIDE_ROW_BYTES = 128, WIDE_ECAP = 512;
 struct alignas(16) WideTile {
   int32_t rot, has_b, b_inner, nrows;
-  int64_t row_begin;  // index into the per-row tables
-  int64_t tab;        // index of the first row's CSR pointer
-  int64_t brow;       // b table offset of the first row
-  int32_t first_u, nu;
-  int64_t e0;         // first entry (csr_ptr[tab])
-  int32_t ne, pad_;   // entries of the tile's rows
+  int64_t row_base;  // the segment's first row in the per-row tables
+  int64_t brow;      // the segment's first row in the b table
+  int32_t first_u, nu;  // distinct source cells: w_ucell[first_u, first_u + nu)
+  int32_t e0, ne;       // entries: w_ent*[e0, e0 + ne)
+  int32_t r0, rp0;      // rows: w_row[r0, r0 + nrows); row starts: w_rp[rp0, rp0 + nrows]
 };
 
 // Adjoint: one entry per (source cell, ghost row) contribution, sorted by
@@ -264,7 +266,11 @@ struct HostTables {
   std::vector<char> seg_wide;
   std::vector<WideTile> wtiles;
   std::vector<int32_t> w_ucell;
-  std::vector<uint16_t> w_slot;  // parallel to csr_col (0 outside wide segments)
+  std::vector<int32_t> w_row;    // segment-relative row of each tile row
+  std::vector<int32_t> w_rp;     // per tile: nrows + 1 row starts, relative to the tile's e0
+  std::vector<double> w_entw;    // entries in tile order: weight
+  std::vector<int32_t> w_ents;   // entries in tile order: LDS slot of the source cell
+  int32_t w_maxu = 0, w_maxe = 0;  // largest nu and ne over the tiles (LDS sizing)
   // data rows: destination cells, CSR over data cells (absolute pointers)
   std::vector<int32_t> dr_cell;
   std::vector<int64_t> dr_ptr;
@@ -311,7 +317,9 @@ struct Plan {
   const void* d_bval = nullptr;
   const WideTile* d_wtiles = nullptr;
   const int32_t* d_w_ucell = nullptr;
-  const uint16_t* d_w_slot = nullptr;
+  const int32_t* d_w_row = nullptr;
+  const int32_t* d_w_rp = nullptr;
+  const void* d_w_ent = nullptr;  // packed {weight, slot * values per slice} per entry
   const int32_t* d_dr_cell = nullptr;
   const int64_t* d_dr_ptr = nullptr;
   const int32_t* d_dr_col = nullptr;

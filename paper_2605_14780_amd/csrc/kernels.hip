@@ -508,107 +508,197 @@ __device__ __forceinline__ void rt_tile(const PlanDesc& d, const RowTile& tl, bo
   }
 }
 
-// Wide rows (WideTile).  Workgroup (tile, slice): the tile's distinct
-// source cells are staged in LDS, WIDE_ROW_BYTES of inner values each (the
-// slots this slice's outputs read, through the component rotation); then a
-// group of lanes per row sums the row's entries from LDS in entry order
-// (first product, then FMAs: the same bits as the general row path).
-// zero_only writes +0 to the tile's rows (the adjoint's ghost reset).
+// One staged entry of a wide tile: weight and LDS slot of its source cell,
+// read with one LDS instruction.
+template <typename T>
+struct alignas(2 * sizeof(T)) WideEnt {
+  T w;
+  int32_t slot;
+};
+
+template <typename T>
+__device__ __forceinline__ void ld_ent(const WideEnt<T>* p, T& w, int& slot) {
+  if constexpr (sizeof(T) == 8) {
+    typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+    const u4 v = *reinterpret_cast<const u4*>(p);
+    w = __builtin_bit_cast(double, ((uint64_t)v[1] << 32) | v[0]);
+    slot = (int)v[2];
+  } else {
+    typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+    const u2 v = *reinterpret_cast<const u2*>(p);
+    w = __builtin_bit_cast(float, v[0]);
+    slot = (int)v[1];
+  }
+}
+
+// Wide rows (WideTile).  A workgroup takes one tile and a run of spw
+// consecutive slices of WIDE_ROW_BYTES of inner values.  The tile's entries
+// and row starts go to LDS once; then, per slice, the tile's distinct source
+// cells are staged in LDS (the slots this slice's outputs read, through the
+// component rotation) and a group of lanes per row sums the row's entries
+// from LDS in entry order, EC entries per step with every LDS read of the
+// step issued first.  The sum starts from -0.0 and takes only FMAs, which
+// gives the same bits as a first product followed by FMAs (the general row
+// path); the row's last partial step re-reads its last entry for the
+// missing ones and drops them by a select, so no step branches per entry.
+// The next slice's staging loads are in flight while the current slice is
+// summed.  LDS holds ucap cells of the slice, then ecap entries, then the
+// row starts.  zero_only writes +0 to the tile's rows (the adjoint's ghost
+// reset).
 template <typename T, int V, bool NT>
 __global__ __launch_bounds__(256) void k_apply_wide(PlanDesc d, const WideTile* __restrict__ tiles,
                                                     const int32_t* __restrict__ ucell,
-                                                    const uint16_t* __restrict__ slot, int nslices, int zero_only) {
+                                                    const int32_t* __restrict__ wrow,
+                                                    const int32_t* __restrict__ wrp,
+                                                    const WideEnt<T>* __restrict__ went, int ucap, int ecap,
+                                                    int nslices, int spw, int zero_only) {
   extern __shared__ __align__(16) unsigned char wide_smem[];
   constexpr int S = WIDE_ROW_BYTES / (int)sizeof(T);  // values per cell and slice
   constexpr int LPR = S / V;                          // lanes per row
-  T* lds = reinterpret_cast<T*>(wide_smem);                                    // WIDE_UCAP x S values
-  T* lw = reinterpret_cast<T*>(wide_smem + WIDE_UCAP * WIDE_ROW_BYTES);        // WIDE_ECAP weights
-  uint16_t* ls = reinterpret_cast<uint16_t*>(lw + WIDE_ECAP);                  // WIDE_ECAP slots
-  int32_t* lp = reinterpret_cast<int32_t*>(ls + WIDE_ECAP);                    // WIDE_ROWS + 1 row starts
-  const WideTile tl = tiles[blockIdx.x / nslices];
-  const int64_t l0 = (int64_t)(blockIdx.x % nslices) * S;
-  const int nv = (int)min<int64_t>(S, d.inner - l0) / V;  // vectors of this slice
+  constexpr int NGRP = 256 / LPR;                     // row groups (launched with 256 threads)
+  constexpr int RPG = (WIDE_ROWS + NGRP - 1) / NGRP;  // rows per group
+  constexpr int NIT = (WIDE_UCAP * LPR + 255) / 256;  // staging items per thread
+  constexpr int NE = (WIDE_ECAP + 255) / 256;
+  constexpr int EC = 4;                               // entries per step
+  T* lds = reinterpret_cast<T*>(wide_smem);                                            // ucap x S values
+  WideEnt<T>* le = reinterpret_cast<WideEnt<T>*>(wide_smem + (size_t)ucap * WIDE_ROW_BYTES);  // ecap entries
+  int32_t* lp = reinterpret_cast<int32_t*>(le + ecap);                                 // WIDE_ROWS + 1 row starts
+  const int runs = (nslices + spw - 1) / spw;
+  const WideTile tl = tiles[blockIdx.x / runs];
+  const int s0 = (blockIdx.x % runs) * spw;
+  const int s1 = min(nslices, s0 + spw);
   T* __restrict__ f = static_cast<T*>(d.field);
-  const T* __restrict__ vals = static_cast<const T*>(d.csr_val);
   typedef T vt __attribute__((ext_vector_type(V)));
-  if (!zero_only) {
-    // every staging load of this thread (source slices, entries, row starts)
-    // is issued before the first LDS store
-    constexpr int NIT = (WIDE_UCAP * LPR + 255) / 256;  // launched with 256 threads
-    constexpr int NE = (WIDE_ECAP + 255) / 256;
-    Pack<T, V> g[NIT];
+  const int lane = threadIdx.x % LPR, grp = threadIdx.x / LPR;
+  int32_t ridx[RPG];
+  int64_t dst[RPG];
+#pragma unroll
+  for (int q = 0; q < RPG; ++q) {
+    const int r = grp + q * NGRP;
+    ridx[q] = r < tl.nrows ? wrow[tl.r0 + r] : 0;
+  }
+#pragma unroll
+  for (int q = 0; q < RPG; ++q) dst[q] = grp + q * NGRP < tl.nrows ? d.row_dst[tl.row_base + ridx[q]] : 0;
+  if (zero_only) {
+    for (int s = s0; s < s1; ++s) {
+      const int64_t l = (int64_t)s * S + lane * V;
+      if (l >= d.inner) continue;
+      Pack<T, V> z;
+#pragma unroll
+      for (int i = 0; i < V; ++i) z.v[i] = T(0);
+#pragma unroll
+      for (int q = 0; q < RPG; ++q)
+        if (grp + q * NGRP < tl.nrows) stv<T, V, NT>(f + dst[q] * d.cs + l, z);
+    }
+    return;
+  }
+  // source cell of each staging item (the same for every slice)
+  int32_t cb[NIT];
+#pragma unroll
+  for (int k = 0; k < NIT; ++k) {
+    const int u = (threadIdx.x + k * 256) / LPR;
+    cb[k] = u < tl.nu ? ucell[tl.first_u + u] : -1;
+  }
+  Pack<T, V> g[NIT];
+  auto issue = [&](int s) {
+    const int64_t l0 = (int64_t)s * S;
 #pragma unroll
     for (int k = 0; k < NIT; ++k) {
-      const int e = threadIdx.x + k * 256;
-      const int u = e / LPR, v = e - u * LPR;
-      if (u < tl.nu && v < nv) {
+      const int v = (threadIdx.x + k * 256) % LPR;
+      if (cb[k] >= 0 && l0 + v * V < d.inner) {
         T sign;
         const int64_t sl = rot_slot<T>(d, tl.rot, l0 + (int64_t)v * V, sign);
-        g[k] = ldv<T, V>(f + (int64_t)ucell[tl.first_u + u] * d.cs + sl);
+        g[k] = ldv<T, V>(f + (int64_t)cb[k] * d.cs + sl);
       }
     }
-    T ew[NE];
-    uint16_t es[NE];
+  };
+  issue(s0);
+  {
+    WideEnt<T> ev[NE];
 #pragma unroll
     for (int k = 0; k < NE; ++k) {
       const int e = threadIdx.x + k * 256;
-      if (e < tl.ne) {
-        ew[k] = vals[tl.e0 + e];
-        es[k] = slot[tl.e0 + e];
-      }
+      if (e < tl.ne) ev[k] = went[tl.e0 + e];
     }
     int32_t rp = 0;
-    if ((int)threadIdx.x <= tl.nrows) rp = (int32_t)(d.csr_ptr[tl.tab + threadIdx.x] - tl.e0);
+    if ((int)threadIdx.x <= tl.nrows) rp = wrp[tl.rp0 + threadIdx.x];
+#pragma unroll
+    for (int k = 0; k < NE; ++k) {
+      const int e = threadIdx.x + k * 256;
+      if (e < tl.ne) le[e] = ev[k];
+    }
+    if ((int)threadIdx.x <= tl.nrows) lp[threadIdx.x] = rp;
+  }
+  const T* __restrict__ bt = static_cast<const T*>(d.bval) + tl.brow;
+  for (int s = s0; s < s1; ++s) {
+    const int64_t l0 = (int64_t)s * S;
 #pragma unroll
     for (int k = 0; k < NIT; ++k) {
       const int e = threadIdx.x + k * 256;
       const int u = e / LPR, v = e - u * LPR;
-      if (u < tl.nu && v < nv) {
+      if (cb[k] >= 0 && l0 + v * V < d.inner) {
         vt w;
 #pragma unroll
         for (int i = 0; i < V; ++i) w[i] = g[k].v[i];
         *reinterpret_cast<vt*>(&lds[u * S + v * V]) = w;
       }
     }
-#pragma unroll
-    for (int k = 0; k < NE; ++k) {
-      const int e = threadIdx.x + k * 256;
-      if (e < tl.ne) {
-        lw[e] = ew[k];
-        ls[e] = es[k];
-      }
-    }
-    if ((int)threadIdx.x <= tl.nrows) lp[threadIdx.x] = rp;
     __syncthreads();
-  }
-  const int lane = threadIdx.x % LPR, grp = threadIdx.x / LPR, ngrp = blockDim.x / LPR;
-  if (lane >= nv) return;
-  const int64_t l = l0 + (int64_t)lane * V;
-  T sign;
-  (void)rot_slot<T>(d, tl.rot, l, sign);
-  const T* __restrict__ bt = static_cast<const T*>(d.bval) + tl.brow;
-  for (int r = grp; r < tl.nrows; r += ngrp) {
-    const int64_t dst = d.row_dst[tl.row_begin + r];
-    Pack<T, V> y;
+    if (s + 1 < s1) issue(s + 1);
+    const int64_t l = l0 + (int64_t)lane * V;
+    if (l < d.inner) {
+      T sign;
+      (void)rot_slot<T>(d, tl.rot, l, sign);
+      const T* __restrict__ xl = lds + lane * V;
 #pragma unroll
-    for (int i = 0; i < V; ++i) y.v[i] = T(0);
-    if (!zero_only) {
-      const int e0 = lp[r], e1 = lp[r + 1];
-      for (int e = e0; e < e1; ++e) {
-        const T w = lw[e];
-        const vt x = *reinterpret_cast<const vt*>(&lds[(int)ls[e] * S + lane * V]);
+      for (int q = 0; q < RPG; ++q) {
+        const int r = grp + q * NGRP;
+        if (r >= tl.nrows) break;
+        const int e0 = lp[r], e1 = lp[r + 1];
+        vt y;
 #pragma unroll
-        for (int i = 0; i < V; ++i) y.v[i] = e == e0 ? w * x[i] : fma(w, x[i], y.v[i]);
-      }
+        for (int i = 0; i < V; ++i) y[i] = e1 > e0 ? T(-0.0) : T(0);
+        int c = e0;
+        for (; c + EC <= e1; c += EC) {
+          T w[EC];
+          int o[EC];
 #pragma unroll
-      for (int i = 0; i < V; ++i) y.v[i] = sign * y.v[i];
-      if (tl.has_b) {
-        const T* bp = bt + (int64_t)r * tl.b_inner;
+          for (int m = 0; m < EC; ++m) ld_ent<T>(le + c + m, w[m], o[m]);
+          vt x[EC];
 #pragma unroll
-        for (int i = 0; i < V; ++i) y.v[i] += tl.b_inner == 1 ? bp[0] : bp[l + i];
+          for (int m = 0; m < EC; ++m) x[m] = *reinterpret_cast<const vt*>(xl + o[m]);
+#pragma unroll
+          for (int m = 0; m < EC; ++m)
+#pragma unroll
+            for (int i = 0; i < V; ++i) y[i] = fma(w[m], x[m][i], y[i]);
+        }
+        if (c < e1) {  // the last 1..EC-1 entries: clamped reads, dead steps dropped by a select
+          T w[EC - 1];
+          int o[EC - 1];
+#pragma unroll
+          for (int m = 0; m < EC - 1; ++m) ld_ent<T>(le + min(c + m, e1 - 1), w[m], o[m]);
+          vt x[EC - 1];
+#pragma unroll
+          for (int m = 0; m < EC - 1; ++m) x[m] = *reinterpret_cast<const vt*>(xl + o[m]);
+#pragma unroll
+          for (int m = 0; m < EC - 1; ++m) {
+            const bool live = c + m < e1;
+#pragma unroll
+            for (int i = 0; i < V; ++i) y[i] = live ? fma(w[m], x[m][i], y[i]) : y[i];
+          }
+        }
+        Pack<T, V> o;
+#pragma unroll
+        for (int i = 0; i < V; ++i) o.v[i] = sign * y[i];
+        if (tl.has_b) {
+          const T* bp = bt + (int64_t)ridx[q] * tl.b_inner;
+#pragma unroll
+          for (int i = 0; i < V; ++i) o.v[i] += tl.b_inner == 1 ? bp[0] : bp[l + i];
+        }
+        stv<T, V, NT>(f + dst[q] * d.cs + l, o);
       }
     }
-    stv<T, V, NT>(f + dst * d.cs + l, y);
+    __syncthreads();
   }
 }
 
@@ -1273,6 +1363,18 @@ struct Packer {
     for (size_t k = 0; k < v.size(); ++k) f[k] = (float)v[k];  // round to nearest
     return vec(f);
   }
+  // wide-row entries as WideEnt<T>: the weight in the plan's type (rounded as
+  // in reals) and the LDS offset of the source cell's slice (slot * values)
+  size_t wide_entries(const std::vector<double>& w, const std::vector<int32_t>& slot, int dtype) {
+    if (dtype == HBC_F64) {
+      std::vector<WideEnt<double>> e(w.size());
+      for (size_t k = 0; k < w.size(); ++k) e[k] = {w[k], slot[k] * (WIDE_ROW_BYTES / 8)};
+      return vec(e);
+    }
+    std::vector<WideEnt<float>> e(w.size());
+    for (size_t k = 0; k < w.size(); ++k) e[k] = {(float)w[k], slot[k] * (WIDE_ROW_BYTES / 4)};
+    return vec(e);
+  }
 };
 
 int ilog2(int v) {
@@ -1353,7 +1455,9 @@ void device_upload_plan(Plan& p) {
   size_t o_rs = pk.vec(T.row_src);
   size_t o_wt = pk.vec(T.wtiles);
   size_t o_wu = pk.vec(T.w_ucell);
-  size_t o_ws = pk.vec(T.w_slot);
+  size_t o_wr = pk.vec(T.w_row);
+  size_t o_wp = pk.vec(T.w_rp);
+  size_t o_we = pk.wide_entries(T.w_entw, T.w_ents, p.dtype);
   size_t o_drc = pk.vec(T.dr_cell);
   size_t o_drp = pk.vec(T.dr_ptr);
   size_t o_drk = pk.vec(T.dr_col);
@@ -1382,7 +1486,9 @@ void device_upload_plan(Plan& p) {
   p.d_row_src = reinterpret_cast<const int32_t*>(b + o_rs);
   p.d_wtiles = reinterpret_cast<const WideTile*>(b + o_wt);
   p.d_w_ucell = reinterpret_cast<const int32_t*>(b + o_wu);
-  p.d_w_slot = reinterpret_cast<const uint16_t*>(b + o_ws);
+  p.d_w_row = reinterpret_cast<const int32_t*>(b + o_wr);
+  p.d_w_rp = reinterpret_cast<const int32_t*>(b + o_wp);
+  p.d_w_ent = b + o_we;
   p.d_dr_cell = reinterpret_cast<const int32_t*>(b + o_drc);
   p.d_dr_ptr = reinterpret_cast<const int64_t*>(b + o_drp);
   p.d_dr_col = reinterpret_cast<const int32_t*>(b + o_drk);
@@ -1535,20 +1641,33 @@ static void launch_rows(const PlanDesc& d, hipStream_t st, int grid, int blk, co
   }
 }
 
+// Slices per workgroup of the wide-row kernel: as many as keep at least
+// eight workgroups per CU (256 CUs), so the pipelined staging has slices to
+// overlap without leaving CUs idle.
+static int wide_slices_per_wg(int ntiles, int nslices) {
+  int spw = 1;
+  while (spw < nslices && (int64_t)ntiles * ((nslices + 2 * spw - 1) / (2 * spw)) >= 256 * 8) spw *= 2;
+  return spw;
+}
+
 template <typename T, int V>
 static void launch_wide(const Plan& p, const PlanDesc& d, hipStream_t st, bool zero_only) {
   constexpr int S = WIDE_ROW_BYTES / (int)sizeof(T);
   const int nslices = (int)((p.layout.inner + S - 1) / S);
-  const int grid = (int)p.host.wtiles.size() * nslices;
+  const int ntiles = (int)p.host.wtiles.size();
+  const int spw = wide_slices_per_wg(ntiles, nslices);
+  const int grid = ntiles * ((nslices + spw - 1) / spw);
+  const int ucap = p.host.w_maxu, ecap = (p.host.w_maxe + 1) & ~1;  // even: keeps the row starts 16-byte aligned
   const size_t lds = zero_only ? 0
-                              : (size_t)WIDE_UCAP * WIDE_ROW_BYTES + (size_t)WIDE_ECAP * (sizeof(T) + 2) +
+                              : (size_t)ucap * WIDE_ROW_BYTES + (size_t)ecap * sizeof(WideEnt<T>) +
                                     (size_t)(WIDE_ROWS + 1) * 4;
+  const WideEnt<T>* went = static_cast<const WideEnt<T>*>(p.d_w_ent);
   if (d.nt)
     hipLaunchKernelGGL((k_apply_wide<T, V, true>), dim3(grid), dim3(256), lds, st, d, p.d_wtiles, p.d_w_ucell,
-                       p.d_w_slot, nslices, zero_only ? 1 : 0);
+                       p.d_w_row, p.d_w_rp, went, ucap, ecap, nslices, spw, zero_only ? 1 : 0);
   else
     hipLaunchKernelGGL((k_apply_wide<T, V, false>), dim3(grid), dim3(256), lds, st, d, p.d_wtiles, p.d_w_ucell,
-                       p.d_w_slot, nslices, zero_only ? 1 : 0);
+                       p.d_w_row, p.d_w_rp, went, ucap, ecap, nslices, spw, zero_only ? 1 : 0);
   HIP_CHECK(hipGetLastError());
 }
 

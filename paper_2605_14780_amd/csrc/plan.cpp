@@ -735,14 +735,51 @@ hbc_tune default_tune(const Plan& plan) {
   return t;
 }
 
-// Wide-row tiles (see WideTile): consecutive rows of a wide CSR segment, in
-// device order, greedily while their distinct source cells fit WIDE_UCAP.
+// Segment rows in wide-tile order: the thinnest box dimension innermost, the
+// others in box order (the last of equally thin dimensions is taken).
+static std::vector<int64_t> wide_row_order(const DevSeg& sg) {
+  const int nd = sg.nd;
+  int thin = nd - 1;
+  for (int k = 0; k < nd; ++k)
+    if (sg.ext[k] < sg.ext[thin]) thin = k;
+  std::vector<int> dims;
+  for (int k = 0; k < nd; ++k)
+    if (k != thin) dims.push_back(k);
+  dims.push_back(thin);
+  int64_t stride[SEG_MAXD];
+  int64_t s = 1;
+  for (int k = nd - 1; k >= 0; --k) {
+    stride[k] = s;
+    s *= sg.ext[k];
+  }
+  std::vector<int64_t> order((size_t)sg.nrows);
+  int64_t idx[SEG_MAXD] = {0, 0, 0, 0};
+  for (int64_t n = 0; n < sg.nrows; ++n) {
+    int64_t r = 0;
+    for (int k = 0; k < nd; ++k) r += idx[k] * stride[k];
+    order[(size_t)n] = r;
+    for (int q = nd - 1; q >= 0; --q) {  // advance the counter, dims[nd-1] fastest
+      const int k = dims[(size_t)q];
+      if (++idx[k] < sg.ext[k]) break;
+      idx[k] = 0;
+    }
+  }
+  return order;
+}
+
+// Wide-row tiles (see WideTile): the rows of a wide CSR segment in
+// wide_row_order, cut greedily while their distinct source cells and entries
+// fit.
 static void build_wide(Plan& plan) {
   HostTables& T = plan.host;
   T.seg_wide.assign(T.segs.size(), 0);
   T.wtiles.clear();
   T.w_ucell.clear();
-  T.w_slot.assign(T.csr_col.size(), 0);
+  T.w_row.clear();
+  T.w_rp.clear();
+  T.w_entw.clear();
+  T.w_ents.clear();
+  T.w_maxu = T.w_maxe = 0;
   if (plan.layout.order != HBC_POINT_MAJOR) return;
   const int64_t es = plan.dtype == HBC_F64 ? 8 : 4;
   if (plan.layout.inner * es < WIDE_ROW_BYTES) return;
@@ -760,36 +797,45 @@ static void build_wide(Plan& plan) {
     }
     if (!fits) continue;
     T.seg_wide[si] = 1;
-    int64_t r = 0;
-    while (r < sg.nrows) {
+    const std::vector<int64_t> order = wide_row_order(sg);
+    size_t n = 0;
+    while (n < order.size()) {
       WideTile w{};
       w.rot = sg.rot;
       w.has_b = sg.has_b;
       w.b_inner = sg.b_inner;
-      w.row_begin = sg.row_base + r;
-      w.tab = sg.tab + r;
-      w.brow = sg.brow + r * sg.b_inner;
+      w.row_base = sg.row_base;
+      w.brow = sg.brow;
       w.first_u = (int32_t)T.w_ucell.size();
-      w.e0 = T.csr_ptr[sg.tab + r];
+      w.e0 = (int32_t)T.w_entw.size();
+      w.r0 = (int32_t)T.w_row.size();
+      w.rp0 = (int32_t)T.w_rp.size();
+      T.w_rp.push_back(0);
       local.clear();
-      while (r < sg.nrows && w.nrows < WIDE_ROWS) {
+      while (n < order.size() && w.nrows < WIDE_ROWS) {
+        const int64_t r = order[n];
+        const int64_t b = T.csr_ptr[sg.tab + r], e = T.csr_ptr[sg.tab + r + 1];
         int add = 0;
-        for (int64_t e = T.csr_ptr[sg.tab + r]; e < T.csr_ptr[sg.tab + r + 1]; ++e)
-          if (!local.count(T.csr_col[e])) ++add;  // repeats within the row count twice: conservative
-        const int64_t ne = T.csr_ptr[sg.tab + r + 1] - w.e0;
-        if (w.nu + add > WIDE_UCAP || ne > WIDE_ECAP) break;
-        for (int64_t e = T.csr_ptr[sg.tab + r]; e < T.csr_ptr[sg.tab + r + 1]; ++e) {
-          auto it = local.find(T.csr_col[e]);
+        for (int64_t k = b; k < e; ++k)
+          if (!local.count(T.csr_col[k])) ++add;  // repeats within the row count twice: conservative
+        if (w.nu + add > WIDE_UCAP || w.ne + (e - b) > WIDE_ECAP) break;
+        for (int64_t k = b; k < e; ++k) {
+          auto it = local.find(T.csr_col[k]);
           if (it == local.end()) {
-            it = local.emplace(T.csr_col[e], w.nu++).first;
-            T.w_ucell.push_back(T.csr_col[e]);
+            it = local.emplace(T.csr_col[k], w.nu++).first;
+            T.w_ucell.push_back(T.csr_col[k]);
           }
-          T.w_slot[e] = (uint16_t)it->second;
+          T.w_entw.push_back(T.csr_val[k]);
+          T.w_ents.push_back(it->second);
         }
+        w.ne += (int32_t)(e - b);
+        T.w_row.push_back((int32_t)r);
+        T.w_rp.push_back(w.ne);
         ++w.nrows;
-        ++r;
+        ++n;
       }
-      w.ne = (int32_t)(T.csr_ptr[sg.tab + r] - w.e0);
+      T.w_maxu = std::max(T.w_maxu, w.nu);
+      T.w_maxe = std::max(T.w_maxe, w.ne);
       T.wtiles.push_back(w);
     }
   }
