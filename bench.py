@@ -602,7 +602,7 @@ def main():
         print(json.dumps({"calibration": "copy", "bytes_read": a.numel() * 8, "bytes_written": b.numel() * 8}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described, not built"}))
+        print(json.dumps({"error": "the library runs on one GPU; applies sharded over several GPUs are not implemented"}))
         sys.exit(2)
 
     import torch

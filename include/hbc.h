@@ -58,7 +58,7 @@ extern "C" {
 #define HBC_EUNCOVERED (-5)  /* ghost rows covered by nothing under HBC_STRICT_COVER */
 #define HBC_ENOMEM (-6)      /* host or device allocation failed */
 #define HBC_EHIP (-7)        /* a HIP runtime error; its string is in hbc_last_error() */
-#define HBC_EUNSUPPORTED (-8)/* valid request outside what this build implements (e.g. slice step != 1) */
+#define HBC_EUNSUPPORTED (-8)/* valid request outside what the library implements (e.g. slice step != 1) */
 
 /* element types */
 #define HBC_F64 0
@@ -128,6 +128,8 @@ typedef struct {
   int64_t rows_data;        /* data rows written (block-edge averaging), staged through scratch */
   int64_t rows_dead;        /* ghost rows of sub-matrices / sub-vectors dropped: no consumer read reaches them */
   int64_t ghost_cells_live; /* ghost cells some consumer read reaches (all ghost cells without a consumer) */
+  int64_t rows_wide;        /* CSR rows served by the LDS-staged wide-row kernel (point-major, >= 128-byte rows) */
+  int64_t wide_tiles;       /* tiles of those rows */
 } hbc_stats;
 
 /* Launch shape of the apply kernels (chosen by the plan, changed by tuning). */

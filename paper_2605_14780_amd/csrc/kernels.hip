@@ -508,8 +508,8 @@ __device__ __forceinline__ void rt_tile(const PlanDesc& d, const RowTile& tl, bo
   }
 }
 
-// One staged entry of a wide tile: weight and LDS slot of its source cell,
-// read with one LDS instruction.
+// One entry of a wide tile: its weight and the LDS offset (in values) of its
+// source cell's staged slice, read with one LDS instruction.
 template <typename T>
 struct alignas(2 * sizeof(T)) WideEnt {
   T w;

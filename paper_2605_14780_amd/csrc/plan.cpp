@@ -780,6 +780,7 @@ static void build_wide(Plan& plan) {
   T.w_entw.clear();
   T.w_ents.clear();
   T.w_maxu = T.w_maxe = 0;
+  plan.stats.rows_wide = plan.stats.wide_tiles = 0;
   if (plan.layout.order != HBC_POINT_MAJOR) return;
   const int64_t es = plan.dtype == HBC_F64 ? 8 : 4;
   if (plan.layout.inner * es < WIDE_ROW_BYTES) return;
@@ -837,6 +838,8 @@ static void build_wide(Plan& plan) {
       T.w_maxu = std::max(T.w_maxu, w.nu);
       T.w_maxe = std::max(T.w_maxe, w.ne);
       T.wtiles.push_back(w);
+      plan.stats.rows_wide += w.nrows;
+      ++plan.stats.wide_tiles;
     }
   }
 }

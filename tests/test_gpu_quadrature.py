@@ -101,3 +101,35 @@ def test_quadrature_rows_staged(nl, dtype):
     lhs = float(((Ax.double() - z.double()) * y.double()).sum())
     rhs = float((x.double() * Aty.double()).sum())
     assert abs(lhs - rhs) <= (1e-12 if dt == hb.F64 else 1e-5) * max(abs(lhs), abs(rhs))
+
+
+@pytest.mark.parametrize("dtype,h", [("f64", 4), ("f32", 3)])
+def test_wide_kernel_matches_general_rows_bitwise(dtype, h):
+    """The staged wide-row kernel (rows of >= 128 bytes: many tiles per side,
+    every ghost layer of a position in one tile) sums each row in the same
+    order as the general row path (rows of < 128 bytes): applying one program
+    to 64 inner values, and to the same values 8 at a time, gives equal bits."""
+    N, q = 20, 2
+    dt, npdt = (hb.F64, np.float64) if dtype == "f64" else (hb.F32, np.float32)
+    g = hb.Grid.cubed_sphere(N, h)
+    p = hb.Program(g)
+    p.cs_add_quadrature(N, h, q)
+    wide = hb.Plan(p, inner=64, dtype=dt)
+    narrow = hb.Plan(p, inner=8 if dt == hb.F64 else 4, dtype=dt)
+    sw, sn = wide.stats(), narrow.stats()
+    assert sw["rows_wide"] == sw["rows_csr"] and sw["wide_tiles"] > 24
+    assert sn["rows_wide"] == 0
+    full = cs_full_field(N, h, 1, 64, seed=11 + h).astype(npdt)
+    t = torch.from_numpy(full.copy()).cuda()
+    hb.apply(wide, t)
+    k = 8 if dt == hb.F64 else 4  # rows of 64 or 16 bytes: the general row path
+    parts = []
+    for c0 in range(0, 64, k):
+        s = torch.from_numpy(np.ascontiguousarray(full[:, c0:c0 + k])).cuda()
+        hb.apply(narrow, s)
+        parts.append(s)
+    torch.cuda.synchronize()
+    got_wide = t.cpu().numpy()
+    got_narrow = torch.cat(parts, dim=1).cpu().numpy()
+    assert np.array_equal(got_wide.view(np.uint64 if dt == hb.F64 else np.uint32),
+                          got_narrow.view(np.uint64 if dt == hb.F64 else np.uint32))
