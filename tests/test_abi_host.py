@@ -279,6 +279,26 @@ def test_quadrature_plan_equals_oracle(N, h, q):
     compare_plan_with_oracle(plan, og, assemble(og, oq.subs(N, h, q)), tol=1e-13)
 
 
+@pytest.mark.parametrize("inner,dtype,order,wide", [(16, "f64", hb.POINT_MAJOR, True), (8, "f64", hb.POINT_MAJOR, False),
+                                                   (32, "f32", hb.POINT_MAJOR, True), (16, "f32", hb.POINT_MAJOR, False),
+                                                   (64, "f64", hb.PLANE_MAJOR, False)])
+def test_wide_row_selection(inner, dtype, order, wide):
+    """Rows of >= 128 bytes in point-major plans go to the LDS-staged kernel;
+    every CSR row is served exactly once (tiles hold at most 32 rows, so the
+    24 halo strips of h * N rows need at least ceil(h * N / 32) tiles each)."""
+    N, h = 20, 3
+    g = hb.Grid.cubed_sphere(N, h)
+    p = hb.Program(g)
+    p.cs_add_quadrature(N, h, 2)
+    dt = hb.F64 if dtype == "f64" else hb.F32
+    st = hb.Plan(p, inner=inner, dtype=dt, order=order, host_only=True).stats()
+    if wide:
+        assert st["rows_wide"] == st["rows_csr"] == 24 * h * N
+        assert st["wide_tiles"] >= 24 * -(-h * N // 32)
+    else:
+        assert st["rows_wide"] == 0 and st["wide_tiles"] == 0
+
+
 def test_smoke_entry_is_importable_and_shapes_consistent():
     """smoke() needs a GPU; here only its module imports and its field layout
     matches the oracle grid (cells face by face, inner trailing)."""
