@@ -154,7 +154,10 @@ __device__ __forceinline__ void run_tile_pm(const PlanDesc& d, const DevSeg& s, 
     const int64_t row = row0 + r;
     uint32_t q = (uint32_t)row;
     int64_t dst = s.dst_base, src = s.src_base;
-    for (int k = s.nd - 1; k >= 0; --k) {
+    // every SEG_MAXD dimension (unused ones have extent 1 and stride 0), so
+    // that the segment's arrays are read at constant indices, from registers
+#pragma unroll
+    for (int k = SEG_MAXD - 1; k >= 0; --k) {
       const uint32_t e = (uint32_t)s.ext[k];
       const uint32_t c = q % e;
       q /= e;
@@ -614,18 +617,22 @@ __global__ __launch_bounds__(256) void k_apply_wide(PlanDesc d, const WideTile* 
   };
   issue(s0);
   {
-    WideEnt<T> ev[NE];
+    // entries move as plain vectors (a struct copy would go through scratch)
+    typedef uint32_t eu __attribute__((ext_vector_type(sizeof(WideEnt<T>) / 4)));
+    const eu* __restrict__ gsrc = reinterpret_cast<const eu*>(went + tl.e0);
+    eu* ldst = reinterpret_cast<eu*>(le);
+    eu ev[NE];
 #pragma unroll
     for (int k = 0; k < NE; ++k) {
       const int e = threadIdx.x + k * 256;
-      if (e < tl.ne) ev[k] = went[tl.e0 + e];
+      if (e < tl.ne) ev[k] = gsrc[e];
     }
     int32_t rp = 0;
     if ((int)threadIdx.x <= tl.nrows) rp = wrp[tl.rp0 + threadIdx.x];
 #pragma unroll
     for (int k = 0; k < NE; ++k) {
       const int e = threadIdx.x + k * 256;
-      if (e < tl.ne) le[e] = ev[k];
+      if (e < tl.ne) ldst[e] = ev[k];
     }
     if ((int)threadIdx.x <= tl.nrows) lp[threadIdx.x] = rp;
   }
