@@ -5,7 +5,9 @@
   (all 256 values of each; edge strips and corners) against the rows the
   oracle evaluates one by one from the geometry;
 * C768, halo 3, 32 levels, with a sub-vector b on every side: the adjoint
-  against the forward through the dot-product identity.
+  against the forward through the dot-product identity;
+* C384 wide interpolation rows (16..25 entries, LDS-staged kernel): sampled
+  rows against the oracle's.
 """
 import numpy as np
 import pytest
@@ -108,3 +110,57 @@ def test_c768_adjoint_dot_product():
     G = torch.ones((6, W, W), dtype=torch.bool, device="cuda")
     G[:, h:h + N, h:h + N] = False
     assert (Aty.reshape(6, W, W, L)[G] == 0).all()
+
+
+def test_c384_wide_rows_sampled():
+    """Wide interpolation rows (2x2 Gauss average of cubic reconstructions,
+    16..25 entries) at C384, halo 3, 256 inner values with (u, v) rotated,
+    FP64, through the LDS-staged kernel: sampled ghost rows against the
+    oracle's rows evaluated one by one."""
+    from oracle import quadrature as oq
+    N, h, nf, nl = 384, 3, 4, 64
+    I = nf * nl
+    vec = (2 * nl, nl, nl)
+    W = N + 2 * h
+    g = hb.Grid.cubed_sphere(N, h)
+    p = hb.Program(g)
+    p.cs_add_quadrature(N, h, 2, vector=True)
+    plan = hb.Plan(p, inner=I, vec=vec, dtype=hb.F64)
+    st = plan.stats()
+    assert st["rows_wide"] == st["rows_csr"] == 24 * h * N
+    full = torch.full((6, W, W, I), float("nan"), dtype=torch.float64, device="cuda")
+    full[:, h:h + N, h:h + N] = synthinputs.cs_sh_field_torch(N, nf, nl, seed=3, device="cuda")
+    full = full.reshape(-1, I)
+    out = full.clone()
+    hb.apply(plan, out)
+    torch.cuda.synchronize()
+    assert torch.isfinite(out).all(), "a ghost was left unwritten"
+    rng = np.random.default_rng(1)
+    u_sl = np.arange(vec[0], vec[0] + vec[2])
+    v_sl = u_sl + vec[1]
+    rows = 0
+    while rows < 400:
+        f = int(rng.integers(6))
+        j, i = (int(v) for v in rng.integers(-h, N + h, size=2))
+        if (0 <= j < N and 0 <= i < N) or ocs.is_corner(j, i, N):
+            continue
+        got = out[(f * W + (j + h)) * W + (i + h)].cpu().numpy()
+        ents = oq.quad_entries(f, j, i, N, 2)
+        src = [(gg * W + (jj + h)) * W + (ii + h) for (gg, jj, ii), _ in ents]
+        w = np.array([wv for _, wv in ents])
+        X = full[torch.tensor(src, device="cuda")].cpu().numpy()
+        y = w @ X
+        R = ocs.rside(f, ocs.side_of(j, i, N))
+        ref = y.copy()
+        ref[u_sl] = R[0, 0] * y[u_sl] + R[0, 1] * y[v_sl]
+        ref[v_sl] = R[1, 0] * y[u_sl] + R[1, 1] * y[v_sl]
+        # weights agree with the host's to 1e-13 per entry (pinned host-side);
+        # summation rounding of <= 25 FP64 terms
+        pat = np.abs(X).sum(axis=0)
+        mag = np.abs(w) @ np.abs(X)
+        bnd = 1e-13 * pat + 64 * U64 * mag
+        bnd_rot = bnd.copy()
+        bnd_rot[u_sl] = np.maximum(bnd[u_sl], bnd[v_sl])
+        bnd_rot[v_sl] = bnd_rot[u_sl]
+        assert (np.abs(got - ref) <= bnd_rot).all(), (f, j, i)
+        rows += 1
