@@ -595,23 +595,47 @@ __global__ __launch_bounds__(256) void k_apply_wide(PlanDesc d, const WideTile* 
     }
     return;
   }
-  // source cell of each staging item (the same for every slice)
-  int32_t cb[NIT];
+  // Per staging item (the same for every slice): the source cell's address
+  // and the item's slot offset; per slice only 32-bit slot arithmetic (inner
+  // extents of wide plans stay below 2^30) and, for rotated tiles, the
+  // component rotation remain.  An item's LDS offset is (thread + 256 k) * V.
+  const int inner = (int)d.inner, vlo = (int)d.vec_lo, vst = (int)d.vec_stride, vlen = (int)d.vec_len;
+  const bool rotates = tl.rot != 0 && vlen != 0;
+  auto rslot = [&](int l, T& sign) -> int {  // rot_slot in 32-bit
+    sign = T(1);
+    if (!rotates) return l;
+    int off = l - vlo, a;
+    if (off >= 0 && off < vlen) {
+      a = 0;
+    } else if (off >= vst && off < vst + vlen) {
+      a = 1;
+      off -= vst;
+    } else {
+      return l;
+    }
+    if (tl.rot & (2 << a)) sign = T(-1);
+    return vlo + ((tl.rot & 1) ? 1 - a : a) * vst + off;
+  };
+  const T* sp[NIT];
+  uint32_t live = 0;  // bit k: item k is one of the tile's cells
 #pragma unroll
   for (int k = 0; k < NIT; ++k) {
     const int u = (threadIdx.x + k * 256) / LPR;
-    cb[k] = u < tl.nu ? ucell[tl.first_u + u] : -1;
+    sp[k] = f;
+    if (u < tl.nu) {
+      sp[k] = f + (int64_t)ucell[tl.first_u + u] * d.cs;
+      live |= 1u << k;
+    }
   }
   Pack<T, V> g[NIT];
   auto issue = [&](int s) {
-    const int64_t l0 = (int64_t)s * S;
+    const int l0 = s * S;
 #pragma unroll
     for (int k = 0; k < NIT; ++k) {
-      const int v = (threadIdx.x + k * 256) % LPR;
-      if (cb[k] >= 0 && l0 + v * V < d.inner) {
+      const int lv = l0 + ((threadIdx.x + k * 256) % LPR) * V;
+      if ((live >> k & 1u) && lv < inner) {
         T sign;
-        const int64_t sl = rot_slot<T>(d, tl.rot, l0 + (int64_t)v * V, sign);
-        g[k] = ldv<T, V>(f + (int64_t)cb[k] * d.cs + sl);
+        g[k] = ldv<T, V>(sp[k] + rslot(lv, sign));
       }
     }
   };
@@ -636,26 +660,28 @@ __global__ __launch_bounds__(256) void k_apply_wide(PlanDesc d, const WideTile* 
     }
     if ((int)threadIdx.x <= tl.nrows) lp[threadIdx.x] = rp;
   }
+  T* dp[RPG];
+#pragma unroll
+  for (int q = 0; q < RPG; ++q) dp[q] = f + dst[q] * d.cs;
   const T* __restrict__ bt = static_cast<const T*>(d.bval) + tl.brow;
   for (int s = s0; s < s1; ++s) {
-    const int64_t l0 = (int64_t)s * S;
+    const int l0 = s * S;
 #pragma unroll
     for (int k = 0; k < NIT; ++k) {
       const int e = threadIdx.x + k * 256;
-      const int u = e / LPR, v = e - u * LPR;
-      if (cb[k] >= 0 && l0 + v * V < d.inner) {
+      if ((live >> k & 1u) && l0 + (e % LPR) * V < inner) {
         vt w;
 #pragma unroll
         for (int i = 0; i < V; ++i) w[i] = g[k].v[i];
-        *reinterpret_cast<vt*>(&lds[u * S + v * V]) = w;
+        *reinterpret_cast<vt*>(&lds[e * V]) = w;
       }
     }
     __syncthreads();
     if (s + 1 < s1) issue(s + 1);
-    const int64_t l = l0 + (int64_t)lane * V;
-    if (l < d.inner) {
+    const int l = l0 + lane * V;
+    if (l < inner) {
       T sign;
-      (void)rot_slot<T>(d, tl.rot, l, sign);
+      (void)rslot(l, sign);
       const T* __restrict__ xl = lds + lane * V;
 #pragma unroll
       for (int q = 0; q < RPG; ++q) {
@@ -689,9 +715,9 @@ __global__ __launch_bounds__(256) void k_apply_wide(PlanDesc d, const WideTile* 
           for (int m = 0; m < EC - 1; ++m) x[m] = *reinterpret_cast<const vt*>(xl + o[m]);
 #pragma unroll
           for (int m = 0; m < EC - 1; ++m) {
-            const bool live = c + m < e1;
+            const bool lv = c + m < e1;
 #pragma unroll
-            for (int i = 0; i < V; ++i) y[i] = live ? fma(w[m], x[m][i], y[i]) : y[i];
+            for (int i = 0; i < V; ++i) y[i] = lv ? fma(w[m], x[m][i], y[i]) : y[i];
           }
         }
         Pack<T, V> o;
@@ -702,7 +728,7 @@ __global__ __launch_bounds__(256) void k_apply_wide(PlanDesc d, const WideTile* 
 #pragma unroll
           for (int i = 0; i < V; ++i) o.v[i] += tl.b_inner == 1 ? bp[0] : bp[l + i];
         }
-        stv<T, V, NT>(f + dst[q] * d.cs + l, o);
+        stv<T, V, NT>(dp[q] + l, o);
       }
     }
     __syncthreads();

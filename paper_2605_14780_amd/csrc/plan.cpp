@@ -783,7 +783,7 @@ static void build_wide(Plan& plan) {
   plan.stats.rows_wide = plan.stats.wide_tiles = 0;
   if (plan.layout.order != HBC_POINT_MAJOR) return;
   const int64_t es = plan.dtype == HBC_F64 ? 8 : 4;
-  if (plan.layout.inner * es < WIDE_ROW_BYTES) return;
+  if (plan.layout.inner * es < WIDE_ROW_BYTES || plan.layout.inner > (int64_t(1) << 30)) return;  // 32-bit slots
   std::unordered_map<int32_t, int32_t> local;
   for (size_t si = 0; si < T.segs.size(); ++si) {
     const DevSeg& sg = T.segs[si];
