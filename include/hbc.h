@@ -148,8 +148,18 @@ const char* hbc_last_error(void);
 /* Create a grid over the global box [lo[d], hi[d]), d < ndim (1 <= ndim <= 6). */
 int hbc_grid_create(int32_t ndim, const int64_t* lo, const int64_t* hi, hbc_grid** out);
 /* Add a block: full and data are ndim slices; data inside full, full inside the
- * global box, full regions of different blocks disjoint.  Step must be 1
- * (HBC_EUNSUPPORTED otherwise).  *block_id receives the block's index. */
+ * global box, full regions of different blocks disjoint.  A slice (start, stop,
+ * step) selects the points start + k*step < stop (Sec. IV-A-1: step 2 for a
+ * staggered variable, 2^k for a multigrid level); the block's cells are the
+ * points of its full slices, its data cells those of its data slices.  The
+ * first block fixes the grid's lattice: along each dimension every full and
+ * data slice of the grid must have that block's step and a start congruent to
+ * its start modulo the step (HBC_EUNSUPPORTED otherwise).  Every position later
+ * given to a program on this grid (row boxes, map matrices and offsets,
+ * columns, consumer offsets) is a position of the global box: a row box
+ * selects the grid points it holds, columns must be grid points (HBC_ERANGE),
+ * a map must send grid points to grid points and consumer offsets must be
+ * multiples of the step (HBC_EINVAL).  *block_id receives the block's index. */
 int hbc_grid_add_block(hbc_grid* g, const hbc_slice* full, const hbc_slice* data, int32_t* block_id);
 /* Total cells of all blocks' full regions (the field's cell count). */
 int64_t hbc_grid_cells(const hbc_grid* g);

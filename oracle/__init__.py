@@ -10,7 +10,8 @@ arithmetic).
 What it computes (Mat2Boundary, arXiv 2605.14780):
 
 * ``grid``          the region model: global box, blocks as full/data slices
-                    with the block id as leading coordinate, ghost = full - data
+                    (start, stop, step: the points start + k step < stop) with
+                    the block id as leading coordinate, ghost = full - data
                     (Sec. III-A; Sec. IV-A-1; Alg. 1 region lines).
 * ``operator``      assembly of the affine operator F(x) = A x + b over the
                     ghost rows from basic sub-matrices / sub-vectors, applied

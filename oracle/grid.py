@@ -4,11 +4,14 @@ Follows Sec. III-A (full region = data region + ghost region) and Sec. IV-A-1
 (each block's full and data regions are slices of one global box; the ghost
 region is full minus data).  As in Alg. 1, the block id is the leading
 coordinate of the global box, so blocks never overlap in global coordinates.
-Only slices with step 1 are modelled.
+A slice (start, stop, step) selects the points start + k * step < stop of its
+dimension (Sec. IV-A-1: step 2 for staggered variables, 2^k for multigrid
+levels); a block's cells are the points of its full slices, its data cells
+those that are also points of its data slices, its ghost cells the rest.
 
 Storage convention shared with the tests: cells are numbered block by block
-(in the order blocks were added), each block's full box in row-major order
-(last coordinate fastest).  Inner values (levels x fields x components) form a
+(in the order blocks were added), each block's full-slice points in row-major
+order (last coordinate fastest).  Inner values (levels x fields x components) form a
 separate trailing axis, so the reference is layout-agnostic.
 """
 from __future__ import annotations
@@ -42,6 +45,18 @@ def box_coords(box):
 class Block:
     full: Box
     data: Box
+    fstep: Tuple[int, ...] = ()
+    dstep: Tuple[int, ...] = ()
+
+    def npoints(self, d: int) -> int:
+        a, b = self.full[d]
+        return max(0, -(-(b - a) // self.fstep[d]))
+
+    def has_cell(self, coord) -> bool:
+        return all(a <= c < b and (c - a) % st == 0 for (a, b), st, c in zip(self.full, self.fstep, coord))
+
+    def has_data(self, coord) -> bool:
+        return all(a <= c < b and (c - a) % st == 0 for (a, b), st, c in zip(self.data, self.dstep, coord))
 
 
 class Grid:
@@ -51,25 +66,45 @@ class Grid:
         self.ndim = len(self.lo)
         self.blocks: List[Block] = []
 
-    def add_block(self, full: Box, data: Box) -> int:
-        full = [(int(a), int(b)) for a, b in full]
-        data = [(int(a), int(b)) for a, b in data]
+    def add_block(self, full, data) -> int:
+        """full / data: per dimension (start, stop) or (start, stop, step)."""
+        fstep = tuple(int(s[2]) if len(s) > 2 else 1 for s in full)
+        dstep = tuple(int(s[2]) if len(s) > 2 else 1 for s in data)
+        full = [(int(s[0]), int(s[1])) for s in full]
+        data = [(int(s[0]), int(s[1])) for s in data]
         assert len(full) == self.ndim and len(data) == self.ndim
+        assert min(fstep + dstep) >= 1
         for (fa, fb), (da, db), lo, hi in zip(full, data, self.lo, self.hi):
             assert lo <= fa <= da < db <= fb <= hi, "data must lie inside full, full inside the global box"
         for blk in self.blocks:
             assert not all(max(a0, b0) < min(a1, b1) for (a0, a1), (b0, b1) in zip(blk.full, full)), \
                 "block full regions must not overlap"
-        self.blocks.append(Block(full, data))
+        self.blocks.append(Block(full, data, fstep, dstep))
         self._index = None
         return len(self.blocks) - 1
+
+    def points(self, box) -> np.ndarray:
+        """Cells of the grid inside a box of positions, row-major, as (n, ndim)
+        coordinates.  Positions between the points of a stepped slice are
+        skipped; a position outside every block's full range is an error."""
+        coords = box_coords(box)
+        if all(st == 1 for blk in self.blocks for st in blk.fstep):
+            return coords
+        keep = []
+        for i, c in enumerate(coords):
+            c = tuple(int(v) for v in c)
+            if self.owner(c) >= 0:
+                keep.append(i)
+            elif not any(box_contains(blk.full, c) for blk in self.blocks):
+                raise ValueError(f"position {c} lies outside every block")
+        return coords[keep] if keep else np.zeros((0, self.ndim), dtype=np.int64)
 
     # ---- cell numbering ------------------------------------------------------
     def _build(self):
         bases, shapes = [], []
         n = 0
         for blk in self.blocks:
-            shp = box_shape(blk.full)
+            shp = tuple(blk.npoints(d) for d in range(self.ndim))
             bases.append(n)
             shapes.append(shp)
             n += int(np.prod(shp))
@@ -78,9 +113,14 @@ class Grid:
         self._ncells = n
         is_data = np.zeros(n, dtype=bool)
         for b, blk in enumerate(self.blocks):
-            m = np.zeros(self._shapes[b], dtype=bool)
-            sl = tuple(slice(da - fa, db - fa) for (fa, _), (da, db) in zip(blk.full, blk.data))
-            m[sl] = True
+            pts = [blk.full[d][0] + blk.fstep[d] * np.arange(self._shapes[b][d]) for d in range(self.ndim)]
+            m = np.ones(self._shapes[b], dtype=bool)
+            for d in range(self.ndim):
+                da, db = blk.data[d]
+                ok = (pts[d] >= da) & (pts[d] < db) & ((pts[d] - da) % blk.dstep[d] == 0)
+                shape = [1] * self.ndim
+                shape[d] = -1
+                m &= ok.reshape(shape)
             is_data[bases[b]: bases[b] + m.size] = m.reshape(-1)
         self._is_data = is_data
         self._data_cells = np.nonzero(is_data)[0]
@@ -144,37 +184,38 @@ class Grid:
         return self._shapes[b]
 
     def owner(self, coord) -> int:
-        """Block whose full region holds ``coord``, or -1."""
+        """Block one of whose cells is ``coord``, or -1."""
         for b, blk in enumerate(self.blocks):
-            if box_contains(blk.full, coord):
+            if blk.has_cell(coord):
                 return b
         return -1
 
     def cell(self, coord) -> int:
-        """Cell number of a global multi-index (must lie in some full region)."""
+        """Cell number of a global multi-index (must be a cell of some block)."""
         self._ensure()
         b = self.owner(coord)
         if b < 0:
-            raise IndexError(f"coordinate {tuple(coord)} is outside every block")
+            raise IndexError(f"coordinate {tuple(coord)} is not a cell of any block")
         blk = self.blocks[b]
         off = 0
-        for (fa, fb), c in zip(blk.full, coord):
-            off = off * (fb - fa) + (c - fa)
+        for d, c in enumerate(coord):
+            off = off * blk.npoints(d) + (c - blk.full[d][0]) // blk.fstep[d]
         return self._bases[b] + off
 
     def cells_of_box(self, b: int, box) -> np.ndarray:
-        """Cell numbers of a box inside block ``b``'s full region, row-major."""
+        """Cell numbers of block ``b``'s cells inside a box of positions, row-major."""
         self._ensure()
         blk = self.blocks[b]
-        coords = box_coords(box)
+        coords = np.array([c for c in box_coords(box) if blk.has_cell(tuple(c))], dtype=np.int64)
+        coords = coords.reshape(-1, self.ndim)
         off = np.zeros(coords.shape[0], dtype=np.int64)
-        for d, (fa, fb) in enumerate(blk.full):
-            off = off * (fb - fa) + (coords[:, d] - fa)
+        for d in range(self.ndim):
+            off = off * blk.npoints(d) + (coords[:, d] - blk.full[d][0]) // blk.fstep[d]
         return self._bases[b] + off
 
     def is_data_coord(self, coord) -> bool:
         b = self.owner(coord)
-        return b >= 0 and box_contains(self.blocks[b].data, coord)
+        return b >= 0 and self.blocks[b].has_data(coord)
 
     def coord_of_cell(self, cell: int):
         self._ensure()
@@ -182,7 +223,8 @@ class Grid:
         blk = self.blocks[b]
         off = cell - self._bases[b]
         out = []
-        for (fa, fb) in reversed(blk.full):
-            out.append(fa + off % (fb - fa))
-            off //= (fb - fa)
+        for d in reversed(range(self.ndim)):
+            n = blk.npoints(d)
+            out.append(blk.full[d][0] + blk.fstep[d] * (off % n))
+            off //= n
         return b, tuple(reversed(out))

@@ -89,9 +89,9 @@ class Operator:
 
 def _ghost_row(grid: Grid, coord, block: int) -> int:
     blk = grid.blocks[block]
-    if not box_contains(blk.full, coord):
+    if not blk.has_cell(coord):
         raise ValueError(f"row {coord} leaves block {block}")
-    if box_contains(blk.data, coord):
+    if blk.has_data(coord):
         raise ValueError(f"row {coord} is a data cell; only ghost rows are written")
     return int(grid.cell2row[grid.cell(coord)])
 
@@ -111,7 +111,7 @@ def assemble(grid: Grid, subs: Sequence, allow_overlap_sum: bool = False) -> Ope
     vec_count = np.zeros(nG, dtype=np.int64)
     b = None
     for sub in subs:
-        coords = box_coords(sub.rows)
+        coords = grid.points(sub.rows)  # the grid's cells in the box (every point for step-1 slices)
         if coords.shape[0] == 0:
             continue
         block = grid.owner(tuple(coords[0]))

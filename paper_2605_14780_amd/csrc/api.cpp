@@ -1,5 +1,6 @@
 // C ABI of hipbc: argument checking, object lifetime, error reporting.
 // Every entry point catches all C++ exceptions and turns them into codes.
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -66,16 +67,55 @@ static void need(bool ok, const char* what) {
   if (!ok) fail(HBC_EINVAL, what);
 }
 
+// ---- positions -> lattice indices (stepped slices, Sec. IV-A-1) ----------------
+static int64_t floor_div(int64_t a, int64_t b) { return a / b - ((a % b != 0) && ((a < 0) != (b < 0))); }
+static int64_t ceil_div(int64_t a, int64_t b) { return -floor_div(-a, b); }
+static int64_t floor_mod(int64_t a, int64_t b) { return a - floor_div(a, b) * b; }
+
+// Index of the first lattice point >= p along dimension d.
+static int64_t index_at_or_after(const Grid& g, int d, int64_t p) { return ceil_div(p - g.res[d], g.step[d]); }
+
+// Index of lattice point p (HBC_ERANGE if p is not one).
+static int64_t index_of(const Grid& g, int d, int64_t p) {
+  if (floor_mod(p - g.res[d], g.step[d]) != 0)
+    fail(HBC_ERANGE, "position " + std::to_string(p) + " is not a point of the grid's lattice along dimension " +
+                         std::to_string(d));
+  return (p - g.res[d]) / g.step[d];
+}
+
+// A box of positions -> the box of lattice indices of the points it holds.
 static Box to_box(const Grid& g, const hbc_box* b) {
   need(b != nullptr, "rows box is NULL");
   Box r;
   r.nd = g.nd;
   for (int d = 0; d < g.nd; ++d) {
-    r.lo[d] = b->lo[d];
-    r.hi[d] = b->hi[d];
-    need(r.hi[d] >= r.lo[d], "box with hi < lo");
+    need(b->hi[d] >= b->lo[d], "box with hi < lo");
+    r.lo[d] = index_at_or_after(g, d, b->lo[d]);
+    r.hi[d] = std::max(r.lo[d], index_at_or_after(g, d, b->hi[d]));
   }
   return r;
+}
+
+// A column given as a row-major linear index over the global box of
+// positions -> the linear index over the global box of lattice indices
+// (-1, padding, stays -1).
+static int64_t to_col(const Grid& g, int64_t lin) {
+  if (lin < 0 || g.identity_lattice()) return lin;
+  int64_t c[HBC_MAX_DIM];
+  for (int d = g.nd - 1; d >= 0; --d) {
+    const int64_t n = g.phi[d] - g.plo[d];
+    c[d] = g.plo[d] + lin % n;
+    lin /= n;
+  }
+  if (lin != 0) fail(HBC_ERANGE, "column index outside the global box");
+  int64_t out = 0;
+  for (int d = 0; d < g.nd; ++d) out = out * (g.hi[d] - g.lo[d]) + (index_of(g, d, c[d]) - g.lo[d]);
+  return out;
+}
+
+static void to_cols(const Grid& g, std::vector<int64_t>& cols) {
+  if (g.identity_lattice()) return;
+  for (int64_t& c : cols) c = to_col(g, c);
 }
 
 static void finish_grid(Grid& g) {
@@ -116,8 +156,8 @@ int hbc_grid_create(int32_t ndim, const int64_t* lo, const int64_t* hi, hbc_grid
     auto* g = new hbc_grid;
     g->g.nd = ndim;
     for (int d = 0; d < ndim; ++d) {
-      g->g.lo[d] = lo[d];
-      g->g.hi[d] = hi[d];
+      g->g.lo[d] = g->g.plo[d] = lo[d];
+      g->g.hi[d] = g->g.phi[d] = hi[d];
     }
     *out = g;
   });
@@ -127,18 +167,31 @@ int hbc_grid_add_block(hbc_grid* gh, const hbc_slice* full, const hbc_slice* dat
   return guard([&] {
     need(gh && full && data, "NULL argument");
     Grid& g = gh->g;
+    for (int d = 0; d < g.nd; ++d) need(full[d].step >= 1 && data[d].step >= 1, "slice steps must be >= 1");
+    if (!g.lattice_set) {  // the first block fixes the grid's lattice
+      for (int d = 0; d < g.nd; ++d) {
+        g.step[d] = full[d].step;
+        g.res[d] = floor_mod(full[d].start, full[d].step);
+        g.lo[d] = index_at_or_after(g, d, g.plo[d]);
+        g.hi[d] = index_at_or_after(g, d, g.phi[d]);
+      }
+      g.lattice_set = true;
+    }
     Block b;
     b.full.nd = b.data.nd = g.nd;
     for (int d = 0; d < g.nd; ++d) {
-      if (full[d].step != 1 || data[d].step != 1)
-        fail(HBC_EUNSUPPORTED, "slices with step != 1 (staggered / multigrid) are not implemented");
-      b.full.lo[d] = full[d].start;
-      b.full.hi[d] = full[d].stop;
-      b.data.lo[d] = data[d].start;
-      b.data.hi[d] = data[d].stop;
-      need(g.lo[d] <= b.full.lo[d] && b.full.lo[d] <= b.data.lo[d] && b.data.lo[d] < b.data.hi[d] &&
-               b.data.hi[d] <= b.full.hi[d] && b.full.hi[d] <= g.hi[d],
+      if (full[d].step != g.step[d] || data[d].step != g.step[d] || floor_mod(full[d].start, g.step[d]) != g.res[d] ||
+          floor_mod(data[d].start, g.step[d]) != g.res[d])
+        fail(HBC_EUNSUPPORTED,
+             "the full and data slices of every block of a grid must lie on one lattice (same step, starts "
+             "congruent modulo the step); other step patterns are not implemented");
+      need(g.plo[d] <= full[d].start && full[d].start <= data[d].start && data[d].start < data[d].stop &&
+               data[d].stop <= full[d].stop && full[d].stop <= g.phi[d],
            "need lo <= full.start <= data.start < data.stop <= full.stop <= hi");
+      b.full.lo[d] = index_of(g, d, full[d].start);
+      b.full.hi[d] = index_at_or_after(g, d, full[d].stop);
+      b.data.lo[d] = index_of(g, d, data[d].start);
+      b.data.hi[d] = index_at_or_after(g, d, data[d].stop);
     }
     for (const Block& o : g.blocks) need(!intersects(o.full, b.full), "block full regions overlap");
     g.blocks.push_back(b);
@@ -243,7 +296,13 @@ int hbc_program_set_consumer(hbc_program* p, int32_t noffsets, const int64_t* of
     need(p != nullptr, "NULL argument");
     need(noffsets >= 0, "noffsets must be >= 0");
     need(noffsets == 0 || offsets != nullptr, "NULL offsets");
-    p->p.consumer.assign(offsets, offsets + (size_t)noffsets * p->p.grid.nd);
+    const Grid& g = p->p.grid;
+    p->p.consumer.assign(offsets, offsets + (size_t)noffsets * g.nd);
+    for (size_t k = 0; k < p->p.consumer.size(); ++k) {  // positions -> lattice steps
+      const int d = (int)(k % (size_t)g.nd);
+      need(p->p.consumer[k] % g.step[d] == 0, "consumer offsets must be multiples of the grid's step");
+      p->p.consumer[k] /= g.step[d];
+    }
   });
 }
 
@@ -253,10 +312,24 @@ int hbc_program_add_map(hbc_program* p, const hbc_box* rows, const int64_t* M, c
     need(p && M && offset, "NULL argument");
     Sub s;
     s.kind = SUB_MAP;
-    s.rows = to_box(p->p.grid, rows);
-    const int nd = p->p.grid.nd;
-    for (int k = 0; k < nd * nd; ++k) s.M[k] = M[k];
-    for (int d = 0; d < nd; ++d) s.off[d] = offset[d];
+    const Grid& g = p->p.grid;
+    s.rows = to_box(g, rows);
+    const int nd = g.nd;
+    // col = M row + offset in positions; with row = res + step k (component-
+    // wise) the map in lattice indices has M'[i][j] = M[i][j] step[j] / step[i]
+    // and offset'[i] = (sum_j M[i][j] res[j] + offset[i] - res[i]) / step[i],
+    // both required to be integers
+    for (int i = 0; i < nd; ++i) {
+      int64_t o = offset[i] - g.res[i];
+      for (int j = 0; j < nd; ++j) {
+        const int64_t m = M[i * nd + j] * g.step[j];
+        need(m % g.step[i] == 0, "map does not send lattice points to lattice points");
+        s.M[i * nd + j] = m / g.step[i];
+        o += M[i * nd + j] * g.res[j];
+      }
+      need(floor_mod(o, g.step[i]) == 0, "map does not send lattice points to lattice points");
+      s.off[i] = floor_div(o, g.step[i]);
+    }
     s.w = weight;
     s.rot = rot_code(rot);
     need(s.rot >= 0, "rot must be a 2x2 signed permutation");
@@ -298,6 +371,7 @@ int hbc_program_add_ell(hbc_program* p, const hbc_box* rows, int32_t width, cons
     need(n == 0 || (cols && vals), "NULL cols / vals");
     s.width = width;
     s.cols.assign(cols, cols + n);
+    to_cols(p->p.grid, s.cols);
     s.vals.assign(vals, vals + n);
     s.rot = rot_code(rot);
     need(s.rot >= 0, "rot must be a 2x2 signed permutation");
@@ -319,6 +393,7 @@ int hbc_program_add_csr(hbc_program* p, const hbc_box* rows, const int64_t* row_
     need(nnz == 0 || (cols && vals), "NULL cols / vals");
     s.ptr.assign(row_ptr, row_ptr + nr + 1);
     s.cols.assign(cols, cols + nnz);
+    to_cols(p->p.grid, s.cols);
     s.vals.assign(vals, vals + nnz);
     s.rot = rot_code(rot);
     need(s.rot >= 0, "rot must be a 2x2 signed permutation");
@@ -355,6 +430,7 @@ int hbc_program_add_data_csr(hbc_program* p, const hbc_box* rows, const int64_t*
     need(nnz == 0 || (cols && vals), "NULL cols / vals");
     s.ptr.assign(row_ptr, row_ptr + nr + 1);
     s.cols.assign(cols, cols + nnz);
+    to_cols(p->p.grid, s.cols);
     s.vals.assign(vals, vals + nnz);
     p->p.dsubs.push_back(std::move(s));
     if (sub_id) *sub_id = (int32_t)(p->p.dsubs.size() - 1);

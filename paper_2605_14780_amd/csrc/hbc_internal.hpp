@@ -56,6 +56,20 @@ struct Block {
 struct Grid {
   int nd = 0;
   int64_t lo[HBC_MAX_DIM] = {0}, hi[HBC_MAX_DIM] = {0};
+  // Lattice of stepped slices (Sec. IV-A-1): along dimension d the grid's
+  // points are the positions res[d] + step[d] * k, and everything inside the
+  // library (lo, hi, blocks, boxes, cells) is in the index k.  Set by the
+  // first block added through the C ABI; the global box in positions is
+  // [plo, phi).  The identity lattice (step 1, res 0) leaves positions as
+  // they are.
+  int64_t step[HBC_MAX_DIM] = {1, 1, 1, 1, 1, 1}, res[HBC_MAX_DIM] = {0};
+  int64_t plo[HBC_MAX_DIM] = {0}, phi[HBC_MAX_DIM] = {0};
+  bool lattice_set = false;
+  bool identity_lattice() const {
+    for (int d = 0; d < nd; ++d)
+      if (step[d] != 1 || res[d] != 0) return false;
+    return true;
+  }
   std::vector<Block> blocks;
   int64_t ncells = 0;
   int owner(const int64_t* c) const;          // block whose full box holds c, or -1

@@ -306,3 +306,68 @@ def test_smoke_entry_is_importable_and_shapes_consistent():
     assert callable(ge.smoke) and callable(ge.build)
     og = ocs.grid(12, 3)
     assert og.ncells == 6 * 18 * 18
+
+
+# ---- stepped slices (staggered variables, multigrid levels) ----------------------------
+def _stepped_programs(nx=5, ny=4):
+    from oracle import MapSub as OMap, RowsSub as ORows, ZeroSub as OZero, VectorSub as OVec
+    from oracle.grid import Grid as OGrid
+    lo, hi = [-2, -1], [2 * nx + 2, ny + 1]
+    full, data = [(-2, 2 * nx + 2, 2), (-1, ny + 1, 1)], [(0, 2 * nx, 2), (0, ny, 1)]
+    g = hb.Grid(lo, hi)
+    g.add_block(full, data)
+    p = hb.Program(g)
+    og = OGrid(lo, hi)
+    og.add_block(full, data)
+    W = hi[1] - lo[1]
+
+    def lin(x, y):  # row-major linear index over the global box of positions
+        return (x - lo[0]) * W + (y - lo[1])
+
+    p.add_map([(-2, 0), (0, ny)], np.eye(2, dtype=np.int64), [2 * nx, 0])
+    p.add_map([(2 * nx, 2 * nx + 2), (0, ny)], np.eye(2, dtype=np.int64), [-2 * nx, 0], weight=-0.5)
+    xs = list(range(0, 2 * nx, 2))
+    p.add_csr([(0, 2 * nx), (-1, 0)], np.arange(0, 2 * len(xs) + 1, 2),
+              [c for x in xs for c in (lin(x, 0), lin(x, 1))], [0.75, 0.25] * len(xs))
+    p.add_zero([(0, 2 * nx), (ny, ny + 1)])
+    bvals = 0.125 * (1.0 + np.arange(len(xs)))
+    p.add_vector([(0, 2 * nx), (ny, ny + 1)], bvals)
+    subs = [OMap([(-2, 0), (0, ny)], lambda c: (c[0] + 2 * nx, c[1])),
+            OMap([(2 * nx, 2 * nx + 2), (0, ny)], lambda c: (c[0] - 2 * nx, c[1]), -0.5),
+            ORows([(0, 2 * nx), (-1, 0)], lambda c: [((c[0], 0), 0.75), ((c[0], 1), 0.25)]),
+            OZero([(0, 2 * nx), (ny, ny + 1)]),
+            OVec([(0, 2 * nx), (ny, ny + 1)], bvals)]
+    return g, p, og, subs
+
+
+def test_stepped_grid_plan_equals_oracle():
+    g, p, og, subs = _stepped_programs()
+    assert g.cells == og.ncells
+    plan = hb.Plan(p, inner=1, host_only=True)
+    op = assemble(og, subs)
+    compare_plan_with_oracle(plan, og, op)
+    st = plan.stats()
+    assert st["rows_covered"] == int(op.covered.sum())
+    # b of the top rows
+    for r, cell in enumerate(og.ghost_cells):
+        if op.has_b[r]:
+            assert plan.row(int(cell))[3] == op.b[r, 0]
+
+
+def test_stepped_grid_errors():
+    g = hb.Grid([0, 0], [16, 8])
+    g.add_block([(0, 8, 2), (0, 8, 1)], [(2, 6, 2), (1, 7, 1)])
+    with pytest.raises(hb.HbcError) as e:  # a second block on another lattice
+        g.add_block([(9, 16, 2), (0, 8, 1)], [(11, 15, 2), (1, 7, 1)])
+    assert e.value.code == hb.EUNSUPPORTED
+    p = hb.Program(g)
+    with pytest.raises(hb.HbcError) as e:  # a column between the lattice points
+        p.add_csr([(0, 1), (0, 1)], [0, 1], [3 * 8 + 1], [1.0])
+    assert e.value.code == hb.ERANGE
+    with pytest.raises(hb.HbcError) as e:  # a map that leaves the lattice
+        p.add_map([(0, 1), (0, 8)], np.eye(2, dtype=np.int64), [1, 0])
+    assert e.value.code == hb.EINVAL
+    with pytest.raises(hb.HbcError) as e:  # consumer offsets must be whole steps
+        p.set_consumer([[1, 0]])
+    assert e.value.code == hb.EINVAL
+    p.set_consumer([[2, 0], [-2, 0], [0, 1], [0, -1]])
