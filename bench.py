@@ -376,6 +376,30 @@ def extra_wide_rows(ctx, hb, torch, tm):
     return out
 
 
+def extra_copy_ceiling(ctx, hb, torch, tm):
+    """A plain device-to-device copy (the runtime's copy kernel) that reads and
+    writes the headline apply's algorithmic bytes (half read, half written),
+    cycling 9 buffers in one graph like the headline: what a straight copy of
+    the same byte count reaches on this GPU at this size."""
+    alg = ctx["c2_alg_bytes"]
+    n = int(alg / 2 / 8)
+    bufs = [torch.randn(2 * n, dtype=torch.float64, device="cuda") for _ in range(9)]
+    R = 90
+
+    def copies():
+        for r in range(R):
+            b = bufs[r % len(bufs)]
+            b[n:].copy_(b[:n])
+
+    g = torch_graph(torch, copies)
+    us = tm(g.replay, R)
+    del g, bufs
+    torch.cuda.empty_cache()
+    return {"bytes_per_copy": 2 * n * 8, "us_per_copy": us, "GBs": 2 * n * 8 / us / 1e3,
+            "hbm_frac": 2 * n * 8 / us / 1e3 / HBM_PEAK_GBS,
+            "apply_over_copy_rate": (ctx["c2_apply_GBs"] / (2 * n * 8 / us / 1e3))}
+
+
 def extra_c48(ctx, hb, torch, tm):
     from tests.helpers import cs_full_field
     N, h = 48, 3
@@ -586,7 +610,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extras", default="all",
-                    help="comma-separated subset of: c384_plane_major, c384_cross_footprint, wide_rows, edge_average_np385, "
+                    help="comma-separated subset of: copy_ceiling, c384_plane_major, c384_cross_footprint, wide_rows, edge_average_np385, "
                          "c48_latency, hpcg_256cube, "
                          "batched_64_grids_f32, c768_adjoint")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -618,10 +642,13 @@ def main():
     res = headline(ctx, args, hb, torch, tm)
     st = res["stats"]
     log("headline done")
+    ctx["c2_alg_bytes"] = st["alg_bytes"]
+    ctx["c2_apply_GBs"] = st["alg_bytes"] / (res["ms"] / args.steps / 1e3) / 1e9
     extras = {"c384_warm_cache_us_per_apply": res["warm_us"], "c384_eager_us_per_apply": res["eager_us"],
               "c384_f32": res["f32"], "c384_launch_shape": res["tuning"]}
     if not args.no_extras:
-        table = (("c384_plane_major", extra_c384_plane_major), ("c384_cross_footprint", extra_footprint),
+        table = (("copy_ceiling", extra_copy_ceiling),
+                 ("c384_plane_major", extra_c384_plane_major), ("c384_cross_footprint", extra_footprint),
                  ("wide_rows", extra_wide_rows),
                  ("edge_average_np385", extra_edge_average),
                  ("c48_latency", extra_c48),
