@@ -1094,13 +1094,30 @@ __global__ __launch_bounds__(256) void k_adjoint_lds(PlanDesc d, AdjDesc a, AdjL
   }
   const AdjLdsTile tl = q.tiles[blockIdx.x];
   const int nu = tl.nu;
-  for (int e = threadIdx.x; e < nu * nvec; e += blockDim.x) {
-    const int u = e / nvec, v = e - u * nvec;
-    const Pack<T, V> g = ldv<T, V>(f + (int64_t)q.ucell[tl.first_u + u] * d.cs + (int64_t)v * V);
-    vt w;
+  // staging: SG vector loads of ghost rows in flight per thread, then their
+  // LDS stores (row u of the tile at u * inner)
+  constexpr int SG = 4;
+  const int nstage = nu * nvec, bd = (int)blockDim.x;
+  for (int e0 = threadIdx.x; e0 < nstage; e0 += SG * bd) {
+    Pack<T, V> g[SG];
 #pragma unroll
-    for (int i = 0; i < V; ++i) w[i] = g.v[i];
-    *reinterpret_cast<vt*>(&rows[(int64_t)u * inner + (int64_t)v * V]) = w;
+    for (int j = 0; j < SG; ++j) {
+      const int e = e0 + j * bd;
+      if (e < nstage) {
+        const int u = e / nvec, v = e - u * nvec;
+        g[j] = ldv<T, V>(f + (int64_t)q.ucell[tl.first_u + u] * d.cs + (int64_t)v * V);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < SG; ++j) {
+      const int e = e0 + j * bd;
+      if (e < nstage) {
+        vt w;
+#pragma unroll
+        for (int i = 0; i < V; ++i) w[i] = g[j].v[i];
+        *reinterpret_cast<vt*>(&rows[(int64_t)e * V]) = w;  // = u * inner + v * V
+      }
+    }
   }
   __syncthreads();  // every load of this tile's ghost rows has returned
   if ((int)threadIdx.x < nu) {
