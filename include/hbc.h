@@ -130,6 +130,7 @@ typedef struct {
   int64_t ghost_cells_live; /* ghost cells some consumer read reaches (all ghost cells without a consumer) */
   int64_t rows_wide;        /* CSR rows served by the LDS-staged wide-row kernel (point-major, >= 128-byte rows) */
   int64_t wide_tiles;       /* tiles of those rows */
+  int64_t rows_narrow;      /* CSR rows of >= 8 entries and < 32 bytes served by the entry-splitting kernel */
 } hbc_stats;
 
 /* Launch shape of the apply kernels (chosen by the plan, changed by tuning). */

@@ -52,7 +52,7 @@ class StatsT(C.Structure):
         "rows_vector_only", "rows_with_b", "nnz", "unique_sources", "segments", "tiles", "ghost_values")] + [
         ("alg_bytes", C.c_double), ("alg_bytes_adjoint", C.c_double), ("table_bytes", C.c_int64),
         ("rows_data", C.c_int64), ("rows_dead", C.c_int64), ("ghost_cells_live", C.c_int64),
-        ("rows_wide", C.c_int64), ("wide_tiles", C.c_int64)]
+        ("rows_wide", C.c_int64), ("wide_tiles", C.c_int64), ("rows_narrow", C.c_int64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

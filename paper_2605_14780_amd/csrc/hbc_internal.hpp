@@ -202,6 +202,20 @@ struct alignas(16) WideTile {
   int32_t r0, rp0;      // rows: w_row[r0, r0 + nrows); row starts: w_rp[rp0, rp0 + nrows]
 };
 
+// Narrow wide rows: CSR segments averaging >= WIDE_NNZ entries per row whose
+// rows are shorter than NARROW_ROW_BYTES (point-major).  A group of
+// NARROW_LANES lanes takes one row and splits its entries (lane j takes
+// entries j, j + NARROW_LANES, ...), each lane keeps partial sums of every
+// inner slot, and the partials are added across the group by a fixed xor
+// butterfly.  Tiles are runs of NARROW_ROWS consecutive rows (one workgroup).
+constexpr int NARROW_LANES = 16, NARROW_ROW_BYTES = 32, NARROW_ROWS = 256 / NARROW_LANES;
+struct alignas(16) NarrowTile {
+  int32_t rot, has_b, b_inner, nrows;
+  int64_t row_begin;  // index into the per-row tables
+  int64_t tab;        // index of the first row's CSR pointer
+  int64_t brow;       // b table offset of the first row
+};
+
 // Adjoint: one entry per (source cell, ghost row) contribution, sorted by
 // source cell then ghost cell.
 struct CscHost {
@@ -285,6 +299,9 @@ struct HostTables {
   std::vector<double> w_entw;    // entries in tile order: weight
   std::vector<int32_t> w_ents;   // entries in tile order: LDS slot of the source cell
   int32_t w_maxu = 0, w_maxe = 0;  // largest nu and ne over the tiles (LDS sizing)
+  // narrow wide rows (see NarrowTile); seg_narrow marks the segments they take
+  std::vector<char> seg_narrow;
+  std::vector<NarrowTile> ntiles;
   // data rows: destination cells, CSR over data cells (absolute pointers)
   std::vector<int32_t> dr_cell;
   std::vector<int64_t> dr_ptr;
@@ -334,6 +351,7 @@ struct Plan {
   const int32_t* d_w_row = nullptr;
   const int32_t* d_w_rp = nullptr;
   const void* d_w_ent = nullptr;  // packed {weight, slot * values per slice} per entry
+  const NarrowTile* d_ntiles = nullptr;
   const int32_t* d_dr_cell = nullptr;
   const int64_t* d_dr_ptr = nullptr;
   const int32_t* d_dr_col = nullptr;

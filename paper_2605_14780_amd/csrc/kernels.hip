@@ -735,6 +735,77 @@ __global__ __launch_bounds__(256) void k_apply_wide(PlanDesc d, const WideTile* 
   }
 }
 
+// Narrow wide rows (NarrowTile): rows of >= WIDE_NNZ entries and fewer than
+// NARROW_ROW_BYTES (a few inner values).  A group of NARROW_LANES lanes takes
+// one row: lane j sums entries j, j + NARROW_LANES, ... of the row for every
+// source slot (starting from -0.0, the additive identity, with FMAs; two
+// entries' loads in flight at a time), the partial sums are added across
+// the group by an xor butterfly (every lane ends with the same bits), and
+// lane l < inner writes output slot l through the component rotation.  The
+// order of the sum differs from the general row path, the result is
+// deterministic.  zero_only writes +0 to the tile's rows.
+template <typename T>
+__global__ __launch_bounds__(256) void k_apply_narrow(PlanDesc d, const NarrowTile* __restrict__ tiles,
+                                                      int zero_only) {
+  constexpr int G = NARROW_LANES, IM = NARROW_ROW_BYTES / (int)sizeof(T);
+  const NarrowTile tl = tiles[blockIdx.x];
+  const int j = threadIdx.x % G, rr = threadIdx.x / G;
+  const bool live = rr < tl.nrows;  // every lane takes part in the butterfly
+  const int inner = (int)d.inner;
+  T* __restrict__ f = static_cast<T*>(d.field);
+  const T* __restrict__ vals = static_cast<const T*>(d.csr_val);
+  int64_t e0 = 0, e1 = 0, dst = 0;
+  if (live) {
+    e0 = d.csr_ptr[tl.tab + rr];
+    e1 = d.csr_ptr[tl.tab + rr + 1];
+    dst = d.row_dst[tl.row_begin + rr];
+  }
+  T p[IM];
+#pragma unroll
+  for (int l = 0; l < IM; ++l) p[l] = T(-0.0);
+  if (!zero_only) {
+    for (int64_t e = e0 + j; e < e1; e += 2 * G) {
+      const bool two = e + G < e1;
+      const int64_t c0 = d.csr_col[e], c1 = two ? d.csr_col[e + G] : c0;
+      const T w0 = vals[e], w1 = two ? vals[e + G] : T(0);
+      T x0[IM], x1[IM];
+#pragma unroll
+      for (int l = 0; l < IM; ++l)
+        if (l < inner) {
+          x0[l] = f[c0 * d.cs + l];
+          x1[l] = f[c1 * d.cs + l];
+        }
+#pragma unroll
+      for (int l = 0; l < IM; ++l)
+        if (l < inner) {
+          p[l] = fma(w0, x0[l], p[l]);
+          if (two) p[l] = fma(w1, x1[l], p[l]);
+        }
+    }
+#pragma unroll
+    for (int off = G / 2; off >= 1; off /= 2)
+#pragma unroll
+      for (int l = 0; l < IM; ++l)
+        if (l < inner) p[l] += __shfl_xor(p[l], off, G);
+  }
+  if (!live || j >= inner) return;
+  T out = T(0);
+  if (!zero_only) {
+    T sign;
+    const int src = (int)rot_slot<T>(d, tl.rot, j, sign);
+    T v = p[0];
+#pragma unroll
+    for (int m = 1; m < IM; ++m)
+      if (m == src) v = p[m];
+    out = sign * (e1 > e0 ? v : T(0));
+    if (tl.has_b) {
+      const T* bp = static_cast<const T*>(d.bval) + tl.brow + (int64_t)rr * tl.b_inner;
+      out += tl.b_inner == 1 ? bp[0] : bp[j];
+    }
+  }
+  f[dst * d.cs + j] = out;
+}
+
 // Data rows (block-edge averaging).  Every row of an apply reads the input
 // field, so data rows are first computed into scratch by extra workgroups of
 // the ghost-row launch (they only read data cells and write scratch), and
@@ -1508,6 +1579,7 @@ void device_upload_plan(Plan& p) {
   size_t o_wr = pk.vec(T.w_row);
   size_t o_wp = pk.vec(T.w_rp);
   size_t o_we = pk.wide_entries(T.w_entw, T.w_ents, p.dtype);
+  size_t o_nt = pk.vec(T.ntiles);
   size_t o_drc = pk.vec(T.dr_cell);
   size_t o_drp = pk.vec(T.dr_ptr);
   size_t o_drk = pk.vec(T.dr_col);
@@ -1539,6 +1611,7 @@ void device_upload_plan(Plan& p) {
   p.d_w_row = reinterpret_cast<const int32_t*>(b + o_wr);
   p.d_w_rp = reinterpret_cast<const int32_t*>(b + o_wp);
   p.d_w_ent = b + o_we;
+  p.d_ntiles = reinterpret_cast<const NarrowTile*>(b + o_nt);
   p.d_dr_cell = reinterpret_cast<const int32_t*>(b + o_drc);
   p.d_dr_ptr = reinterpret_cast<const int64_t*>(b + o_drp);
   p.d_dr_col = reinterpret_cast<const int32_t*>(b + o_drk);
@@ -1723,6 +1796,11 @@ static void launch_wide(const Plan& p, const PlanDesc& d, hipStream_t st, bool z
 
 template <typename T>
 static void launch_apply_t(const Plan& p, const PlanDesc& d, hipStream_t st, bool zero_only) {
+  if (p.layout.order == HBC_POINT_MAJOR && !p.host.ntiles.empty()) {
+    hipLaunchKernelGGL((k_apply_narrow<T>), dim3((int)p.host.ntiles.size()), dim3(256), 0, st, d, p.d_ntiles,
+                       zero_only ? 1 : 0);
+    HIP_CHECK(hipGetLastError());
+  }
   if (p.layout.order == HBC_POINT_MAJOR && !p.host.wtiles.empty()) {
     if (sizeof(T) == 4 && p.vec == 4)
       launch_wide<T, (sizeof(T) == 4 ? 4 : 2)>(p, d, st, zero_only);

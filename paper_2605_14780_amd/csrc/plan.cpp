@@ -844,6 +844,36 @@ static void build_wide(Plan& plan) {
   }
 }
 
+// Narrow wide-row tiles (see NarrowTile): runs of NARROW_ROWS consecutive rows.
+static void build_narrow(Plan& plan) {
+  HostTables& T = plan.host;
+  T.seg_narrow.assign(T.segs.size(), 0);
+  T.ntiles.clear();
+  plan.stats.rows_narrow = 0;
+  if (plan.layout.order != HBC_POINT_MAJOR) return;
+  const int64_t es = plan.dtype == HBC_F64 ? 8 : 4;
+  if (plan.layout.inner * es >= NARROW_ROW_BYTES) return;
+  for (size_t si = 0; si < T.segs.size(); ++si) {
+    const DevSeg& sg = T.segs[si];
+    if (sg.kind != SEG_CSR || sg.nrows == 0 || T.seg_wide[si]) continue;
+    const int64_t nnz = T.csr_ptr[sg.tab + sg.nrows] - T.csr_ptr[sg.tab];
+    if (nnz < WIDE_NNZ * sg.nrows) continue;
+    T.seg_narrow[si] = 1;
+    for (int64_t r = 0; r < sg.nrows; r += NARROW_ROWS) {
+      NarrowTile t{};
+      t.rot = sg.rot;
+      t.has_b = sg.has_b;
+      t.b_inner = sg.b_inner;
+      t.nrows = (int32_t)std::min<int64_t>(NARROW_ROWS, sg.nrows - r);
+      t.row_begin = sg.row_base + r;
+      t.tab = sg.tab + r;
+      t.brow = sg.brow + r * sg.b_inner;
+      T.ntiles.push_back(t);
+      plan.stats.rows_narrow += t.nrows;
+    }
+  }
+}
+
 void build_tiles(Plan& plan, const hbc_tune& t) {
   if (t.block < 64 || t.block > 256 || t.block % 64) fail(HBC_EINVAL, "block must be 64, 128, 192 or 256");
   if (t.lanes_per_row < 1 || (t.lanes_per_row & (t.lanes_per_row - 1)) || t.lanes_per_row > t.block)
@@ -883,9 +913,10 @@ void build_tiles(Plan& plan, const hbc_tune& t) {
   // the same cut as point-major row tiles (same XCD-aware order)
   plan.host.rtiles.clear();
   if (plan.host.seg_wide.size() != plan.host.segs.size()) build_wide(plan);
+  if (plan.host.seg_narrow.size() != plan.host.segs.size()) build_narrow(plan);
   for (const DevTile& tl : plan.host.tiles) {
     const DevSeg& sg = plan.host.segs[tl.seg];
-    if (plan.host.seg_wide[tl.seg]) continue;  // served by the wide-row tiles
+    if (plan.host.seg_wide[tl.seg] || plan.host.seg_narrow[tl.seg]) continue;  // served by the wide-row kernels
     RowTile rt{};
     rt.kind = sg.kind;
     rt.rot = sg.rot;

@@ -297,6 +297,23 @@ def test_wide_row_selection(inner, dtype, order, wide):
         assert st["wide_tiles"] >= 24 * -(-h * N // 32)
     else:
         assert st["rows_wide"] == 0 and st["wide_tiles"] == 0
+    assert st["rows_narrow"] == 0
+
+
+@pytest.mark.parametrize("inner,dtype,order,narrow", [(3, "f64", hb.POINT_MAJOR, True), (4, "f64", hb.POINT_MAJOR, False),
+                                                     (7, "f32", hb.POINT_MAJOR, True), (8, "f32", hb.POINT_MAJOR, False),
+                                                     (1, "f64", hb.PLANE_MAJOR, False)])
+def test_narrow_row_selection(inner, dtype, order, narrow):
+    """CSR rows of >= 8 entries and < 32 bytes in point-major plans go to the
+    entry-splitting kernel; everything else stays on the other paths."""
+    N, h = 12, 2
+    g = hb.Grid.cubed_sphere(N, h)
+    p = hb.Program(g)
+    p.cs_add_quadrature(N, h, 2)
+    dt = hb.F64 if dtype == "f64" else hb.F32
+    st = hb.Plan(p, inner=inner, dtype=dt, order=order, host_only=True).stats()
+    assert st["rows_narrow"] == (st["rows_csr"] if narrow else 0)
+    assert st["rows_wide"] == 0
 
 
 def test_smoke_entry_is_importable_and_shapes_consistent():

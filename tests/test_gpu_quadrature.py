@@ -107,22 +107,23 @@ def test_quadrature_rows_staged(nl, dtype):
 def test_wide_kernel_matches_general_rows_bitwise(dtype, h):
     """The staged wide-row kernel (rows of >= 128 bytes: many tiles per side,
     every ghost layer of a position in one tile) sums each row in the same
-    order as the general row path (rows of < 128 bytes): applying one program
-    to 64 inner values, and to the same values 8 at a time, gives equal bits."""
+    order as the general row path (rows of 32 to 127 bytes): applying one
+    program to 64 inner values, and to the same values 8 at a time, gives
+    equal bits."""
     N, q = 20, 2
     dt, npdt = (hb.F64, np.float64) if dtype == "f64" else (hb.F32, np.float32)
     g = hb.Grid.cubed_sphere(N, h)
     p = hb.Program(g)
     p.cs_add_quadrature(N, h, q)
     wide = hb.Plan(p, inner=64, dtype=dt)
-    narrow = hb.Plan(p, inner=8 if dt == hb.F64 else 4, dtype=dt)
+    narrow = hb.Plan(p, inner=8, dtype=dt)
     sw, sn = wide.stats(), narrow.stats()
     assert sw["rows_wide"] == sw["rows_csr"] and sw["wide_tiles"] > 24
-    assert sn["rows_wide"] == 0
+    assert sn["rows_wide"] == 0 and sn["rows_narrow"] == 0
     full = cs_full_field(N, h, 1, 64, seed=11 + h).astype(npdt)
     t = torch.from_numpy(full.copy()).cuda()
     hb.apply(wide, t)
-    k = 8 if dt == hb.F64 else 4  # rows of 64 or 16 bytes: the general row path
+    k = 8  # rows of 64 or 32 bytes: the general row path
     parts = []
     for c0 in range(0, 64, k):
         s = torch.from_numpy(np.ascontiguousarray(full[:, c0:c0 + k])).cuda()
@@ -133,3 +134,59 @@ def test_wide_kernel_matches_general_rows_bitwise(dtype, h):
     got_narrow = torch.cat(parts, dim=1).cpu().numpy()
     assert np.array_equal(got_wide.view(np.uint64 if dt == hb.F64 else np.uint32),
                           got_narrow.view(np.uint64 if dt == hb.F64 else np.uint32))
+
+
+@pytest.mark.parametrize("I,vector,dtype", [(3, True, "f64"), (1, False, "f64"), (7, False, "f32"),
+                                            (3, True, "f32")])
+def test_quadrature_rows_narrow(I, vector, dtype):
+    """Rows of < 32 bytes (the shallow-water (h, u, v) case) take the kernel
+    that splits a row's entries over 16 lanes and adds the partial sums by a
+    butterfly: oracle parity with b on one side and the (u, v) rotation,
+    determinism over repeated applies, and the adjoint's dot-product identity
+    (its ghost reset goes through the same kernel)."""
+    N, h, q = 14, 3, 2
+    vec = (1, 1, 1) if vector else None
+    dt, npdt = (hb.F64, np.float64) if dtype == "f64" else (hb.F32, np.float32)
+    g = hb.Grid.cubed_sphere(N, h)
+    p = hb.Program(g)
+    p.cs_add_quadrature(N, h, q, vector=vector)
+    rng = np.random.default_rng(I)
+    b = rng.standard_normal((N * h, I))
+    p.add_vector(ocs.side_box(2, ocs.TOP, N, h), b, ninner=I)
+    plan = hb.Plan(p, inner=I, vec=vec, dtype=dt)
+    st = plan.stats()
+    assert st["rows_narrow"] == st["rows_csr"] == 24 * h * N and st["rows_wide"] == 0
+    full = cs_full_field(N, h, I, 1, seed=50 + I)
+    t = torch.from_numpy(full.astype(npdt)).cuda()
+    hb.apply(plan, t)
+    torch.cuda.synchronize()
+    got = t.cpu().numpy().astype(np.float64)
+    og = ocs.grid(N, h)
+    from oracle import VectorSub
+    op = assemble(og, oq.subs(N, h, q, vector=vector) + [VectorSub(ocs.side_box(2, ocs.TOP, N, h), b)])
+    ref = o_apply(op, full, vec)
+    G = og.ghost_cells
+    pat, mag = wide_bounds(op, full, og, vec)
+    ulp = 2.0 ** -53 if dt == hb.F64 else 2.0 ** -24
+    tol = 1e-13 * pat + 64 * ulp * (mag + np.abs(ref[G]))
+    d = np.abs(got[G] - ref[G])
+    assert (d <= tol).all(), float((d / np.maximum(tol, 1e-300)).max())
+    corners = np.isin(G, np.concatenate([og.cells_of_box(f, bx) for f in range(6) for bx in ocs.corner_boxes(f, N, h)]))
+    assert (got[G][corners] == 0).all()
+    for _ in range(3):  # same bits on every apply
+        t2 = torch.from_numpy(full.astype(npdt)).cuda()
+        hb.apply(plan, t2)
+        torch.cuda.synchronize()
+        assert np.array_equal(t2.cpu().numpy().astype(np.float64), got, equal_nan=True)
+    y = torch.randn(g.cells, I, dtype=t.dtype, device="cuda", generator=torch.Generator("cuda").manual_seed(4))
+    x = torch.from_numpy(np.nan_to_num(full, nan=0.0).astype(npdt)).cuda()
+    Ax, z, Aty = x.clone(), torch.zeros_like(x), y.clone()
+    hb.apply(plan, Ax)
+    hb.apply(plan, z)
+    hb.apply_adjoint(plan, Aty)
+    torch.cuda.synchronize()
+    lhs = float(((Ax.double() - z.double()) * y.double()).sum())
+    rhs = float((x.double() * Aty.double()).sum())
+    assert abs(lhs - rhs) <= (1e-12 if dt == hb.F64 else 1e-5) * max(abs(lhs), abs(rhs))
+    Gm = torch.from_numpy(og.ghost_cells).cuda()
+    assert (Aty[Gm] == 0).all()  # covered ghosts cleared
