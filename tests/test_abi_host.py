@@ -388,3 +388,23 @@ def test_stepped_grid_errors():
         p.set_consumer([[1, 0]])
     assert e.value.code == hb.EINVAL
     p.set_consumer([[2, 0], [-2, 0], [0, 1], [0, -1]])
+
+
+def test_cell_count_limit():
+    """Cell numbers are 32-bit on the device: a grid of 2^31 - 2 cells
+    compiles (host work is per row, not per cell), one more cell is refused."""
+    n = (1 << 31) - 2
+    g = hb.Grid([-1], [n - 1])
+    g.add_block([(-1, n - 1)], [(0, n - 2)])
+    p = hb.Program(g)
+    p.add_zero([(-1, 0)])
+    p.add_map([(n - 2, n - 1)], [[1]], [-1])
+    plan = hb.Plan(p, inner=1, host_only=True)
+    assert g.cells == n and plan.stats()["rows_covered"] == 2
+    g2 = hb.Grid([-1], [n])
+    g2.add_block([(-1, n)], [(0, n - 1)])
+    p2 = hb.Program(g2)
+    p2.add_zero([(-1, 0)])
+    with pytest.raises(hb.HbcError) as e:
+        hb.Plan(p2, inner=1, host_only=True)
+    assert e.value.code == hb.EUNSUPPORTED

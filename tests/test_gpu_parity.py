@@ -319,3 +319,70 @@ def test_size_and_alignment_errors():
     t = torch.zeros(grid.cells * 2 + 1, dtype=torch.float64, device="cuda")[1:]
     with pytest.raises(hb.HbcError):
         hb.apply(plan, t)
+
+
+@pytest.mark.parametrize("I,order,dtype", [(3, 0, "f64"), (8, 0, "f64"), (32, 0, "f64"), (64, 0, "f32"),
+                                           (4, 1, "f64"), (7, 0, "f32")])
+def test_csr_segments_with_empty_rows(I, order, dtype):
+    """CSR rows alternating 16 entries and none (8 per row on average), with
+    b on half of them: the segment goes to the entry-splitting kernel (rows
+    < 32 bytes), the general row path, the LDS-staged kernel (rows >= 128
+    bytes) or the plane-major kernel; empty rows give 0 (+ b)."""
+    from oracle import RowsSub, VectorSub
+    from oracle.grid import Grid as OGrid
+    n0, n1, h = 40, 24, 2
+    lo, hi = [-h, -h], [n0 + h, n1 + h]
+    g = hb.Grid(lo, hi)
+    g.add_block([(-h, n0 + h), (-h, n1 + h)], [(0, n0), (0, n1)])
+    og = OGrid(lo, hi)
+    og.add_block([(-h, n0 + h), (-h, n1 + h)], [(0, n0), (0, n1)])
+    rows = [(-h, 0), (0, n1)]
+    nrows = h * n1
+    rng = np.random.default_rng(I)
+    W = hi[1] - lo[1]
+    ptr, cols, vals, ents = [0], [], [], []
+    for r in range(nrows):
+        e = []
+        if r % 2 == 0:
+            for _ in range(16):
+                x, y = int(rng.integers(0, n0)), int(rng.integers(0, n1))
+                w = float(rng.standard_normal())
+                e.append(((x, y), w))
+                cols.append((x - lo[0]) * W + (y - lo[1]))
+                vals.append(w)
+        ptr.append(len(cols))
+        ents.append(e)
+    p = hb.Program(g)
+    p.add_csr(rows, ptr, cols, vals)
+    b_rows = [(-1, 0), (0, n1)]
+    b = rng.standard_normal((n1, I))
+    p.add_vector(b_rows, b, ninner=I)
+    dt, npdt = (hb.F64, np.float64) if dtype == "f64" else (hb.F32, np.float32)
+    plan = hb.Plan(p, inner=I, order=order, dtype=dt)
+    st = plan.stats()
+    if order == 0 and I * np.dtype(npdt).itemsize < 32:
+        assert st["rows_narrow"] == nrows
+    elif order == 0 and I * np.dtype(npdt).itemsize >= 128:
+        assert st["rows_wide"] == nrows
+    else:
+        assert st["rows_narrow"] == 0 and st["rows_wide"] == 0
+    order_of = {}
+    for k, (x, y) in enumerate((x, y) for x in range(-h, 0) for y in range(0, n1)):
+        order_of[(x, y)] = k
+    sub = RowsSub(rows, lambda c: ents[order_of[(c[0], c[1])]])
+    op = assemble(og, [sub, VectorSub(b_rows, b)])
+    full = rng.standard_normal((og.ncells, I)).astype(npdt).astype(np.float64)  # inputs as the GPU holds them
+    ref = o_apply(op, full)
+    got = run_apply(plan, full, order, npdt)
+    G = og.ghost_cells
+    eps = 2.0 ** -53 if dtype == "f64" else 2.0 ** -24
+    mag = np.abs(op.dense()) @ np.abs(full[og.data_cells])
+    mag = mag + (np.abs(op.b) if op.b is not None else 0.0)
+    err = np.abs(got[G] - ref[G])
+    bad = np.argwhere(err > 32 * eps * mag + 1e-300)
+    assert bad.size == 0, (bad[:5].tolist(), err[tuple(bad[0])], mag[tuple(bad[0])], got[G][tuple(bad[0])],
+                           ref[G][tuple(bad[0])], og.coord_of_cell(int(G[bad[0][0]])))
+    empty = np.array([len(e) == 0 for e in ents])
+    cells = og.cells_of_box(0, rows)
+    no_b = og.cells_of_box(0, [(-h, -1), (0, n1)])
+    assert (got[np.intersect1d(cells[empty], no_b)] == 0).all()
