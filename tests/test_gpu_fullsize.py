@@ -7,7 +7,9 @@
 * C768, halo 3, 32 levels, with a sub-vector b on every side: the adjoint
   against the forward through the dot-product identity;
 * C384 wide interpolation rows (16..25 entries, LDS-staged kernel): sampled
-  rows against the oracle's.
+  rows against the oracle's;
+* the 64-grid FP32 batch in its autotuned graph launch: bit identity with
+  plain applies and sampled rows against the oracle's.
 """
 import numpy as np
 import pytest
@@ -164,3 +166,61 @@ def test_c384_wide_rows_sampled():
         bnd_rot[v_sl] = bnd_rot[u_sl]
         assert (np.abs(got - ref) <= bnd_rot).all(), (f, j, i)
         rows += 1
+
+
+def test_batch_64_grids_full_size(tmp_path):
+    """The batch of 64 cubed-sphere grids (C48..C768, halo 2..4, 1..128
+    levels, FP32) in the autotuned, graph-captured launch: bit-identical to
+    64 plain applies, and sampled rows of three grids against the oracle's
+    rows (FP32 weights and accumulation: 8 roundings of sum |w x|)."""
+    draws = synthinputs.batch_draw()
+    plans, inputs = [], []
+    for k, (N, h, L) in enumerate(draws):
+        grid, prog = hb.cs_program(N, h, hb.CS_LAGRANGE)
+        plans.append(hb.Plan(prog, inner=L, dtype=hb.F32))
+        W = N + 2 * h
+        full = torch.full((6, W, W, L), float("nan"), dtype=torch.float32, device="cuda")
+        full[:, h:h + N, h:h + N, :] = synthinputs.cs_sh_field_torch(N, 1, L, seed=4000 + k, dtype=torch.float32)
+        inputs.append(full.reshape(-1))
+    want = []
+    for plan, x in zip(plans, inputs):
+        y = x.clone()
+        hb.apply(plan, y)
+        want.append(y)
+    batch = hb.Batch(plans)
+    fields = [x.clone() for x in inputs]
+    batch.bind(fields)
+    batch.autotune(str(tmp_path / "batch_tune.jsonl"))
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        batch.graph_capture(s.cuda_stream)
+        for rep in range(2):
+            for f, x in zip(fields, inputs):
+                f.copy_(x)
+            torch.cuda.synchronize()
+            batch.graph_launch(s.cuda_stream)
+            torch.cuda.synchronize()
+            for k, (f, w) in enumerate(zip(fields, want)):
+                assert torch.equal(f, w), (rep, k, draws[k])
+    del want
+    rng = np.random.default_rng(8)
+    sizes = [N for N, _, _ in draws]
+    for k in {int(np.argmin(sizes)), int(np.argmax(sizes)), 17}:
+        N, h, L = draws[k]
+        W = N + 2 * h
+        x = inputs[k].reshape(-1, L)
+        out = fields[k].reshape(-1, L)
+        checked = 0
+        while checked < 60:
+            f = int(rng.integers(6))
+            j, i = (int(v) for v in rng.integers(-h, N + h, size=2))
+            if (0 <= j < N and 0 <= i < N) or ocs.is_corner(j, i, N):
+                continue
+            ents = ocs.lagrange_entries(f, j, i, N)
+            src = [(g * W + (jj + h)) * W + (ii + h) for (g, jj, ii), _ in ents]
+            w = np.array([wv for _, wv in ents])
+            X = x[torch.tensor(src, device="cuda")].cpu().numpy().astype(np.float64)
+            ref = w @ X
+            got = out[(f * W + (j + h)) * W + (i + h)].cpu().numpy().astype(np.float64)
+            assert (np.abs(got - ref) <= 8 * 2.0 ** -24 * (np.abs(w) @ np.abs(X))).all(), (k, f, j, i)
+            checked += 1
