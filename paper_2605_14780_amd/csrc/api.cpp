@@ -166,8 +166,11 @@ int hbc_grid_create(int32_t ndim, const int64_t* lo, const int64_t* hi, hbc_grid
 int hbc_grid_add_block(hbc_grid* gh, const hbc_slice* full, const hbc_slice* data, int32_t* block_id) {
   return guard([&] {
     need(gh && full && data, "NULL argument");
-    Grid& g = gh->g;
-    for (int d = 0; d < g.nd; ++d) need(full[d].step >= 1 && data[d].step >= 1, "slice steps must be >= 1");
+    Grid& live = gh->g;
+    for (int d = 0; d < live.nd; ++d) need(full[d].step >= 1 && data[d].step >= 1, "slice steps must be >= 1");
+    // work on a copy: the grid (and, for its first block, its lattice) changes
+    // only if the block is accepted
+    Grid g = live;
     if (!g.lattice_set) {  // the first block fixes the grid's lattice
       for (int d = 0; d < g.nd; ++d) {
         g.step[d] = full[d].step;
@@ -197,7 +200,8 @@ int hbc_grid_add_block(hbc_grid* gh, const hbc_slice* full, const hbc_slice* dat
     g.blocks.push_back(b);
     finish_grid(g);
     need(g.ncells < (int64_t(1) << 40), "grid too large");
-    if (block_id) *block_id = (int32_t)g.blocks.size() - 1;
+    live = std::move(g);
+    if (block_id) *block_id = (int32_t)live.blocks.size() - 1;
   });
 }
 

@@ -408,3 +408,12 @@ def test_cell_count_limit():
     with pytest.raises(hb.HbcError) as e:
         hb.Plan(p2, inner=1, host_only=True)
     assert e.value.code == hb.EUNSUPPORTED
+
+
+def test_rejected_first_block_leaves_the_grid_unchanged():
+    g = hb.Grid([0, 0], [16, 8])
+    with pytest.raises(hb.HbcError):  # data outside full: rejected
+        g.add_block([(0, 8, 2), (0, 8, 1)], [(2, 10, 2), (1, 7, 1)])
+    assert g.cells == 0
+    g.add_block([(0, 16, 1), (0, 8, 1)], [(1, 15, 1), (1, 7, 1)])  # another lattice is still possible
+    assert g.cells == 16 * 8
