@@ -169,7 +169,10 @@ int hbc_grid_block_cells(const hbc_grid* g, int32_t b, int64_t* first_cell, int6
 void hbc_grid_destroy(hbc_grid* g);
 
 /* Cubed sphere (equiangular gnomonic): 6 blocks along coordinate 0, block f has
- * full (f, f+1) x [-h, N+h)^2 and data (f, f+1) x [0, N)^2; index (face, j, i). */
+ * full (f, f+1) x [-h, N+h)^2 and data (f, f+1) x [0, N)^2; index (face, j, i).
+ * N >= 4 and 1 <= h <= N/2: a ghost layer's centre angle pi/4 + (k + 1/2) pi/(2N)
+ * must stay below pi/2, inside the face's gnomonic chart (HBC_EINVAL otherwise;
+ * the same bound holds for every cubed-sphere entry point). */
 int hbc_cs_grid_create(int64_t N, int64_t h, hbc_grid** out);
 /* Cartesian multi-block: nb[0]*nb[1]*nb[2] blocks of n[0] x n[1] x n[2] data cells
  * with halo h, block id b = (bz*nb1 + by)*nb2 + bx along coordinate 0, then (z, y, x). */

@@ -221,7 +221,8 @@ void hbc_grid_destroy(hbc_grid* g) { delete g; }
 int hbc_cs_grid_create(int64_t N, int64_t h, hbc_grid** out) {
   return guard([&] {
     need(out != nullptr, "NULL argument");
-    need(N >= 4 && h >= 1 && h <= N, "cubed sphere needs N >= 4 and 1 <= h <= N");
+    need(N >= 4 && h >= 1 && 2 * h <= N,
+         "cubed sphere needs N >= 4 and 1 <= h <= N/2 (deeper ghost layers leave the face's gnomonic chart)");
     auto* g = new hbc_grid;
     Grid& G = g->g;
     G.nd = 3;
@@ -673,7 +674,8 @@ int hbc_fused_stencil27(const hbc_plan* plan, void* x, int64_t x_nelem, void* y,
 int hbc_cs_lagrange_weights(int64_t N, int64_t h, int32_t* base_dev, double* w_dev, void* stream) {
   return guard([&] {
     need(base_dev && w_dev, "NULL argument");
-    need(N >= 4 && h >= 1 && h <= N, "cubed sphere needs N >= 4 and 1 <= h <= N");
+    need(N >= 4 && h >= 1 && 2 * h <= N,
+         "cubed sphere needs N >= 4 and 1 <= h <= N/2 (deeper ghost layers leave the face's gnomonic chart)");
     device_cs_weights(N, h, base_dev, w_dev, stream);
   });
 }

@@ -93,7 +93,8 @@ SideLink link(int f, int side) {
 
 void cs_add_program(Program& p, int64_t N, int64_t h, int mode, int vector, const int32_t* base, const double* w) {
   const Grid& g = p.grid;
-  if (N < 4 || h < 1 || h > N) fail(HBC_EINVAL, "cubed sphere needs N >= 4 and 1 <= h <= N");
+  if (N < 4 || h < 1 || 2 * h > N)
+    fail(HBC_EINVAL, "cubed sphere needs N >= 4 and 1 <= h <= N/2 (deeper ghost layers leave the face's gnomonic chart)");
   if (g.nd != 3 || g.blocks.size() != 6 || g.blocks[0].data.extent(1) != N ||
       g.blocks[0].full.lo[1] != -h || g.blocks[0].full.hi[1] != N + h)
     fail(HBC_EINVAL, "program grid is not the cubed-sphere grid of this N and h");
@@ -320,7 +321,8 @@ void cs_add_edge_average(Program& p, int64_t Np) {
 // ghosts are zero rows.  FP64 geometry on the host, from the integer frames.
 void cs_add_quadrature(Program& p, int64_t N, int64_t h, int q, int vector) {
   const Grid& g = p.grid;
-  if (N < 4 || h < 1 || h > N) fail(HBC_EINVAL, "cubed sphere needs N >= 4 and 1 <= h <= N");
+  if (N < 4 || h < 1 || 2 * h > N)
+    fail(HBC_EINVAL, "cubed sphere needs N >= 4 and 1 <= h <= N/2 (deeper ghost layers leave the face's gnomonic chart)");
   if (g.nd != 3 || g.blocks.size() != 6 || g.blocks[0].data.extent(1) != N ||
       g.blocks[0].full.lo[1] != -h || g.blocks[0].full.hi[1] != N + h)
     fail(HBC_EINVAL, "program grid is not the cubed-sphere grid of this N and h");

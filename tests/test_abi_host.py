@@ -49,7 +49,7 @@ def compare_plan_with_oracle(plan, og, op, tol=0.0):
             assert abs(got[c] - ref[c]) <= tol, (cell, c, got[c], ref[c])
 
 
-@pytest.mark.parametrize("N,h", [(4, 1), (6, 3), (13, 3), (24, 2)])
+@pytest.mark.parametrize("N,h", [(4, 1), (6, 3), (13, 3), (24, 2), (5, 2), (8, 4)])
 def test_cs_sync_plan_equals_oracle(N, h):
     g = hb.Grid.cubed_sphere(N, h)
     p = hb.Program(g)
@@ -69,7 +69,7 @@ def test_cs_sync_plan_equals_oracle(N, h):
             assert rot == code, (f, side, rot, R)
 
 
-@pytest.mark.parametrize("N,h", [(4, 1), (6, 3), (13, 3), (24, 2)])
+@pytest.mark.parametrize("N,h", [(4, 1), (6, 3), (13, 3), (24, 2), (5, 2), (8, 4)])
 def test_cs_lagrange_plan_equals_oracle(N, h):
     base, w = closed_form_weights(N, h)
     g = hb.Grid.cubed_sphere(N, h)
@@ -417,3 +417,21 @@ def test_rejected_first_block_leaves_the_grid_unchanged():
     assert g.cells == 0
     g.add_block([(0, 16, 1), (0, 8, 1)], [(1, 15, 1), (1, 7, 1)])  # another lattice is still possible
     assert g.cells == 16 * 8
+
+
+@pytest.mark.parametrize("N,h", [(5, 3), (8, 5), (8, 8)])
+def test_cubed_sphere_halo_limited_to_half_a_face(N, h):
+    """Ghost layer k sits at angle pi/4 + (k + 1/2) pi/(2N) in its face's frame;
+    from k = N/2 on it passes pi/2 and leaves the face's gnomonic chart, so
+    every cubed-sphere entry point refuses h > N/2."""
+    import math
+    assert math.pi / 4 + (h - 0.5) * math.pi / (2 * N) > math.pi / 2 - 1e-12
+    with pytest.raises(hb.HbcError) as e:
+        hb.Grid.cubed_sphere(N, h)
+    assert e.value.code == hb.EINVAL
+    g = hb.Grid.cubed_sphere(N, N // 2)
+    p = hb.Program(g)
+    with pytest.raises(hb.HbcError):
+        p.cs_add(N, h, hb.CS_SYNC)
+    with pytest.raises(hb.HbcError):
+        p.cs_add_quadrature(N, h, 2)
