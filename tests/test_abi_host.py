@@ -49,7 +49,7 @@ def compare_plan_with_oracle(plan, og, op, tol=0.0):
             assert abs(got[c] - ref[c]) <= tol, (cell, c, got[c], ref[c])
 
 
-@pytest.mark.parametrize("N,h", [(4, 1), (6, 3), (13, 3), (24, 2), (5, 2), (8, 4)])
+@pytest.mark.parametrize("N,h", [(4, 1), (4, 2), (6, 3), (13, 3), (24, 2), (5, 2), (8, 4)])
 def test_cs_sync_plan_equals_oracle(N, h):
     g = hb.Grid.cubed_sphere(N, h)
     p = hb.Program(g)
@@ -69,7 +69,7 @@ def test_cs_sync_plan_equals_oracle(N, h):
             assert rot == code, (f, side, rot, R)
 
 
-@pytest.mark.parametrize("N,h", [(4, 1), (6, 3), (13, 3), (24, 2), (5, 2), (8, 4)])
+@pytest.mark.parametrize("N,h", [(4, 1), (4, 2), (6, 3), (13, 3), (24, 2), (5, 2), (8, 4)])
 def test_cs_lagrange_plan_equals_oracle(N, h):
     base, w = closed_form_weights(N, h)
     g = hb.Grid.cubed_sphere(N, h)

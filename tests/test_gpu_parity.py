@@ -69,13 +69,14 @@ def check_cs(N, h, nf, nl, mode, vector, seed=1, noise=0.0, order=0):
 
 
 @pytest.mark.parametrize("N,h,nf,nl,vector", [(8, 3, 1, 1, False), (12, 3, 4, 2, True), (13, 2, 4, 3, True),
-                                              (48, 3, 1, 1, False)])
+                                              (48, 3, 1, 1, False), (4, 2, 4, 1, True)])
 def test_cs_sync_bit_exact(N, h, nf, nl, vector):
     check_cs(N, h, nf, nl, "sync", vector)
 
 
 @pytest.mark.parametrize("N,h,nf,nl,vector", [(8, 3, 1, 1, False), (12, 3, 4, 2, True), (13, 2, 4, 3, True),
-                                              (48, 3, 1, 1, False), (48, 3, 4, 8, True)])
+                                              (48, 3, 1, 1, False), (48, 3, 4, 8, True), (4, 2, 4, 1, True),
+                                              (5, 2, 1, 2, False)])
 def test_cs_lagrange_fp64(N, h, nf, nl, vector):
     check_cs(N, h, nf, nl, "lagrange", vector, noise=1e-3)
 
