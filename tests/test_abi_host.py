@@ -82,8 +82,8 @@ def test_cs_lagrange_plan_equals_oracle(N, h):
     compare_plan_with_oracle(plan, og, assemble(og, ocs.subs(N, h, "lagrange")), tol=64 * N * 2.0 ** -53)
 
 
-def test_hpcg_plan_equals_oracle():
-    nb, n = 2, 4
+@pytest.mark.parametrize("nb,n", [(2, 4), (1, 5), (3, 3)])
+def test_hpcg_plan_equals_oracle(nb, n):
     g = hb.Grid.cartesian([nb] * 3, [n] * 3, 1)
     p = hb.Program(g)
     p.cart_add_halo([nb] * 3, [n] * 3, 1)

@@ -134,7 +134,7 @@ def hpcg_field(nb, n, x):
     return g, blocks, full
 
 
-@pytest.mark.parametrize("nb,n", [(2, 8), (2, 13), (2, 128)])
+@pytest.mark.parametrize("nb,n", [(2, 8), (2, 13), (2, 128), (1, 16), (3, 9)])
 def test_hpcg_bc_and_stencil(nb, n):
     x = synthinputs.uniform((nb * n,) * 3, seed=3)
     g, blocks, full = hpcg_field(nb, n, x)
