@@ -372,7 +372,8 @@ def extra_wide_rows(ctx, hb, torch, tm):
     gr = hb.ApplyGraph(plan, [full], 2000)
     us = tm(gr.launch, 2000)
     out["c90_hUV_f64"] = {"us_per_apply": us, "ghost_cells_per_s": st["ghost_values"] / us * 1e6,
-                          "nnz_per_row": st["nnz"] / st["rows_csr"]}
+                          "nnz_per_row": st["nnz"] / st["rows_csr"], "alg_bytes": st["alg_bytes"],
+                          "rows_narrow": st["rows_narrow"]}
     return out
 
 
