@@ -511,6 +511,19 @@ __device__ __forceinline__ void rt_tile(const PlanDesc& d, const RowTile& tl, bo
   }
 }
 
+// Zero rows of a row tile (point-major), written by extra workgroups of the
+// wide-row launches when a plan's other rows are all zero rows without b, so
+// that such a plan needs one launch.
+template <typename T>
+__device__ __forceinline__ void zero_row_tile(const PlanDesc& d, const RowTile& t) {
+  T* __restrict__ f = static_cast<T*>(d.field);
+  const int64_t inner = d.inner, n = (int64_t)t.nrows * inner;
+  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
+    const int64_t r = e / inner, l = e - r * inner;
+    f[(int64_t)d.row_dst[t.row_begin + r] * d.cs + l] = T(0);
+  }
+}
+
 // One entry of a wide tile: its weight and the LDS offset (in values) of its
 // source cell's staged slice, read with one LDS instruction.
 template <typename T>
@@ -554,7 +567,8 @@ __global__ __launch_bounds__(256) void k_apply_wide(PlanDesc d, const WideTile* 
                                                     const int32_t* __restrict__ wrow,
                                                     const int32_t* __restrict__ wrp,
                                                     const WideEnt<T>* __restrict__ went, int ucap, int ecap,
-                                                    int nslices, int spw, int zero_only) {
+                                                    int nslices, int spw, int zero_only,
+                                                    const RowTile* __restrict__ ztiles, int nwide) {
   extern __shared__ __align__(16) unsigned char wide_smem[];
   constexpr int S = WIDE_ROW_BYTES / (int)sizeof(T);  // values per cell and slice
   constexpr int LPR = S / V;                          // lanes per row
@@ -566,6 +580,10 @@ __global__ __launch_bounds__(256) void k_apply_wide(PlanDesc d, const WideTile* 
   T* lds = reinterpret_cast<T*>(wide_smem);                                            // ucap x S values
   WideEnt<T>* le = reinterpret_cast<WideEnt<T>*>(wide_smem + (size_t)ucap * WIDE_ROW_BYTES);  // ecap entries
   int32_t* lp = reinterpret_cast<int32_t*>(le + ecap);                                 // WIDE_ROWS + 1 row starts
+  if ((int)blockIdx.x >= nwide) {  // a zero-row tile (no barrier is reached)
+    zero_row_tile<T>(d, ztiles[blockIdx.x - nwide]);
+    return;
+  }
   const int runs = (nslices + spw - 1) / spw;
   const WideTile tl = tiles[blockIdx.x / runs];
   const int s0 = (blockIdx.x % runs) * spw;
@@ -746,8 +764,13 @@ __global__ __launch_bounds__(256) void k_apply_wide(PlanDesc d, const WideTile* 
 // deterministic.  zero_only writes +0 to the tile's rows.
 template <typename T>
 __global__ __launch_bounds__(256) void k_apply_narrow(PlanDesc d, const NarrowTile* __restrict__ tiles,
-                                                      int zero_only) {
+                                                      int zero_only, const RowTile* __restrict__ ztiles,
+                                                      int nnarrow) {
   constexpr int G = NARROW_LANES, IM = NARROW_ROW_BYTES / (int)sizeof(T);
+  if ((int)blockIdx.x >= nnarrow) {  // a zero-row tile
+    zero_row_tile<T>(d, ztiles[blockIdx.x - nnarrow]);
+    return;
+  }
   const NarrowTile tl = tiles[blockIdx.x];
   const int j = threadIdx.x % G, rr = threadIdx.x / G;
   const bool live = rr < tl.nrows;  // every lane takes part in the butterfly
@@ -1774,12 +1797,13 @@ static int wide_slices_per_wg(int ntiles, int nslices) {
 }
 
 template <typename T, int V>
-static void launch_wide(const Plan& p, const PlanDesc& d, hipStream_t st, bool zero_only) {
+static void launch_wide(const Plan& p, const PlanDesc& d, hipStream_t st, bool zero_only, int nzero) {
   constexpr int S = WIDE_ROW_BYTES / (int)sizeof(T);
   const int nslices = (int)((p.layout.inner + S - 1) / S);
   const int ntiles = (int)p.host.wtiles.size();
   const int spw = wide_slices_per_wg(ntiles, nslices);
-  const int grid = ntiles * ((nslices + spw - 1) / spw);
+  const int nwide = ntiles * ((nslices + spw - 1) / spw);
+  const int grid = nwide + nzero;
   const int ucap = p.host.w_maxu, ecap = (p.host.w_maxe + 1) & ~1;  // even: keeps the row starts 16-byte aligned
   const size_t lds = zero_only ? 0
                               : (size_t)ucap * WIDE_ROW_BYTES + (size_t)ecap * sizeof(WideEnt<T>) +
@@ -1787,29 +1811,17 @@ static void launch_wide(const Plan& p, const PlanDesc& d, hipStream_t st, bool z
   const WideEnt<T>* went = static_cast<const WideEnt<T>*>(p.d_w_ent);
   if (d.nt)
     hipLaunchKernelGGL((k_apply_wide<T, V, true>), dim3(grid), dim3(256), lds, st, d, p.d_wtiles, p.d_w_ucell,
-                       p.d_w_row, p.d_w_rp, went, ucap, ecap, nslices, spw, zero_only ? 1 : 0);
+                       p.d_w_row, p.d_w_rp, went, ucap, ecap, nslices, spw, zero_only ? 1 : 0, p.d_rtiles, nwide);
   else
     hipLaunchKernelGGL((k_apply_wide<T, V, false>), dim3(grid), dim3(256), lds, st, d, p.d_wtiles, p.d_w_ucell,
-                       p.d_w_row, p.d_w_rp, went, ucap, ecap, nslices, spw, zero_only ? 1 : 0);
+                       p.d_w_row, p.d_w_rp, went, ucap, ecap, nslices, spw, zero_only ? 1 : 0, p.d_rtiles, nwide);
   HIP_CHECK(hipGetLastError());
 }
 
 template <typename T>
 static void launch_apply_t(const Plan& p, const PlanDesc& d, hipStream_t st, bool zero_only) {
-  if (p.layout.order == HBC_POINT_MAJOR && !p.host.ntiles.empty()) {
-    hipLaunchKernelGGL((k_apply_narrow<T>), dim3((int)p.host.ntiles.size()), dim3(256), 0, st, d, p.d_ntiles,
-                       zero_only ? 1 : 0);
-    HIP_CHECK(hipGetLastError());
-  }
-  if (p.layout.order == HBC_POINT_MAJOR && !p.host.wtiles.empty()) {
-    if (sizeof(T) == 4 && p.vec == 4)
-      launch_wide<T, (sizeof(T) == 4 ? 4 : 2)>(p, d, st, zero_only);
-    else if (p.vec >= 2)
-      launch_wide<T, 2>(p, d, st, zero_only);
-    else
-      launch_wide<T, 1>(p, d, st, zero_only);
-  }
-  const int nt = (int)(p.layout.order == HBC_POINT_MAJOR ? p.host.rtiles.size() : p.host.tiles.size());
+  const bool pm = p.layout.order == HBC_POINT_MAJOR;
+  const int nt = (int)(pm ? p.host.rtiles.size() : p.host.tiles.size());
   const int grid = p.tune.persistent > 0 ? std::min(p.tune.persistent, nt) : nt;
   const int blk = p.tune.block;
   const int z = zero_only ? 1 : 0;
@@ -1820,8 +1832,29 @@ static void launch_apply_t(const Plan& p, const PlanDesc& d, hipStream_t st, boo
     dd.nrows = (int32_t)p.stats.rows_data;
     dd.grid = (int32_t)std::min<int64_t>((p.stats.rows_data + groups - 1) / groups, 4096);
   }
-  if (grid + dd.grid == 0) return;
-  if (p.layout.order == HBC_PLANE_MAJOR) {
+  // fold the row tiles into the first wide-row launch when they are all zero
+  // rows without b (the corners of the cubed-sphere quadrature programs)
+  const bool has_narrow = pm && !p.host.ntiles.empty(), has_wide = pm && !p.host.wtiles.empty();
+  bool fold = (has_narrow || has_wide) && dd.grid == 0 && nt > 0;
+  for (size_t k = 0; fold && k < p.host.rtiles.size(); ++k)
+    fold = p.host.rtiles[k].kind == SEG_ZERO && !p.host.rtiles[k].has_b;
+  if (has_narrow) {
+    const int nn = (int)p.host.ntiles.size();
+    hipLaunchKernelGGL((k_apply_narrow<T>), dim3(nn + (fold ? nt : 0)), dim3(256), 0, st, d, p.d_ntiles, z,
+                       p.d_rtiles, nn);
+    HIP_CHECK(hipGetLastError());
+  }
+  if (has_wide) {
+    const int nz = fold && !has_narrow ? nt : 0;
+    if (sizeof(T) == 4 && p.vec == 4)
+      launch_wide<T, (sizeof(T) == 4 ? 4 : 2)>(p, d, st, zero_only, nz);
+    else if (p.vec >= 2)
+      launch_wide<T, 2>(p, d, st, zero_only, nz);
+    else
+      launch_wide<T, 1>(p, d, st, zero_only, nz);
+  }
+  if (fold || grid + dd.grid == 0) return;
+  if (!pm) {
     if (grid > 0) hipLaunchKernelGGL((k_apply_pm<T>), dim3(grid), dim3(blk), 0, st, d, p.d_tiles, nt, z);
   } else {
     launch_rows<T>(d, st, grid, blk, p.d_rtiles, nt, z, dd);
