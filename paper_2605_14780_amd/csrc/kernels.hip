@@ -548,7 +548,7 @@ __device__ __forceinline__ void ld_ent(const WideEnt<T>* p, T& w, int& slot) {
 }
 
 // Wide rows (WideTile).  A workgroup takes one tile and a run of spw
-// consecutive slices of WIDE_ROW_BYTES of inner values.  The tile's entries
+// consecutive slices of SB bytes of inner values.  The tile's entries
 // and row starts go to LDS once; then, per slice, the tile's distinct source
 // cells are staged in LDS (the slots this slice's outputs read, through the
 // component rotation) and a group of lanes per row sums the row's entries
@@ -561,7 +561,7 @@ __device__ __forceinline__ void ld_ent(const WideEnt<T>* p, T& w, int& slot) {
 // summed.  LDS holds ucap cells of the slice, then ecap entries, then the
 // row starts.  zero_only writes +0 to the tile's rows (the adjoint's ghost
 // reset).
-template <typename T, int V, bool NT>
+template <typename T, int V, int SB, bool NT>
 __global__ __launch_bounds__(256) void k_apply_wide(PlanDesc d, const WideTile* __restrict__ tiles,
                                                     const int32_t* __restrict__ ucell,
                                                     const int32_t* __restrict__ wrow,
@@ -570,7 +570,7 @@ __global__ __launch_bounds__(256) void k_apply_wide(PlanDesc d, const WideTile* 
                                                     int nslices, int spw, int zero_only,
                                                     const RowTile* __restrict__ ztiles, int nwide) {
   extern __shared__ __align__(16) unsigned char wide_smem[];
-  constexpr int S = WIDE_ROW_BYTES / (int)sizeof(T);  // values per cell and slice
+  constexpr int S = SB / (int)sizeof(T);              // values per cell and slice
   constexpr int LPR = S / V;                          // lanes per row
   constexpr int NGRP = 256 / LPR;                     // row groups (launched with 256 threads)
   constexpr int RPG = (WIDE_ROWS + NGRP - 1) / NGRP;  // rows per group
@@ -578,7 +578,7 @@ __global__ __launch_bounds__(256) void k_apply_wide(PlanDesc d, const WideTile* 
   constexpr int NE = (WIDE_ECAP + 255) / 256;
   constexpr int EC = 4;                               // entries per step
   T* lds = reinterpret_cast<T*>(wide_smem);                                            // ucap x S values
-  WideEnt<T>* le = reinterpret_cast<WideEnt<T>*>(wide_smem + (size_t)ucap * WIDE_ROW_BYTES);  // ecap entries
+  WideEnt<T>* le = reinterpret_cast<WideEnt<T>*>(wide_smem + (size_t)ucap * SB);  // ecap entries
   int32_t* lp = reinterpret_cast<int32_t*>(le + ecap);                                 // WIDE_ROWS + 1 row starts
   if ((int)blockIdx.x >= nwide) {  // a zero-row tile (no barrier is reached)
     zero_row_tile<T>(d, ztiles[blockIdx.x - nwide]);
@@ -1489,6 +1489,17 @@ namespace {
 
 size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
 
+// Slice width of the wide-row kernel: 256 bytes (lanes of four FP64 values)
+// for FP64 plans of at least 32 inner values whose layout is 4-aligned, else
+// 128 bytes.
+static int wide_slice_bytes(const Plan& p) {
+  const Layout& L = p.layout;
+  const bool a4 = L.inner % 4 == 0 && (L.vec_len == 0 || (L.vec_lo % 4 == 0 && L.vec_stride % 4 == 0 &&
+                                                          L.vec_len % 4 == 0));
+  return p.dtype == HBC_F64 && L.order == HBC_POINT_MAJOR && a4 && L.inner >= 32 ? 2 * WIDE_ROW_BYTES
+                                                                                  : WIDE_ROW_BYTES;
+}
+
 struct Packer {
   std::vector<char> buf;
   size_t put(const void* p, size_t n) {
@@ -1508,15 +1519,16 @@ struct Packer {
     return vec(f);
   }
   // wide-row entries as WideEnt<T>: the weight in the plan's type (rounded as
-  // in reals) and the LDS offset of the source cell's slice (slot * values)
-  size_t wide_entries(const std::vector<double>& w, const std::vector<int32_t>& slot, int dtype) {
+  // in reals) and the LDS offset of the source cell's slice (slot * values
+  // per slice of sb bytes)
+  size_t wide_entries(const std::vector<double>& w, const std::vector<int32_t>& slot, int dtype, int sb) {
     if (dtype == HBC_F64) {
       std::vector<WideEnt<double>> e(w.size());
-      for (size_t k = 0; k < w.size(); ++k) e[k] = {w[k], slot[k] * (WIDE_ROW_BYTES / 8)};
+      for (size_t k = 0; k < w.size(); ++k) e[k] = {w[k], slot[k] * (sb / 8)};
       return vec(e);
     }
     std::vector<WideEnt<float>> e(w.size());
-    for (size_t k = 0; k < w.size(); ++k) e[k] = {(float)w[k], slot[k] * (WIDE_ROW_BYTES / 4)};
+    for (size_t k = 0; k < w.size(); ++k) e[k] = {(float)w[k], slot[k] * (sb / 4)};
     return vec(e);
   }
 };
@@ -1601,7 +1613,7 @@ void device_upload_plan(Plan& p) {
   size_t o_wu = pk.vec(T.w_ucell);
   size_t o_wr = pk.vec(T.w_row);
   size_t o_wp = pk.vec(T.w_rp);
-  size_t o_we = pk.wide_entries(T.w_entw, T.w_ents, p.dtype);
+  size_t o_we = pk.wide_entries(T.w_entw, T.w_ents, p.dtype, wide_slice_bytes(p));
   size_t o_nt = pk.vec(T.ntiles);
   size_t o_drc = pk.vec(T.dr_cell);
   size_t o_drp = pk.vec(T.dr_ptr);
@@ -1796,9 +1808,9 @@ static int wide_slices_per_wg(int ntiles, int nslices) {
   return spw;
 }
 
-template <typename T, int V>
+template <typename T, int V, int SB>
 static void launch_wide(const Plan& p, const PlanDesc& d, hipStream_t st, bool zero_only, int nzero) {
-  constexpr int S = WIDE_ROW_BYTES / (int)sizeof(T);
+  constexpr int S = SB / (int)sizeof(T);
   const int nslices = (int)((p.layout.inner + S - 1) / S);
   const int ntiles = (int)p.host.wtiles.size();
   const int spw = wide_slices_per_wg(ntiles, nslices);
@@ -1806,14 +1818,14 @@ static void launch_wide(const Plan& p, const PlanDesc& d, hipStream_t st, bool z
   const int grid = nwide + nzero;
   const int ucap = p.host.w_maxu, ecap = (p.host.w_maxe + 1) & ~1;  // even: keeps the row starts 16-byte aligned
   const size_t lds = zero_only ? 0
-                              : (size_t)ucap * WIDE_ROW_BYTES + (size_t)ecap * sizeof(WideEnt<T>) +
+                              : (size_t)ucap * SB + (size_t)ecap * sizeof(WideEnt<T>) +
                                     (size_t)(WIDE_ROWS + 1) * 4;
   const WideEnt<T>* went = static_cast<const WideEnt<T>*>(p.d_w_ent);
   if (d.nt)
-    hipLaunchKernelGGL((k_apply_wide<T, V, true>), dim3(grid), dim3(256), lds, st, d, p.d_wtiles, p.d_w_ucell,
+    hipLaunchKernelGGL((k_apply_wide<T, V, SB, true>), dim3(grid), dim3(256), lds, st, d, p.d_wtiles, p.d_w_ucell,
                        p.d_w_row, p.d_w_rp, went, ucap, ecap, nslices, spw, zero_only ? 1 : 0, p.d_rtiles, nwide);
   else
-    hipLaunchKernelGGL((k_apply_wide<T, V, false>), dim3(grid), dim3(256), lds, st, d, p.d_wtiles, p.d_w_ucell,
+    hipLaunchKernelGGL((k_apply_wide<T, V, SB, false>), dim3(grid), dim3(256), lds, st, d, p.d_wtiles, p.d_w_ucell,
                        p.d_w_row, p.d_w_rp, went, ucap, ecap, nslices, spw, zero_only ? 1 : 0, p.d_rtiles, nwide);
   HIP_CHECK(hipGetLastError());
 }
@@ -1846,12 +1858,21 @@ static void launch_apply_t(const Plan& p, const PlanDesc& d, hipStream_t st, boo
   }
   if (has_wide) {
     const int nz = fold && !has_narrow ? nt : 0;
-    if (sizeof(T) == 4 && p.vec == 4)
-      launch_wide<T, (sizeof(T) == 4 ? 4 : 2)>(p, d, st, zero_only, nz);
-    else if (p.vec >= 2)
-      launch_wide<T, 2>(p, d, st, zero_only, nz);
-    else
-      launch_wide<T, 1>(p, d, st, zero_only, nz);
+    if constexpr (sizeof(T) == 8) {
+      if (wide_slice_bytes(p) == 2 * WIDE_ROW_BYTES)
+        launch_wide<T, 4, 2 * WIDE_ROW_BYTES>(p, d, st, zero_only, nz);
+      else if (p.vec >= 2)
+        launch_wide<T, 2, WIDE_ROW_BYTES>(p, d, st, zero_only, nz);
+      else
+        launch_wide<T, 1, WIDE_ROW_BYTES>(p, d, st, zero_only, nz);
+    } else {
+      if (p.vec == 4)
+        launch_wide<T, 4, WIDE_ROW_BYTES>(p, d, st, zero_only, nz);
+      else if (p.vec >= 2)
+        launch_wide<T, 2, WIDE_ROW_BYTES>(p, d, st, zero_only, nz);
+      else
+        launch_wide<T, 1, WIDE_ROW_BYTES>(p, d, st, zero_only, nz);
+    }
   }
   if (fold || grid + dd.grid == 0) return;
   if (!pm) {

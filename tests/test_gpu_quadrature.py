@@ -60,10 +60,12 @@ def test_quadrature_rows(N, h, nf, nl, q, dtype):
     assert (got[G][corners] == 0).all()
 
 
-@pytest.mark.parametrize("nl,dtype", [(8, "f64"), (16, "f32"), (12, "f64")])
+@pytest.mark.parametrize("nl,dtype", [(8, "f64"), (16, "f32"), (12, "f64"), (6, "f64")])
 def test_quadrature_rows_staged(nl, dtype):
-    """Rows of >= 256 bytes take the LDS-staged wide-row kernel (several
-    inner-value slices per tile, partial last slice for nl = 12)."""
+    """Rows of >= 128 bytes take the LDS-staged wide-row kernel (several
+    inner-value slices per tile, partial last slice for nl = 12; FP64 slices
+    of 256 bytes for nl = 8 and 12, of 128 bytes for nl = 6, whose vector
+    components are not 4-aligned)."""
     N, h, nf, q = 10, 3, 4, 2
     I = nf * nl
     vec = (2 * nl, nl, nl)
@@ -103,29 +105,29 @@ def test_quadrature_rows_staged(nl, dtype):
     assert abs(lhs - rhs) <= (1e-12 if dt == hb.F64 else 1e-5) * max(abs(lhs), abs(rhs))
 
 
-@pytest.mark.parametrize("dtype,h", [("f64", 4), ("f32", 3)])
-def test_wide_kernel_matches_general_rows_bitwise(dtype, h):
+@pytest.mark.parametrize("dtype,h,I", [("f64", 4, 64), ("f32", 3, 64), ("f64", 3, 24)])
+def test_wide_kernel_matches_general_rows_bitwise(dtype, h, I):
     """The staged wide-row kernel (rows of >= 128 bytes: many tiles per side,
-    every ghost layer of a position in one tile) sums each row in the same
-    order as the general row path (rows of 32 to 127 bytes): applying one
-    program to 64 inner values, and to the same values 8 at a time, gives
-    equal bits."""
+    every ghost layer of a position in one tile; FP64 slices of 256 bytes for
+    64 inner values, of 128 bytes for 24) sums each row in the same order as
+    the general row path (rows of 32 to 127 bytes): applying one program to I
+    inner values, and to the same values 8 at a time, gives equal bits."""
     N, q = 20, 2
     dt, npdt = (hb.F64, np.float64) if dtype == "f64" else (hb.F32, np.float32)
     g = hb.Grid.cubed_sphere(N, h)
     p = hb.Program(g)
     p.cs_add_quadrature(N, h, q)
-    wide = hb.Plan(p, inner=64, dtype=dt)
+    wide = hb.Plan(p, inner=I, dtype=dt)
     narrow = hb.Plan(p, inner=8, dtype=dt)
     sw, sn = wide.stats(), narrow.stats()
     assert sw["rows_wide"] == sw["rows_csr"] and sw["wide_tiles"] > 24
     assert sn["rows_wide"] == 0 and sn["rows_narrow"] == 0
-    full = cs_full_field(N, h, 1, 64, seed=11 + h).astype(npdt)
+    full = cs_full_field(N, h, 1, I, seed=11 + h).astype(npdt)
     t = torch.from_numpy(full.copy()).cuda()
     hb.apply(wide, t)
     k = 8  # rows of 64 or 32 bytes: the general row path
     parts = []
-    for c0 in range(0, 64, k):
+    for c0 in range(0, I, k):
         s = torch.from_numpy(np.ascontiguousarray(full[:, c0:c0 + k])).cuda()
         hb.apply(narrow, s)
         parts.append(s)
