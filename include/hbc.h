@@ -58,7 +58,7 @@ extern "C" {
 #define HBC_EUNCOVERED (-5)  /* ghost rows covered by nothing under HBC_STRICT_COVER */
 #define HBC_ENOMEM (-6)      /* host or device allocation failed */
 #define HBC_EHIP (-7)        /* a HIP runtime error; its string is in hbc_last_error() */
-#define HBC_EUNSUPPORTED (-8)/* valid request outside what the library implements (e.g. slice step != 1) */
+#define HBC_EUNSUPPORTED (-8)/* valid request outside what the library implements (e.g. a block whose step differs from the grid's lattice) */
 
 /* element types */
 #define HBC_F64 0

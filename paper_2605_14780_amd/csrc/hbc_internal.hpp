@@ -189,7 +189,8 @@ struct alignas(16) RowTile {
 // tangential position, then the next position), and cut greedily into tiles
 // of at most WIDE_ROWS rows whose distinct source cells (at most WIDE_UCAP)
 // and entries (at most WIDE_ECAP) fit.  The kernel stages a tile's source
-// cells in LDS one slice of WIDE_ROW_BYTES of inner values at a time; each
+// cells in LDS one slice of inner values at a time (WIDE_ROW_BYTES, or twice
+// that for FP64 plans whose layout is 4-aligned); each
 // tile has its own copy of its rows' entries (weight, LDS slot of the source)
 // and row starts, in tile order.
 constexpr int WIDE_NNZ = 8, WIDE_UCAP = 128, WIDE_ROWS = 32, WIDE_ROW_BYTES = 128, WIDE_ECAP = 512;
