@@ -51,6 +51,8 @@ struct PlanDesc {
   int32_t nt;         // results go out with non-temporal stores (rows of >= 128 bytes)
   int32_t unroll;     // accesses of vec elements per lane and row (point-major)
   int32_t general;    // the row tiles hold general ELL/CSR rows
+  int32_t ua;         // point-major rows as 16-byte vectors on 4-byte (FP32) or 8-byte (FP64)
+                      // boundaries, the last one ending at the row's end (see rt_tile)
   const int32_t* row_dst;  // point-major row tables
   const int32_t* row_src;
 };
@@ -73,13 +75,15 @@ struct Pack {
   T v[V];
 };
 
-template <typename T, int V>
+// UA: p is aligned only to the element size (vector accesses on element
+// boundaries are legal for global memory on gfx9 and later).
+template <typename T, int V, bool UA = false>
 __device__ __forceinline__ Pack<T, V> ldv(const T* p) {
   Pack<T, V> r;
   if constexpr (V == 1) {
     r.v[0] = *p;
   } else {
-    typedef T vt __attribute__((ext_vector_type(V)));
+    typedef T vt __attribute__((ext_vector_type(V), aligned(UA ? sizeof(T) : V * sizeof(T))));
     vt x = *reinterpret_cast<const vt*>(p);
 #pragma unroll
     for (int i = 0; i < V; ++i) r.v[i] = x[i];
@@ -91,7 +95,7 @@ __device__ __forceinline__ Pack<T, V> ldv(const T* p) {
 // non-temporal stores (streamed past the caches rather than allocated in
 // them).  That pays for whole rows of 128 bytes or more; for short scattered
 // rows the caches merge partial lines and plain stores are faster.
-template <typename T, int V, bool NT>
+template <typename T, int V, bool NT, bool UA = false>
 __device__ __forceinline__ void stv(T* p, const Pack<T, V>& r) {
   if constexpr (V == 1) {
     if (NT)
@@ -99,7 +103,7 @@ __device__ __forceinline__ void stv(T* p, const Pack<T, V>& r) {
     else
       *p = r.v[0];
   } else {
-    typedef T vt __attribute__((ext_vector_type(V)));
+    typedef T vt __attribute__((ext_vector_type(V), aligned(UA ? sizeof(T) : V * sizeof(T))));
     vt x;
 #pragma unroll
     for (int i = 0; i < V; ++i) x[i] = r.v[i];
@@ -284,14 +288,20 @@ __device__ __forceinline__ void run_tile_pm(const PlanDesc& d, const DevSeg& s, 
 // bit 0 the 4-wide Lagrange rows, bit 1 general ELL/CSR rows.  Paths of
 // absent kinds are compiled out (their registers would lower the occupancy of
 // every other kind).
-constexpr int KM_ELL4 = 1, KM_GENERAL = 2;
+constexpr int KM_ELL4 = 1, KM_GENERAL = 2, KM_UNAL = 4;
 template <typename T, int V, int U, bool NT, int RB, int KM>
 __device__ __forceinline__ void rt_tile(const PlanDesc& d, const RowTile& tl, bool zero_only) {
   const int lpr = 1 << d.lpr_shift;
   const int ngroups = (int)blockDim.x >> d.lpr_shift;
   const int grp = (int)threadIdx.x >> d.lpr_shift;
   const int lane = (int)threadIdx.x & (lpr - 1);
-  const int64_t nvec = d.inner / V;
+  // KM_UNAL: rows whose length is not a multiple of V go as ceil(inner / V)
+  // vectors on element boundaries, the last one moved back to end at the
+  // row's end.  The slots it shares with the vector before it get the same
+  // value twice (every slot's arithmetic is independent of the vector it
+  // sits in), and stores reach only ghost rows, which no load reads.
+  constexpr bool UA = (KM & KM_UNAL) != 0;
+  const int64_t nvec = UA ? (d.inner + V - 1) / V : d.inner / V;
   T* __restrict__ f = static_cast<T*>(d.field);
   const int kind = zero_only ? (int)SEG_ZERO : tl.kind;
   const bool with_b = !zero_only && tl.has_b;
@@ -323,6 +333,7 @@ __device__ __forceinline__ void rt_tile(const PlanDesc& d, const RowTile& tl, bo
       const int64_t v = v0 + (int64_t)u * lpr;
       ok[u] = v < nvec;
       l[u] = (ok[u] ? v : v0) * V;  // a spare access repeats a valid one and is not stored
+      if (UA) l[u] = min(l[u], d.inner - V);
       sign[u] = T(1);
       sl[u] = rotates ? rot_slot<T>(d, tl.rot, l[u], sign[u]) : l[u];
     }
@@ -341,7 +352,7 @@ __device__ __forceinline__ void rt_tile(const PlanDesc& d, const RowTile& tl, bo
         for (int q = 0; q < RB; ++q) {
           const T* src = f + (int64_t)rsrc[rr[q]] * d.cs;
 #pragma unroll
-          for (int u = 0; u < U; ++u) x[q][u] = ldv<T, V>(src + sl[u]);
+          for (int u = 0; u < U; ++u) x[q][u] = ldv<T, V, UA>(src + sl[u]);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -380,7 +391,7 @@ __device__ __forceinline__ void rt_tile(const PlanDesc& d, const RowTile& tl, bo
           for (int j = 0; j < RB + 3; ++j) {
             const T* src = f + (int64_t)(c00 + j * dl) * d.cs;
 #pragma unroll
-            for (int u = 0; u < U; ++u) w[j][u] = ldv<T, V>(src + sl[u]);
+            for (int u = 0; u < U; ++u) w[j][u] = ldv<T, V, UA>(src + sl[u]);
           }
 #pragma unroll
           for (int q = 0; q < RB; ++q)
@@ -402,7 +413,7 @@ __device__ __forceinline__ void rt_tile(const PlanDesc& d, const RowTile& tl, bo
             for (int m = 0; m < 4; ++m) {
               const T* src = f + (int64_t)c[q][m] * d.cs;
 #pragma unroll
-              for (int u = 0; u < U; ++u) x[q][m][u] = ldv<T, V>(src + sl[u]);
+              for (int u = 0; u < U; ++u) x[q][m][u] = ldv<T, V, UA>(src + sl[u]);
             }
 #pragma unroll
           for (int q = 0; q < RB; ++q)
@@ -463,7 +474,7 @@ __device__ __forceinline__ void rt_tile(const PlanDesc& d, const RowTile& tl, bo
               if (cc[k] >= 0) {
                 const T* src = f + (int64_t)cc[k] * d.cs;
 #pragma unroll
-                for (int u = 0; u < U; ++u) x[k][u] = ldv<T, V>(src + sl[u]);
+                for (int u = 0; u < U; ++u) x[k][u] = ldv<T, V, UA>(src + sl[u]);
               }
 #pragma unroll
             for (int k = 0; k < EC; ++k)
@@ -506,7 +517,7 @@ __device__ __forceinline__ void rt_tile(const PlanDesc& d, const RowTile& tl, bo
       for (int q = 0; q < RB; ++q)
 #pragma unroll
         for (int u = 0; u < U; ++u)
-          if (r + q * rs < re && ok[u]) stv<T, V, NT>(f + dst[q] * d.cs + l[u], y[q][u]);
+          if (r + q * rs < re && ok[u]) stv<T, V, NT, UA>(f + dst[q] * d.cs + l[u], y[q][u]);
     }
   }
 }
@@ -914,6 +925,10 @@ __global__ __launch_bounds__(256) void k_apply_pm(PlanDesc d, const DevTile* __r
 // Batch tiles of different plans: (vec, unroll) chosen per tile at run time.
 template <typename T, bool NT, int KM>
 __device__ __forceinline__ void rt_tile_any(const PlanDesc& d, const RowTile& tl) {
+  if (d.ua) {
+    rt_tile<T, (sizeof(T) == 4 ? 4 : 2), 1, NT, 4, KM | KM_UNAL>(d, tl, false);
+    return;
+  }
   if (sizeof(T) == 4) {
     if (d.vec == 4)
       rt_tile<T, (sizeof(T) == 4 ? 4 : 2), 1, NT, 4, KM>(d, tl, false);
@@ -1570,6 +1585,11 @@ PlanDesc make_desc(const Plan& p, void* field) {
   d.general = 0;
   for (const RowTile& t : p.host.rtiles)
     if (t.kind == SEG_CSR || (t.kind == SEG_ELL && (t.width != 4 || (t.flags & SEGF_ELL_PADDED)))) d.general = 1;
+  // rows of a length that 16-byte vectors do not divide, with no vector
+  // components to rotate and no data rows (whose gather assumes whole vectors)
+  const int64_t vfull = p.dtype == HBC_F64 ? 2 : 4;
+  d.ua = p.layout.order == HBC_POINT_MAJOR && p.layout.vec_len == 0 && p.stats.rows_data == 0 &&
+         p.layout.inner % vfull != 0 && p.layout.inner > vfull;
   return d;
 }
 
@@ -1749,29 +1769,29 @@ void device_upload_csc(Plan& p) {
   p.d_adj_tiles = static_cast<const AdjTile*>(t);
 }
 
-template <typename T, int V, int U>
+template <typename T, int V, int U, int KX = 0>
 static void launch_rows_vu(const PlanDesc& d, hipStream_t st, int grid, int blk, const RowTile* tiles, int nt, int z,
                            const DataDesc& dd) {
   const bool rb2 = rows_per_batch(1 << d.lpr_shift) == 2;
   const dim3 g(grid + dd.grid), b(blk);
   if (d.general) {
     if (d.nt && rb2)
-      hipLaunchKernelGGL((k_apply_rows<T, V, U, true, 2, 3>), g, b, 0, st, d, tiles, nt, z, dd);
+      hipLaunchKernelGGL((k_apply_rows<T, V, U, true, 2, 3 | KX>), g, b, 0, st, d, tiles, nt, z, dd);
     else if (d.nt)
-      hipLaunchKernelGGL((k_apply_rows<T, V, U, true, 4, 3>), g, b, 0, st, d, tiles, nt, z, dd);
+      hipLaunchKernelGGL((k_apply_rows<T, V, U, true, 4, 3 | KX>), g, b, 0, st, d, tiles, nt, z, dd);
     else if (rb2)
-      hipLaunchKernelGGL((k_apply_rows<T, V, U, false, 2, 3>), g, b, 0, st, d, tiles, nt, z, dd);
+      hipLaunchKernelGGL((k_apply_rows<T, V, U, false, 2, 3 | KX>), g, b, 0, st, d, tiles, nt, z, dd);
     else
-      hipLaunchKernelGGL((k_apply_rows<T, V, U, false, 4, 3>), g, b, 0, st, d, tiles, nt, z, dd);
+      hipLaunchKernelGGL((k_apply_rows<T, V, U, false, 4, 3 | KX>), g, b, 0, st, d, tiles, nt, z, dd);
   } else {
     if (d.nt && rb2)
-      hipLaunchKernelGGL((k_apply_rows<T, V, U, true, 2, 1>), g, b, 0, st, d, tiles, nt, z, dd);
+      hipLaunchKernelGGL((k_apply_rows<T, V, U, true, 2, 1 | KX>), g, b, 0, st, d, tiles, nt, z, dd);
     else if (d.nt)
-      hipLaunchKernelGGL((k_apply_rows<T, V, U, true, 4, 1>), g, b, 0, st, d, tiles, nt, z, dd);
+      hipLaunchKernelGGL((k_apply_rows<T, V, U, true, 4, 1 | KX>), g, b, 0, st, d, tiles, nt, z, dd);
     else if (rb2)
-      hipLaunchKernelGGL((k_apply_rows<T, V, U, false, 2, 1>), g, b, 0, st, d, tiles, nt, z, dd);
+      hipLaunchKernelGGL((k_apply_rows<T, V, U, false, 2, 1 | KX>), g, b, 0, st, d, tiles, nt, z, dd);
     else
-      hipLaunchKernelGGL((k_apply_rows<T, V, U, false, 4, 1>), g, b, 0, st, d, tiles, nt, z, dd);
+      hipLaunchKernelGGL((k_apply_rows<T, V, U, false, 4, 1 | KX>), g, b, 0, st, d, tiles, nt, z, dd);
   }
 }
 
@@ -1779,6 +1799,10 @@ static void launch_rows_vu(const PlanDesc& d, hipStream_t st, int grid, int blk,
 template <typename T>
 static void launch_rows(const PlanDesc& d, hipStream_t st, int grid, int blk, const RowTile* tiles, int nt, int z,
                         const DataDesc& dd) {
+  if (d.ua && dd.grid == 0) {
+    launch_rows_vu<T, (sizeof(T) == 4 ? 4 : 2), 1, KM_UNAL>(d, st, grid, blk, tiles, nt, z, dd);
+    return;
+  }
   if (sizeof(T) == 4) {
     if (d.vec == 4)
       launch_rows_vu<T, (sizeof(T) == 4 ? 4 : 2), 1>(d, st, grid, blk, tiles, nt, z, dd);

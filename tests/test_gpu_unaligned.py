@@ -1,0 +1,105 @@
+"""Rows whose length 16-byte vectors do not divide (FP32 rows of I % 4 != 0
+values, FP64 rows of odd I, no vector components) go to the row kernel as
+overlapping vectors on element boundaries, the last one ending at the row's
+end.  Each slot's arithmetic is the same as on the aligned path, so the
+results must equal, bit for bit, those of the same program applied to the
+field padded with zero columns to a whole number of vectors (Sec. III-B: the
+operator acts on every inner slot alike; rows of the padded width take the
+same row kind, ELL(4), general CSR or copies, in the same entry order)."""
+import numpy as np
+import pytest
+
+from helpers import cs_full_field, gpu_available
+from oracle import cubed_sphere as ocs
+
+pytestmark = pytest.mark.gpu
+
+if gpu_available():
+    import torch
+
+    import paper_2605_14780_amd as hb
+
+
+def _cs_lagrange(N, h, b=None):
+    grid, prog = hb.cs_program(N, h, hb.CS_LAGRANGE)
+    if b is not None:
+        prog.add_vector(ocs.side_box(1, ocs.TOP, N, h), b, ninner=b.shape[1])
+    return grid, prog
+
+
+def _cs_quadrature(N, h, b=None):
+    grid = hb.Grid.cubed_sphere(N, h)
+    prog = hb.Program(grid)
+    prog.cs_add_quadrature(N, h, 2)
+    if b is not None:
+        prog.add_vector(ocs.side_box(4, ocs.LEFT, N, h), b, ninner=b.shape[1])
+    return grid, prog
+
+
+def _cart(N, h, b=None):
+    nb, n = (2, 2, 1), (N, N, 4)
+    grid = hb.Grid.cartesian(nb, n, h)
+    prog = hb.Program(grid)
+    prog.cart_add_halo(nb, n, h, periodic=1)
+    return grid, prog
+
+
+def _bits(a):
+    return a.view(np.uint64 if a.dtype == np.float64 else np.uint32)
+
+
+@pytest.mark.parametrize("build,dtype,I,with_b", [
+    (_cs_lagrange, "f32", 7, True), (_cs_lagrange, "f32", 6, False), (_cs_lagrange, "f32", 5, True),
+    (_cs_lagrange, "f64", 5, True), (_cs_lagrange, "f64", 3, False), (_cs_lagrange, "f32", 37, True),
+    (_cs_quadrature, "f32", 9, True), (_cs_quadrature, "f64", 5, True),
+    (_cart, "f32", 7, False), (_cart, "f64", 3, False)])
+def test_unaligned_rows_equal_padded_apply_bitwise(build, dtype, I, with_b):
+    N, h = 12, 3
+    dt, npdt = (hb.F64, np.float64) if dtype == "f64" else (hb.F32, np.float32)
+    vfull = 2 if dt == hb.F64 else 4
+    Ip = -(-I // vfull) * vfull  # padded to whole 16-byte vectors
+    rng = np.random.default_rng(I)
+    b = rng.standard_normal((N * h, I)) if with_b else None
+    grid, prog = build(N, h, b)
+    plan = hb.Plan(prog, inner=I, dtype=dt)
+    bp = np.concatenate([b, np.zeros((N * h, Ip - I))], axis=1) if with_b else None
+    gp, progp = build(N, h, bp)
+    planp = hb.Plan(progp, inner=Ip, dtype=dt)
+    n = grid.cells
+    full = rng.standard_normal((n, I)).astype(npdt)
+    fullp = np.concatenate([full, np.zeros((n, Ip - I), dtype=npdt)], axis=1)
+    t = torch.from_numpy(full.copy()).cuda()
+    tp = torch.from_numpy(fullp).cuda()
+    hb.apply(plan, t)
+    hb.apply(planp, tp)
+    torch.cuda.synchronize()
+    got = t.cpu().numpy()
+    ref = np.ascontiguousarray(tp.cpu().numpy()[:, :I])
+    assert np.array_equal(_bits(got), _bits(ref))
+
+
+@pytest.mark.parametrize("dtype,I", [("f32", 7), ("f64", 5)])
+def test_unaligned_rows_adjoint_dot_identity(dtype, I):
+    """<A x, y> = <x, A^T y> on a plan of unaligned rows (the adjoint's ghost
+    reset goes through the same row kernel)."""
+    N, h = 12, 3
+    dt, tdt = (hb.F64, torch.float64) if dtype == "f64" else (hb.F32, torch.float32)
+    rng = np.random.default_rng(40 + I)
+    b = rng.standard_normal((N * h, I))
+    grid, prog = _cs_lagrange(N, h, b)
+    plan = hb.Plan(prog, inner=I, dtype=dt)
+    full = np.nan_to_num(cs_full_field(N, h, 1, I, seed=7), nan=0.0)
+    x = torch.from_numpy(full.astype(np.float64 if dt == hb.F64 else np.float32)).cuda()
+    y = torch.randn(grid.cells, I, dtype=tdt, device="cuda", generator=torch.Generator("cuda").manual_seed(5))
+    Ax, z, Aty = x.clone(), torch.zeros_like(x), y.clone()
+    hb.apply(plan, Ax)
+    hb.apply(plan, z)
+    hb.apply_adjoint(plan, Aty)
+    torch.cuda.synchronize()
+    lhs = float(((Ax.double() - z.double()) * y.double()).sum())
+    rhs = float((x.double() * Aty.double()).sum())
+    assert abs(lhs - rhs) <= (1e-12 if dt == hb.F64 else 1e-5) * max(abs(lhs), abs(rhs))
+    # every ghost value of A^T y is zero, every data value finite
+    og = ocs.grid(N, h)
+    a = Aty.cpu().numpy()
+    assert (a[og.ghost_cells] == 0).all() and np.isfinite(a).all()
