@@ -51,9 +51,13 @@ def _bits(a):
 @pytest.mark.parametrize("build,dtype,I,with_b", [
     (_cs_lagrange, "f32", 7, True), (_cs_lagrange, "f32", 6, False), (_cs_lagrange, "f32", 5, True),
     (_cs_lagrange, "f64", 5, True), (_cs_lagrange, "f64", 3, False), (_cs_lagrange, "f32", 37, True),
+    (_cs_lagrange, "f32", 13, True), (_cs_lagrange, "f32", 30, False), (_cs_lagrange, "f32", 65, True),
+    (_cs_lagrange, "f32", 127, True), (_cs_lagrange, "f64", 7, True), (_cs_lagrange, "f64", 33, True),
     (_cs_quadrature, "f32", 9, True), (_cs_quadrature, "f64", 5, True),
-    (_cart, "f32", 7, False), (_cart, "f64", 3, False)])
+    (_cart, "f32", 7, False), (_cart, "f64", 3, False), (_cart, "f32", 66, False)])
 def test_unaligned_rows_equal_padded_apply_bitwise(build, dtype, I, with_b):
+    """Rows of 4 to 508 bytes: one or two rows per batch of a row group,
+    plain and non-temporal stores, b per slot or none."""
     N, h = 12, 3
     dt, npdt = (hb.F64, np.float64) if dtype == "f64" else (hb.F32, np.float32)
     vfull = 2 if dt == hb.F64 else 4
