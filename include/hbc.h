@@ -289,6 +289,20 @@ int hbc_plan_stats(const hbc_plan* plan, hbc_stats* out);
  * may then name a data cell), -1 uncovered). */
 int hbc_plan_row(const hbc_plan* plan, int64_t ghost_cell, int64_t l, int32_t cap, int64_t* cols,
                  double* vals, int32_t* nnz, double* b, int32_t* kind, int32_t* rot);
+/* New values for a basic sub-vector of the plan's program (Sec. III-B: the
+ * affine part b of F, e.g. a Dirichlet value that changes from step to step),
+ * without compiling the plan again.  sub_id is the id hbc_program_add_vector
+ * returned; values (host, caller-owned, FP64) has the layout and length given
+ * there (rows of the sub-vector's box, row-major, times its ninner).  Every b
+ * value the sub-vector contributes to is recomputed as at plan creation (the
+ * sum over the sub-vectors covering the row, rounded to the plan's type) and
+ * copied to the device, ordered after earlier work on `stream`; the call
+ * returns when the copy is done.  Captured graphs and batches holding the
+ * plan read the new values from their next launch.  Work on other streams
+ * that uses the plan must not overlap the call.  Host-only plans update their
+ * host tables (hbc_plan_row).  HBC_EINVAL: sub_id is not a sub-vector of the
+ * program, or NULL values for a non-empty sub-vector. */
+int hbc_plan_set_vector(hbc_plan* plan, int32_t sub_id, const double* values, void* stream);
 int hbc_plan_get_tune(const hbc_plan* plan, hbc_tune* out);
 /* Replace the launch shape (rebuilds the tile table).  Results are identical
  * for every valid shape. */

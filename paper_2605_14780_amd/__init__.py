@@ -99,6 +99,7 @@ SIGNATURES = {
     "hbc_plan_destroy": (None, [P]),
     "hbc_plan_stats": (I32, [P, C.POINTER(StatsT)]),
     "hbc_plan_row": (I32, [P, I64, I64, I32, PI64, PD, PI32, PD, PI32, PI32]),
+    "hbc_plan_set_vector": (I32, [P, I32, PD, P]),
     "hbc_plan_get_tune": (I32, [P, C.POINTER(TuneT)]),
     "hbc_plan_set_tune": (I32, [P, C.POINTER(TuneT)]),
     "hbc_plan_autotune": (I32, [P, C.POINTER(P), I64, I32, C.c_char_p, P, PD]),
@@ -338,6 +339,7 @@ class Plan:
         self.inner = inner
         self.order = order
         self.dtype = dtype
+        self.host_only = host_only
         self.ncells = program.grid.cells
         self.nelem = self.ncells * inner
 
@@ -355,6 +357,12 @@ class Plan:
                                   C.byref(rot)))
         n = min(nnz.value, cap)
         return kind.value, list(cols[:n]), list(vals[:n]), b.value, rot.value
+
+    def set_vector(self, sub_id, values, stream=None):
+        """New values for sub-vector sub_id, laid out as for Program.add_vector."""
+        v_a, v_p = _f64(np.asarray(values).reshape(-1))
+        st = P(0) if self.host_only else _stream(stream)
+        _check(lib().hbc_plan_set_vector(self._h, sub_id, v_p, st))
 
     @property
     def tune(self):

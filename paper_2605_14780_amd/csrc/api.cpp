@@ -524,6 +524,14 @@ int hbc_plan_row(const hbc_plan* plan, int64_t ghost_cell, int64_t l, int32_t ca
   });
 }
 
+int hbc_plan_set_vector(hbc_plan* plan, int32_t sub_id, const double* values, void* stream) {
+  return guard([&] {
+    need(plan != nullptr, "NULL argument");
+    const std::pair<int64_t, int64_t> r = plan_set_vector(plan->p, sub_id, values);
+    if (!(plan->p.flags & HBC_PLAN_HOST_ONLY)) device_update_b(plan->p, r.first, r.second, stream);
+  });
+}
+
 int hbc_plan_get_tune(const hbc_plan* plan, hbc_tune* out) {
   return guard([&] {
     need(plan && out, "NULL argument");

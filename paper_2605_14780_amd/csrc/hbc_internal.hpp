@@ -323,12 +323,27 @@ struct Layout {
   int64_t vec_len = 0, vec_lo = 0, vec_stride = 0;
 };
 
+// The b values of one segment as plan compile laid them out: the rows of
+// `box` visited in `order`, bi values per row at host.bval[brow + q * bi + l],
+// each the sum, in the order of `vecs`, of those sub-vectors' values
+// (indices into Plan::vsubs).
+struct BSeg {
+  Box box;
+  std::vector<int> order;
+  std::vector<int> vecs;
+  int64_t bi = 1;
+  int64_t brow = 0;
+};
+
 struct Plan {
   Grid grid;
   Layout layout;
   int dtype = HBC_F64;
   uint32_t flags = 0;
   HostTables host;
+  std::vector<Sub> vsubs;        // the program's sub-vectors, values as last set
+  std::vector<int32_t> vsub_id;  // their ids in the program
+  std::vector<BSeg> bsegs;       // segments with b
   hbc_stats stats{};
   hbc_tune tune{};
   int vec = 1;     // elements per lane access (point-major)
@@ -400,6 +415,9 @@ void build_tiles(Plan& plan, const hbc_tune& t);
 hbc_tune default_tune(const Plan& plan);
 void build_csc(Plan& plan);
 void compute_stencil_info(Plan& plan);
+// new values for sub-vector sub_id: recomputes the b values it contributes
+// to; returns the changed range [first, last) of host.bval (empty if none)
+std::pair<int64_t, int64_t> plan_set_vector(Plan& plan, int32_t sub_id, const double* values);
 // host evaluation of a compiled row
 int plan_row(const Plan& plan, int64_t cell, int64_t l, int cap, int64_t* cols, double* vals, int32_t* nnz,
              double* b, int32_t* kind, int32_t* rot);

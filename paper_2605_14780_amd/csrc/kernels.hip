@@ -2294,6 +2294,22 @@ void device_batch_destroy(Batch* b) {
   delete b;
 }
 
+void device_update_b(Plan& p, int64_t first, int64_t last, void* stream) {
+  if (last <= first) return;
+  const size_t es = p.dtype == HBC_F64 ? 8 : 4, n = (size_t)(last - first);
+  std::vector<unsigned char> buf(n * es);
+  if (p.dtype == HBC_F64) {
+    std::memcpy(buf.data(), p.host.bval.data() + first, n * es);
+  } else {
+    float* f = reinterpret_cast<float*>(buf.data());
+    for (size_t k = 0; k < n; ++k) f[k] = (float)p.host.bval[first + k];  // rounded as at plan creation
+  }
+  // ordered after earlier work on the stream; the call returns once the copy is done
+  unsigned char* dst = static_cast<unsigned char*>(const_cast<void*>(p.d_bval)) + (size_t)first * es;
+  HIP_CHECK(hipMemcpyAsync(dst, buf.data(), n * es, hipMemcpyHostToDevice, S(stream)));
+  HIP_CHECK(hipStreamSynchronize(S(stream)));
+}
+
 void device_batch_bind(Batch* b, void* const* fields) {
   if (fields)
     for (size_t k = 0; k < b->plans.size(); ++k) {

@@ -9,6 +9,7 @@
 // sub-matrices / sub-vectors covering them, and each piece becomes one
 // segment (a box with one kind of row).
 #include <algorithm>
+#include <climits>
 #include <cstring>
 #include <map>
 #include <numeric>
@@ -270,6 +271,44 @@ static void build_data_components(HostTables& T) {
   T.dc_ok = true;
 }
 
+// b values of one segment (Sec. III-B: the affine part of F, the sum of the
+// sub-vectors that cover a row)
+static void fill_bseg(const BSeg& bs, const std::vector<Sub>& vsubs, std::vector<double>& bval) {
+  for_box_order(bs.box, bs.order, [&](const int64_t* r, int64_t q) {
+    for (int64_t l = 0; l < bs.bi; ++l) {
+      double acc = 0.0;
+      bool first = true;
+      for (int v : bs.vecs) {
+        const Sub& s = vsubs[v];
+        const int64_t k = box_linear(s.rows, r);
+        const double x = s.b[k * s.ninner + (s.ninner == 1 ? 0 : l)];
+        acc = first ? x : acc + x;
+        first = false;
+      }
+      bval[bs.brow + q * bs.bi + l] = acc;
+    }
+  });
+}
+
+std::pair<int64_t, int64_t> plan_set_vector(Plan& plan, int32_t sub_id, const double* values) {
+  int k = -1;
+  for (size_t j = 0; j < plan.vsub_id.size(); ++j)
+    if (plan.vsub_id[j] == sub_id) k = (int)j;
+  if (k < 0) fail(HBC_EINVAL, "sub_id " + std::to_string(sub_id) + " is not a sub-vector of the plan's program");
+  Sub& s = plan.vsubs[k];
+  if (!values && !s.b.empty()) fail(HBC_EINVAL, "NULL values");
+  std::copy(values, values + s.b.size(), s.b.begin());
+  int64_t first = INT64_MAX, last = 0;
+  for (const BSeg& bs : plan.bsegs) {
+    if (std::find(bs.vecs.begin(), bs.vecs.end(), k) == bs.vecs.end()) continue;
+    fill_bseg(bs, plan.vsubs, plan.host.bval);
+    first = std::min(first, bs.brow);
+    last = std::max(last, bs.brow + bs.box.count() * bs.bi);
+  }
+  if (first >= last) return {0, 0};
+  return {first, last};
+}
+
 void compile_plan(const Program& prog, const Layout& lay, int dtype, Plan& plan) {
   const Grid& g = prog.grid;
   plan.grid = g;
@@ -283,10 +322,22 @@ void compile_plan(const Program& prog, const Layout& lay, int dtype, Plan& plan)
   if (g.ncells >= (int64_t(1) << 31) - 1) fail(HBC_EUNSUPPORTED, "more than 2^31-2 cells per plan");
   if (g.blocks.empty()) fail(HBC_EINVAL, "grid has no blocks");
 
-  // 1. validate rows; expand the zero-rest subs
+  // 1. validate rows; expand the zero-rest subs; keep the sub-vectors
+  //    (their values can be replaced after compile, plan_set_vector)
   std::vector<Sub> subs;
+  std::vector<int> vsub_of;  // per entry of subs: its index in plan.vsubs, or -1
   std::vector<int> zero_rest_blocks;
-  for (const Sub& s0 : prog.subs) {
+  plan.vsubs.clear();
+  plan.vsub_id.clear();
+  plan.bsegs.clear();
+  for (size_t id = 0; id < prog.subs.size(); ++id) {
+    const Sub& s0 = prog.subs[id];
+    int vk = -1;
+    if (s0.kind == SUB_VEC) {
+      vk = (int)plan.vsubs.size();
+      plan.vsubs.push_back(s0);
+      plan.vsub_id.push_back((int32_t)id);
+    }
     if (s0.kind == SUB_ZERO_REST) {
       zero_rest_blocks.push_back(s0.block);
       continue;
@@ -300,6 +351,7 @@ void compile_plan(const Program& prog, const Layout& lay, int dtype, Plan& plan)
       fail(HBC_ERANGE, "sub-matrix rows include data cells (only ghost rows are written)");
     s.block = b;
     subs.push_back(std::move(s));
+    vsub_of.push_back(vk);
   }
   for (int b : zero_rest_blocks) {
     if (b < 0 || b >= (int)g.blocks.size()) fail(HBC_EINVAL, "zero-rest block out of range");
@@ -318,6 +370,7 @@ void compile_plan(const Program& prog, const Layout& lay, int dtype, Plan& plan)
       z.rows = r;
       z.block = b;
       subs.push_back(z);
+      vsub_of.push_back(-1);
     }
   }
 
@@ -552,20 +605,15 @@ void compile_plan(const Program& prog, const Layout& lay, int dtype, Plan& plan)
       seg.has_b = 1;
       seg.b_inner = (int32_t)bi;
       seg.brow = (int64_t)T.bval.size();
-      for_box_order(pc.box, order, [&](const int64_t* r, int64_t) {
-        for (int64_t l = 0; l < bi; ++l) {
-          double acc = 0.0;
-          bool first = true;
-          for (int v : vecs) {
-            const Sub& s = subs[v];
-            int64_t k = box_linear(s.rows, r);
-            double x = s.b[k * s.ninner + (s.ninner == 1 ? 0 : l)];
-            acc = first ? x : acc + x;
-            first = false;
-          }
-          T.bval.push_back(acc);
-        }
-      });
+      BSeg bs;
+      bs.box = pc.box;
+      bs.order = order;
+      for (int v : vecs) bs.vecs.push_back(vsub_of[v]);
+      bs.bi = bi;
+      bs.brow = seg.brow;
+      T.bval.resize((size_t)(seg.brow + seg.nrows * bi));
+      fill_bseg(bs, plan.vsubs, T.bval);
+      plan.bsegs.push_back(std::move(bs));
       st.rows_with_b += seg.nrows;
     }
 

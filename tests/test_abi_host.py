@@ -435,3 +435,46 @@ def test_cubed_sphere_halo_limited_to_half_a_face(N, h):
         p.cs_add(N, h, hb.CS_SYNC)
     with pytest.raises(hb.HbcError):
         p.cs_add_quadrature(N, h, 2)
+
+
+def _set_vector_program(b1, b2, b3, I):
+    """One 4^3 block, halo 1: zero halo rows, a b of width I on the z = -1
+    face, a b of width 1 on part of it (summed), a b of width I on z = 4."""
+    g = hb.Grid.cartesian([1, 1, 1], [4, 4, 4], 1)
+    p = hb.Program(g)
+    p.set_flags(hb.ALLOW_OVERLAP_SUM)
+    p.cart_add_halo([1, 1, 1], [4, 4, 4], 1)
+    s1 = p.add_vector([(0, 1), (-1, 0), (0, 4), (0, 4)], b1, ninner=I)
+    s2 = p.add_vector([(0, 1), (-1, 0), (1, 3), (0, 4)], b2, ninner=1)
+    s3 = p.add_vector([(0, 1), (4, 5), (0, 4), (0, 4)], b3, ninner=I)
+    return g, p, (s1, s2, s3)
+
+
+@pytest.mark.parametrize("order", [hb.POINT_MAJOR, hb.PLANE_MAJOR])
+def test_set_vector_gives_the_b_of_a_plan_built_with_the_new_values(order):
+    """Sec. III-B (b of F): new values for sub-vectors of a compiled plan give,
+    row by row and slot by slot, the b a plan compiled from those values has
+    (sums over overlapping sub-vectors included); matrix rows are unchanged."""
+    I = 3
+    rng = np.random.default_rng(21)
+    b1, b2, b3 = rng.standard_normal((16, I)), rng.standard_normal(8), rng.standard_normal((16, I))
+    n2, n3 = rng.standard_normal(8), rng.standard_normal((16, I))
+    g, p, (s1, s2, s3) = _set_vector_program(b1, b2, b3, I)
+    plan = hb.Plan(p, inner=I, order=order, host_only=True)
+    plan.set_vector(s2, n2)
+    plan.set_vector(s3, n3)
+    _, pf, _ = _set_vector_program(b1, n2, n3, I)
+    fresh = hb.Plan(pf, inner=I, order=order, host_only=True)
+    _, po, _ = _set_vector_program(b1, b2, b3, I)
+    old = hb.Plan(po, inner=I, order=order, host_only=True)
+    changed = 0
+    for cell in range(g.cells):
+        for l in range(I):
+            got, want, before = plan.row(cell, l), fresh.row(cell, l), old.row(cell, l)
+            assert got == want, (cell, l)
+            changed += got[3] != before[3]
+    assert changed == (8 + 16) * I  # the rows of s2 and s3, every slot
+    with pytest.raises(hb.HbcError, match="not a sub-vector"):
+        plan.set_vector(0, n2)  # a halo sub-matrix
+    with pytest.raises(hb.HbcError, match="not a sub-vector"):
+        plan.set_vector(s3 + 1, n2)
