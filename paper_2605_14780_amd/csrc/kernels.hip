@@ -1823,12 +1823,15 @@ static void launch_rows(const PlanDesc& d, hipStream_t st, int grid, int blk, co
   }
 }
 
-// Slices per workgroup of the wide-row kernel: as many as keep at least
-// eight workgroups per CU (256 CUs), so the pipelined staging has slices to
-// overlap without leaving CUs idle.
-static int wide_slices_per_wg(int ntiles, int nslices) {
+// Slices per workgroup of the wide-row kernel: up to 1 KiB of each row (the
+// pipelined staging then has slices to overlap; measured best for 128- and
+// 256-byte slices alike), while at least four workgroups per CU (256 CUs)
+// remain.
+static int wide_slices_per_wg(int ntiles, int nslices, int slice_bytes) {
   int spw = 1;
-  while (spw < nslices && (int64_t)ntiles * ((nslices + 2 * spw - 1) / (2 * spw)) >= 256 * 8) spw *= 2;
+  while (spw < nslices && 2 * spw * slice_bytes <= 1024 &&
+         (int64_t)ntiles * ((nslices + 2 * spw - 1) / (2 * spw)) >= 256 * 4)
+    spw *= 2;
   return spw;
 }
 
@@ -1837,7 +1840,7 @@ static void launch_wide(const Plan& p, const PlanDesc& d, hipStream_t st, bool z
   constexpr int S = SB / (int)sizeof(T);
   const int nslices = (int)((p.layout.inner + S - 1) / S);
   const int ntiles = (int)p.host.wtiles.size();
-  const int spw = wide_slices_per_wg(ntiles, nslices);
+  const int spw = wide_slices_per_wg(ntiles, nslices, SB);
   const int nwide = ntiles * ((nslices + spw - 1) / spw);
   const int grid = nwide + nzero;
   const int ucap = p.host.w_maxu, ecap = (p.host.w_maxe + 1) & ~1;  // even: keeps the row starts 16-byte aligned
