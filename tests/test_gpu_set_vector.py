@@ -61,3 +61,36 @@ def test_set_vector_equals_a_plan_built_with_the_new_values(dtype, order, I):
         got = a.cpu().numpy()
         tol = lagrange_tolerance(N, h, full, ref, None)
         assert (np.abs(got[G] - ref[G]) <= tol).all()
+
+
+def test_set_vector_reaches_a_batch_and_its_graph():
+    """A batch holding the plan (and the batch's captured graph) reads the new
+    values from its next launch, as a plan compiled with them would give."""
+    N, h, I = 12, 2, 5
+    rng = np.random.default_rng(11)
+    b_old, b_new = rng.standard_normal((N * h, I)), rng.standard_normal((N * h, I))
+    grid, prog, sid = _program(N, h, I, b_old)
+    plan = hb.Plan(prog, inner=I, dtype=hb.F32)
+    other_grid, other_prog = hb.cs_program(16, 3, hb.CS_LAGRANGE)
+    other = hb.Plan(other_prog, inner=3, dtype=hb.F32)
+    _, prog_new, _ = _program(N, h, I, b_new)
+    fresh = hb.Plan(prog_new, inner=I, dtype=hb.F32)
+    x = torch.from_numpy(cs_full_field(N, h, 1, I, seed=9).astype(np.float32)).cuda()
+    y = torch.from_numpy(cs_full_field(16, 3, 1, 3, seed=10).astype(np.float32)).cuda()
+    want = x.clone()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        hb.apply(fresh, want, stream=s.cuda_stream)
+        batch = hb.Batch([plan, other])
+        fx, fy = x.clone(), y.clone()
+        batch.bind([fx, fy])
+        batch.graph_capture(s.cuda_stream)  # captured with the old values
+        plan.set_vector(sid, b_new, stream=s.cuda_stream)
+        batch.apply(s.cuda_stream)
+    torch.cuda.synchronize()
+    assert torch.equal(fx, want)
+    with torch.cuda.stream(s):
+        fx.copy_(x)
+        batch.graph_launch(s.cuda_stream)
+    torch.cuda.synchronize()
+    assert torch.equal(fx, want)
