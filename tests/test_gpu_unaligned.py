@@ -54,19 +54,20 @@ def _bits(a):
     (_cs_lagrange, "f32", 13, True), (_cs_lagrange, "f32", 30, False), (_cs_lagrange, "f32", 65, True),
     (_cs_lagrange, "f32", 127, True), (_cs_lagrange, "f64", 7, True), (_cs_lagrange, "f64", 33, True),
     (_cs_quadrature, "f32", 9, True), (_cs_quadrature, "f64", 5, True),
-    (_cart, "f32", 7, False), (_cart, "f64", 3, False), (_cart, "f32", 66, False)])
+    (_cart, "f32", 7, False), (_cart, "f64", 3, False), (_cart, "f32", 66, False),
+    (_cs_lagrange, "f32", 7, "scalar"), (_cs_lagrange, "f64", 5, "scalar")])
 def test_unaligned_rows_equal_padded_apply_bitwise(build, dtype, I, with_b):
     """Rows of 4 to 508 bytes: one or two rows per batch of a row group,
-    plain and non-temporal stores, b per slot or none."""
+    plain and non-temporal stores, b per slot, one b for every slot, or none."""
     N, h = 12, 3
     dt, npdt = (hb.F64, np.float64) if dtype == "f64" else (hb.F32, np.float32)
     vfull = 2 if dt == hb.F64 else 4
     Ip = -(-I // vfull) * vfull  # padded to whole 16-byte vectors
     rng = np.random.default_rng(I)
-    b = rng.standard_normal((N * h, I)) if with_b else None
+    b = rng.standard_normal((N * h, 1 if with_b == "scalar" else I)) if with_b else None
     grid, prog = build(N, h, b)
     plan = hb.Plan(prog, inner=I, dtype=dt)
-    bp = np.concatenate([b, np.zeros((N * h, Ip - I))], axis=1) if with_b else None
+    bp = b if with_b == "scalar" else np.concatenate([b, np.zeros((N * h, Ip - I))], axis=1) if with_b else None
     gp, progp = build(N, h, bp)
     planp = hb.Plan(progp, inner=Ip, dtype=dt)
     n = grid.cells
