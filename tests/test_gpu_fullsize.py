@@ -114,11 +114,13 @@ def test_c768_adjoint_dot_product():
     assert (Aty.reshape(6, W, W, L)[G] == 0).all()
 
 
-def test_c384_wide_rows_sampled():
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_c384_wide_rows_sampled(dtype):
     """Wide interpolation rows (2x2 Gauss average of cubic reconstructions,
     16..25 entries) at C384, halo 3, 256 inner values with (u, v) rotated,
-    FP64, through the LDS-staged kernel: sampled ghost rows against the
-    oracle's rows evaluated one by one."""
+    through the LDS-staged kernel in the bench's launch (FP64: 256-byte
+    slices, FP32: 128-byte slices): sampled ghost rows against the oracle's
+    rows evaluated one by one (FP32: weights and sums in FP32)."""
     from oracle import quadrature as oq
     N, h, nf, nl = 384, 3, 4, 64
     I = nf * nl
@@ -127,11 +129,12 @@ def test_c384_wide_rows_sampled():
     g = hb.Grid.cubed_sphere(N, h)
     p = hb.Program(g)
     p.cs_add_quadrature(N, h, 2, vector=True)
-    plan = hb.Plan(p, inner=I, vec=vec, dtype=hb.F64)
+    dt, tdt, eps = (hb.F64, torch.float64, U64) if dtype == "f64" else (hb.F32, torch.float32, 2.0 ** -24)
+    plan = hb.Plan(p, inner=I, vec=vec, dtype=dt)
     st = plan.stats()
     assert st["rows_wide"] == st["rows_csr"] == 24 * h * N
-    full = torch.full((6, W, W, I), float("nan"), dtype=torch.float64, device="cuda")
-    full[:, h:h + N, h:h + N] = synthinputs.cs_sh_field_torch(N, nf, nl, seed=3, device="cuda")
+    full = torch.full((6, W, W, I), float("nan"), dtype=tdt, device="cuda")
+    full[:, h:h + N, h:h + N] = synthinputs.cs_sh_field_torch(N, nf, nl, seed=3, device="cuda").to(tdt)
     full = full.reshape(-1, I)
     out = full.clone()
     hb.apply(plan, out)
@@ -146,21 +149,21 @@ def test_c384_wide_rows_sampled():
         j, i = (int(v) for v in rng.integers(-h, N + h, size=2))
         if (0 <= j < N and 0 <= i < N) or ocs.is_corner(j, i, N):
             continue
-        got = out[(f * W + (j + h)) * W + (i + h)].cpu().numpy()
+        got = out[(f * W + (j + h)) * W + (i + h)].cpu().numpy().astype(np.float64)
         ents = oq.quad_entries(f, j, i, N, 2)
         src = [(gg * W + (jj + h)) * W + (ii + h) for (gg, jj, ii), _ in ents]
         w = np.array([wv for _, wv in ents])
-        X = full[torch.tensor(src, device="cuda")].cpu().numpy()
+        X = full[torch.tensor(src, device="cuda")].cpu().numpy().astype(np.float64)  # inputs as the GPU holds them
         y = w @ X
         R = ocs.rside(f, ocs.side_of(j, i, N))
         ref = y.copy()
         ref[u_sl] = R[0, 0] * y[u_sl] + R[0, 1] * y[v_sl]
         ref[v_sl] = R[1, 0] * y[u_sl] + R[1, 1] * y[v_sl]
         # weights agree with the host's to 1e-13 per entry (pinned host-side);
-        # summation rounding of <= 25 FP64 terms
+        # rounding of the weights to the plan's type and of <= 25 terms' sum
         pat = np.abs(X).sum(axis=0)
         mag = np.abs(w) @ np.abs(X)
-        bnd = 1e-13 * pat + 64 * U64 * mag
+        bnd = 1e-13 * pat + 64 * eps * mag
         bnd_rot = bnd.copy()
         bnd_rot[u_sl] = np.maximum(bnd[u_sl], bnd[v_sl])
         bnd_rot[v_sl] = bnd_rot[u_sl]
