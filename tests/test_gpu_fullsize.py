@@ -28,16 +28,22 @@ if gpu_available():
     import paper_2605_14780_amd as hb
 
 
-def test_c384_sampled_rows_tuned_shape(tmp_path):
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_c384_sampled_rows_tuned_shape(tmp_path, dtype):
+    """The bench's C384 operator (4-point Lagrange rows, (u, v) rotated) in the
+    autotuned launch shape: sampled ghost rows against the oracle's rows
+    evaluated one by one, corners +0 (FP32: weights rounded from FP64, four
+    FP32 terms summed)."""
     N, h, nf, nl = 384, 3, 4, 64
     I = nf * nl
     vec = (2 * nl, nl, nl)
     W = N + 2 * h
     grid, prog = hb.cs_program(N, h, hb.CS_LAGRANGE, vector=True)
-    plan = hb.Plan(prog, inner=I, vec=vec, dtype=hb.F64)
+    dt, tdt = (hb.F64, torch.float64) if dtype == "f64" else (hb.F32, torch.float32)
+    plan = hb.Plan(prog, inner=I, vec=vec, dtype=dt)
     data = synthinputs.cs_sh_field_torch(N, nf, nl, seed=2, device="cuda")
-    full = torch.full((6, W, W, I), float("nan"), dtype=torch.float64, device="cuda")
-    full[:, h:h + N, h:h + N] = data
+    full = torch.full((6, W, W, I), float("nan"), dtype=tdt, device="cuda")
+    full[:, h:h + N, h:h + N] = data.to(tdt)
     full = full.reshape(-1, I)
     del data
     plan.autotune([full.clone() for _ in range(2)], str(tmp_path / "tune.jsonl"))
@@ -54,7 +60,7 @@ def test_c384_sampled_rows_tuned_shape(tmp_path):
         j, i = (int(v) for v in rng.integers(-h, N + h, size=2))
         if 0 <= j < N and 0 <= i < N:
             continue
-        got = out[(f * W + (j + h)) * W + (i + h)].cpu().numpy()
+        got = out[(f * W + (j + h)) * W + (i + h)].cpu().numpy().astype(np.float64)
         if ocs.is_corner(j, i, N):
             assert (got == 0).all() and not np.signbit(got).any(), (f, j, i)
             corners += 1
@@ -62,7 +68,7 @@ def test_c384_sampled_rows_tuned_shape(tmp_path):
         ents = ocs.lagrange_entries(f, j, i, N)
         src = [(g * W + (jj + h)) * W + (ii + h) for (g, jj, ii), _ in ents]
         w = np.array([wv for _, wv in ents])
-        X = full[torch.tensor(src, device="cuda")].cpu().numpy()
+        X = full[torch.tensor(src, device="cuda")].cpu().numpy().astype(np.float64)  # inputs as the GPU holds them
         y = w @ X
         R = ocs.rside(f, ocs.side_of(j, i, N))
         ref = y.copy()
@@ -73,6 +79,8 @@ def test_c384_sampled_rows_tuned_shape(tmp_path):
         ax = np.abs(X).sum(axis=0)
         wx = np.abs(w) @ np.abs(X)
         bnd = 1e-13 * np.maximum(wx, 1e-300) + 8 * N * U64 * 4 * ax
+        if dt == hb.F32:  # weight rounding (1 ulp each) and four FP32 roundings of the sum
+            bnd = bnd + 8 * 2.0 ** -24 * wx
         bnd_rot = bnd.copy()
         bnd_rot[u_sl] = np.maximum(bnd[u_sl], bnd[v_sl])
         bnd_rot[v_sl] = bnd_rot[u_sl]
