@@ -347,10 +347,20 @@ def extra_footprint(ctx, hb, torch, tm):
     fields = [src.clone() for _ in range(9)]
     del src
     us0, us = default_and_tuned(hb, plan, fields, 90, tm)
+    del fields
+    # the kept rows equal the headline's (oracle-checked) rows bit for bit;
+    # dead rows stay untouched (NaN in the input)
+    x = torch.from_numpy(ctx["c2_full"]).cuda()
+    ghost = torch.isnan(x).any(dim=1)
+    hb.apply(plan, x)
+    ref = torch.from_numpy(ctx["c2_got"]).cuda()
+    kept = ghost & ~torch.isnan(x).any(dim=1)
+    same = int(kept.sum()) == st["rows_covered"] and torch.equal(x[kept], ref[kept])
+    del x, ref, ghost, kept
     out = {"consumer": "cross radius 1", "rows_covered": st["rows_covered"], "rows_dead": st["rows_dead"],
            "us_per_apply": us, "default_shape_us_per_apply": us0, "alg_bytes": st["alg_bytes"],
-           "hbm_frac": st["alg_bytes"] / us / 1e3 / HBM_PEAK_GBS}
-    del fields
+           "hbm_frac": st["alg_bytes"] / us / 1e3 / HBM_PEAK_GBS,
+           "kept_rows_equal_full_halo_rows_bitwise": bool(same)}
     torch.cuda.empty_cache()
     return out
 
