@@ -32,10 +32,12 @@
  *    16-byte aligned.
  *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  Apply
  *    calls are asynchronous on that stream.
- *  - Plans are immutable after creation (apart from tuning), so applies on
- *    different streams may run concurrently on different fields.  The one
- *    exception is the adjoint: calls of hbc_apply_adjoint on one plan must not
- *    overlap in time (see there).
+ *  - Plans are immutable after creation (apart from tuning and new sub-vector
+ *    values, hbc_plan_set_vector), so applies on different streams may run
+ *    concurrently on different fields.  The exceptions are the adjoint (calls
+ *    of hbc_apply_adjoint on one plan must not overlap in time, see there)
+ *    and hbc_plan_set_vector, which no work on another stream that uses the
+ *    plan may overlap.
  *  - destroy(NULL) is a no-op.
  */
 #ifndef HBC_H
