@@ -478,3 +478,40 @@ def test_set_vector_gives_the_b_of_a_plan_built_with_the_new_values(order):
         plan.set_vector(0, n2)  # a halo sub-matrix
     with pytest.raises(hb.HbcError, match="not a sub-vector"):
         plan.set_vector(s3 + 1, n2)
+
+
+def test_set_vector_with_a_consumer_footprint():
+    """A sub-vector over a whole halo strip of which the consumer footprint
+    keeps one layer: new values reach the kept rows (as in a plan built with
+    them) and the dropped rows stay uncovered; a sub-vector whose rows are all
+    dropped takes new values without error."""
+    N, h = 8, 3
+    box = ocs.side_box(0, ocs.LEFT, N, h)  # the h layers of face 0's left strip
+    outer_layer = [box[0], (-h, -h + 1), box[2]] if box[1][0] < 0 else [box[0], box[1], (-h, -h + 1)]
+    rng = np.random.default_rng(4)
+    b0, b1 = rng.standard_normal(h * N), rng.standard_normal(h * N)
+    o0, o1 = rng.standard_normal(N), rng.standard_normal(N)
+    offs = [(0, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]
+
+    def build(bv, ov):
+        g = hb.Grid.cubed_sphere(N, h)
+        p = hb.Program(g)
+        p.set_flags(hb.ALLOW_OVERLAP_SUM)
+        p.cs_add(N, h, hb.CS_SYNC)
+        s_strip = p.add_vector(box, bv)
+        s_outer = p.add_vector(outer_layer, ov)
+        p.set_consumer(offs)
+        return g, hb.Plan(p, inner=1, host_only=True), s_strip, s_outer
+
+    g, plan, s_strip, s_outer = build(b0, o0)
+    plan.set_vector(s_strip, b1)
+    plan.set_vector(s_outer, o1)  # every row of it is dropped
+    _, fresh, _, _ = build(b1, o1)
+    og = ocs.grid(N, h)
+    kept = 0
+    for cell in og.cells_of_box(0, box):
+        got, want = plan.row(int(cell)), fresh.row(int(cell))
+        assert got == want, cell
+        kept += got[0] >= 0
+    assert kept == N  # one layer of the strip
+    assert all(plan.row(int(c))[0] == -1 for c in og.cells_of_box(0, outer_layer))
