@@ -76,6 +76,8 @@ extern "C" {
 
 /* plan flags */
 #define HBC_PLAN_HOST_ONLY 1u      /* compile and validate only; no device tables (no GPU needed) */
+#define HBC_PLAN_NO_WINDOWS 2u     /* serve sliding-window rows (see hbc_stats.rows_window) with the general
+                                      row kernel instead of the window kernel; results are bit-identical */
 
 /* cubed-sphere program modes */
 #define HBC_CS_SYNC 0              /* rotated halo copy of the neighbour's cell */
@@ -133,13 +135,18 @@ typedef struct {
   int64_t rows_wide;        /* CSR rows served by the LDS-staged wide-row kernel (point-major, >= 128-byte rows) */
   int64_t wide_tiles;       /* tiles of those rows */
   int64_t rows_narrow;      /* CSR rows of >= 8 entries and < 32 bytes served by the entry-splitting kernel */
+  int64_t rows_window;      /* 4-entry rows on four consecutive points of a grid line, each row's window at
+                               the previous row's or one point further (Sec. III-B interpolation rows of a
+                               face-edge strip), served by the window kernel: point-major, rows of >= 512
+                               bytes in whole 16-byte vectors; each wavefront loads a run's cells once */
+  int64_t window_runs;      /* runs of those rows (at most rows_per_tile rows each) */
 } hbc_stats;
 
 /* Launch shape of the apply kernels (chosen by the plan, changed by tuning). */
 typedef struct {
   int32_t block;            /* threads per workgroup: 64, 128, 192 or 256 */
   int32_t lanes_per_row;    /* power of two; lanes that share one row */
-  int32_t rows_per_tile;    /* rows per work tile */
+  int32_t rows_per_tile;    /* rows per work tile (sliding-window rows: rows per run, at most 16) */
   int32_t persistent;       /* 0: one workgroup per tile; >0: that many workgroups loop over tiles */
 } hbc_tune;
 
@@ -307,7 +314,10 @@ int hbc_plan_row(const hbc_plan* plan, int64_t ghost_cell, int64_t l, int32_t ca
 int hbc_plan_set_vector(hbc_plan* plan, int32_t sub_id, const double* values, void* stream);
 int hbc_plan_get_tune(const hbc_plan* plan, hbc_tune* out);
 /* Replace the launch shape (rebuilds the tile table).  Results are identical
- * for every valid shape. */
+ * for every valid shape.  Graphs captured from the plan before the call
+ * (hbc_graph_create) point at the old tile table: hbc_graph_launch refuses
+ * them afterwards (HBC_EINVAL) and they must be captured again; the same
+ * holds after hbc_plan_autotune. */
 int hbc_plan_set_tune(hbc_plan* plan, const hbc_tune* t);
 
 /* Try candidate launch shapes (workgroup size, lanes per row, rows per tile,
@@ -344,8 +354,10 @@ int hbc_time_apply(const hbc_plan* plan, void* const* fields, int64_t nelem, int
 /* Capture `reps` calls of `plan` (op HBC_OP_APPLY: hbc_apply; HBC_OP_ADJOINT:
  * hbc_apply_adjoint), cycling over the `nfields` device fields (each of
  * `nelem` values), into one HIP graph on `stream` (not NULL), for replay
- * without per-launch overhead.  The fields must stay alive while the graph
- * exists. */
+ * without per-launch overhead.  The fields and the plan must stay alive while
+ * the graph exists.  A later change of the plan's launch shape
+ * (hbc_plan_set_tune, hbc_plan_autotune) makes hbc_graph_launch return
+ * HBC_EINVAL without launching: capture the graph again. */
 #define HBC_OP_APPLY 0
 #define HBC_OP_ADJOINT 1
 typedef struct hbc_graph hbc_graph;
@@ -387,7 +399,10 @@ int hbc_batch_bind(hbc_batch* b, void* const* fields, const int64_t* nelem);
 /* One persistent launch applying every plan to its bound field. */
 int hbc_batch_apply(hbc_batch* b, void* stream);
 /* Capture one hbc_batch_apply into a HIP graph (re-captured on each call), then
- * hbc_batch_graph_launch replays it. */
+ * hbc_batch_graph_launch replays it.  hbc_batch_set_tune and
+ * hbc_batch_autotune drop the captured graph (the tile table it points at is
+ * replaced): hbc_batch_graph_launch then returns HBC_EINVAL until the next
+ * capture. */
 int hbc_batch_graph_capture(hbc_batch* b, void* stream);
 int hbc_batch_graph_launch(hbc_batch* b, void* stream);
 int hbc_batch_get_tune(const hbc_batch* b, hbc_tune* out);

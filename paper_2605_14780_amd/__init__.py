@@ -21,6 +21,7 @@ F64, F32 = 0, 1
 POINT_MAJOR, PLANE_MAJOR = 0, 1
 STRICT_COVER, ALLOW_OVERLAP_SUM = 1, 2
 PLAN_HOST_ONLY = 1
+PLAN_NO_WINDOWS = 2
 CS_SYNC, CS_LAGRANGE = 0, 1
 OP_APPLY, OP_ADJOINT = 0, 1
 
@@ -52,7 +53,8 @@ class StatsT(C.Structure):
         "rows_vector_only", "rows_with_b", "nnz", "unique_sources", "segments", "tiles", "ghost_values")] + [
         ("alg_bytes", C.c_double), ("alg_bytes_adjoint", C.c_double), ("table_bytes", C.c_int64),
         ("rows_data", C.c_int64), ("rows_dead", C.c_int64), ("ghost_cells_live", C.c_int64),
-        ("rows_wide", C.c_int64), ("wide_tiles", C.c_int64), ("rows_narrow", C.c_int64)]
+        ("rows_wide", C.c_int64), ("wide_tiles", C.c_int64), ("rows_narrow", C.c_int64),
+        ("rows_window", C.c_int64), ("window_runs", C.c_int64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -326,16 +328,18 @@ class Program:
 
 # ---- plan ------------------------------------------------------------------------------
 class Plan:
-    def __init__(self, program: Program, inner=1, order=POINT_MAJOR, vec=None, dtype=F64, host_only=False):
-        """vec = (lo, stride, len) of the two vector components' inner slots, or None."""
+    def __init__(self, program: Program, inner=1, order=POINT_MAJOR, vec=None, dtype=F64, host_only=False,
+                 windows=True):
+        """vec = (lo, stride, len) of the two vector components' inner slots, or None;
+        windows=False serves sliding-window rows with the general row kernel."""
         self._h = P()
         lay = LayoutT()
         lay.inner = inner
         lay.order = order
         if vec is not None:
             lay.vec_lo, lay.vec_stride, lay.vec_len = vec
-        _check(lib().hbc_plan_create(program._h, C.byref(lay), dtype, PLAN_HOST_ONLY if host_only else 0,
-                                     C.byref(self._h)))
+        flags = (PLAN_HOST_ONLY if host_only else 0) | (0 if windows else PLAN_NO_WINDOWS)
+        _check(lib().hbc_plan_create(program._h, C.byref(lay), dtype, flags, C.byref(self._h)))
         self.inner = inner
         self.order = order
         self.dtype = dtype

@@ -478,7 +478,7 @@ int hbc_plan_create(const hbc_program* prog, const hbc_layout* layout, int32_t d
   int rc = guard([&] {
     need(prog && layout && out, "NULL argument");
     need(dtype == HBC_F64 || dtype == HBC_F32, "dtype must be HBC_F64 or HBC_F32");
-    need((flags & ~HBC_PLAN_HOST_ONLY) == 0, "unknown plan flag");
+    need((flags & ~(HBC_PLAN_HOST_ONLY | HBC_PLAN_NO_WINDOWS)) == 0, "unknown plan flag");
     pl = new hbc_plan;
     Layout lay;
     lay.inner = layout->inner;

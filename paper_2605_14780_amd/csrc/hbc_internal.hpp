@@ -217,6 +217,24 @@ struct alignas(16) NarrowTile {
   int64_t brow;       // b table offset of the first row
 };
 
+// Sliding-window rows: 4-wide ELL segments (point-major, whole 16-byte
+// vectors, rows of at least WIN_MIN_BYTES) in which every row reads four
+// consecutive points of one grid line (the 4-point Lagrange rows of a
+// face-edge strip).  Their rows are cut, in device order, into runs of at
+// most rows_per_tile (<= WIN_MAXR) rows in which each row's window starts one
+// point further along the line than the previous row's: row r of a run reads
+// the cells src0 + (r + m) * dl, m < 4, so a run of R rows reads R + 3
+// distinct cells.  One wavefront takes a run and a slice of 64 16-byte
+// vectors of the inner values and loads each of the run's cells once.
+constexpr int WIN_MAXR = 16, WIN_MIN_BYTES = 512, WIN_DEFAULT_ROWS = 8;
+struct alignas(16) WinRun {
+  int32_t src0, dl, nrows, nsrc;
+  int64_t row_begin;  // first row in the per-row tables (row_dst)
+  int64_t tab;        // element offset of the first row's ELL entries
+  int64_t brow;       // b table offset of the first row (has_b)
+  int32_t rot, has_b, b_inner, pad_;
+};
+
 // Adjoint: one entry per (source cell, ghost row) contribution, sorted by
 // source cell then ghost cell.
 struct CscHost {
@@ -303,6 +321,10 @@ struct HostTables {
   // narrow wide rows (see NarrowTile); seg_narrow marks the segments they take
   std::vector<char> seg_narrow;
   std::vector<NarrowTile> ntiles;
+  // sliding-window rows (see WinRun); seg_win marks the segments they take
+  std::vector<char> seg_win;
+  std::vector<WinRun> wruns;
+  int32_t win_maxr = 0;  // longest run
   // data rows: destination cells, CSR over data cells (absolute pointers)
   std::vector<int32_t> dr_cell;
   std::vector<int64_t> dr_ptr;
@@ -368,6 +390,8 @@ struct Plan {
   const int32_t* d_w_rp = nullptr;
   const void* d_w_ent = nullptr;  // packed {weight, slot * values per slice} per entry
   const NarrowTile* d_ntiles = nullptr;
+  const WinRun* d_wruns = nullptr;  // in the tile allocation (depends on the launch shape)
+  uint64_t tile_gen = 0;            // bumped whenever the tile tables are rebuilt on the device
   const int32_t* d_dr_cell = nullptr;
   const int64_t* d_dr_ptr = nullptr;
   const int32_t* d_dr_col = nullptr;
@@ -413,6 +437,7 @@ struct Plan {
 void compile_plan(const Program& prog, const Layout& lay, int dtype, Plan& plan);
 void build_tiles(Plan& plan, const hbc_tune& t);
 hbc_tune default_tune(const Plan& plan);
+bool windows_possible(const Plan& plan);
 void build_csc(Plan& plan);
 void compute_stencil_info(Plan& plan);
 // new values for sub-vector sub_id: recomputes the b values it contributes

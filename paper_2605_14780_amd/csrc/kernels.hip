@@ -535,6 +535,107 @@ __device__ __forceinline__ void zero_row_tile(const PlanDesc& d, const RowTile& 
   }
 }
 
+// Lane k's value of a wavefront-uniform lane index k (v_readlane: no LDS).
+__device__ __forceinline__ int rdl(int v, int k) { return __builtin_amdgcn_readlane(v, k); }
+__device__ __forceinline__ float rdl(float v, int k) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+__device__ __forceinline__ double rdl(double v, int k) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(b & 0xffffffffll), k);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+  return __longlong_as_double(((long long)hi << 32) | lo);
+}
+
+// Sliding-window rows (WinRun): one wavefront per (run, slice of 64 16-byte
+// vectors).  Row r of a run reads cells r .. r + 3 of the run's window, so a
+// run of R rows reads R + 3 cells.  Lane k < R first reads row k's
+// destination and four weights; row r's values are then taken from lane r
+// with v_readlane.  Every load of the run (its cells, 1 KiB per wavefront
+// access) is issued before the first store: loads and stores share one
+// in-order counter on this architecture, so a load issued after a store
+// could not be waited for without also waiting for that store.  Rows are
+// then summed and stored in order, each as soon as its last cell arrives.
+// The sum is the general row path's (first product, then FMAs in entry
+// order, then the component sign, then b), so both give the same bits.
+// Workgroups past the window items write the plan's zero rows (ztiles), when
+// those are all its other rows.
+template <typename T, int V, bool NT, int RM>
+__global__ __launch_bounds__(256) void k_apply_win(PlanDesc d, const WinRun* __restrict__ runs, int nitems,
+                                                   int nslices, int zero_only, const RowTile* __restrict__ ztiles,
+                                                   int nz) {
+  const int nwin = (nitems + 3) >> 2;
+  if ((int)blockIdx.x >= nwin) {
+    for (int t = (int)blockIdx.x - nwin; t < nz; t += (int)gridDim.x - nwin) zero_row_tile<T>(d, ztiles[t]);
+    return;
+  }
+  // workgroups are dealt to the 8 XCDs round-robin: give each XCD a
+  // contiguous range of runs (neighbouring runs share three cells)
+  int b = (int)blockIdx.x;
+  {
+    const int q = nwin >> 3, rem = nwin & 7, x = b & 7, jx = b >> 3;
+    b = x * q + min(x, rem) + jx;
+  }
+  const int lane = (int)threadIdx.x & 63;
+  const int item = b * 4 + ((int)threadIdx.x >> 6);
+  if (item >= nitems) return;
+  const int ri = item / nslices, slc = item - ri * nslices;
+  const WinRun rn = runs[ri];
+  T* __restrict__ f = static_cast<T*>(d.field);
+  const int64_t nvec = d.inner / V;
+  const int64_t vi = (int64_t)slc * 64 + lane;
+  const bool ok = vi < nvec;
+  const int64_t l = (ok ? vi : 0) * V;  // lanes past the row's end repeat vector 0 and store nothing
+  T sign = T(1);
+  const int64_t sl = rot_slot<T>(d, rn.rot, l, sign);
+  const int R = rn.nrows;
+  int my_dst = 0;
+  T my_w[4] = {T(0), T(0), T(0), T(0)};
+  if (lane < R) {
+    my_dst = d.row_dst[rn.row_begin + lane];
+    const T* wp = static_cast<const T*>(d.ell_val) + rn.tab + 4 * lane;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) my_w[m] = wp[m];
+  }
+  if (zero_only) {
+    Pack<T, V> z;
+#pragma unroll
+    for (int i = 0; i < V; ++i) z.v[i] = T(0);
+#pragma unroll
+    for (int r = 0; r < RM; ++r)
+      if (r < R && ok) stv<T, V, NT>(f + (int64_t)rdl(my_dst, r) * d.cs + l, z);
+    return;
+  }
+  const int64_t step = (int64_t)rn.dl * d.cs;
+  const T* x0 = f + (int64_t)rn.src0 * d.cs + sl;
+  Pack<T, V> x[RM + 3];
+#pragma unroll
+  for (int j = 0; j < RM + 3; ++j)
+    if (j < R + 3) x[j] = ldv<T, V>(x0 + (int64_t)j * step);
+  const T* __restrict__ bt = static_cast<const T*>(d.bval) + rn.brow;
+#pragma unroll
+  for (int r = 0; r < RM; ++r) {
+    if (r < R) {
+      const T c0 = rdl(my_w[0], r), c1 = rdl(my_w[1], r), c2 = rdl(my_w[2], r), c3 = rdl(my_w[3], r);
+      Pack<T, V> y;
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        T a = c0 * x[r].v[i];
+        a = fma(c1, x[r + 1].v[i], a);
+        a = fma(c2, x[r + 2].v[i], a);
+        a = fma(c3, x[r + 3].v[i], a);
+        y.v[i] = sign * a;
+      }
+      if (rn.has_b) {
+        const T* bp = bt + (int64_t)r * rn.b_inner;
+#pragma unroll
+        for (int i = 0; i < V; ++i) y.v[i] = y.v[i] + (rn.b_inner == 1 ? bp[0] : bp[l + i]);
+      }
+      if (ok) stv<T, V, NT>(f + (int64_t)rdl(my_dst, r) * d.cs + l, y);
+    }
+  }
+}
+
 // One entry of a wide tile: its weight and the LDS offset (in values) of its
 // source cell's staged slice, read with one LDS instruction.
 template <typename T>
@@ -1699,17 +1800,24 @@ void device_upload_tiles(Plan& p) {
   if (p.d_tiles) HIP_CHECK(hipFree(const_cast<DevTile*>(p.d_tiles)));
   p.d_tiles = nullptr;
   p.d_rtiles = nullptr;
+  p.d_wruns = nullptr;
+  ++p.tile_gen;  // graphs captured before this point hold the old tables
   const size_t n1 = align256(std::max<size_t>(1, p.host.tiles.size()) * sizeof(DevTile));
-  const size_t n2 = std::max<size_t>(1, p.host.rtiles.size()) * sizeof(RowTile);
+  const size_t n2 = align256(std::max<size_t>(1, p.host.rtiles.size()) * sizeof(RowTile));
+  const size_t n3 = std::max<size_t>(1, p.host.wruns.size()) * sizeof(WinRun);
   void* t = nullptr;
-  HIP_CHECK(hipMalloc(&t, n1 + n2));
+  HIP_CHECK(hipMalloc(&t, n1 + n2 + n3));
   if (!p.host.tiles.empty())
     HIP_CHECK(hipMemcpy(t, p.host.tiles.data(), p.host.tiles.size() * sizeof(DevTile), hipMemcpyHostToDevice));
   if (!p.host.rtiles.empty())
     HIP_CHECK(hipMemcpy(static_cast<char*>(t) + n1, p.host.rtiles.data(), p.host.rtiles.size() * sizeof(RowTile),
                         hipMemcpyHostToDevice));
+  if (!p.host.wruns.empty())
+    HIP_CHECK(hipMemcpy(static_cast<char*>(t) + n1 + n2, p.host.wruns.data(), p.host.wruns.size() * sizeof(WinRun),
+                        hipMemcpyHostToDevice));
   p.d_tiles = static_cast<const DevTile*>(t);
   p.d_rtiles = reinterpret_cast<const RowTile*>(static_cast<char*>(t) + n1);
+  p.d_wruns = reinterpret_cast<const WinRun*>(static_cast<char*>(t) + n1 + n2);
 }
 
 void device_upload_csc(Plan& p) {
@@ -1857,6 +1965,38 @@ static void launch_wide(const Plan& p, const PlanDesc& d, hipStream_t st, bool z
   HIP_CHECK(hipGetLastError());
 }
 
+// Sliding-window runs: one wavefront per (run, slice of 64 vectors), four
+// per workgroup; nz zero-row tiles ride in extra workgroups.
+template <typename T>
+static void launch_win(const Plan& p, const PlanDesc& d, hipStream_t st, bool zero_only, int nz) {
+  constexpr int V = 16 / (int)sizeof(T);
+  const int64_t nvec = p.layout.inner / V;
+  const int64_t nsl = (nvec + 63) / 64;
+  const int64_t nitems = (int64_t)p.host.wruns.size() * nsl;
+  if (nitems >= (int64_t(1) << 30)) fail(HBC_EUNSUPPORTED, "too many window runs for one launch");
+  const int nwin = (int)((nitems + 3) / 4);
+  const dim3 g((unsigned)(nwin + nz)), b(256);
+  const int z = zero_only ? 1 : 0;
+  const int rm = p.host.win_maxr;  // longest run: the smallest instance that holds it
+#define HBC_WIN(RM)                                                                                               \
+  do {                                                                                                              \
+    if (d.nt)                                                                                                       \
+      hipLaunchKernelGGL((k_apply_win<T, V, true, RM>), g, b, 0, st, d, p.d_wruns, (int)nitems, (int)nsl, z,         \
+                         p.d_rtiles, nz);                                                                          \
+    else                                                                                                            \
+      hipLaunchKernelGGL((k_apply_win<T, V, false, RM>), g, b, 0, st, d, p.d_wruns, (int)nitems, (int)nsl, z,        \
+                         p.d_rtiles, nz);                                                                          \
+  } while (0)
+  if (rm <= 4)
+    HBC_WIN(4);
+  else if (rm <= 8)
+    HBC_WIN(8);
+  else
+    HBC_WIN(16);
+#undef HBC_WIN
+  HIP_CHECK(hipGetLastError());
+}
+
 template <typename T>
 static void launch_apply_t(const Plan& p, const PlanDesc& d, hipStream_t st, bool zero_only) {
   const bool pm = p.layout.order == HBC_POINT_MAJOR;
@@ -1871,10 +2011,11 @@ static void launch_apply_t(const Plan& p, const PlanDesc& d, hipStream_t st, boo
     dd.nrows = (int32_t)p.stats.rows_data;
     dd.grid = (int32_t)std::min<int64_t>((p.stats.rows_data + groups - 1) / groups, 4096);
   }
-  // fold the row tiles into the first wide-row launch when they are all zero
-  // rows without b (the corners of the cubed-sphere quadrature programs)
+  // fold the row tiles into the first wide-row or window launch when they are
+  // all zero rows without b (the corners of the cubed-sphere programs)
   const bool has_narrow = pm && !p.host.ntiles.empty(), has_wide = pm && !p.host.wtiles.empty();
-  bool fold = (has_narrow || has_wide) && dd.grid == 0 && nt > 0;
+  const bool has_win = pm && !p.host.wruns.empty();
+  bool fold = (has_narrow || has_wide || has_win) && dd.grid == 0 && nt > 0;
   for (size_t k = 0; fold && k < p.host.rtiles.size(); ++k)
     fold = p.host.rtiles[k].kind == SEG_ZERO && !p.host.rtiles[k].has_b;
   if (has_narrow) {
@@ -1901,6 +2042,7 @@ static void launch_apply_t(const Plan& p, const PlanDesc& d, hipStream_t st, boo
         launch_wide<T, 1, WIDE_ROW_BYTES>(p, d, st, zero_only, nz);
     }
   }
+  if (has_win) launch_win<T>(p, d, st, zero_only, fold && !has_narrow && !has_wide ? nt : 0);
   if (fold || grid + dd.grid == 0) return;
   if (!pm) {
     if (grid > 0) hipLaunchKernelGGL((k_apply_pm<T>), dim3(grid), dim3(blk), 0, st, d, p.d_tiles, nt, z);
@@ -2130,11 +2272,15 @@ double device_time_apply(const Plan& p, void* const* fields, int nfields, int re
 struct ApplyGraph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  const Plan* plan = nullptr;
+  uint64_t gen = 0;  // the plan's tile generation at capture
 };
 
 void* device_graph_create(const Plan& p, int op, void* const* fields, int nfields, int reps, void* stream) {
   if (!stream) fail(HBC_EINVAL, "graph capture needs a stream");
   auto* g = new ApplyGraph;
+  g->plan = &p;
+  g->gen = p.tile_gen;
   hipStream_t s = S(stream);
   hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) {
@@ -2165,6 +2311,9 @@ void* device_graph_create(const Plan& p, int op, void* const* fields, int nfield
 
 void device_graph_launch(void* gp, void* stream) {
   auto* g = static_cast<ApplyGraph*>(gp);
+  if (g->plan->tile_gen != g->gen)
+    fail(HBC_EINVAL, "the plan's launch shape changed after this graph was captured (tuning rebuilds the tile "
+                     "tables the graph points at); capture it again");
   HIP_CHECK(hipGraphLaunch(g->exec, S(stream)));
 }
 
@@ -2236,6 +2385,11 @@ static void batch_tiles(Batch* b) {
         more = 1;
       }
   }
+  // the captured graph (if any) points at the old tile table
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
   if (b->d_tiles) HIP_CHECK(hipFree(b->d_tiles));
   b->d_tiles = nullptr;
   HIP_CHECK(hipMalloc(&b->d_tiles, std::max<size_t>(1, b->tiles.size()) * sizeof(RowTile)));
@@ -2429,7 +2583,8 @@ static std::string plan_key(const Plan& p) {
   std::ostringstream k;
   k << prop.gcnArchName << "|plan|" << (p.dtype == HBC_F64 ? "f64" : "f32") << "|"
     << (p.layout.order == HBC_POINT_MAJOR ? "point" : "plane") << "|" << p.layout.inner << "|" << p.vec << "|"
-    << p.stats.rows_covered << "|" << p.stats.segments << "|" << p.stats.nnz << "|" << p.stats.rows_data;
+    << p.stats.rows_covered << "|" << p.stats.segments << "|" << p.stats.nnz << "|" << p.stats.rows_data << "|w"
+    << (windows_possible(p) ? 1 : 0);
   std::string s = k.str();
   for (char& c : s)
     if (c == '"' || c == '\\') c = '_';
@@ -2463,13 +2618,23 @@ double device_plan_autotune(Plan& p, void* const* fields, int nfields, const cha
   HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   const hbc_tune def = default_tune(p);
   std::vector<hbc_tune> cand;
-  for (int bl : {128, 256})
-    for (int lf : {1, 2}) {
-      const int lpr = std::max(1, std::min(bl, def.lanes_per_row / lf));
-      const int rp = bl / lpr;
-      for (int m : {1, 2, 4, 8})
-        for (int pf : {0, 4}) cand.push_back(hbc_tune{bl, lpr, rp * m, pf * ncu});
+  if (p.stats.rows_window > 0) {
+    // window plans: the run length (a run's three extra cells against the
+    // number of wavefronts in flight)
+    for (int r : {4, 6, 8, 12, 16}) {
+      hbc_tune t = def;
+      t.rows_per_tile = r;
+      cand.push_back(t);
     }
+  } else {
+    for (int bl : {128, 256})
+      for (int lf : {1, 2}) {
+        const int lpr = std::max(1, std::min(bl, def.lanes_per_row / lf));
+        const int rp = bl / lpr;
+        for (int m : {1, 2, 4, 8})
+          for (int pf : {0, 4}) cand.push_back(hbc_tune{bl, lpr, rp * m, pf * ncu});
+      }
+  }
   cand.push_back(def);
   hbc_tune best = def;
   double best_ms = 1e30;

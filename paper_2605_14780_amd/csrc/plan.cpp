@@ -748,6 +748,19 @@ static int64_t pow2_ceil(int64_t v) {
   return p;
 }
 
+// Whether build_windows can take a segment of the plan (its per-segment
+// checks aside): point-major, whole 16-byte vectors, rows of >= WIN_MIN_BYTES,
+// a 4-wide ELL segment without padding.
+bool windows_possible(const Plan& plan) {
+  const Layout& L = plan.layout;
+  const int64_t es = plan.dtype == HBC_F64 ? 8 : 4;
+  if (L.order != HBC_POINT_MAJOR || (plan.flags & HBC_PLAN_NO_WINDOWS) || plan.stats.rows_data > 0) return false;
+  if (plan.vec * es != 16 || L.inner * es < WIN_MIN_BYTES) return false;
+  for (const DevSeg& sg : plan.host.segs)
+    if (sg.kind == SEG_ELL && sg.width == 4 && !(sg.flags & SEGF_ELL_PADDED) && sg.nrows > 0) return true;
+  return false;
+}
+
 hbc_tune default_tune(const Plan& plan) {
   hbc_tune t{};
   t.block = 256;
@@ -779,6 +792,7 @@ hbc_tune default_tune(const Plan& plan) {
     rpt = ((rpt + rows_per_pass - 1) / rows_per_pass) * rows_per_pass;
   }
   rpt = std::min<int64_t>(rpt, 16384);
+  if (windows_possible(plan)) rpt = WIN_DEFAULT_ROWS;  // rows per sliding-window run
   t.rows_per_tile = (int32_t)rpt;
   return t;
 }
@@ -922,6 +936,64 @@ static void build_narrow(Plan& plan) {
   }
 }
 
+// Sliding-window runs (see WinRun).  A segment qualifies when every row is a
+// window (four cells c, c + dl, c + 2 dl, c + 3 dl, dl != 0).  Its rows are
+// cut, in device order, into runs of at most rmax rows in which each row's
+// window starts one cell further along the same line than the previous
+// row's; a new run starts where that fails (at the next ghost layer of a
+// strip, or where two neighbouring ghosts share a stencil).  Rows of other
+// segments keep the row tiles.
+static void build_windows(Plan& plan, int rmax) {
+  HostTables& T = plan.host;
+  T.seg_win.assign(T.segs.size(), 0);
+  T.wruns.clear();
+  T.win_maxr = 0;
+  plan.stats.rows_window = plan.stats.window_runs = 0;
+  if (!windows_possible(plan)) return;
+  rmax = std::max(1, std::min(rmax, WIN_MAXR));
+  for (size_t si = 0; si < T.segs.size(); ++si) {
+    const DevSeg& sg = T.segs[si];
+    if (sg.kind != SEG_ELL || sg.width != 4 || (sg.flags & SEGF_ELL_PADDED) || sg.nrows == 0) continue;
+    if (T.seg_wide.size() == T.segs.size() && T.seg_wide[si]) continue;
+    const int32_t* c = T.ell_col.data() + sg.tab;
+    auto dl_of = [&](int64_t r) { return (int64_t)c[4 * r + 1] - c[4 * r]; };
+    bool ok = true;
+    for (int64_t r = 0; r < sg.nrows && ok; ++r) {
+      const int64_t dl = dl_of(r);
+      ok = dl != 0 && dl > INT32_MIN && dl < INT32_MAX;
+      for (int m = 2; m < 4 && ok; ++m) ok = (int64_t)c[4 * r + m] - c[4 * r] == m * dl;
+    }
+    if (!ok) continue;
+    T.seg_win[si] = 1;
+    int64_t r0 = 0;
+    while (r0 < sg.nrows) {
+      const int64_t dl = dl_of(r0);
+      int64_t n = 1;
+      while (r0 + n < sg.nrows && n < rmax) {
+        const int64_t r = r0 + n;
+        if (dl_of(r) != dl || (int64_t)c[4 * r] - c[4 * (r - 1)] != dl) break;
+        ++n;
+      }
+      WinRun w{};
+      w.src0 = c[4 * r0];
+      w.dl = (int32_t)dl;
+      w.nrows = (int32_t)n;
+      w.nsrc = (int32_t)(n + 3);
+      w.row_begin = sg.row_base + r0;
+      w.tab = sg.tab + 4 * r0;
+      w.brow = sg.brow + r0 * sg.b_inner;
+      w.rot = sg.rot;
+      w.has_b = sg.has_b;
+      w.b_inner = sg.b_inner;
+      T.wruns.push_back(w);
+      T.win_maxr = std::max<int32_t>(T.win_maxr, (int32_t)n);
+      r0 += n;
+    }
+    plan.stats.rows_window += sg.nrows;
+  }
+  plan.stats.window_runs = (int64_t)T.wruns.size();
+}
+
 void build_tiles(Plan& plan, const hbc_tune& t) {
   if (t.block < 64 || t.block > 256 || t.block % 64) fail(HBC_EINVAL, "block must be 64, 128, 192 or 256");
   if (t.lanes_per_row < 1 || (t.lanes_per_row & (t.lanes_per_row - 1)) || t.lanes_per_row > t.block)
@@ -962,9 +1034,11 @@ void build_tiles(Plan& plan, const hbc_tune& t) {
   plan.host.rtiles.clear();
   if (plan.host.seg_wide.size() != plan.host.segs.size()) build_wide(plan);
   if (plan.host.seg_narrow.size() != plan.host.segs.size()) build_narrow(plan);
+  build_windows(plan, t.rows_per_tile);
   for (const DevTile& tl : plan.host.tiles) {
     const DevSeg& sg = plan.host.segs[tl.seg];
     if (plan.host.seg_wide[tl.seg] || plan.host.seg_narrow[tl.seg]) continue;  // served by the wide-row kernels
+    if (plan.host.seg_win[tl.seg]) continue;                                     // served by the window kernel
     RowTile rt{};
     rt.kind = sg.kind;
     rt.rot = sg.rot;
