@@ -3,9 +3,13 @@
 * C384, halo 3, 256 inner values (4 fields x 64 levels, (u, v) rotated),
   FP64, after the autotuner has picked the launch shape: sampled ghost rows
   (all 256 values of each; edge strips and corners) against the rows the
-  oracle evaluates one by one from the geometry;
+  oracle evaluates one by one from the geometry (arithmetic bound plus the
+  position bound of the library's FP64 weights); and every ghost of the
+  program built from the oracle's own weights at the plain arithmetic bound;
 * C768, halo 3, 32 levels, with a sub-vector b on every side: the adjoint
-  against the forward through the dot-product identity;
+  against the forward through the dot-product identity, and sampled source
+  rows of A^T y against the oracle's (FP64 and FP32); finite differences of
+  a loss through one linearised shallow-water RK4 step with (h, u, v);
 * C384 wide interpolation rows (16..25 entries, LDS-staged kernel): sampled
   rows against the oracle's;
 * the 64-grid FP32 batch in its autotuned graph launch: bit identity with
@@ -15,7 +19,9 @@ import numpy as np
 import pytest
 
 import synthinputs
-from helpers import gpu_available
+from helpers import (DS_ULPS, gpu_available, lagrange_dw, lagrange_tolerance, oracle_lagrange_rows,
+                     oracle_weights_program, ulp_n)
+from oracle import apply as o_apply, assemble
 from oracle import cubed_sphere as ocs
 
 pytestmark = [pytest.mark.gpu]
@@ -74,11 +80,14 @@ def test_c384_sampled_rows_tuned_shape(tmp_path, dtype):
         ref = y.copy()
         ref[u_sl] = R[0, 0] * y[u_sl] + R[0, 1] * y[v_sl]
         ref[v_sl] = R[1, 0] * y[u_sl] + R[1, 1] * y[v_sl]
-        # arithmetic: 1e-13 of sum |w x|; position: the fractional index is
-        # known to ~8 N eps and the weights' slopes stay below 4
-        ax = np.abs(X).sum(axis=0)
+        # arithmetic: 1e-13 of sum |w x|; position: the library's s is held
+        # to DS_ULPS ulp(N) of the oracle's, which moves the value by that
+        # times sum |dw/ds| |x| (nodes as the oracle orders them)
+        _, _, _, s_or = ocs.neighbour_line(f, j, i, N)
+        base, _, s_or = ocs.lagrange_weights(s_or, N)
+        dw = np.abs(np.array(lagrange_dw(s_or, base)))
         wx = np.abs(w) @ np.abs(X)
-        bnd = 1e-13 * np.maximum(wx, 1e-300) + 8 * N * U64 * 4 * ax
+        bnd = 1e-13 * np.maximum(wx, 1e-300) + DS_ULPS * ulp_n(N) * (dw @ np.abs(X))
         if dt == hb.F32:  # weight rounding (1 ulp each) and four FP32 roundings of the sum
             bnd = bnd + 8 * 2.0 ** -24 * wx
         bnd_rot = bnd.copy()
@@ -87,6 +96,134 @@ def test_c384_sampled_rows_tuned_shape(tmp_path, dtype):
         assert (np.abs(got - ref) <= bnd_rot).all(), (f, j, i)
         rows += 1
     assert corners > 0
+
+
+def test_c384_oracle_weights_every_ghost_plain_bound(tmp_path):
+    """The kernel's arithmetic on the full C384 x 256 FP64 field ((u, v)
+    rotated, SH fields + N(0, 1e-3) noise, 9 cold copies for the autotuner):
+    the program carries the oracle's own columns and weights, so every ghost
+    value must lie within the plain bound 1e-13 * max(|ref|, sum |w x|)."""
+    from helpers import cs_full_field
+    N, h, nf, nl = 384, 3, 4, 64
+    I = nf * nl
+    vec = (2 * nl, nl, nl)
+    grid, prog = oracle_weights_program(hb, N, h, True)
+    plan = hb.Plan(prog, inner=I, vec=vec, dtype=hb.F64)
+    st = plan.stats()
+    assert st["rows_window"] == st["rows_ell"] == 24 * h * N
+    full = cs_full_field(N, h, nf, nl, seed=2, noise=1e-3)
+    x = torch.from_numpy(full).cuda()
+    plan.autotune([x.clone() for _ in range(3)], str(tmp_path / "tune.jsonl"))
+    out = x.clone()
+    hb.apply(plan, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    del out, x
+    og = ocs.grid(N, h)
+    ref = o_apply(assemble(og, ocs.subs(N, h, "lagrange", vector=True)), full, vec)
+    G, Dc = og.ghost_cells, og.data_cells
+    assert np.array_equal(got[Dc], full[Dc])
+    tol = lagrange_tolerance(N, h, full, ref, vec, ds=0.0)
+    ratio = np.abs(got[G] - ref[G]) / np.maximum(tol, 1e-300)
+    assert ratio.max() <= 1.0, (float(ratio.max()), plan.tune)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_c768_adjoint_sampled_source_rows(dtype):
+    """The adjoint at C768, halo 3, 32 levels (b on every ghost, as the bench
+    runs it), in the bench's launch, element by element on sampled source
+    rows against the oracle's VJP: xbar_j = ybar_j + sum_i A_ij ybar_i over the
+    ghost rows i that read j, with A the oracle's own rows (the program carries
+    them, so only the sums differ).  FP64: 1e-13 of the sum of magnitudes;
+    FP32 (weights rounded to FP32, FP32 sums of at most 12 terms): 16 FP32
+    roundings of it.  Covered ghosts end at +0."""
+    N, h, L = 768, 3, 32
+    W = N + 2 * h
+    rows = oracle_lagrange_rows(N, h)
+    rng = np.random.default_rng(5)
+    b = []
+    for f in range(6):
+        for side in (ocs.LEFT, ocs.RIGHT, ocs.BOTTOM, ocs.TOP):
+            b.append((ocs.side_box(f, side, N, h), rng.normal(size=(N * h, L))))
+        for box in ocs.corner_boxes(f, N, h):
+            b.append((box, rng.normal(size=(h * h, L))))
+    grid, prog = oracle_weights_program(hb, N, h, False, rows=rows, b=b)
+    dt, tdt, eps, k = (hb.F64, torch.float64, 2.0 ** -53, 1e-13 / 2.0 ** -53) if dtype == "f64" else \
+        (hb.F32, torch.float32, 2.0 ** -24, 16.0)
+    plan = hb.Plan(prog, inner=L, dtype=dt)
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    y = torch.randn(grid.cells * L, dtype=tdt, device="cuda", generator=gen)
+    aty = y.clone()
+    hb.apply_adjoint(plan, aty)
+    torch.cuda.synchronize()
+    ybar = y.view(-1, L).cpu().numpy().astype(np.float64)
+    got = aty.view(-1, L).cpu().numpy().astype(np.float64)
+    # the transpose of the oracle's rows: source cell -> [(ghost cell, weight)]
+    cols = {}
+    for (f, side), (box, ents) in rows.items():
+        r = 0
+        for j in range(*box[1]):
+            for i in range(*box[2]):
+                gcell = (f * W + (j + h)) * W + (i + h)
+                for (gg, jj, ii), wv in ents[r]:
+                    wv = float(np.float32(wv)) if dt == hb.F32 else wv
+                    cols.setdefault((gg * W + (jj + h)) * W + (ii + h), []).append((gcell, wv))
+                r += 1
+    srcs = np.array(sorted(cols))
+    pick = rng.choice(srcs, size=3000, replace=False)
+    for c in pick:
+        ents = cols[int(c)]
+        gi = np.array([g for g, _ in ents])
+        wv = np.array([w for _, w in ents])
+        ref = ybar[c] + wv @ ybar[gi]
+        mag = np.abs(ybar[c]) + np.abs(wv) @ np.abs(ybar[gi])
+        assert (np.abs(got[c] - ref) <= k * eps * mag).all(), (int(c), len(ents))
+    # data cells no ghost reads keep their gradient; covered ghosts are +0
+    interior = (3 * W + (N // 2 + h)) * W + (N // 2 + h)
+    assert interior not in cols and np.array_equal(got[interior], ybar[interior])
+    G = np.ones((6, W, W), dtype=bool)
+    G[:, h:h + N, h:h + N] = False
+    gg = got.reshape(6, W, W, L)[G]
+    assert (gg == 0).all() and not np.signbit(gg).any()
+
+
+def test_c768_fd_linearised_swe_step_hUV():
+    """Finite differences of a loss through one linearised shallow-water RK4
+    step at C768, halo 3, 32 levels with (h, u, v) (u, v rotated across faces,
+    b on one side), the BC applied before every stage through bc_apply: the
+    step is affine in the state, so the centred difference with eps = 1 is
+    exact up to rounding and must equal <grad, d> to 1e-12 of the sums'
+    magnitudes."""
+    from swe import make_step
+    N, h, L = 768, 3, 32
+    I = 3 * L
+    W = N + 2 * h
+    grid, prog = hb.cs_program(N, h, hb.CS_LAGRANGE, vector=True)
+    rng = np.random.default_rng(11)
+    prog.add_vector(ocs.side_box(2, ocs.TOP, N, h), rng.standard_normal((N * h, I)), ninner=I)
+    plan = hb.Plan(prog, inner=I, vec=(L, L, L))
+    step = make_step(lambda t: hb.bc_apply(plan, t), N, h, L, dx=np.pi / (2 * N), dt=0.2 * np.pi / (2 * N))
+    u0 = torch.zeros((6, W, W, I), dtype=torch.float64, device="cuda")
+    u0[:, h:h + N, h:h + N] = synthinputs.cs_sh_field_torch(N, 3, L, seed=12, device="cuda")
+    u0 = u0.reshape(-1, I)
+    gen = torch.Generator("cuda").manual_seed(1)
+    wgt = torch.randn(grid.cells, I, dtype=torch.float64, device="cuda", generator=gen)
+    d = torch.randn(grid.cells, I, dtype=torch.float64, device="cuda", generator=gen)
+
+    def loss(u):
+        return (step(u) * wgt).sum()
+
+    u = u0.clone().requires_grad_(True)
+    loss(u).backward()
+    gd = float((u.grad * d).sum())
+    mag_g = float((u.grad * d).abs().sum())
+    del u
+    with torch.no_grad():
+        lp, lm = step(u0 + d) * wgt, step(u0 - d) * wgt
+        fd = (float(lp.sum()) - float(lm.sum())) / 2.0
+        mag_f = (float(lp.abs().sum()) + float(lm.abs().sum())) / 2.0
+    assert abs(fd - gd) <= 1e-12 * (mag_g + mag_f), (fd, gd, mag_g, mag_f)
+    assert abs(gd) > 1e-9 * mag_g
 
 
 def test_c768_adjoint_dot_product():

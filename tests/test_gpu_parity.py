@@ -1,8 +1,11 @@
 """GPU parity of the BC apply against the CPU oracle, through the C ABI.
 
-Bar: copies, rotations and zero padding bit-exact (+0.0 for zeros);
-FP64 interpolated ghosts within 1e-13 * max(|ref|, sum_m |w_m x_m|) per value;
-data cells never written; NaN-poisoned ghosts all overwritten.
+Bar: copies, rotations and zero padding bit-exact (+0.0 for zeros); FP64
+interpolated ghosts within 1e-13 * max(|ref|, sum_m |w_m x_m|) per value when
+the library applies the oracle's own weights (the kernel's arithmetic), and
+the library's FP64 weights within DS_ULPS ulp(N) of the oracle's position s
+(the geometry); end to end, the sum of the two.  Data cells never written;
+NaN-poisoned ghosts all overwritten.
 """
 import math
 
@@ -10,7 +13,8 @@ import numpy as np
 import pytest
 
 import synthinputs
-from helpers import cs_full_field, gpu_available, lagrange_tolerance, normwise_error
+from helpers import (DS_ULPS, cs_full_field, gpu_available, lagrange_dw, lagrange_tolerance, normwise_error,
+                     oracle_weights_program, ulp_n)
 from oracle import apply as o_apply, assemble, vjp as o_vjp
 from oracle import cubed_sphere as ocs
 from oracle import hpcg as ohpcg
@@ -86,6 +90,13 @@ def test_cs_plane_major(mode):
     check_cs(12, 3, 4, 2, mode, True, order=hb.PLANE_MAJOR)
 
 
+def weight_bound(s, base, N):
+    """|w_gpu - w_oracle| allowed per node: the position s held to DS_ULPS
+    ulp(N) moves w_m by at most that times |dw_m/ds|; 16 eps for the roundings
+    of the weight formula on either side."""
+    return [DS_ULPS * ulp_n(N) * abs(dw) + 16 * 2.0 ** -53 for dw in lagrange_dw(s, base)]
+
+
 def test_cs_weights_match_oracle():
     for N, h in [(8, 3), (13, 3), (48, 3), (384, 3), (768, 4)]:
         base, w = hb.cs_lagrange_weights(N, h)
@@ -96,14 +107,77 @@ def test_cs_weights_match_oracle():
         for k in range(h):
             for t in range(N):
                 g, axis, L, s = ocs.neighbour_line(0, t, N + k, N)
-                ob, ow, _ = ocs.lagrange_weights(s, N)
+                ob, ow, s = ocs.lagrange_weights(s, N)
                 if abs(s - round(s)) > 1e-9:
                     assert base[k, t] == ob, (N, k, t)
-                    # weights agree to within N * eps (s itself carries that error)
-                    assert np.abs(w[k, t] - np.array(ow)).max() <= 64 * N * 2.0 ** -53, (N, k, t)
+                    bnd = weight_bound(s, ob, N)
+                    assert (np.abs(w[k, t] - np.array(ow)) <= bnd).all(), (N, k, t)
                 else:
                     node = int(round(s))
                     assert w[k, t][node - base[k, t]] == 1.0
+
+
+@pytest.mark.parametrize("N,h", [(8, 3), (13, 3), (48, 3), (384, 3), (768, 3)])
+def test_cs_weights_in_plan_match_oracle_all_sides(N, h):
+    """The weights the library builds on the GPU, as they land in the compiled
+    plan on every one of the 24 face sides (orientation tables included):
+    columns identical to the oracle's, weights within the position bound."""
+    grid, prog = hb.cs_program(N, h, hb.CS_LAGRANGE)
+    plan = hb.Plan(prog, inner=1, host_only=False)
+    W = N + 2 * h
+    worst = 0.0
+    for f in range(6):
+        for side in (ocs.LEFT, ocs.RIGHT, ocs.BOTTOM, ocs.TOP):
+            box = ocs.side_box(f, side, N, h)
+            for j in range(*box[1]):
+                for i in range(*box[2]):
+                    kind, cols, vals, b, rot = plan.row((f * W + (j + h)) * W + (i + h))
+                    g, axis, L, s = ocs.neighbour_line(f, j, i, N)
+                    ob, ow, s = ocs.lagrange_weights(s, N)
+                    node = (lambda m: (g, m, L)) if axis == "i" else (lambda m: (g, L, m))
+                    cell = [(gg * W + (jj + h)) * W + (ii + h) for gg, jj, ii in (node(ob + m) for m in range(4))]
+                    got = dict(zip(cols, vals))
+                    assert kind == 2 and len(cols) == 4, (f, j, i, kind)
+                    if abs(s - round(s)) <= 1e-9:
+                        # snapped to a node (R7): weight 1 there, 0 elsewhere; on a
+                        # side whose index runs against the neighbour's, the stencil
+                        # is the other one of the two around that node (same value)
+                        nz = {c: v for c, v in got.items() if v != 0}
+                        assert nz == {cell[list(ow).index(1.0)]: 1.0}, (f, j, i, got)
+                        continue
+                    assert set(got) == set(cell), (f, j, i)
+                    bnd = weight_bound(s, ob, N)
+                    dw = lagrange_dw(s, ob)
+                    for m in range(4):
+                        err = abs(got[cell[m]] - ow[m])
+                        assert err <= bnd[m], (f, j, i, m, err, bnd[m])
+                        if abs(dw[m]) > 0.1:
+                            worst = max(worst, err / abs(dw[m]) / ulp_n(N))
+    print(f"C{N}: largest implied position difference {worst:.2f} ulp(N)")
+
+
+@pytest.mark.parametrize("N,h,nf,nl,vector", [(48, 3, 4, 8, True), (48, 3, 4, 16, True), (48, 3, 1, 1, False),
+                                              (13, 2, 4, 3, True), (5, 2, 1, 2, False), (96, 3, 4, 64, True)])
+def test_cs_lagrange_kernel_arithmetic_plain_bound(N, h, nf, nl, vector):
+    """The kernel's arithmetic alone, held to the plain bound
+    1e-13 * max(|ref|, sum_m |w_m x_m|) with no position term: the program
+    carries the oracle's own columns and weights (add_ell, one sub-matrix per
+    face side with its rotation), so the library and the oracle apply the same
+    A and differ only in the rounding of the sums.  Rows of 512 bytes and more
+    run the window kernel, shorter ones the row kernel."""
+    I = nf * nl
+    vec = (2 * nl, nl, nl) if vector else None
+    grid, prog = oracle_weights_program(hb, N, h, vector)
+    plan = hb.Plan(prog, inner=I, vec=vec)
+    full = cs_full_field(N, h, nf, nl, seed=1, noise=1e-3)
+    got = run_apply(plan, full)
+    og = ocs.grid(N, h)
+    ref = o_apply(assemble(og, ocs.subs(N, h, "lagrange", vector=vector)), full, vec)
+    G, Dc = og.ghost_cells, og.data_cells
+    assert np.array_equal(got[Dc], full[Dc])
+    tol = lagrange_tolerance(N, h, full, ref, vec, ds=0.0)
+    diff = np.abs(got[G] - ref[G])
+    assert (diff <= tol).all(), float((diff / np.maximum(tol, 1e-300)).max())
 
 
 def test_unit_vector_probing_recovers_A():
