@@ -346,6 +346,18 @@ int hbc_apply(const hbc_plan* plan, void* field, int64_t nelem, void* stream);
  * The first call builds the transposed tables (allocates; not inside graph
  * capture: hbc_graph_create with HBC_OP_ADJOINT builds them first). */
 int hbc_apply_adjoint(const hbc_plan* plan, void* grad, int64_t nelem, void* stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the adjoint
+ * of hbc_apply_adjoint, with the same result bit for bit, that allocates
+ * nothing.  Its reader counters live in one static device array of 2^20
+ * int32 (4 MiB) per GPU, held until the process ends; every call starts them
+ * at their reader counts with a small copy kernel on `stream`, so calls on
+ * one GPU must not overlap in time (whatever their plans), and they race with
+ * each other if they do.  Needs the plan's transposed tables, which the first
+ * hbc_apply_adjoint or hbc_graph_create(HBC_OP_ADJOINT) builds (HBC_EINVAL
+ * otherwise), and at most 2^20 counters (HBC_EINVAL beyond; hbc_apply_adjoint
+ * has no such limit). */
+int hbc_apply_adjoint_noalloc(const hbc_plan* plan, void* grad, int64_t nelem, void* stream);
 /* Time `reps` applies captured in one HIP graph on `stream`; *ms receives the
  * mean milliseconds per apply (device events around the graph launch). */
 int hbc_time_apply(const hbc_plan* plan, void* const* fields, int64_t nelem, int32_t nfields, int32_t reps,

@@ -107,6 +107,7 @@ SIGNATURES = {
     "hbc_plan_autotune": (I32, [P, C.POINTER(P), I64, I32, C.c_char_p, P, PD]),
     "hbc_apply": (I32, [P, P, I64, P]),
     "hbc_apply_adjoint": (I32, [P, P, I64, P]),
+    "hbc_apply_adjoint_noalloc": (I32, [P, P, I64, P]),
     "hbc_time_apply": (I32, [P, C.POINTER(P), I64, I32, I32, P, PD]),
     "hbc_graph_create": (I32, [P, I32, C.POINTER(P), I64, I32, I32, P, C.POINTER(P)]),
     "hbc_graph_launch": (I32, [P, P]),
@@ -413,6 +414,13 @@ def apply_adjoint(plan: Plan, grad, stream=None):
     """In place: data += A^T (covered ghost part), covered ghosts := 0."""
     ptr, n = _field(plan, grad)
     _check(lib().hbc_apply_adjoint(plan._h, ptr, n, _stream(stream)))
+    return grad
+
+
+def apply_adjoint_noalloc(plan: Plan, grad, stream=None):
+    """As apply_adjoint, allocating nothing (the library's static counter array)."""
+    ptr, n = _field(plan, grad)
+    _check(lib().hbc_apply_adjoint_noalloc(plan._h, ptr, n, _stream(stream)))
     return grad
 
 

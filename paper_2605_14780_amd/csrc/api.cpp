@@ -593,6 +593,22 @@ int hbc_apply_adjoint(const hbc_plan* plan_c, void* grad, int64_t nelem, void* s
   });
 }
 
+int hbc_apply_adjoint_noalloc(const hbc_plan* plan, void* grad, int64_t nelem, void* stream) {
+  return guard([&] {
+    check_device_plan(plan);
+    check_field(grad);
+    check_size(plan, nelem);
+    if (plan->p.stats.rows_data > 0) fail(HBC_EUNSUPPORTED, "no adjoint for plans with data rows");
+    {
+      std::lock_guard<std::mutex> lk(const_cast<hbc_plan*>(plan)->csc_mu);
+      if (!plan->csc_ready)
+        fail(HBC_EINVAL, "the plan's transposed tables are not built yet: call hbc_apply_adjoint or "
+                         "hbc_graph_create(HBC_OP_ADJOINT) once, where allocation is allowed");
+    }
+    device_adjoint_noalloc(plan->p, grad, stream);
+  });
+}
+
 int hbc_time_apply(const hbc_plan* plan, void* const* fields, int64_t nelem, int32_t nfields, int32_t reps,
                    void* stream, double* ms) {
   return guard([&] {

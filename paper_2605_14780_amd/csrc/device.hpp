@@ -12,6 +12,7 @@ void device_free_plan(Plan& p);
 void device_apply(const Plan& p, void* field, void* stream, bool zero_only);
 void device_update_b(Plan& p, int64_t first, int64_t last, void* stream);  // host.bval[first, last) to the device
 void device_adjoint(const Plan& p, void* grad, void* stream);
+void device_adjoint_noalloc(const Plan& p, void* grad, void* stream);  // counters in the static scratch
 void device_stencil27(Plan& p, const void* x, void* y, void* stream, bool fused, void* xghost);
 void device_cs_weights(int64_t N, int64_t h, int32_t* base, double* w, void* stream);
 double device_time_apply(const Plan& p, void* const* fields, int nfields, int reps, void* stream);

@@ -272,6 +272,9 @@ inline int rows_per_batch(int lanes_per_row) { return lanes_per_row >= 128 ? 2 :
 constexpr int ADJ_LDS_ROWS = 64;
 constexpr int ADJ_LDS_BYTES = 40 * 1024;
 constexpr int ADJ_ZERO_ROWS = 64;  // rows per zeroing workgroup
+// Reader counters the allocation-free adjoint keeps in its static device
+// array (4 MiB).
+constexpr int ADJ_NOALLOC_COUNTERS = 1 << 20;
 struct AdjLdsTile {
   int32_t first_src, nsrc, first_u, nu;
 };

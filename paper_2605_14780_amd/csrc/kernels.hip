@@ -18,6 +18,7 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -2110,10 +2111,10 @@ void device_apply(const Plan& p, void* field, void* stream, bool zero_only) {
 }
 
 template <typename T, int V>
-static void launch_adjoint_lds(const Plan& p, const PlanDesc& d, const AdjDesc& a, hipStream_t st) {
+static void launch_adjoint_lds(const Plan& p, const PlanDesc& d, const AdjDesc& a, hipStream_t st, int32_t* ctr) {
   const AdjLdsHost& A = p.host.adj_lds;
-  AdjLdsDesc q{p.d_al_tiles, p.d_al_ucell, p.d_al_uctr, p.d_al_ctrinit, p.d_al_ctr, p.d_al_slot, p.d_al_zero,
-               (int32_t)A.tiles.size(), (int32_t)A.zero_rows.size()};
+  AdjLdsDesc q{p.d_al_tiles, p.d_al_ucell, p.d_al_uctr, p.d_al_ctrinit, ctr ? ctr : p.d_al_ctr, p.d_al_slot,
+               p.d_al_zero, (int32_t)A.tiles.size(), (int32_t)A.zero_rows.size()};
   const int grid = q.ntiles + (q.nzero + ADJ_ZERO_ROWS - 1) / ADJ_ZERO_ROWS;
   if (grid == 0) return;
   const size_t lds = (size_t)A.brows * p.layout.inner * sizeof(T);
@@ -2124,17 +2125,47 @@ static void launch_adjoint_lds(const Plan& p, const PlanDesc& d, const AdjDesc& 
   HIP_CHECK(hipGetLastError());
 }
 
+// Reader counters of the allocation-free adjoint: a file-scope device array
+// (each GPU the library runs on holds its own copy until the process ends),
+// shared by every such call on that GPU.
+static __device__ __align__(256) int32_t scratch[ADJ_NOALLOC_COUNTERS];
+
+// Device address of `scratch` on the current device, taken once per device
+// with hipGetSymbolAddress (in host code the array's name is no device
+// address).  No allocation: fixed slots for up to 64 devices.
+static int32_t* scratch_address() {
+  static std::mutex mu;
+  static int32_t* addr[64] = {};
+  int dev = 0;
+  HIP_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) fail(HBC_EUNSUPPORTED, "device index beyond 63");
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[dev]) {
+    void* a = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !a) fail(HBC_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    addr[dev] = static_cast<int32_t*>(a);
+  }
+  return addr[dev];
+}
+
+__global__ __launch_bounds__(256) void k_copy_i32(int32_t* __restrict__ dst, const int32_t* __restrict__ src,
+                                                  int n) {
+  for (int i = blockIdx.x * 256 + (int)threadIdx.x; i < n; i += gridDim.x * 256) dst[i] = src[i];
+}
+
+// ctr: the reader counters to use (the plan's own, or the static scratch).
 template <typename T>
-static void launch_adjoint_t(const Plan& p, const PlanDesc& d, hipStream_t st) {
+static void launch_adjoint_t(const Plan& p, const PlanDesc& d, hipStream_t st, int32_t* ctr = nullptr) {
   AdjDesc a{p.d_csc_src, p.d_csc_ptr,  p.d_csc_ghost, p.d_csc_w,          p.d_csc_rot,
             p.d_adj_cnt, p.d_adj_fg, p.d_adj_fw,    p.d_adj_frot, p.host.csc.aw};
   if (p.host.adj_lds.ok && p.layout.order == HBC_POINT_MAJOR) {
     if (sizeof(T) == 4 && p.vec == 4)
-      launch_adjoint_lds<T, (sizeof(T) == 4 ? 4 : 2)>(p, d, a, st);
+      launch_adjoint_lds<T, (sizeof(T) == 4 ? 4 : 2)>(p, d, a, st, ctr);
     else if (p.vec >= 2)
-      launch_adjoint_lds<T, 2>(p, d, a, st);
+      launch_adjoint_lds<T, 2>(p, d, a, st, ctr);
     else
-      launch_adjoint_lds<T, 1>(p, d, a, st);
+      launch_adjoint_lds<T, 1>(p, d, a, st, ctr);
     return;
   }
   const int nt = (int)p.host.adj_tiles.size();
@@ -2165,6 +2196,29 @@ void device_adjoint(const Plan& p, void* grad, void* stream) {
     launch_adjoint_t<double>(p, d, S(stream));
   else
     launch_adjoint_t<float>(p, d, S(stream));
+}
+
+void device_adjoint_noalloc(const Plan& p, void* grad, void* stream) {
+  PlanDesc d = make_desc(p, grad);
+  int32_t* ctr = nullptr;
+  if (p.host.adj_lds.ok && p.layout.order == HBC_POINT_MAJOR) {
+    const size_t n = p.host.adj_lds.ctr_init.size();
+    if (n > (size_t)ADJ_NOALLOC_COUNTERS)
+      fail(HBC_EINVAL, "the plan needs " + std::to_string(n) + " reader counters; the allocation-free adjoint holds " +
+                           std::to_string(ADJ_NOALLOC_COUNTERS));
+    ctr = scratch_address();
+    if (n > 0) {
+      // the array keeps whatever the last call on this GPU left: start every
+      // counter at its reader count (a copy kernel, so the call can be captured)
+      const int grid = (int)std::min<size_t>((n + 255) / 256, 1024);
+      hipLaunchKernelGGL(k_copy_i32, dim3(grid), dim3(256), 0, S(stream), ctr, p.d_al_ctrinit, (int)n);
+      HIP_CHECK(hipGetLastError());
+    }
+  }
+  if (p.dtype == HBC_F64)
+    launch_adjoint_t<double>(p, d, S(stream), ctr);
+  else
+    launch_adjoint_t<float>(p, d, S(stream), ctr);
 }
 
 void device_stencil27(Plan& p, const void* x, void* y, void* stream, bool fused, void* xghost) {
