@@ -25,7 +25,9 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
+import subprocess
 import sys
 import tempfile
 import time
@@ -94,34 +96,45 @@ def torch_graph(torch, fn):
 # ---------------------------------------------------------------------------------------------
 def cpu_baseline_and_checks(ctx, budget_s):
     import numpy as np
-    from oracle import VectorSub, apply as o_apply, assemble
+    import torch
+
+    import paper_2605_14780_amd as hb
+    from oracle import VectorSub, apply as o_apply, assemble, vjp as o_vjp
     from oracle import cubed_sphere as ocs
     from oracle import hpcg as ohpcg
-    from tests.helpers import lagrange_tolerance, normwise_error
+    from tests.helpers import lagrange_tolerance, normwise_error, oracle_weights_program
 
     out = {}
-    # headline: assemble once, time full single-thread applies
+    # headline: the library's own FP64 weights (arithmetic + position bound, and
+    # the plain arithmetic bound for reference), then the program carrying the
+    # oracle's own weights in the headline's launch shape (plain bound)
     N, h, vec, full = ctx["c2_N"], ctx["c2_h"], ctx["c2_vec"], ctx["c2_full"]
     og = ocs.grid(N, h)
     op = assemble(og, ocs.subs(N, h, "lagrange", vector=True))
-    reps, t0 = 0, time.perf_counter()
-    while True:
-        ref = o_apply(op, full, vec)
-        reps += 1
-        if time.perf_counter() - t0 >= budget_s:
-            break
-    dt = time.perf_counter() - t0
-    out["timing"] = (reps, dt)
+    ref = o_apply(op, full, vec)
     G, Dc = og.ghost_cells, og.data_cells
     got = ctx["c2_got"]
     tol = lagrange_tolerance(N, h, full, ref, vec)
+    tol0 = lagrange_tolerance(N, h, full, ref, vec, ds=0.0)
     diff = np.abs(got[G] - ref[G])
+    grid_o, prog_o = oracle_weights_program(hb, N, h, True)
+    plan_o = hb.Plan(prog_o, inner=full.shape[1], vec=vec, dtype=hb.F64)
+    plan_o.tune = ctx["c2_tune"]
+    x = torch.from_numpy(full).cuda()
+    hb.apply(plan_o, x)
+    got_o = x.cpu().numpy()
+    del x
     out["c384_f64"] = {
         "normwise_rel_err": normwise_error(got[G], ref[G], full[Dc]),
         "max_err_over_tolerance": float((diff / np.maximum(tol, 1e-300)).max()),
+        "tolerance": "1e-13 max(|ref|, sum|w x|) + 4 ulp(N) sum|dw/ds||x|",
+        "max_err_over_plain_bound": float((diff / np.maximum(tol0, 1e-300)).max()),
+        "oracle_weights_program_max_err_over_plain_bound":
+            float((np.abs(got_o[G] - ref[G]) / np.maximum(tol0, 1e-300)).max()),
         "data_cells_untouched": bool(np.array_equal(got[Dc], full[Dc])),
         "all_ghosts_written": bool(np.isfinite(got[G]).all()),
     }
+    del got_o, tol0
     if "c2_got32" in ctx:
         g32 = ctx["c2_got32"]
         ref32in = o_apply(op, full.astype(np.float32).astype(np.float64), vec)
@@ -155,9 +168,42 @@ def cpu_baseline_and_checks(ctx, budget_s):
         bound = np.concatenate([ohpcg.abs_row_sum(b).reshape(-1) for b in blocks])
         for name, y in (("fused", y_fused), ("unfused", y_unfused)):
             out[f"hpcg_{name}_max_err_over_bound"] = float((np.abs(y - yref) / (64 * 2.0 ** -53 * bound)).max())
-    # C768 forward with b
+    # 64-grid FP32 batch: sampled ghost rows of three grids against the FP64
+    # oracle on the FP64 fields the FP32 inputs were rounded from
+    if "c4" in ctx:
+        rng = np.random.default_rng(8)
+        worst = worst_in = 0.0
+        sq, cnt = 0.0, 0
+        for k, N4, h4, L4, out32, x64 in ctx["c4"]:
+            W4 = N4 + 2 * h4
+            scale = float(x64.abs().max())
+            picked = 0
+            while picked < 300:
+                f = int(rng.integers(6))
+                j, i = (int(v) for v in rng.integers(-h4, N4 + h4, size=2))
+                if (0 <= j < N4 and 0 <= i < N4) or ocs.is_corner(j, i, N4):
+                    continue
+                ents = ocs.lagrange_entries(f, j, i, N4)
+                src = [(g * W4 + (jj + h4)) * W4 + (ii + h4) for (g, jj, ii), _ in ents]
+                w = np.array([wv for _, wv in ents])
+                X = x64[torch.tensor(src, device=x64.device)].cpu().numpy()
+                ref4 = w @ X
+                ref4in = w @ X.astype(np.float32).astype(np.float64)
+                got4 = out32[(f * W4 + (j + h4)) * W4 + (i + h4)].cpu().numpy().astype(np.float64)
+                e = np.abs(got4 - ref4) / scale
+                worst = max(worst, float(e.max()))
+                worst_in = max(worst_in, float((np.abs(got4 - ref4in) / scale).max()))
+                sq += float((e ** 2).sum())
+                cnt += e.size
+                picked += 1
+        out["batch_64_grids_f32"] = {
+            "grids_checked": [k for k, *_ in ctx["c4"]], "rows_per_grid": 300,
+            "normwise_err_vs_fp64_oracle": worst, "normwise_err_vs_oracle_on_fp32_input": worst_in,
+            "rms_err_vs_fp64_oracle_rel": float(np.sqrt(sq / max(cnt, 1)))}
+    # C768 forward (FP64 and FP32) and adjoint (FP64 and FP32) against the oracle
     if "c5" in ctx:
-        N5, h5, f5, bvals, got5 = ctx["c5"]
+        c5 = ctx["c5"]
+        N5, h5, f5, bvals = c5["N"], c5["h"], c5["x"], c5["b"]
         og5 = ocs.grid(N5, h5)
         subs = ocs.subs(N5, h5, "lagrange")
         k = 0
@@ -167,9 +213,93 @@ def cpu_baseline_and_checks(ctx, budget_s):
             k += n
         op5 = assemble(og5, subs)
         r5 = o_apply(op5, f5)
-        G5 = og5.ghost_cells
-        out["c768_f64_forward_normwise_err"] = normwise_error(got5[G5], r5[G5], f5[og5.data_cells])
+        G5, D5 = og5.ghost_cells, og5.data_cells
+        out["c768_f64_forward_normwise_err"] = normwise_error(c5["fwd_f64"][G5], r5[G5], f5[D5])
+        r5in = o_apply(op5, f5.astype(np.float32).astype(np.float64))
+        out["c768_f32_forward"] = {
+            "normwise_err_vs_fp64_oracle": normwise_error(c5["fwd_f32"][G5], r5[G5], f5[D5]),
+            "normwise_err_vs_oracle_on_fp32_input": normwise_error(c5["fwd_f32"][G5], r5in[G5], f5[D5]),
+            "rms_err_vs_fp64_oracle_rel": float(np.sqrt(np.mean((c5["fwd_f32"][G5] - r5[G5]) ** 2)) /
+                                                np.abs(f5[D5]).max())}
+        del r5, r5in
+        for name in ("f64", "f32"):
+            ybar, aty = c5[f"adj_{name}"]
+            vref = o_vjp(op5, ybar)
+            scale = np.abs(ybar).max(axis=0)
+            out[f"c768_{name}_adjoint_normwise_err_vs_fp64_oracle"] = float(
+                (np.abs(aty - vref).max(axis=0) / np.where(scale > 0, scale, 1.0)).max())
     return out
+
+
+# The oracle timed on the host: runs in a child process of bench.py started
+# before the parent touches the GPU (a fresh interpreter with no GPU handles);
+# it waits on stdin for the path of the headline field, then times full C384
+# applies single-threaded and split over a pool of worker processes, and
+# prints one JSON line.
+_CL = {}
+
+
+def _cpu_leg_work(cols):
+    import numpy as np
+    from oracle import apply as o_apply
+    nlw = len(cols) // 4
+    out = o_apply(_CL["op"], _CL["full"][:, cols], (2 * nlw, nlw, nlw))
+    return float(np.abs(out[_CL["G"][:8]]).sum())
+
+
+def cpu_leg_child(budget_s):
+    import multiprocessing as mp
+    import numpy as np
+    from oracle import apply as o_apply, assemble
+    from oracle import cubed_sphere as ocs
+    N, h, nf, nl = 384, 3, 4, 64
+    path = sys.stdin.readline().strip()
+    if not path:
+        return
+    full = np.load(path, mmap_mode="r")
+    og = ocs.grid(N, h)
+    op = assemble(og, ocs.subs(N, h, "lagrange", vector=True))
+    vec = (2 * nl, nl, nl)
+    ghost_values = len(og.ghost_cells) * nf * nl
+    res = {"ghost_values_per_apply": ghost_values}
+    # (i) one thread: whole applies (A @ X over all 256 slots, rotation, scatter)
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        o_apply(op, full, vec)
+        reps += 1
+        if time.perf_counter() - t0 >= budget_s / 2:
+            break
+    dt = time.perf_counter() - t0
+    res["single"] = {"applies": reps, "seconds": dt, "cells_per_s": ghost_values * reps / dt}
+    # (ii) every core of this process's share: the 64 levels split over worker
+    # processes (each takes its levels of all four fields, so (u, v) stay paired)
+    naff = len(os.sched_getaffinity(0))
+    nw = max(1, min(naff, 16, nl))
+    lv = np.array_split(np.arange(nl), nw)
+    chunks = [[f * nl + int(l) for f in range(nf) for l in ls] for ls in lv]
+    _CL.update(op=op, full=full, G=og.ghost_cells)
+    ctx = mp.get_context("fork")
+    with ctx.Pool(nw) as pool:
+        pool.map(_cpu_leg_work, chunks)  # warm
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            pool.map(_cpu_leg_work, chunks)
+            reps += 1
+            if time.perf_counter() - t0 >= budget_s / 2:
+                break
+        dt = time.perf_counter() - t0
+    res["all_cores"] = {"workers": nw, "affinity_cpus": naff, "applies": reps, "seconds": dt,
+                        "cells_per_s": ghost_values * reps / dt}
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    res["cpu_model"] = model
+    print(json.dumps(res), flush=True)
 
 
 def c768_b_boxes(N, h):
@@ -214,24 +344,35 @@ def headline(ctx, args, hb, torch, tm):
     default_tune = plan.tune
     del g0
     tune_ms = plan.autotune(fields, os.path.join(tempfile.gettempdir(), "hbc_plan_tune.jsonl"))
-    # timed region: K applies in one graph, cycling over the copies
-    graph = hb.ApplyGraph(plan, fields, args.steps)
+    ctx["c2_tune"] = plan.tune
+    # timed region: 7 launches of one graph of R applies cycling over the
+    # copies, R >= K and >= 2 ms of work; the median launch gives the time per
+    # apply
+    R = max(args.steps, int(math.ceil(2.0 / max(tune_ms, 1e-4))))
+    graph = hb.ApplyGraph(plan, fields, R)
     for k in range(args.warmup):
         hb.apply(plan, fields[k % len(fields)])
     graph.launch()
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    launches = []
     w0 = time.perf_counter()
-    e0.record()
-    graph.launch()
-    e1.record()
+    for _ in range(7):
+        e0.record()
+        graph.launch()
+        e1.record()
+        e1.synchronize()
+        launches.append(e0.elapsed_time(e1))
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
-    ms = e0.elapsed_time(e1)
-    res = {"plan": plan, "stats": st, "ms": ms, "wall": wall,
+    ms_step = sorted(launches)[3] / R
+    res = {"plan": plan, "stats": st, "ms_step": ms_step, "wall": wall,
+           "protocol": {"applies_per_launch": R, "launches": 7, "ms_per_launch": launches,
+                        "median_ms_per_launch": sorted(launches)[3]},
            "tuning": {"default_tune": default_tune, "default_us_per_apply": default_us, "tuned": plan.tune,
-                      "tuned_ms_in_autotune": tune_ms}}
+                      "tuned_ms_in_autotune": tune_ms},
+           "kernels": plan.kernels()}
     # warm (cache-resident) and eager numbers for context
     g1 = hb.ApplyGraph(plan, [fields[0]], args.steps)
     res["warm_us"] = tm(g1.launch, args.steps)
@@ -258,7 +399,7 @@ def headline(ctx, args, hb, torch, tm):
     st32 = plan32.stats()
     res["f32"] = {"us_per_apply": us32, "ghost_cells_per_s": st32["ghost_values"] / us32 * 1e6,
                   "hbm_frac": st32["alg_bytes"] / us32 / 1e3 / HBM_PEAK_GBS,
-                  "f64_over_f32_time": (ms * 1e3 / args.steps) / us32,
+                  "f64_over_f32_time": (ms_step * 1e3) / us32,
                   "default_shape_us_per_apply": us32_default, "tune": plan32.tune}
     del g32, f32, src32, fields
     torch.cuda.empty_cache()
@@ -570,6 +711,17 @@ def extra_batch(ctx, hb, torch, tm):
     batch.graph_launch(s.cuda_stream)
     torch.cuda.synchronize()
     same = all(torch.equal(p, b) for p, b in zip(plain, batched))
+    # three grids' FP32 results and the FP64 fields their inputs were rounded
+    # from, for the error against the FP64 oracle (cpu_baseline leg)
+    sizes = [N for N, _, _ in draws]
+    ctx["c4"] = []
+    for k in sorted({int(min(range(len(draws)), key=lambda q: sizes[q])),
+                     int(max(range(len(draws)), key=lambda q: sizes[q])), 17}):
+        N, h, L = draws[k]
+        W = N + 2 * h
+        x64 = torch.zeros((6, W, W, L), dtype=torch.float64, device="cuda")
+        x64[:, h:h + N, h:h + N, :] = synthinputs.cs_sh_field_torch(N, 1, L, seed=4000 + k)
+        ctx["c4"].append((k, N, h, L, batched[k].view(-1, L), x64.view(-1, L)))
     out = {"grids": len(plans), "ghost_values": ghost_values, "alg_bytes": alg,
            "plain_64_launches_us": us_plain, "batched_default_us": us_default, "batched_tuned_us": us_tuned,
            "tune": batch.tune, "autotune_ms": tuned_ms,
@@ -608,11 +760,13 @@ def extra_adjoint(ctx, hb, torch, tm):
         full = full.reshape(-1)
         C = 3
         xs = [full.clone() for _ in range(C)]
+        c5 = ctx.setdefault("c5", {"N": N, "h": h, "b": bvals})
         if name == "f64":
-            hb.apply(plan, xs[0])
-            torch.cuda.synchronize()
-            ctx["c5"] = (N, h, full.view(-1, L).cpu().numpy(), bvals, xs[0].view(-1, L).cpu().numpy())
-            xs[0].copy_(full)
+            c5["x"] = full.view(-1, L).cpu().numpy()
+        hb.apply(plan, xs[0])
+        torch.cuda.synchronize()
+        c5[f"fwd_{name}"] = xs[0].view(-1, L).cpu().numpy().astype(np.float64)
+        xs[0].copy_(full)
         gf = hb.ApplyGraph(plan, xs, 60)
         us_f = tm(gf.launch, 60)
         gen = torch.Generator(device="cuda")
@@ -632,6 +786,8 @@ def extra_adjoint(ctx, hb, torch, tm):
         torch.cuda.synchronize()
         lhs = float(((Ax.double() - z.double()) * y.double()).sum())
         rhs = float((x.double() * Aty.double()).sum())
+        c5[f"adj_{name}"] = (y.view(-1, L).cpu().numpy().astype(np.float64),
+                             Aty.view(-1, L).cpu().numpy().astype(np.float64))
         out[name] = {"forward_us": us_f, "adjoint_us": us_a, "adjoint_over_forward": us_a / us_f,
                      "forward_hbm_frac": st["alg_bytes"] / us_f / 1e3 / HBM_PEAK_GBS,
                      "adjoint_hbm_frac": st["alg_bytes_adjoint"] / us_a / 1e3 / HBM_PEAK_GBS,
@@ -656,7 +812,11 @@ def main():
                          "batched_64_grids_f32, c768_adjoint")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 256 MiB, 20 times (counter calibration)")
+    ap.add_argument("--cpu-leg", action="store_true", help=argparse.SUPPRESS)  # the child of the cpu_baseline leg
     args = ap.parse_args()
+    if args.cpu_leg:
+        cpu_leg_child(args.cpu_budget)
+        return
     if args.calibrate_copy:
         import torch
         a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
@@ -669,6 +829,11 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "the library runs on one GPU; applies sharded over several GPUs are not implemented"}))
         sys.exit(2)
+
+    # the cpu_baseline leg's child process, started before anything touches
+    # the GPU; it waits for the headline field, then times the oracle
+    cpu_child = subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-leg", "--cpu-budget",
+                                  str(args.cpu_budget)], stdin=subprocess.PIPE, stdout=subprocess.PIPE, text=True)
 
     import torch
 
@@ -684,7 +849,7 @@ def main():
     st = res["stats"]
     log("headline done")
     ctx["c2_alg_bytes"] = st["alg_bytes"]
-    ctx["c2_apply_GBs"] = st["alg_bytes"] / (res["ms"] / args.steps / 1e3) / 1e9
+    ctx["c2_apply_GBs"] = st["alg_bytes"] / (res["ms_step"] / 1e3) / 1e9
     extras = {"c384_warm_cache_us_per_apply": res["warm_us"], "c384_eager_us_per_apply": res["eager_us"],
               "c384_f32": res["f32"], "c384_launch_shape": res["tuning"]}
     if not args.no_extras:
@@ -706,18 +871,26 @@ def main():
             extras[name] = fn(ctx, hb, torch, tm)
             log(f"{name} done in {time.perf_counter() - t0:.1f}s")
         if "batched_64_grids_f32" in extras:
-            f64_ns = res["ms"] * 1e6 / args.steps / st["ghost_values"]
+            f64_ns = res["ms_step"] * 1e6 / st["ghost_values"]
             b32 = extras["batched_64_grids_f32"]
             extras["ns_per_ghost_value_plain_f64_over_batched_f32"] = f64_ns / (b32["batched_tuned_us"] * 1e3 /
                                                                                 b32["ghost_values"])
 
-    log("cpu_baseline leg: oracle timing and checks")
+    log("cpu_baseline leg: oracle timing (child process) and checks")
+    import numpy as np
+    fpath = os.path.join(tempfile.gettempdir(), f"hbc_c384_field_{os.getpid()}.npy")
+    np.save(fpath, ctx["c2_full"])
+    try:
+        out_child, _ = cpu_child.communicate(fpath + "\n", timeout=60 + 20 * args.cpu_budget)
+    finally:
+        os.remove(fpath)
+    timing = json.loads(out_child.strip().splitlines()[-1])
     chk = cpu_baseline_and_checks(ctx, args.cpu_budget)
-    reps, dt = chk.pop("timing")
-    ms = res["ms"]
-    ms_step = ms / args.steps
-    value = st["ghost_values"] * args.steps / (ms / 1e3)
+    ms_step = res["ms_step"]
+    value = st["ghost_values"] / (ms_step / 1e3)
     achieved = st["alg_bytes"] / (ms_step / 1e3) / 1e9
+    kern = [k.split("(")[0].replace("void ", "", 1) for k in res["kernels"]]
+    allc, one = timing["all_cores"], timing["single"]
     out = {
         "metric": "BC-apply ghost cells/s + % HBM peak; batched FP32 & adjoint vs plain FP64",
         "value": value,
@@ -737,11 +910,19 @@ def main():
                    "inner": 256, "ghost_values_per_apply": st["ghost_values"], "copies": args.copies},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile("apply_c384_f64_pmc.json"),
-                     "alg_bytes_per_launch": st["alg_bytes"], "kernel": "hbc::k_apply_rows<double, 2, 1, true, 2, 1>"},
-        "cpu_baseline": {"value": st["ghost_values"] * reps / dt, "unit": "ghost cells/s", "cores": 1,
+                     "alg_bytes_per_launch": st["alg_bytes"], "kernel": kern[0],
+                     **({"kernels": kern} if len(kern) > 1 else {})},
+        "cpu_baseline": {"value": allc["cells_per_s"], "unit": "ghost cells/s", "cores": allc["workers"],
                          "kind": "oracle",
-                         "sample": f"{reps} full applies of the C384 operator (scipy CSR A @ X over 256 inner "
-                                   f"slots + rotation + scatter), assembly excluded"},
+                         "sample": f"{allc['applies']} full applies of the C384 operator (scipy CSR A @ X + "
+                                   f"rotation + scatter; the 64 levels split over {allc['workers']} worker "
+                                   f"processes), assembly excluded",
+                         "cpu_model": timing["cpu_model"], "affinity_cpus": allc["affinity_cpus"],
+                         "single_thread": {"value": one["cells_per_s"], "applies": one["applies"],
+                                           "seconds": one["seconds"]},
+                         "gpu_over_cpu_all_cores": value / allc["cells_per_s"],
+                         "gpu_over_cpu_single_thread": value / one["cells_per_s"]},
+        "timing_protocol": res["protocol"],
         "checks_vs_oracle": chk,
         "wall_s_timed": res["wall"],
         "extras": extras,

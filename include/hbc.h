@@ -202,6 +202,10 @@ int hbc_program_set_flags(hbc_program* p, uint32_t flags);
  * one block's data region (HBC_ERANGE). */
 int hbc_program_add_map(hbc_program* p, const hbc_box* rows, const int64_t* M, const int64_t* offset,
                         double weight, const int32_t* rot, int32_t* sub_id);
+/* Number of rows (grid points) the row box `rows` selects: the row count k
+ * runs over in add_ell, add_csr, add_vector and add_data_csr (on a grid of
+ * stepped slices, the lattice points inside the box). */
+int hbc_program_box_rows(const hbc_program* p, const hbc_box* rows, int64_t* n);
 /* Rows with no entries: padding with zeros (Sec. III-B); written as +0.0. */
 int hbc_program_add_zero(hbc_program* p, const hbc_box* rows, int32_t* sub_id);
 /* Zero rows for every ghost cell of `block` that no other sub-matrix covers,
@@ -358,6 +362,13 @@ int hbc_apply_adjoint(const hbc_plan* plan, void* grad, int64_t nelem, void* str
  * otherwise), and at most 2^20 counters (HBC_EINVAL beyond; hbc_apply_adjoint
  * has no such limit). */
 int hbc_apply_adjoint_noalloc(const hbc_plan* plan, void* grad, int64_t nelem, void* stream);
+/* The kernels one call of `op` (HBC_OP_APPLY: hbc_apply; HBC_OP_ADJOINT:
+ * hbc_apply_adjoint) launches with the plan's current launch shape, in launch
+ * order: their demangled names (as profilers list them), one per line, in
+ * buf (NUL-terminated, truncated to cap bytes); *len (may be NULL) receives
+ * the full length without the NUL.  Launches nothing; for HBC_OP_ADJOINT it
+ * builds the transposed tables if the plan has none yet (allocates). */
+int hbc_plan_kernels(const hbc_plan* plan, int32_t op, char* buf, int64_t cap, int64_t* len);
 /* Time `reps` applies captured in one HIP graph on `stream`; *ms receives the
  * mean milliseconds per apply (device events around the graph launch). */
 int hbc_time_apply(const hbc_plan* plan, void* const* fields, int64_t nelem, int32_t nfields, int32_t reps,

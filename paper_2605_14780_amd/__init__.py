@@ -108,6 +108,8 @@ SIGNATURES = {
     "hbc_apply": (I32, [P, P, I64, P]),
     "hbc_apply_adjoint": (I32, [P, P, I64, P]),
     "hbc_apply_adjoint_noalloc": (I32, [P, P, I64, P]),
+    "hbc_plan_kernels": (I32, [P, I32, C.c_char_p, I64, PI64]),
+    "hbc_program_box_rows": (I32, [P, C.POINTER(BoxT), PI64]),
     "hbc_time_apply": (I32, [P, C.POINTER(P), I64, I32, I32, P, PD]),
     "hbc_graph_create": (I32, [P, I32, C.POINTER(P), I64, I32, I32, P, C.POINTER(P)]),
     "hbc_graph_launch": (I32, [P, P]),
@@ -237,7 +239,18 @@ class Program:
     def __init__(self, grid: Grid):
         self._h = P()
         self.grid = grid
+        self._vec_len = {}  # sub-vector id -> number of values it takes
         _check(lib().hbc_program_create(grid._h, C.byref(self._h)))
+
+    def box_rows(self, rows):
+        """Rows (grid points) the row box selects."""
+        n = I64()
+        _check(lib().hbc_program_box_rows(self._h, C.byref(_box(rows)), C.byref(n)))
+        return n.value
+
+    def _need(self, what, got, want):
+        if got != want:
+            raise ValueError(f"{what}: {got} values given, the row box needs {want}")
 
     def set_flags(self, flags):
         _check(lib().hbc_program_set_flags(self._h, flags))
@@ -245,6 +258,8 @@ class Program:
     def add_map(self, rows, M, offset, weight=1.0, rot=None):
         M_a, M_p = _i64(np.asarray(M).reshape(-1))
         o_a, o_p = _i64(offset)
+        self._need("M", len(M_a), len(rows) ** 2)
+        self._need("offset", len(o_a), len(rows))
         r_a, r_p = _rot(rot)
         sid = I32()
         _check(lib().hbc_program_add_map(self._h, C.byref(_box(rows)), M_p, o_p, float(weight), r_p, C.byref(sid)))
@@ -263,6 +278,9 @@ class Program:
     def add_ell(self, rows, width, cols, vals, rot=None):
         c_a, c_p = _i64(np.asarray(cols).reshape(-1))
         v_a, v_p = _f64(np.asarray(vals).reshape(-1))
+        n = self.box_rows(rows) * width
+        self._need("cols", len(c_a), n)
+        self._need("vals", len(v_a), n)
         r_a, r_p = _rot(rot)
         sid = I32()
         _check(lib().hbc_program_add_ell(self._h, C.byref(_box(rows)), width, c_p, v_p, r_p, C.byref(sid)))
@@ -272,15 +290,24 @@ class Program:
         p_a, p_p = _i64(row_ptr)
         c_a, c_p = _i64(np.asarray(cols).reshape(-1))
         v_a, v_p = _f64(np.asarray(vals).reshape(-1))
+        self._check_csr(rows, p_a, c_a, v_a)
         r_a, r_p = _rot(rot)
         sid = I32()
         _check(lib().hbc_program_add_csr(self._h, C.byref(_box(rows)), p_p, c_p, v_p, r_p, C.byref(sid)))
         return sid.value
 
+    def _check_csr(self, rows, p_a, c_a, v_a):
+        self._need("row_ptr", len(p_a), self.box_rows(rows) + 1)
+        self._need("cols", len(c_a), int(p_a[-1]))
+        self._need("vals", len(v_a), int(p_a[-1]))
+
     def add_vector(self, rows, values, ninner=1):
         v_a, v_p = _f64(np.asarray(values).reshape(-1))
+        n = self.box_rows(rows) * ninner
+        self._need("values", len(v_a), n)
         sid = I32()
         _check(lib().hbc_program_add_vector(self._h, C.byref(_box(rows)), ninner, v_p, C.byref(sid)))
+        self._vec_len[sid.value] = n
         return sid.value
 
     def set_consumer(self, offsets):
@@ -295,6 +322,7 @@ class Program:
         p_a, p_p = _i64(row_ptr)
         c_a, c_p = _i64(np.asarray(cols).reshape(-1))
         v_a, v_p = _f64(np.asarray(vals).reshape(-1))
+        self._check_csr(rows, p_a, c_a, v_a)
         sid = I32()
         _check(lib().hbc_program_add_data_csr(self._h, C.byref(_box(rows)), p_p, c_p, v_p, C.byref(sid)))
         return sid.value
@@ -314,11 +342,15 @@ class Program:
             b_a = np.ascontiguousarray(np.asarray(base, dtype=np.int32).reshape(-1))
             b_p = b_a.ctypes.data_as(PI32)
             w_a, w_p = _f64(np.asarray(w).reshape(-1))
+            if len(b_a) != h * N or len(w_a) != 4 * h * N:
+                raise ValueError(f"base / w: {len(b_a)} / {len(w_a)} values given, {h * N} / {4 * h * N} needed")
         _check(lib().hbc_cs_program_add(self._h, N, h, mode, int(bool(vector)), b_p, w_p))
 
     def cart_add_halo(self, nb, n, h, periodic=0):
         nb_a = np.ascontiguousarray(np.asarray(nb, dtype=np.int32))
         n_a, n_p = _i64(n)
+        if len(nb_a) != 3 or len(n_a) != 3:
+            raise ValueError("nb and n take 3 values each (z, y, x)")
         _check(lib().hbc_cart_program_add_halo(self._h, nb_a.ctypes.data_as(PI32), n_p, h, periodic))
 
     def __del__(self):
@@ -341,6 +373,7 @@ class Plan:
             lay.vec_lo, lay.vec_stride, lay.vec_len = vec
         flags = (PLAN_HOST_ONLY if host_only else 0) | (0 if windows else PLAN_NO_WINDOWS)
         _check(lib().hbc_plan_create(program._h, C.byref(lay), dtype, flags, C.byref(self._h)))
+        self._vec_len = dict(program._vec_len)
         self.inner = inner
         self.order = order
         self.dtype = dtype
@@ -366,8 +399,20 @@ class Plan:
     def set_vector(self, sub_id, values, stream=None):
         """New values for sub-vector sub_id, laid out as for Program.add_vector."""
         v_a, v_p = _f64(np.asarray(values).reshape(-1))
+        # an id that is no sub-vector is refused by the library before it reads values
+        if sub_id in self._vec_len and len(v_a) != self._vec_len[sub_id]:
+            raise ValueError(f"values: {len(v_a)} given, sub-vector {sub_id} takes {self._vec_len[sub_id]}")
         st = P(0) if self.host_only else _stream(stream)
         _check(lib().hbc_plan_set_vector(self._h, sub_id, v_p, st))
+
+    def kernels(self, op=None):
+        """Demangled names of the kernels one apply (or adjoint, op=OP_ADJOINT) launches."""
+        op = OP_APPLY if op is None else op
+        n = I64()
+        _check(lib().hbc_plan_kernels(self._h, op, None, 0, C.byref(n)))
+        buf = C.create_string_buffer(n.value + 1)
+        _check(lib().hbc_plan_kernels(self._h, op, buf, n.value + 1, C.byref(n)))
+        return [x for x in buf.value.decode().split("\n") if x]
 
     @property
     def tune(self):

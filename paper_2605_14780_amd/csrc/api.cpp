@@ -342,6 +342,13 @@ int hbc_program_add_map(hbc_program* p, const hbc_box* rows, const int64_t* M, c
   });
 }
 
+int hbc_program_box_rows(const hbc_program* p, const hbc_box* rows, int64_t* n) {
+  return guard([&] {
+    need(p && n, "NULL argument");
+    *n = to_box(p->p.grid, rows).count();
+  });
+}
+
 int hbc_program_add_zero(hbc_program* p, const hbc_box* rows, int32_t* sub_id) {
   return guard([&] {
     need(p != nullptr, "NULL argument");
@@ -606,6 +613,26 @@ int hbc_apply_adjoint_noalloc(const hbc_plan* plan, void* grad, int64_t nelem, v
                          "hbc_graph_create(HBC_OP_ADJOINT) once, where allocation is allowed");
     }
     device_adjoint_noalloc(plan->p, grad, stream);
+  });
+}
+
+int hbc_plan_kernels(const hbc_plan* plan, int32_t op, char* buf, int64_t cap, int64_t* len) {
+  return guard([&] {
+    check_device_plan(plan);
+    need(op == HBC_OP_APPLY || op == HBC_OP_ADJOINT, "op must be HBC_OP_APPLY or HBC_OP_ADJOINT");
+    need(cap >= 0 && (cap == 0 || buf), "NULL buffer");
+    if (op == HBC_OP_ADJOINT) {
+      if (plan->p.stats.rows_data > 0) fail(HBC_EUNSUPPORTED, "no adjoint for plans with data rows");
+      ensure_csc(const_cast<hbc_plan*>(plan));
+    }
+    std::string all;
+    for (const std::string& n : device_kernel_names(plan->p, op)) all += n + "\n";
+    if (len) *len = (int64_t)all.size();
+    if (cap > 0) {
+      const size_t n = std::min<size_t>(all.size(), (size_t)cap - 1);
+      std::memcpy(buf, all.data(), n);
+      buf[n] = 0;
+    }
   });
 }
 

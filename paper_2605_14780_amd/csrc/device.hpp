@@ -13,6 +13,8 @@ void device_apply(const Plan& p, void* field, void* stream, bool zero_only);
 void device_update_b(Plan& p, int64_t first, int64_t last, void* stream);  // host.bval[first, last) to the device
 void device_adjoint(const Plan& p, void* grad, void* stream);
 void device_adjoint_noalloc(const Plan& p, void* grad, void* stream);  // counters in the static scratch
+// demangled names of the kernels one apply (op HBC_OP_APPLY) or adjoint launches, in launch order
+std::vector<std::string> device_kernel_names(const Plan& p, int op);
 void device_stencil27(Plan& p, const void* x, void* y, void* stream, bool fused, void* xghost);
 void device_cs_weights(int64_t N, int64_t h, int32_t* base, double* w, void* stream);
 double device_time_apply(const Plan& p, void* const* fields, int nfields, int reps, void* stream);

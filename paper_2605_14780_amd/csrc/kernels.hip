@@ -16,7 +16,9 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <cxxabi.h>
 #include <fstream>
 #include <mutex>
 #include <sstream>
@@ -1878,6 +1880,18 @@ void device_upload_csc(Plan& p) {
   p.d_adj_tiles = static_cast<const AdjTile*>(t);
 }
 
+// While hbc_plan_kernels asks which kernels a call launches, the launch
+// helpers below record each kernel instead of launching it (the same
+// decisions as a real call, no GPU work).
+static thread_local std::vector<const void*>* t_rec = nullptr;
+#define HBC_LAUNCH(fn, ...)                                  \
+  do {                                                       \
+    if (t_rec)                                               \
+      t_rec->push_back((const void*)(fn));                   \
+    else                                                     \
+      hipLaunchKernelGGL(fn, __VA_ARGS__);                   \
+  } while (0)
+
 template <typename T, int V, int U, int KX = 0>
 static void launch_rows_vu(const PlanDesc& d, hipStream_t st, int grid, int blk, const RowTile* tiles, int nt, int z,
                            const DataDesc& dd) {
@@ -1885,22 +1899,22 @@ static void launch_rows_vu(const PlanDesc& d, hipStream_t st, int grid, int blk,
   const dim3 g(grid + dd.grid), b(blk);
   if (d.general) {
     if (d.nt && rb2)
-      hipLaunchKernelGGL((k_apply_rows<T, V, U, true, 2, 3 | KX>), g, b, 0, st, d, tiles, nt, z, dd);
+      HBC_LAUNCH((k_apply_rows<T, V, U, true, 2, 3 | KX>), g, b, 0, st, d, tiles, nt, z, dd);
     else if (d.nt)
-      hipLaunchKernelGGL((k_apply_rows<T, V, U, true, 4, 3 | KX>), g, b, 0, st, d, tiles, nt, z, dd);
+      HBC_LAUNCH((k_apply_rows<T, V, U, true, 4, 3 | KX>), g, b, 0, st, d, tiles, nt, z, dd);
     else if (rb2)
-      hipLaunchKernelGGL((k_apply_rows<T, V, U, false, 2, 3 | KX>), g, b, 0, st, d, tiles, nt, z, dd);
+      HBC_LAUNCH((k_apply_rows<T, V, U, false, 2, 3 | KX>), g, b, 0, st, d, tiles, nt, z, dd);
     else
-      hipLaunchKernelGGL((k_apply_rows<T, V, U, false, 4, 3 | KX>), g, b, 0, st, d, tiles, nt, z, dd);
+      HBC_LAUNCH((k_apply_rows<T, V, U, false, 4, 3 | KX>), g, b, 0, st, d, tiles, nt, z, dd);
   } else {
     if (d.nt && rb2)
-      hipLaunchKernelGGL((k_apply_rows<T, V, U, true, 2, 1 | KX>), g, b, 0, st, d, tiles, nt, z, dd);
+      HBC_LAUNCH((k_apply_rows<T, V, U, true, 2, 1 | KX>), g, b, 0, st, d, tiles, nt, z, dd);
     else if (d.nt)
-      hipLaunchKernelGGL((k_apply_rows<T, V, U, true, 4, 1 | KX>), g, b, 0, st, d, tiles, nt, z, dd);
+      HBC_LAUNCH((k_apply_rows<T, V, U, true, 4, 1 | KX>), g, b, 0, st, d, tiles, nt, z, dd);
     else if (rb2)
-      hipLaunchKernelGGL((k_apply_rows<T, V, U, false, 2, 1 | KX>), g, b, 0, st, d, tiles, nt, z, dd);
+      HBC_LAUNCH((k_apply_rows<T, V, U, false, 2, 1 | KX>), g, b, 0, st, d, tiles, nt, z, dd);
     else
-      hipLaunchKernelGGL((k_apply_rows<T, V, U, false, 4, 1 | KX>), g, b, 0, st, d, tiles, nt, z, dd);
+      HBC_LAUNCH((k_apply_rows<T, V, U, false, 4, 1 | KX>), g, b, 0, st, d, tiles, nt, z, dd);
   }
 }
 
@@ -1958,10 +1972,10 @@ static void launch_wide(const Plan& p, const PlanDesc& d, hipStream_t st, bool z
                                     (size_t)(WIDE_ROWS + 1) * 4;
   const WideEnt<T>* went = static_cast<const WideEnt<T>*>(p.d_w_ent);
   if (d.nt)
-    hipLaunchKernelGGL((k_apply_wide<T, V, SB, true>), dim3(grid), dim3(256), lds, st, d, p.d_wtiles, p.d_w_ucell,
+    HBC_LAUNCH((k_apply_wide<T, V, SB, true>), dim3(grid), dim3(256), lds, st, d, p.d_wtiles, p.d_w_ucell,
                        p.d_w_row, p.d_w_rp, went, ucap, ecap, nslices, spw, zero_only ? 1 : 0, p.d_rtiles, nwide);
   else
-    hipLaunchKernelGGL((k_apply_wide<T, V, SB, false>), dim3(grid), dim3(256), lds, st, d, p.d_wtiles, p.d_w_ucell,
+    HBC_LAUNCH((k_apply_wide<T, V, SB, false>), dim3(grid), dim3(256), lds, st, d, p.d_wtiles, p.d_w_ucell,
                        p.d_w_row, p.d_w_rp, went, ucap, ecap, nslices, spw, zero_only ? 1 : 0, p.d_rtiles, nwide);
   HIP_CHECK(hipGetLastError());
 }
@@ -1982,10 +1996,10 @@ static void launch_win(const Plan& p, const PlanDesc& d, hipStream_t st, bool ze
 #define HBC_WIN(RM)                                                                                               \
   do {                                                                                                              \
     if (d.nt)                                                                                                       \
-      hipLaunchKernelGGL((k_apply_win<T, V, true, RM>), g, b, 0, st, d, p.d_wruns, (int)nitems, (int)nsl, z,         \
+      HBC_LAUNCH((k_apply_win<T, V, true, RM>), g, b, 0, st, d, p.d_wruns, (int)nitems, (int)nsl, z,         \
                          p.d_rtiles, nz);                                                                          \
     else                                                                                                            \
-      hipLaunchKernelGGL((k_apply_win<T, V, false, RM>), g, b, 0, st, d, p.d_wruns, (int)nitems, (int)nsl, z,        \
+      HBC_LAUNCH((k_apply_win<T, V, false, RM>), g, b, 0, st, d, p.d_wruns, (int)nitems, (int)nsl, z,        \
                          p.d_rtiles, nz);                                                                          \
   } while (0)
   if (rm <= 4)
@@ -2021,7 +2035,7 @@ static void launch_apply_t(const Plan& p, const PlanDesc& d, hipStream_t st, boo
     fold = p.host.rtiles[k].kind == SEG_ZERO && !p.host.rtiles[k].has_b;
   if (has_narrow) {
     const int nn = (int)p.host.ntiles.size();
-    hipLaunchKernelGGL((k_apply_narrow<T>), dim3(nn + (fold ? nt : 0)), dim3(256), 0, st, d, p.d_ntiles, z,
+    HBC_LAUNCH((k_apply_narrow<T>), dim3(nn + (fold ? nt : 0)), dim3(256), 0, st, d, p.d_ntiles, z,
                        p.d_rtiles, nn);
     HIP_CHECK(hipGetLastError());
   }
@@ -2046,7 +2060,7 @@ static void launch_apply_t(const Plan& p, const PlanDesc& d, hipStream_t st, boo
   if (has_win) launch_win<T>(p, d, st, zero_only, fold && !has_narrow && !has_wide ? nt : 0);
   if (fold || grid + dd.grid == 0) return;
   if (!pm) {
-    if (grid > 0) hipLaunchKernelGGL((k_apply_pm<T>), dim3(grid), dim3(blk), 0, st, d, p.d_tiles, nt, z);
+    if (grid > 0) HBC_LAUNCH((k_apply_pm<T>), dim3(grid), dim3(blk), 0, st, d, p.d_tiles, nt, z);
   } else {
     launch_rows<T>(d, st, grid, blk, p.d_rtiles, nt, z, dd);
   }
@@ -2059,7 +2073,7 @@ static void launch_data_scatter(const Plan& p, const PlanDesc& d, hipStream_t st
   const int blk = p.tune.block;
   const int groups = blk >> d.lpr_shift;
   const int grid = (int)std::min<int64_t>((n + groups - 1) / groups, 4096);
-  hipLaunchKernelGGL((k_data_scatter<T, V>), dim3(grid), dim3(blk), 0, st, d, p.d_dr_cell,
+  HBC_LAUNCH((k_data_scatter<T, V>), dim3(grid), dim3(blk), 0, st, d, p.d_dr_cell,
                      static_cast<const T*>(p.d_dr_scratch), n);
   HIP_CHECK(hipGetLastError());
 }
@@ -2071,10 +2085,10 @@ static void launch_data_components(const Plan& p, const PlanDesc& d, hipStream_t
   const int groups = blk >> d.lpr_shift;
   const int grid = (int)std::min<int64_t>((n + groups - 1) / groups, 4096);
   if (d.nt)
-    hipLaunchKernelGGL((k_data_components<T, V, true>), dim3(grid), dim3(blk), 0, st, d, p.d_dc_comp, p.d_dc_row_dst,
+    HBC_LAUNCH((k_data_components<T, V, true>), dim3(grid), dim3(blk), 0, st, d, p.d_dc_comp, p.d_dc_row_dst,
                        p.d_dc_row_ent, p.d_dc_row_n, p.d_dc_slot, static_cast<const T*>(p.d_dc_w), n);
   else
-    hipLaunchKernelGGL((k_data_components<T, V, false>), dim3(grid), dim3(blk), 0, st, d, p.d_dc_comp, p.d_dc_row_dst,
+    HBC_LAUNCH((k_data_components<T, V, false>), dim3(grid), dim3(blk), 0, st, d, p.d_dc_comp, p.d_dc_row_dst,
                        p.d_dc_row_ent, p.d_dc_row_n, p.d_dc_slot, static_cast<const T*>(p.d_dc_w), n);
   HIP_CHECK(hipGetLastError());
 }
@@ -2119,9 +2133,9 @@ static void launch_adjoint_lds(const Plan& p, const PlanDesc& d, const AdjDesc& 
   if (grid == 0) return;
   const size_t lds = (size_t)A.brows * p.layout.inner * sizeof(T);
   if (d.nt)
-    hipLaunchKernelGGL((k_adjoint_lds<T, V, true>), dim3(grid), dim3(p.tune.block), lds, st, d, a, q);
+    HBC_LAUNCH((k_adjoint_lds<T, V, true>), dim3(grid), dim3(p.tune.block), lds, st, d, a, q);
   else
-    hipLaunchKernelGGL((k_adjoint_lds<T, V, false>), dim3(grid), dim3(p.tune.block), lds, st, d, a, q);
+    HBC_LAUNCH((k_adjoint_lds<T, V, false>), dim3(grid), dim3(p.tune.block), lds, st, d, a, q);
   HIP_CHECK(hipGetLastError());
 }
 
@@ -2172,19 +2186,19 @@ static void launch_adjoint_t(const Plan& p, const PlanDesc& d, hipStream_t st, i
   if (nt > 0) {
     const int blk = p.tune.block;
     if (p.layout.order == HBC_PLANE_MAJOR)
-      hipLaunchKernelGGL((k_adjoint<T, 1, true, false>), dim3(nt), dim3(blk), 0, st, d, a, p.d_adj_tiles, nt);
+      HBC_LAUNCH((k_adjoint<T, 1, true, false>), dim3(nt), dim3(blk), 0, st, d, a, p.d_adj_tiles, nt);
     else if (p.vec == 4 && d.nt)
-      hipLaunchKernelGGL((k_adjoint<T, 4, false, true>), dim3(nt), dim3(blk), 0, st, d, a, p.d_adj_tiles, nt);
+      HBC_LAUNCH((k_adjoint<T, 4, false, true>), dim3(nt), dim3(blk), 0, st, d, a, p.d_adj_tiles, nt);
     else if (p.vec == 4)
-      hipLaunchKernelGGL((k_adjoint<T, 4, false, false>), dim3(nt), dim3(blk), 0, st, d, a, p.d_adj_tiles, nt);
+      HBC_LAUNCH((k_adjoint<T, 4, false, false>), dim3(nt), dim3(blk), 0, st, d, a, p.d_adj_tiles, nt);
     else if (p.vec == 2 && d.nt)
-      hipLaunchKernelGGL((k_adjoint<T, 2, false, true>), dim3(nt), dim3(blk), 0, st, d, a, p.d_adj_tiles, nt);
+      HBC_LAUNCH((k_adjoint<T, 2, false, true>), dim3(nt), dim3(blk), 0, st, d, a, p.d_adj_tiles, nt);
     else if (p.vec == 2)
-      hipLaunchKernelGGL((k_adjoint<T, 2, false, false>), dim3(nt), dim3(blk), 0, st, d, a, p.d_adj_tiles, nt);
+      HBC_LAUNCH((k_adjoint<T, 2, false, false>), dim3(nt), dim3(blk), 0, st, d, a, p.d_adj_tiles, nt);
     else if (d.nt)
-      hipLaunchKernelGGL((k_adjoint<T, 1, false, true>), dim3(nt), dim3(blk), 0, st, d, a, p.d_adj_tiles, nt);
+      HBC_LAUNCH((k_adjoint<T, 1, false, true>), dim3(nt), dim3(blk), 0, st, d, a, p.d_adj_tiles, nt);
     else
-      hipLaunchKernelGGL((k_adjoint<T, 1, false, false>), dim3(nt), dim3(blk), 0, st, d, a, p.d_adj_tiles, nt);
+      HBC_LAUNCH((k_adjoint<T, 1, false, false>), dim3(nt), dim3(blk), 0, st, d, a, p.d_adj_tiles, nt);
     HIP_CHECK(hipGetLastError());
   }
   launch_apply_t<T>(p, d, st, true);  // covered ghost gradients := 0, after the gather
@@ -2196,6 +2210,31 @@ void device_adjoint(const Plan& p, void* grad, void* stream) {
     launch_adjoint_t<double>(p, d, S(stream));
   else
     launch_adjoint_t<float>(p, d, S(stream));
+}
+
+std::vector<std::string> device_kernel_names(const Plan& p, int op) {
+  std::vector<const void*> fns;
+  t_rec = &fns;
+  try {
+    if (op == HBC_OP_ADJOINT)
+      device_adjoint(p, nullptr, nullptr);
+    else
+      device_apply(p, nullptr, nullptr, false);
+  } catch (...) {
+    t_rec = nullptr;
+    throw;
+  }
+  t_rec = nullptr;
+  std::vector<std::string> out;
+  for (const void* f : fns) {
+    const char* nm = hipKernelNameRefByPtr(f, nullptr);
+    if (!nm) fail(HBC_EHIP, "hipKernelNameRefByPtr gave no name");
+    int status = 0;
+    char* dm = abi::__cxa_demangle(nm, nullptr, nullptr, &status);
+    out.emplace_back(status == 0 && dm ? dm : nm);
+    std::free(dm);
+  }
+  return out;
 }
 
 void device_adjoint_noalloc(const Plan& p, void* grad, void* stream) {
@@ -2675,7 +2714,7 @@ double device_plan_autotune(Plan& p, void* const* fields, int nfields, const cha
   if (p.stats.rows_window > 0) {
     // window plans: the run length (a run's three extra cells against the
     // number of wavefronts in flight)
-    for (int r : {4, 6, 8, 12, 16}) {
+    for (int r : {4, 6, 8, 10, 12, 16}) {
       hbc_tune t = def;
       t.rows_per_tile = r;
       cand.push_back(t);

@@ -515,3 +515,35 @@ def test_set_vector_with_a_consumer_footprint():
         kept += got[0] >= 0
     assert kept == N  # one layer of the strip
     assert all(plan.row(int(c))[0] == -1 for c in og.cells_of_box(0, outer_layer))
+
+
+def test_binding_checks_host_array_lengths():
+    """The binding refuses host arrays whose length does not match what the
+    C ABI will read (it copies rows x width values from the pointer), before
+    calling the library; the box row count comes from the library itself
+    (lattice points on stepped grids)."""
+    g = hb.Grid.cubed_sphere(8, 2)
+    p = hb.Program(g)
+    box = [(0, 1), (0, 8), (-2, 0)]
+    assert p.box_rows(box) == 16
+    with pytest.raises(ValueError):
+        p.add_vector(box, np.zeros(15))
+    with pytest.raises(ValueError):
+        p.add_ell(box, 4, np.zeros(63, dtype=np.int64), np.zeros(64))
+    with pytest.raises(ValueError):
+        p.add_csr(box, np.zeros(16, dtype=np.int64), [], [])
+    with pytest.raises(ValueError):
+        p.add_map(box, np.eye(2, dtype=np.int64), [0, 0, 0])
+    sid = p.add_vector(box, np.ones((16, 3)), ninner=3)
+    p.add_zero_rest(0)
+    plan = hb.Plan(p, inner=3, host_only=True)
+    with pytest.raises(ValueError):
+        plan.set_vector(sid, np.ones(47))
+    with pytest.raises(hb.HbcError, match="not a sub-vector"):
+        plan.set_vector(sid + 1, np.ones(48))
+    plan.set_vector(sid, np.full(48, 2.0))
+    # stepped slices: the box selects lattice points only
+    gs = hb.Grid([0, 0], [1, 20])
+    gs.add_block([(0, 1), (0, 20, 2)], [(0, 1), (4, 16, 2)])
+    ps = hb.Program(gs)
+    assert ps.box_rows([(0, 1), (0, 4)]) == 2
