@@ -428,6 +428,10 @@ int hbc_batch_apply(hbc_batch* b, void* stream);
  * capture. */
 int hbc_batch_graph_capture(hbc_batch* b, void* stream);
 int hbc_batch_graph_launch(hbc_batch* b, void* stream);
+/* Launch shape of the batch: block, lanes_per_row (0: each plan's own, else a
+ * cap), rows_per_tile (inner values per tile; 0: one batch of rows per row
+ * group, so a workgroup issues all its loads before its first store),
+ * persistent workgroups. */
 int hbc_batch_get_tune(const hbc_batch* b, hbc_tune* out);
 int hbc_batch_set_tune(hbc_batch* b, const hbc_tune* t);
 /* Try candidate launch shapes on the bound fields, keep the fastest; when

@@ -2433,8 +2433,23 @@ struct Batch {
   hbc_stats stats{};
 };
 
+// Rows per batch of a row group in the batch kernel (rt_tile_any's choice
+// for the plan's vector width and unroll).
+static int batch_rows_per_batch(const PlanDesc& d, int dtype) {
+  if (d.ua) return 4;
+  if (dtype == HBC_F32) {
+    if (d.vec == 4) return 4;
+    if (d.vec == 2) return d.unroll >= 2 ? 2 : 4;
+    return d.unroll >= 2 ? 2 : 4;
+  }
+  if (d.vec >= 2) return 4;
+  return d.unroll >= 2 ? 2 : 4;
+}
+
 static void batch_tiles(Batch* b) {
-  // per plan: rows per tile so that a tile holds about tune.rows_per_tile inner values
+  // per plan: rows per tile so that a tile holds about tune.rows_per_tile inner
+  // values; rows_per_tile = 0 gives every row group one batch of rows (all
+  // loads of a workgroup issued before its first store)
   std::vector<std::vector<RowTile>> per(b->plans.size());
   for (size_t k = 0; k < b->plans.size(); ++k) {
     const Plan& p = *b->plans[k];
@@ -2446,6 +2461,7 @@ static void batch_tiles(Batch* b) {
     const int64_t rp = std::max<int64_t>(1, b->tune.block / lpr);
     int64_t rpt = std::max<int64_t>(1, (int64_t)b->tune.rows_per_tile / I);
     rpt = ((rpt + rp - 1) / rp) * rp;
+    if (b->tune.rows_per_tile == 0) rpt = rp * batch_rows_per_batch(b->descs[k], b->dtype);
     rpt = std::min<int64_t>(rpt, 1 << 20);
     for (size_t s = 0; s < p.host.segs.size(); ++s) {
       const DevSeg& sg = p.host.segs[s];
@@ -2622,7 +2638,7 @@ hbc_tune device_batch_get_tune(const Batch* b) { return b->tune; }
 void device_batch_set_tune(Batch* b, const hbc_tune& t) {
   if (t.block < 64 || t.block > 256 || t.block % 64) fail(HBC_EINVAL, "block must be 64, 128, 192 or 256");
   if (t.lanes_per_row < 0 || (t.lanes_per_row & (t.lanes_per_row - 1))) fail(HBC_EINVAL, "lanes_per_row: 0 or a power of two");
-  if (t.rows_per_tile < 1 || t.persistent < 0) fail(HBC_EINVAL, "bad tile size or persistent count");
+  if (t.rows_per_tile < 0 || t.persistent < 0) fail(HBC_EINVAL, "bad tile size or persistent count");
   b->tune = t;
   batch_tiles(b);
 }
@@ -2777,7 +2793,7 @@ double device_batch_autotune(Batch* b, const char* cache_path, void* stream) {
   hbc_tune best = start;
   double best_ms = 1e30;
   const int blocks[] = {128, 256};
-  const int elems[] = {4096, 8192, 16384, 32768};
+  const int elems[] = {0, 4096, 8192, 16384, 32768};  // 0: one batch of rows per row group
   const int pers[] = {0, 2, 4, 8};
   const int lprs[] = {0, 32};
   for (int bl : blocks)

@@ -212,7 +212,9 @@ def test_batch_bit_identical_to_plain(dtype):
     # every launch shape gives the same bits
     for tune in [dict(block=128, lanes_per_row=0, rows_per_tile=4096, persistent=0),
                  dict(block=256, lanes_per_row=32, rows_per_tile=1024, persistent=512),
-                 dict(block=64, lanes_per_row=0, rows_per_tile=64, persistent=7)]:
+                 dict(block=64, lanes_per_row=0, rows_per_tile=64, persistent=7),
+                 dict(block=256, lanes_per_row=0, rows_per_tile=0, persistent=0),
+                 dict(block=128, lanes_per_row=32, rows_per_tile=0, persistent=300)]:
         batch.tune = tune
         for f, x in zip(fields, inputs):
             f.copy_(x)
