@@ -34,6 +34,9 @@ What it computes (Mat2Boundary, arXiv 2605.14780):
 * ``footprint``     the consumer footprint of Sec. IV-C: ghost rows that no
                     read of the consuming operator reaches, and the operator
                     restricted to the others.
+* ``consumer``      the operator that reads the BC's ghosts (Sec. IV-C): a
+                    stencil of offsets and weights on the field the BC has
+                    written, the BC applied first, then the shifted sums.
 * ``averaging``     block-edge averaging of co-located points (data rows,
                     Sec. III-B), on a vertex-centred cubed sphere, sets found
                     by 3-D position; applied together with the ghost rows, all
