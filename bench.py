@@ -517,6 +517,62 @@ def extra_footprint(ctx, hb, torch, tm):
     return out
 
 
+def extra_consumer(ctx, hb, torch, tm):
+    """The C384 fields (I = 256, FP64) read by a radius-1 cross stencil after
+    the BC (Sec. IV-C): the BC compiled for the stencil's footprint, then the
+    stencil reading the stored ghosts (unfused), against the stencil fused
+    with the BC (boundary cells' rows composed with the BC rows, x only
+    read)."""
+    N, h, nf, nl = 384, 3, 4, 64
+    I = nf * nl
+    vec = (2 * nl, nl, nl)
+    cross = [(0, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]
+    wts = [-4.0, 1.0, 1.0, 1.0, 1.0]
+    grid, prog = hb.cs_program(N, h, hb.CS_LAGRANGE, vector=True)
+    prog.set_consumer(cross)
+    plan = hb.Plan(prog, inner=I, vec=vec, dtype=hb.F64)
+    cons = hb.Consumer(plan, cross, wts)
+    src = torch.from_numpy(ctx["c2_full"]).cuda()
+    C = 3
+    xs = [src.clone() for _ in range(C)]
+    del src
+    ndata = 6 * N * N
+    ys = [torch.empty(ndata * I, dtype=torch.float64, device="cuda") for _ in range(C)]
+    R = 12
+
+    def apply_only():
+        for r in range(R):
+            hb.apply(plan, xs[r % C])
+
+    def stencil_only():
+        for r in range(R):
+            cons.apply(xs[r % C], ys[r % C], fused=False)
+
+    def unfused():
+        for r in range(R):
+            hb.apply(plan, xs[r % C])
+            cons.apply(xs[r % C], ys[r % C], fused=False)
+
+    def fused():
+        for r in range(R):
+            cons.apply(xs[r % C], ys[r % C], fused=True)
+
+    alg = 2.0 * ndata * I * 8  # x data read once, y written once
+    out = {"consumer": "cross radius 1, weights (-4, 1, 1, 1, 1)", "boundary_rows": cons.stats()["boundary_rows"],
+           "alg_bytes_stencil": alg}
+    for name, fn in (("bc_apply_footprint", apply_only), ("stencil_on_stored_ghosts", stencil_only),
+                     ("unfused_apply_then_stencil", unfused), ("fused", fused)):
+        g = torch_graph(torch, fn)
+        us = tm(g.replay, R)
+        del g
+        out[name] = {"us": us, "hbm_frac": (alg if name != "bc_apply_footprint" else plan.stats()["alg_bytes"]) /
+                     us / 1e3 / HBM_PEAK_GBS}
+    out["fused_speedup_vs_unfused"] = out["unfused_apply_then_stencil"]["us"] / out["fused"]["us"]
+    del xs, ys
+    torch.cuda.empty_cache()
+    return out
+
+
 def extra_wide_rows(ctx, hb, torch, tm):
     """Wide interpolation rows (Gauss average over each ghost cell of cubic
     tensor-product reconstructions, 16..25 entries per row, CSR): the
@@ -807,7 +863,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extras", default="all",
-                    help="comma-separated subset of: copy_ceiling, c384_plane_major, c384_cross_footprint, wide_rows, edge_average_np385, "
+                    help="comma-separated subset of: copy_ceiling, c384_plane_major, c384_cross_footprint, c384_cross_consumer, wide_rows, edge_average_np385, "
                          "c48_latency, hpcg_256cube, "
                          "batched_64_grids_f32, c768_adjoint")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -855,6 +911,7 @@ def main():
     if not args.no_extras:
         table = (("copy_ceiling", extra_copy_ceiling),
                  ("c384_plane_major", extra_c384_plane_major), ("c384_cross_footprint", extra_footprint),
+                 ("c384_cross_consumer", extra_consumer),
                  ("wide_rows", extra_wide_rows),
                  ("edge_average_np385", extra_edge_average),
                  ("c48_latency", extra_c48),

@@ -404,6 +404,35 @@ int hbc_stencil27(const hbc_plan* plan, const void* x, int64_t x_nelem, void* y,
 int hbc_fused_stencil27(const hbc_plan* plan, void* x, int64_t x_nelem, void* y, int64_t y_nelem,
                         int32_t write_ghosts, void* stream);
 
+/* ---- consumer of the BC's ghosts: a stencil fused with the BC (Sec. IV-C) ----- */
+/* Sec. IV-C: the boundary writes exist to feed the computation that follows,
+ * and the two are optimised together.  The consumer here is a stencil of
+ * offsets and weights: y[c, l] = sum_o weights[o] * x'[c + offsets[o], l] for
+ * every data cell c of every block, where x' is the field after hbc_apply of
+ * the plan.  offsets: noffsets x ndim positions of the global box (multiples
+ * of the grid's step), 1 <= noffsets <= 64; every read of every data cell must
+ * stay in its block's full region (HBC_EINVAL).  Point-major plans without
+ * data rows (HBC_EUNSUPPORTED otherwise).  The consumer keeps a pointer to the
+ * plan, which must outlive it; it reads the plan's rows as compiled at
+ * creation (later new sub-vector values need a new consumer). */
+typedef struct hbc_consumer hbc_consumer;
+int hbc_consumer_create(const hbc_plan* plan, int32_t noffsets, const int64_t* offsets, const double* weights,
+                        hbc_consumer** out);
+/* y: device, y_nelem = data cells x inner values (block by block, each block's
+ * data box row-major, inner values contiguous per cell); x: the plan's field
+ * (x_nelem = cells x inner).  Sums in offset order (first product, then FMAs).
+ * fused = 0: every read from x, ghosts as stored (run hbc_apply first).
+ * fused = 1: reads of covered ghosts go through the BC: each cell whose
+ * stencil reaches ghosts has one row composed at creation, entries (source
+ * cell, weight x BC weight, the ghost row's component rotation) in offset
+ * order then BC entry order, plus the weighted b; x is only read (its covered
+ * ghosts are not; uncovered ghosts are read as stored). */
+int hbc_consumer_apply(const hbc_consumer* c, const void* x, int64_t x_nelem, void* y, int64_t y_nelem,
+                       int32_t fused, void* stream);
+/* Cells whose stencil reaches a ghost (rows composed with the BC), and their entries. */
+int hbc_consumer_stats(const hbc_consumer* c, int64_t* boundary_rows, int64_t* boundary_entries);
+void hbc_consumer_destroy(hbc_consumer* c);
+
 /* ---- FP64 interpolation weights on the device (setup, not part of an apply) -- */
 /* For ghost layer k < h and tangential index t < N of any cubed-sphere face
  * side: base_dev[k*N + t] = first node, w_dev[(k*N + t)*4 + m] = weight of node

@@ -110,6 +110,10 @@ SIGNATURES = {
     "hbc_apply_adjoint_noalloc": (I32, [P, P, I64, P]),
     "hbc_plan_kernels": (I32, [P, I32, C.c_char_p, I64, PI64]),
     "hbc_program_box_rows": (I32, [P, C.POINTER(BoxT), PI64]),
+    "hbc_consumer_create": (I32, [P, I32, PI64, PD, C.POINTER(P)]),
+    "hbc_consumer_apply": (I32, [P, P, I64, P, I64, I32, P]),
+    "hbc_consumer_stats": (I32, [P, PI64, PI64]),
+    "hbc_consumer_destroy": (None, [P]),
     "hbc_time_apply": (I32, [P, C.POINTER(P), I64, I32, I32, P, PD]),
     "hbc_graph_create": (I32, [P, I32, C.POINTER(P), I64, I32, I32, P, C.POINTER(P)]),
     "hbc_graph_launch": (I32, [P, P]),
@@ -496,6 +500,39 @@ class ApplyGraph:
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
             _lib.hbc_graph_destroy(self._h)
+            self._h = None
+
+
+class Consumer:
+    """A stencil (offsets, weights) reading the plan's field after the BC; apply(x, y, fused)."""
+
+    def __init__(self, plan: Plan, offsets, weights):
+        o = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        if o.ndim != 2:
+            raise ValueError("offsets: (noffsets, ndim)")
+        w_a, w_p = _f64(np.asarray(weights, dtype=np.float64).reshape(-1))
+        if len(w_a) != o.shape[0]:
+            raise ValueError("one weight per offset")
+        self._h = P()
+        self.plan = plan  # the library keeps a pointer to the plan
+        _check(lib().hbc_consumer_create(plan._h, o.shape[0], o.ctypes.data_as(PI64), w_p, C.byref(self._h)))
+
+    def stats(self):
+        r, e = I64(), I64()
+        _check(lib().hbc_consumer_stats(self._h, C.byref(r), C.byref(e)))
+        return {"boundary_rows": r.value, "boundary_entries": e.value}
+
+    def apply(self, x, y, fused=True, stream=None):
+        xp, xn = _field(self.plan, x)
+        if y.dtype != x.dtype or not y.is_contiguous() or not y.is_cuda:
+            raise ValueError("y must be a contiguous GPU tensor of x's dtype")
+        _check(lib().hbc_consumer_apply(self._h, xp, xn, P(y.data_ptr()), int(y.numel()), int(bool(fused)),
+                                        _stream(stream)))
+        return y
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.hbc_consumer_destroy(self._h)
             self._h = None
 
 

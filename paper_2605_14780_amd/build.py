@@ -13,7 +13,7 @@ SRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libhbc.so")
 BUILD = os.path.join(ROOT, "_build")
 
-HOST_SOURCES = ["api.cpp", "plan.cpp", "cubed_sphere.cpp"]
+HOST_SOURCES = ["api.cpp", "plan.cpp", "cubed_sphere.cpp", "consumer.cpp"]
 DEVICE_SOURCES = ["kernels.hip"]
 
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")

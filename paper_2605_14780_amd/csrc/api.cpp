@@ -23,6 +23,11 @@ struct hbc_plan {
 struct hbc_graph {
   void* g = nullptr;
 };
+struct hbc_consumer {
+  const hbc_plan* plan = nullptr;
+  hbc::ConsumerHost host;
+  void* dev = nullptr;
+};
 struct hbc_batch {
   hbc::Batch* b = nullptr;
   std::vector<const hbc::Plan*> plans;
@@ -699,6 +704,54 @@ void hbc_graph_destroy(hbc_graph* g) {
   if (!g) return;
   device_graph_destroy(g->g);
   delete g;
+}
+
+int hbc_consumer_create(const hbc_plan* plan, int32_t noffsets, const int64_t* offsets, const double* weights,
+                        hbc_consumer** out) {
+  hbc_consumer* c = nullptr;
+  const int rc = guard([&] {
+    check_device_plan(plan);
+    need(offsets && weights && out, "NULL argument");
+    c = new hbc_consumer;
+    c->plan = plan;
+    compile_consumer(plan->p, noffsets, offsets, weights, c->host);
+    c->dev = device_consumer_upload(plan->p, c->host);
+    *out = c;
+    c = nullptr;
+  });
+  if (c) {
+    device_consumer_free(c->dev);
+    delete c;
+  }
+  return rc;
+}
+
+int hbc_consumer_apply(const hbc_consumer* c, const void* x, int64_t x_nelem, void* y, int64_t y_nelem,
+                       int32_t fused, void* stream) {
+  return guard([&] {
+    need(c != nullptr, "NULL consumer");
+    check_field(x);
+    check_field(y);
+    check_size(c->plan, x_nelem);
+    const int64_t want = c->host.ndata * c->plan->p.layout.inner;
+    if (y_nelem != want)
+      fail(HBC_EINVAL, "y has " + std::to_string(y_nelem) + " values, the consumer writes " + std::to_string(want));
+    device_consumer_apply(c->plan->p, c->host, c->dev, x, y, fused != 0, stream);
+  });
+}
+
+int hbc_consumer_stats(const hbc_consumer* c, int64_t* boundary_rows, int64_t* boundary_entries) {
+  return guard([&] {
+    need(c && boundary_rows && boundary_entries, "NULL argument");
+    *boundary_rows = (int64_t)c->host.brow_y.size();
+    *boundary_entries = (int64_t)c->host.bcol.size();
+  });
+}
+
+void hbc_consumer_destroy(hbc_consumer* c) {
+  if (!c) return;
+  device_consumer_free(c->dev);
+  delete c;
 }
 
 int hbc_stencil27(const hbc_plan* plan, const void* x, int64_t x_nelem, void* y, int64_t y_nelem, void* stream) {

@@ -16,6 +16,10 @@ void device_adjoint_noalloc(const Plan& p, void* grad, void* stream);  // counte
 // demangled names of the kernels one apply (op HBC_OP_APPLY) or adjoint launches, in launch order
 std::vector<std::string> device_kernel_names(const Plan& p, int op);
 void device_stencil27(Plan& p, const void* x, void* y, void* stream, bool fused, void* xghost);
+void* device_consumer_upload(const Plan& p, const ConsumerHost& C);  // the consumer's device tables
+void device_consumer_free(void* h);
+void device_consumer_apply(const Plan& p, const ConsumerHost& C, void* h, const void* x, void* y, bool fused,
+                           void* stream);
 void device_cs_weights(int64_t N, int64_t h, int32_t* base, double* w, void* stream);
 double device_time_apply(const Plan& p, void* const* fields, int nfields, int reps, void* stream);
 double device_plan_autotune(Plan& p, void* const* fields, int nfields, const char* cache_path, void* stream);

@@ -436,6 +436,42 @@ struct Plan {
   int st_nblocks = 0;
 };
 
+// ---- consumer: the operator that reads the BC's ghosts (Sec. IV-C) ----------
+// y[c, l] = sum_o w_o x'[c + o, l] for every data cell c of every block, with
+// x' the field after the apply.  Structured tiles cover runs of cells along the
+// last dimension of a block's data box and read x at c + o directly (every
+// read a data cell, or a ghost already stored); the boundary rows of the fused
+// form are the stencil composed with the BC rows of the ghosts it reaches:
+// entries (source cell, w_o * A[g, k], the ghost row's component rotation) in
+// offset order then BC entry order, plus sum_o w_o b[g] per row.
+struct alignas(16) CTile {
+  int32_t cell0;  // first cell of the run
+  int32_t y0;     // its row in the output (data cells block by block, each data box row-major)
+  int32_t n;      // cells
+  int32_t blk;    // block (cell deltas of the offsets)
+};
+constexpr int CONS_RB = 2;      // cells (or boundary rows) per batch of a row group
+constexpr int CONS_CELLS = 16;  // cells of a structured tile per row group
+constexpr int CONS_MAXOFF = 64; // offsets at most
+struct ConsumerHost {
+  int noff = 0;
+  std::vector<int64_t> off;        // noff x nd, lattice steps
+  std::vector<double> w;           // noff
+  std::vector<int32_t> delta;      // nblocks x noff cell deltas
+  std::vector<CTile> tiles_all;    // every data cell (unfused: ghosts read from the field)
+  std::vector<CTile> tiles_int;    // cells whose reads are all data cells (fused)
+  std::vector<int32_t> brow_y;     // boundary rows (fused): output row
+  std::vector<int32_t> bptr;       // entries [bptr[r], bptr[r + 1])
+  std::vector<int32_t> bcol;
+  std::vector<double> bw;
+  std::vector<int8_t> brot;
+  std::vector<int32_t> bconst_row; // per boundary row: row of bconst, or -1
+  std::vector<double> bconst;      // rows x inner
+  int32_t tile_cells = 0;          // cells per structured tile (row groups x CONS_CELLS)
+  int32_t tile_rows = 0;           // boundary rows per tile (row groups x CONS_RB)
+  int64_t ndata = 0;
+};
+
 // host plan compiler (plan.cpp)
 void compile_plan(const Program& prog, const Layout& lay, int dtype, Plan& plan);
 void build_tiles(Plan& plan, const hbc_tune& t);
@@ -449,6 +485,9 @@ std::pair<int64_t, int64_t> plan_set_vector(Plan& plan, int32_t sub_id, const do
 // host evaluation of a compiled row
 int plan_row(const Plan& plan, int64_t cell, int64_t l, int cap, int64_t* cols, double* vals, int32_t* nnz,
              double* b, int32_t* kind, int32_t* rot);
+
+// consumer compile (consumer.cpp): offsets in positions of the global box
+void compile_consumer(const Plan& plan, int noff, const int64_t* offsets, const double* weights, ConsumerHost& C);
 
 // cubed sphere helpers (cubed_sphere.cpp)
 void cs_add_program(Program& p, int64_t N, int64_t h, int mode, int vector, const int32_t* base,

@@ -1578,6 +1578,174 @@ __global__ __launch_bounds__(256) void k_stencil27(const T* __restrict__ x, T* _
   }
 }
 
+// ---- consumer of the BC's ghosts (stencil of offsets and weights) --------------------
+// Structured tiles: a run of cells along the last dimension; each row group
+// takes CONS_RB cells, issues all their reads (EC offsets at a time) and sums
+// them in offset order (first product, then FMAs).  Boundary rows (fused
+// form): the stencil composed with the BC rows of the ghosts it reaches, as
+// entries (cell, weight, component rotation) summed in order, plus the
+// composed b.  The output y holds the data cells block by block, each block's
+// data box row-major, inner values point-major.
+struct ConsDesc {
+  const int32_t* delta;  // per block: noff cell deltas
+  const void* w;         // noff weights
+  int32_t noff;
+  int32_t ntiles;
+  const CTile* tiles;
+  const int32_t* brow_y;
+  const int32_t* bptr;
+  const int32_t* bcol;
+  const void* bw;
+  const int8_t* brot;
+  const int32_t* bconst_row;
+  const void* bconst;
+  int32_t nbrow;  // boundary rows (0: unfused)
+  int32_t tile_rows;  // boundary rows per tile
+  void* y;
+};
+
+// PIPE: at most 8 offsets and one pass of a row group per cell (the
+// pipelined walk); else the offsets go 8 at a time, a batch of cells at once.
+// The boundary rows' tiles come first in the grid (they then overlap the
+// structured tiles instead of trailing them).
+template <typename T, int V, bool NT, bool PIPE>
+__global__ __launch_bounds__(256) void k_consumer(PlanDesc d, ConsDesc c) {
+  constexpr int RB = CONS_RB, EC = 8;
+  const int lpr = 1 << d.lpr_shift;
+  const int ngroups = (int)blockDim.x >> d.lpr_shift;
+  const int grp = (int)threadIdx.x >> d.lpr_shift, lane = (int)threadIdx.x & (lpr - 1);
+  const T* __restrict__ x = static_cast<const T*>(d.field);
+  T* __restrict__ y = static_cast<T*>(c.y);
+  const int64_t nvec = d.inner / V;
+  const int nbt = (c.nbrow + c.tile_rows - 1) / c.tile_rows;
+  if ((int)blockIdx.x >= nbt) {
+    // workgroups are dealt to the 8 XCDs round-robin: give each XCD a
+    // contiguous band of tiles, so the rows a cell's neighbours share were
+    // read shortly before into that XCD's L2
+    int b = (int)blockIdx.x - nbt;
+    {
+      const int q = c.ntiles >> 3, rem = c.ntiles & 7, xcd = b & 7, jx = b >> 3;
+      b = xcd * q + min(xcd, rem) + jx;
+    }
+    const CTile t = c.tiles[b];
+    const int32_t* __restrict__ dl = c.delta + (int64_t)t.blk * c.noff;
+    const T* __restrict__ w = static_cast<const T*>(c.w);
+    // a row group walks a contiguous part of the tile's run
+    const int cpg = (t.n + ngroups - 1) / ngroups;
+    const int kb = grp * cpg, ke = min(t.n, kb + cpg);
+    if constexpr (PIPE) {
+      // one pass per cell: the next cell's reads issued before the current
+      // cell's store (two register sets, A and B)
+      if (lane >= nvec) return;
+      const int64_t l = (int64_t)lane * V;
+      int32_t dm[EC];
+      T wm[EC];
+#pragma unroll
+      for (int m = 0; m < EC; ++m) {
+        dm[m] = m < c.noff ? dl[m] : 0;
+        wm[m] = m < c.noff ? w[m] : T(0);
+      }
+      const T* xb = x + (int64_t)t.cell0 * d.cs + l;
+      Pack<T, V> A[EC], B[EC];
+      auto issue = [&](Pack<T, V> (&buf)[EC], int k) {
+#pragma unroll
+        for (int m = 0; m < EC; ++m)
+          if (m < c.noff) buf[m] = ldv<T, V>(xb + (int64_t)(k + dm[m]) * d.cs);
+      };
+      auto finish = [&](Pack<T, V> (&buf)[EC], int k) {
+        Pack<T, V> acc;
+#pragma unroll
+        for (int m = 0; m < EC; ++m)
+          if (m < c.noff) {
+#pragma unroll
+            for (int i = 0; i < V; ++i) acc.v[i] = m == 0 ? wm[m] * buf[m].v[i] : fma(wm[m], buf[m].v[i], acc.v[i]);
+          }
+        stv<T, V, NT>(y + (int64_t)(t.y0 + k) * d.inner + l, acc);
+      };
+      if (kb < ke) issue(A, kb);
+      for (int k = kb; k < ke; k += 2) {
+        if (k + 1 < ke) issue(B, k + 1);
+        finish(A, k);
+        if (k + 1 < ke) {
+          if (k + 2 < ke) issue(A, k + 2);
+          finish(B, k + 1);
+        }
+      }
+      return;
+    } else {
+    for (int k0 = kb; k0 < ke; k0 += RB)
+      for (int64_t v = lane; v < nvec; v += lpr) {
+        const int64_t l = v * V;
+        Pack<T, V> acc[RB];
+        for (int e0 = 0; e0 < c.noff; e0 += EC) {
+          Pack<T, V> xv[RB][EC];
+#pragma unroll
+          for (int q = 0; q < RB; ++q)
+            if (k0 + q < ke)
+#pragma unroll
+              for (int m = 0; m < EC; ++m)
+                if (e0 + m < c.noff) xv[q][m] = ldv<T, V>(x + (int64_t)(t.cell0 + k0 + q + dl[e0 + m]) * d.cs + l);
+#pragma unroll
+          for (int q = 0; q < RB; ++q)
+#pragma unroll
+            for (int m = 0; m < EC; ++m)
+              if (e0 + m < c.noff) {
+                const T wv = w[e0 + m];
+#pragma unroll
+                for (int i = 0; i < V; ++i)
+                  acc[q].v[i] = e0 + m == 0 ? wv * xv[q][m].v[i] : fma(wv, xv[q][m].v[i], acc[q].v[i]);
+              }
+        }
+#pragma unroll
+        for (int q = 0; q < RB; ++q)
+          if (k0 + q < ke) stv<T, V, NT>(y + (int64_t)(t.y0 + k0 + q) * d.inner + l, acc[q]);
+      }
+    }
+    return;
+  }
+  // boundary rows: a row group takes one row at a time, EC entries' loads
+  // in flight, summed in entry order
+  const T* __restrict__ bw = static_cast<const T*>(c.bw);
+  const T* __restrict__ bc = static_cast<const T*>(c.bconst);
+  const int r0 = (int)blockIdx.x * c.tile_rows;
+  const int r1 = min(c.nbrow, r0 + c.tile_rows);
+  for (int r = r0 + grp; r < r1; r += ngroups)
+    for (int64_t v = lane; v < nvec; v += lpr) {
+      const int64_t l = v * V;
+      const int eb = c.bptr[r], ee = c.bptr[r + 1];
+      Pack<T, V> acc;
+#pragma unroll
+      for (int i = 0; i < V; ++i) acc.v[i] = T(0);
+      for (int j0 = eb; j0 < ee; j0 += EC) {
+        Pack<T, V> xv[EC];
+        T wv[EC];
+#pragma unroll
+        for (int m = 0; m < EC; ++m) {
+          wv[m] = T(0);
+          if (j0 + m < ee) {
+            T sign;
+            const int64_t sl = rot_slot<T>(d, c.brot[j0 + m], l, sign);
+            wv[m] = bw[j0 + m] * sign;
+            xv[m] = ldv<T, V>(x + (int64_t)c.bcol[j0 + m] * d.cs + sl);
+          }
+        }
+#pragma unroll
+        for (int m = 0; m < EC; ++m)
+          if (j0 + m < ee) {
+#pragma unroll
+            for (int i = 0; i < V; ++i)
+              acc.v[i] = j0 + m == eb ? wv[m] * xv[m].v[i] : fma(wv[m], xv[m].v[i], acc.v[i]);
+          }
+      }
+      const int br = c.bconst_row[r];
+      if (br >= 0)
+#pragma unroll
+        for (int i = 0; i < V; ++i) acc.v[i] = acc.v[i] + bc[(int64_t)br * d.inner + l + i];
+      stv<T, V, NT>(y + (int64_t)c.brow_y[r] * d.inner + l, acc);
+    }
+}
+
+
 // ---- FP64 cubed-sphere interpolation weights ------------------------------------------
 // Ghost layer k beyond an edge, tangential index t: the ray through the ghost
 // meets the neighbour face on its grid line at distance k from the edge, at
@@ -2309,6 +2477,119 @@ void device_cs_weights(int64_t N, int64_t h, int32_t* base, double* w, void* str
   if (N * h >= (int64_t(1) << 30)) fail(HBC_EUNSUPPORTED, "grid too large");
   const int n = (int)(N * h);
   hipLaunchKernelGGL(k_cs_weights, dim3((n + 255) / 256), dim3(256), 0, S(stream), (int)N, (int)h, base, w);
+  HIP_CHECK(hipGetLastError());
+}
+
+// ---- consumer tables and launch -------------------------------------------------------
+struct ConsDev {
+  void* dev = nullptr;
+  const int32_t* delta = nullptr;
+  const void* w = nullptr;
+  const CTile* tiles_all = nullptr;
+  const CTile* tiles_int = nullptr;
+  const int32_t* brow_y = nullptr;
+  const int32_t* bptr = nullptr;
+  const int32_t* bcol = nullptr;
+  const void* bw = nullptr;
+  const int8_t* brot = nullptr;
+  const int32_t* bconst_row = nullptr;
+  const void* bconst = nullptr;
+};
+
+void* device_consumer_upload(const Plan& p, const ConsumerHost& C) {
+  Packer pk;
+  const size_t o_dl = pk.vec(C.delta), o_w = pk.reals(C.w, p.dtype), o_ta = pk.vec(C.tiles_all),
+               o_ti = pk.vec(C.tiles_int), o_by = pk.vec(C.brow_y), o_bp = pk.vec(C.bptr), o_bc = pk.vec(C.bcol),
+               o_bw = pk.reals(C.bw, p.dtype), o_br = pk.vec(C.brot), o_bk = pk.vec(C.bconst_row),
+               o_bv = pk.reals(C.bconst, p.dtype);
+  auto* cd = new ConsDev;
+  void* dev = nullptr;
+  const hipError_t e = hipMalloc(&dev, pk.buf.size());
+  if (e != hipSuccess) {
+    delete cd;
+    fail(e == hipErrorOutOfMemory ? HBC_ENOMEM : HBC_EHIP, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  cd->dev = dev;
+  const hipError_t e2 = hipMemcpy(dev, pk.buf.data(), pk.buf.size(), hipMemcpyHostToDevice);
+  if (e2 != hipSuccess) {
+    (void)hipFree(dev);
+    delete cd;
+    fail(HBC_EHIP, std::string("hipMemcpy: ") + hipGetErrorString(e2));
+  }
+  char* b = static_cast<char*>(dev);
+  cd->delta = reinterpret_cast<const int32_t*>(b + o_dl);
+  cd->w = b + o_w;
+  cd->tiles_all = reinterpret_cast<const CTile*>(b + o_ta);
+  cd->tiles_int = reinterpret_cast<const CTile*>(b + o_ti);
+  cd->brow_y = reinterpret_cast<const int32_t*>(b + o_by);
+  cd->bptr = reinterpret_cast<const int32_t*>(b + o_bp);
+  cd->bcol = reinterpret_cast<const int32_t*>(b + o_bc);
+  cd->bw = b + o_bw;
+  cd->brot = reinterpret_cast<const int8_t*>(b + o_br);
+  cd->bconst_row = reinterpret_cast<const int32_t*>(b + o_bk);
+  cd->bconst = b + o_bv;
+  return cd;
+}
+
+void device_consumer_free(void* h) {
+  auto* cd = static_cast<ConsDev*>(h);
+  if (!cd) return;
+  if (cd->dev) (void)hipFree(cd->dev);
+  delete cd;
+}
+
+template <typename T, int V>
+static void launch_consumer(bool nt, dim3 g, dim3 b, hipStream_t st, const PlanDesc& d, const ConsDesc& c) {
+  const bool pipe = c.noff <= 8 && d.inner / V <= (int64_t(1) << d.lpr_shift);
+  if (nt && pipe)
+    hipLaunchKernelGGL((k_consumer<T, V, true, true>), g, b, 0, st, d, c);
+  else if (nt)
+    hipLaunchKernelGGL((k_consumer<T, V, true, false>), g, b, 0, st, d, c);
+  else if (pipe)
+    hipLaunchKernelGGL((k_consumer<T, V, false, true>), g, b, 0, st, d, c);
+  else
+    hipLaunchKernelGGL((k_consumer<T, V, false, false>), g, b, 0, st, d, c);
+}
+
+void device_consumer_apply(const Plan& p, const ConsumerHost& C, void* h, const void* x, void* y, bool fused,
+                           void* stream) {
+  const auto* cd = static_cast<const ConsDev*>(h);
+  PlanDesc d = make_desc(p, const_cast<void*>(x));
+  ConsDesc c{};
+  c.delta = cd->delta;
+  c.w = cd->w;
+  c.noff = C.noff;
+  c.tiles = fused ? cd->tiles_int : cd->tiles_all;
+  c.ntiles = (int32_t)(fused ? C.tiles_int.size() : C.tiles_all.size());
+  c.brow_y = cd->brow_y;
+  c.bptr = cd->bptr;
+  c.bcol = cd->bcol;
+  c.bw = cd->bw;
+  c.brot = cd->brot;
+  c.bconst_row = cd->bconst_row;
+  c.bconst = cd->bconst;
+  c.nbrow = fused ? (int32_t)C.brow_y.size() : 0;
+  c.tile_rows = std::max(1, C.tile_rows);
+  c.y = y;
+  const int64_t nbt = (c.nbrow + c.tile_rows - 1) / c.tile_rows;
+  const int64_t grid = (int64_t)c.ntiles + nbt;
+  if (grid >= (int64_t(1) << 31)) fail(HBC_EUNSUPPORTED, "consumer grid too large");
+  if (grid == 0) return;
+  const dim3 g((unsigned)grid), blk(256);
+  hipStream_t st = S(stream);
+  if (p.dtype == HBC_F64) {
+    if (p.vec >= 2)
+      launch_consumer<double, 2>(d.nt != 0, g, blk, st, d, c);
+    else
+      launch_consumer<double, 1>(d.nt != 0, g, blk, st, d, c);
+  } else {
+    if (p.vec == 4)
+      launch_consumer<float, 4>(d.nt != 0, g, blk, st, d, c);
+    else if (p.vec == 2)
+      launch_consumer<float, 2>(d.nt != 0, g, blk, st, d, c);
+    else
+      launch_consumer<float, 1>(d.nt != 0, g, blk, st, d, c);
+  }
   HIP_CHECK(hipGetLastError());
 }
 

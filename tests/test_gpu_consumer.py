@@ -1,0 +1,176 @@
+"""GPU parity of the consumer (a stencil of offsets and weights reading the
+field after the BC, Sec. IV-C) against oracle.consumer.stencil_after_bc.
+
+The fused form composes each boundary cell's stencil with the BC rows of the
+ghosts it reaches; the unfused form reads the ghosts hbc_apply stored.  With
+programs that carry the oracle's own weights, both must lie within
+1e-13 (FP64) or 16 FP32 roundings of sum_o |w_o| T[c + o], where T is |u| on
+data cells and sum |A| |x| + |b| on ghosts (the magnitudes the sums add).
+"""
+import dataclasses
+import itertools
+
+import numpy as np
+import pytest
+
+import synthinputs
+from helpers import cs_full_field, gpu_available, oracle_weights_program
+from oracle import VectorSub, apply as o_apply, assemble
+from oracle import cubed_sphere as ocs
+from oracle import hpcg as ohpcg
+from oracle.consumer import stencil_after_bc
+
+pytestmark = pytest.mark.gpu
+
+if gpu_available():
+    import torch
+
+    import paper_2605_14780_amd as hb
+
+CROSS = [(0, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]
+CROSS_W = [-4.0, 1.0, 1.0, 1.0, 1.0]
+SKEW = [(0, 2, -1), (0, 0, 0), (0, -1, 0), (0, 0, 2), (0, -2, -2), (0, 1, 1)]
+SKEW_W = [0.25, -1.5, 2.0, 0.75, -0.5, 1.0]
+
+
+def magnitude_bound(op, u, offs, w, vec):
+    """sum_o |w_o| T[c + o]: T = |u| on data cells, |A| |x| + |b| on covered ghosts."""
+    aop = dataclasses.replace(op, parts={k: abs(A) for k, A in op.parts.items()},
+                              b=None if op.b is None else np.abs(op.b))
+    T = np.abs(o_apply(aop, np.abs(u), vec))
+    empty = assemble(op.grid, [])
+    return stencil_after_bc(empty, T, offs, [abs(v) for v in w])
+
+
+def run(cons, plan, x_np, tdt, fused):
+    x = torch.from_numpy(x_np).to(tdt).cuda()
+    ndata = cons._ndata
+    y = torch.full((ndata * plan.inner,), float("nan"), dtype=tdt, device="cuda")
+    if not fused:
+        hb.apply(plan, x)
+    cons.apply(x, y, fused=fused)
+    torch.cuda.synchronize()
+    return y.cpu().numpy().astype(np.float64).reshape(ndata, plan.inner), x
+
+
+def make(plan, offs, w, ndata):
+    c = hb.Consumer(plan, offs, w)
+    c._ndata = ndata
+    return c
+
+
+@pytest.mark.parametrize("N,h,nf,nl,offs,w,dtype", [
+    (12, 3, 4, 2, CROSS, CROSS_W, "f64"),
+    (13, 3, 4, 1, SKEW, SKEW_W, "f64"),
+    (48, 3, 4, 16, CROSS, CROSS_W, "f64"),   # 512-byte rows
+    (48, 3, 4, 16, SKEW, SKEW_W, "f32"),
+    (24, 2, 1, 3, CROSS, CROSS_W, "f64"),
+])
+def test_consumer_oracle_weights_fused_and_unfused(N, h, nf, nl, offs, w, dtype):
+    I = nf * nl
+    vec = (2 * nl, nl, nl) if nf == 4 else None
+    rng = np.random.default_rng(N * I)
+    bvals = rng.standard_normal((h * N, I))
+    b = [(ocs.side_box(2, ocs.LEFT, N, h), bvals)]
+    grid, prog = oracle_weights_program(hb, N, h, vec is not None, b=b)
+    dt, tdt, k = (hb.F64, torch.float64, 1e-13) if dtype == "f64" else (hb.F32, torch.float32, 16 * 2.0 ** -24)
+    plan = hb.Plan(prog, inner=I, vec=vec, dtype=dt)
+    og = ocs.grid(N, h)
+    op = assemble(og, ocs.subs(N, h, "lagrange", vector=vec is not None) +
+                  [VectorSub(ocs.side_box(2, ocs.LEFT, N, h), bvals)])
+    full = cs_full_field(N, h, nf, nl, seed=N, noise=1e-3)
+    cons = make(plan, offs, w, og.ndata)
+    st = cons.stats()
+    assert st["boundary_rows"] > 0 and st["boundary_entries"] > st["boundary_rows"]
+    ref = stencil_after_bc(op, full, offs, w, vec)
+    bound = k * magnitude_bound(op, full, offs, w, vec)
+    for fused in (True, False):
+        y, x = run(cons, plan, full, tdt, fused)
+        assert np.isfinite(y).all(), fused
+        if fused:  # x is only read
+            assert np.isnan(x.cpu().numpy()[og.ghost_cells]).all()
+        assert (np.abs(y - ref) <= bound).all(), (fused, float((np.abs(y - ref) / bound).max()))
+
+
+@pytest.mark.parametrize("N,h,nl", [(48, 3, 8), (96, 3, 64)])
+def test_consumer_library_weights_fused_equals_unfused(N, h, nl):
+    """With the library's own FP64 weights (the bench's program) the fused and
+    unfused forms agree to the arithmetic bound, and the fused form leaves x
+    untouched."""
+    I = 4 * nl
+    vec = (2 * nl, nl, nl)
+    grid, prog = hb.cs_program(N, h, hb.CS_LAGRANGE, vector=True)
+    plan = hb.Plan(prog, inner=I, vec=vec)
+    og = ocs.grid(N, h)
+    full = cs_full_field(N, h, 4, nl, seed=2, noise=1e-3)
+    cons = make(plan, CROSS, CROSS_W, og.ndata)
+    yf, xf = run(cons, plan, full, torch.float64, True)
+    yu, _ = run(cons, plan, full, torch.float64, False)
+    scale = np.abs(full[og.data_cells]).max(axis=0)
+    assert (np.abs(yf - yu) <= 1e-13 * 8 * scale).all()
+    assert np.array_equal(np.nan_to_num(xf.cpu().numpy(), nan=7.0), np.nan_to_num(full, nan=7.0))
+
+
+def test_consumer_footprint_plan():
+    """A plan compiled with the consumer's own footprint (only the ghosts the
+    stencil reads) gives the same fused and unfused results as the full plan."""
+    N, h, nl = 24, 3, 4
+    I = 4 * nl
+    vec = (2 * nl, nl, nl)
+    og = ocs.grid(N, h)
+    full = cs_full_field(N, h, 4, nl, seed=6)
+    out = []
+    for consumer in (False, True):
+        grid, prog = oracle_weights_program(hb, N, h, True)
+        if consumer:
+            prog.set_consumer(CROSS)
+        plan = hb.Plan(prog, inner=I, vec=vec)
+        if consumer:
+            assert plan.stats()["rows_dead"] > 0
+        cons = make(plan, CROSS, CROSS_W, og.ndata)
+        out += [run(cons, plan, full, torch.float64, f)[0] for f in (True, False)]
+    ref = stencil_after_bc(assemble(og, ocs.subs(N, h, "lagrange", vector=True)), full, CROSS, CROSS_W, vec)
+    for y in out:
+        assert np.abs(y - ref).max() <= 1e-12 * np.abs(full[og.data_cells]).max()
+    assert np.array_equal(out[0], out[2]) and np.array_equal(out[1], out[3])
+
+
+@pytest.mark.parametrize("nb,n", [(2, 16), (3, 7)])
+def test_consumer_27_point_on_cartesian_blocks(nb, n):
+    """The 27-point operator as a consumer of the halo-1 Cartesian program:
+    against the oracle's ghosted-block operator (bound 64 eps of the absolute
+    row sums), fused and unfused."""
+    x = synthinputs.uniform((nb * n,) * 3, seed=3)
+    grid = hb.Grid.cartesian([nb] * 3, [n] * 3, 1)
+    prog = hb.Program(grid)
+    prog.cart_add_halo([nb] * 3, [n] * 3, 1)
+    plan = hb.Plan(prog, inner=1)
+    og = ohpcg.grid(nb, n)
+    blocks = ohpcg.ghosted_blocks(x, nb)
+    full = np.full(og.ncells, np.nan)
+    for b in range(nb ** 3):
+        full[og.cells_of_box(b, og.blocks[b].data)] = blocks[b][1:-1, 1:-1, 1:-1].reshape(-1)
+    offs = [(0,) + d for d in itertools.product((-1, 0, 1), repeat=3)]
+    w = [26.0 if d == (0, 0, 0, 0) else -1.0 for d in offs]
+    want = np.concatenate([ohpcg.stencil27(b).reshape(-1) for b in blocks])
+    bound = 64 * 2.0 ** -53 * np.concatenate([ohpcg.abs_row_sum(b).reshape(-1) for b in blocks])
+    cons = make(plan, offs, w, og.ndata)
+    for fused in (True, False):
+        y, _ = run(cons, plan, full[:, None], torch.float64, fused)
+        assert (np.abs(y[:, 0] - want) <= bound).all(), fused
+
+
+def test_consumer_errors():
+    grid, prog = hb.cs_program(12, 2, hb.CS_SYNC)
+    plan = hb.Plan(prog, inner=2)
+    with pytest.raises(hb.HbcError) as e:
+        hb.Consumer(plan, [(0, 3, 0)], [1.0])  # reads beyond the halo
+    assert e.value.code == hb.EINVAL
+    with pytest.raises(hb.HbcError) as e:
+        hb.Consumer(hb.Plan(prog, inner=2, order=hb.PLANE_MAJOR), CROSS, CROSS_W)
+    assert e.value.code == hb.EUNSUPPORTED
+    cons = hb.Consumer(plan, CROSS, CROSS_W)
+    x = torch.zeros(grid.cells * 2, dtype=torch.float64, device="cuda")
+    with pytest.raises(hb.HbcError) as e:
+        cons.apply(x, torch.zeros(7, dtype=torch.float64, device="cuda"))
+    assert e.value.code == hb.EINVAL
