@@ -2,6 +2,7 @@
 // Every entry point catches all C++ exceptions and turns them into codes.
 #include <algorithm>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -158,13 +159,13 @@ int hbc_grid_create(int32_t ndim, const int64_t* lo, const int64_t* hi, hbc_grid
     need(out && lo && hi, "NULL argument");
     need(ndim >= 1 && ndim <= HBC_MAX_DIM, "ndim must be in [1, 6]");
     for (int d = 0; d < ndim; ++d) need(hi[d] > lo[d], "global box must be non-empty");
-    auto* g = new hbc_grid;
+    auto g = std::make_unique<hbc_grid>();
     g->g.nd = ndim;
     for (int d = 0; d < ndim; ++d) {
       g->g.lo[d] = g->g.plo[d] = lo[d];
       g->g.hi[d] = g->g.phi[d] = hi[d];
     }
-    *out = g;
+    *out = g.release();
   });
 }
 
@@ -228,7 +229,7 @@ int hbc_cs_grid_create(int64_t N, int64_t h, hbc_grid** out) {
     need(out != nullptr, "NULL argument");
     need(N >= 4 && h >= 1 && 2 * h <= N,
          "cubed sphere needs N >= 4 and 1 <= h <= N/2 (deeper ghost layers leave the face's gnomonic chart)");
-    auto* g = new hbc_grid;
+    auto g = std::make_unique<hbc_grid>();  // freed if a later allocation throws
     Grid& G = g->g;
     G.nd = 3;
     G.lo[0] = 0; G.hi[0] = 6;
@@ -246,7 +247,7 @@ int hbc_cs_grid_create(int64_t N, int64_t h, hbc_grid** out) {
       G.blocks.push_back(b);
     }
     finish_grid(G);
-    *out = g;
+    *out = g.release();
   });
 }
 
@@ -255,7 +256,7 @@ int hbc_cart_grid_create(const int32_t* nb, const int64_t* n, int64_t h, hbc_gri
     need(out && nb && n, "NULL argument");
     need(h >= 1, "halo must be >= 1");
     for (int d = 0; d < 3; ++d) need(nb[d] >= 1 && n[d] >= 1, "block counts and sizes must be >= 1");
-    auto* g = new hbc_grid;
+    auto g = std::make_unique<hbc_grid>();  // freed if a later allocation throws
     Grid& G = g->g;
     G.nd = 4;
     const int64_t nblk = (int64_t)nb[0] * nb[1] * nb[2];
@@ -276,7 +277,7 @@ int hbc_cart_grid_create(const int32_t* nb, const int64_t* n, int64_t h, hbc_gri
       G.blocks.push_back(B);
     }
     finish_grid(G);
-    *out = g;
+    *out = g.release();
   });
 }
 
@@ -285,9 +286,9 @@ int hbc_program_create(const hbc_grid* g, hbc_program** out) {
   return guard([&] {
     need(g && out, "NULL argument");
     need(!g->g.blocks.empty(), "grid has no blocks");
-    auto* p = new hbc_program;
+    auto p = std::make_unique<hbc_program>();
     p->p.grid = g->g;
-    *out = p;
+    *out = p.release();
   });
 }
 
@@ -682,14 +683,9 @@ int hbc_graph_create(const hbc_plan* plan, int32_t op, void* const* fields, int6
       if (plan->p.stats.rows_data > 0) fail(HBC_EUNSUPPORTED, "no adjoint for plans with data rows");
       ensure_csc(const_cast<hbc_plan*>(plan));
     }
-    auto* g = new hbc_graph;
-    try {
-      g->g = device_graph_create(plan->p, op, fields, nfields, reps, stream);
-    } catch (...) {
-      delete g;
-      throw;
-    }
-    *out = g;
+    auto g = std::make_unique<hbc_graph>();
+    g->g = device_graph_create(plan->p, op, fields, nfields, reps, stream);
+    *out = g.release();
   });
 }
 
@@ -796,15 +792,10 @@ int hbc_batch_create(hbc_plan* const* plans, int32_t n, hbc_batch** out) {
       need(plans[k]->p.layout.order == HBC_POINT_MAJOR, "batches take point-major plans");
       if (plans[k]->p.stats.rows_data > 0) fail(HBC_EUNSUPPORTED, "batches do not take plans with data rows");
     }
-    auto* b = new hbc_batch;
+    auto b = std::make_unique<hbc_batch>();
     b->plans.assign(ps.begin(), ps.end());
-    try {
-      b->b = device_batch_create(ps.data(), n);
-    } catch (...) {
-      delete b;
-      throw;
-    }
-    *out = b;
+    b->b = device_batch_create(ps.data(), n);
+    *out = b.release();
   });
 }
 
