@@ -400,7 +400,11 @@ int hbc_stencil27(const hbc_plan* plan, const void* x, int64_t x_nelem, void* y,
  * in one kernel; with write_ghosts != 0 it also writes x's covered ghost cells
  * (as hbc_apply would), otherwise x is only read (the ghosts are consumed
  * without being stored, Sec. IV-C's removal of BC writes no later reader
- * needs). */
+ * needs).  Each of a block's 26 ghost regions must be wholly one translated
+ * copy of a neighbouring block, wholly zero rows, or wholly uncovered (read
+ * from x as it is), and the plan must have no data rows; HBC_EUNSUPPORTED
+ * otherwise (the unfused form has no such condition).  Blocks whose 32-plane
+ * chunks reach 2 GiB are refused by both forms (HBC_EUNSUPPORTED). */
 int hbc_fused_stencil27(const hbc_plan* plan, void* x, int64_t x_nelem, void* y, int64_t y_nelem,
                         int32_t write_ghosts, void* stream);
 

@@ -426,9 +426,11 @@ struct Plan {
   const int32_t* d_al_zero = nullptr;
   const AdjTile* d_adj_tiles = nullptr;
   // 27-point consumer: per block and neighbour direction, the block the BC
-  // copies from (-1 zero rows, -2 uncovered); computed at plan creation
-  bool st_ok = false;
-  std::string st_reason;
+  // copies from (-1 zero rows, -2 uncovered); computed at plan creation.
+  // st_ok: the grid suits the stencil (equal blocks, one-cell halo, inner 1);
+  // st_fused: the BC can also be read through st_info by the fused form.
+  bool st_ok = false, st_fused = false;
+  std::string st_reason, st_fused_reason;
   std::vector<int64_t> st_info;
   const int64_t* d_st_info = nullptr;
   void* d_st_dev = nullptr;

@@ -23,6 +23,7 @@
 #include <mutex>
 #include <sstream>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "device.hpp"
@@ -1396,123 +1397,158 @@ __global__ __launch_bounds__(256) void k_adjoint_lds(PlanDesc d, AdjDesc a, AdjL
 // ---- 27-point consumer on Cartesian blocks with a one-cell halo ----------------------------
 struct StDesc {
   int32_t nblk, nz, ny, nx;
-  int64_t sz, sy;     // cell strides of a block's full box
-  int64_t bcells;     // cells per block full box
+  int64_t sz, sy;       // cell strides of a block's full box
+  int64_t bcells;       // cells per block full box
   const int64_t* info;  // per block, 27 directions: source block, -1 zero, -2 own ghost
 };
 
-__device__ __forceinline__ int dir_index(int dz, int dy, int dx) { return (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1); }
-
-// Value of local position (z, y, x) of block b (one-cell halo) read through
-// the BC: data cells directly, ghosts from the source block or zero.
-template <typename T>
-__device__ __forceinline__ T bc_load(const T* __restrict__ x, const StDesc& st, const int64_t* info, int b, int z,
-                                     int y, int xx) {
-  const int dz = z < 0 ? -1 : (z >= st.nz ? 1 : 0);
-  const int dy = y < 0 ? -1 : (y >= st.ny ? 1 : 0);
-  const int dx = xx < 0 ? -1 : (xx >= st.nx ? 1 : 0);
-  int64_t blk = b;
-  if (dz | dy | dx) {
-    blk = info[dir_index(dz, dy, dx)];
-    if (blk == -1) return T(0);
-    if (blk == -2) {
-      blk = b;
-    } else {
-      z -= dz * st.nz;
-      y -= dy * st.ny;
-      xx -= dx * st.nx;
-    }
-  }
-  return x[blk * st.bcells + (int64_t)(z + 1) * st.sz + (int64_t)(y + 1) * st.sy + (xx + 1)];
-}
-
 // 27-point operator, LDS-tiled.  A workgroup owns a 64 (x) x 8 (y) column of
-// outputs over ZC planes and marches in z: each (x, y) plane of the tile plus
-// its one-cell halo (66 x (TY + 2) values) is staged in LDS (double buffered: the
-// next plane's global loads are in flight while the current plane is summed),
-// the 3x3 plane sums are formed separably (3 along x, then 3 along y), and
+// outputs over ST_ZC planes and marches in z: each (x, y) plane of the tile
+// with its one-cell halo (66 x 10 values) is staged in LDS, the 3x3 plane sums
+// are formed separably (3 along x, then 3 along y), and
 // y = 27 x_c - (S(z-1) + S(z) + S(z+1)) = 26 x_c - (sum of the 26 neighbours).
-// FUSED: values outside a block's data box are read through the BC (the
-// source block for halo copies, zero for padding).
-constexpr int ST_TX = 64, ST_TY = 8, ST_ZC = 32;  // 64 x 16 and 16..64 planes measured: no gain
+// Two planes of global loads are in flight while one is summed (register sets
+// A and B), and every memory instruction of the march is issued
+// unconditionally: loads take clamped addresses and drop the value, stores go
+// through buffer resources with an out-of-range offset where a lane stores
+// nothing.  Loads and stores retire from one in-order counter, so a guarded
+// instruction would make the compiler wait for everything issued before the
+// plane it needs (earlier stores included); straight-line code lets each wait
+// cover only that plane.
+// FUSED: values outside a block's data box come through the BC (the source
+// block's data cell for halo copies, zero for zero rows, x itself where the
+// BC writes nothing).  GHOSTS: each ghost value read through the BC is also
+// stored into x by the one tile that owns it (the tile whose data range holds
+// the ghost's position clamped into the data box), which leaves x's covered
+// ghosts as the BC's apply would.
+constexpr int ST_TX = 64, ST_TY = 8, ST_ZC = 32;
 constexpr int ST_RPT = ST_TY / 4;  // output rows per thread (4 wavefronts of 64 columns)
 constexpr int ST_LX = ST_TX + 2, ST_LY = ST_TY + 2, ST_PLANE = ST_LX * ST_LY;
+constexpr int ST_NLOAD = (ST_LY * ST_TX + 255) / 256;  // interior columns of the TY + 2 rows
+constexpr int ST_NS = ST_NLOAD + 1;                     // + one value of the two halo columns
+constexpr int ST_LDS = ST_PLANE + 256;                  // + one slot per thread for values with no place
+constexpr uint32_t ST_OOB = 0x80000000u;                // buffer offset past every range (ranges < 2 GiB)
+constexpr int32_t ST_RSRC_WORD3 = 0x00020000;           // raw buffer, 32-bit data format
 static_assert(ST_TY % 4 == 0, "tile rows must split over 4 wavefronts");
 
-// Value of local position (z, y, xx) of block b for the consumer (x holds the
-// ghosted blocks).  FUSED: ghost positions come through the BC.
-template <typename T, bool FUSED>
-__device__ __forceinline__ T st_value(const T* __restrict__ x, const StDesc& st, const int64_t* info, int b, int z,
-                                      int y, int xx) {
-  const int64_t off = b * st.bcells + (int64_t)(z + 1) * st.sz + (int64_t)(y + 1) * st.sy + (xx + 1);
-  if (!FUSED) return x[off];
-  const bool ghost = z < 0 || z >= st.nz || y < 0 || y >= st.ny || xx < 0 || xx >= st.nx;
-  if (!ghost) return x[off];
-  return bc_load<T>(x, st, info, b, z, y, xx);
+// One value a thread fetches per plane: column (y, xx) of the block's halo box.
+struct StSlot {
+  int y, xx;   // block-local position (clamped into the halo box where !valid)
+  int dy, dx;  // -1, 0, 1: below, inside, above the data range
+  int lds;     // LDS slot
+  bool valid;  // a position of the tile's halo box inside the block's halo box
+  bool own;    // this tile stores ghosts of this column (its clamped position lies in the tile)
+};
+
+__device__ __forceinline__ int st_dir(int v, int n) { return v < 0 ? -1 : (v >= n ? 1 : 0); }
+
+// k < ST_NLOAD: interior columns of the TY + 2 rows (element e = thread + 256 k,
+// one row per wavefront access); k == ST_NLOAD: the two halo columns
+// (threads 0 .. 2 (TY + 2) - 1).
+__device__ __forceinline__ StSlot st_slot(const StDesc& st, int k, int y0, int x0) {
+  StSlot s;
+  const int t = threadIdx.x;
+  int ly, lx;
+  if (k < ST_NLOAD) {
+    const int e = t + k * 256;
+    ly = e >> 6;
+    lx = (e & 63) + 1;
+    s.valid = e < ST_LY * ST_TX;
+    s.lds = s.valid ? ly * ST_LX + lx : ST_PLANE + t;
+  } else {
+    const bool h = t < 2 * ST_LY;
+    ly = h ? t >> 1 : 0;
+    lx = h && (t & 1) ? ST_LX - 1 : 0;
+    s.valid = h;
+    s.lds = h ? ly * ST_LX + lx : ST_PLANE + t;
+  }
+  const int y = y0 + ly - 1, xx = x0 + lx - 1;  // xx == nx / y == ny: the far halo of a partial tile
+  s.valid = s.valid && y <= st.ny && xx <= st.nx;
+  s.y = min(y, st.ny);
+  s.xx = min(xx, st.nx);
+  s.dy = st_dir(s.y, st.ny);
+  s.dx = st_dir(s.xx, st.nx);
+  const int cy = min(max(s.y, 0), st.ny - 1), cx = min(max(s.xx, 0), st.nx - 1);
+  s.own = s.valid && cy >= y0 && cy < y0 + ST_TY && cx >= x0 && cx < x0 + ST_TX;
+  return s;
 }
 
-// Loads of one (x, y) plane of the tile with its halo: the 64 interior columns
-// of the TY + 2 rows (one row per wavefront access, so the ghost test is
-// uniform per wavefront) and the two halo columns (2 (TY + 2) values).
-constexpr int ST_NLOAD = (ST_LY * ST_TX + 255) / 256;
+template <typename T, int AUX>
+__device__ __forceinline__ void st_buf_store(T v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+  if constexpr (sizeof(T) == 8) {
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, AUX);
+  } else {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, AUX);
+  }
+}
 
-template <typename T, bool FUSED>
-__device__ __forceinline__ void st_fetch(const T* __restrict__ x, const StDesc& st, const int64_t* info, int b, int z,
-                                         int y0, int x0, T (&r)[ST_NLOAD], T& rh) {
+// Issue the loads of plane z into one register set.  keep: bit k set where
+// value k is used as loaded (a valid position that is not a zero row).
+// goff: byte offsets of the ghost stores in the chunk's x resource (ST_OOB: none).
+template <typename T, bool FUSED, bool GHOSTS>
+__device__ __forceinline__ void st_fetch(const T* __restrict__ x, const StDesc& st, const int64_t* info, int b,
+                                         int z, int z0, int z1, const StSlot (&sl)[ST_NS], T (&v)[ST_NS],
+                                         uint32_t& keep, uint32_t (&goff)[ST_NS]) {
+  const int dz = st_dir(z, st.nz);
+  // ghosts of plane z belong to this chunk when z is a z ghost (only the first
+  // or last chunk reads it) or one of the chunk's own planes
+  const bool zown = dz != 0 || (z >= z0 && z < z1);
+  keep = 0;
 #pragma unroll
-  for (int k = 0; k < ST_NLOAD; ++k) {
-    const int e = threadIdx.x + k * 256;
-    const int ly = e >> 6, xx = x0 + (e & 63);
-    const int y = y0 + ly - 1;
-    T v = T(0);
-    // xx == nx is the right halo of a partial tile
-    if (e < ST_LY * ST_TX && y <= st.ny && xx <= st.nx)
-      v = st_value<T, FUSED>(x, st, info, b, z, y, xx);
-    r[k] = v;
-  }
-  rh = T(0);
-  if (threadIdx.x < 2 * ST_LY) {
-    const int ly = threadIdx.x >> 1, side = threadIdx.x & 1;
-    const int y = y0 + ly - 1, xx = side ? x0 + ST_TX : x0 - 1;
-    if (y <= st.ny && xx <= st.nx) rh = st_value<T, FUSED>(x, st, info, b, z, y, xx);
+  for (int k = 0; k < ST_NS; ++k) {
+    int64_t blk = b;
+    int zz = z, yy = sl[k].y, xx = sl[k].xx;
+    bool zero = false, covered = false;
+    const bool ghost = dz != 0 || sl[k].dy != 0 || sl[k].dx != 0;
+    if (FUSED && ghost) {
+      const int64_t o = info[(dz + 1) * 9 + (sl[k].dy + 1) * 3 + (sl[k].dx + 1)];
+      covered = o != -2;
+      zero = o == -1;
+      if (o >= 0) {
+        blk = o;
+        zz -= dz * st.nz;
+        yy -= sl[k].dy * st.ny;
+        xx -= sl[k].dx * st.nx;
+      }
+    }
+    v[k] = x[blk * st.bcells + (int64_t)(zz + 1) * st.sz + (int64_t)(yy + 1) * st.sy + (xx + 1)];
+    if (sl[k].valid && !zero) keep |= 1u << k;
+    if (GHOSTS) {
+      const bool g = sl[k].own && ghost && covered && zown;
+      goff[k] = g ? (uint32_t)(((int64_t)(z + 1 - z0) * st.sz + (int64_t)(sl[k].y + 1) * st.sy + (sl[k].xx + 1)) *
+                               (int64_t)sizeof(T))
+                  : ST_OOB;
+    }
   }
 }
 
-template <typename T>
-__device__ __forceinline__ void st_store(T* plane, const T (&r)[ST_NLOAD], T rh) {
+// One LDS write per value (values with no place go to the thread's spare
+// slot) and, with GHOSTS, one buffer store per value (dropped where goff is
+// out of range).
+template <typename T, bool GHOSTS>
+__device__ __forceinline__ void st_put(T* plane, const StSlot (&sl)[ST_NS], const T (&v)[ST_NS], uint32_t keep,
+                                       const uint32_t (&goff)[ST_NS], __amdgpu_buffer_rsrc_t xr) {
 #pragma unroll
-  for (int k = 0; k < ST_NLOAD; ++k) {
-    const int e = threadIdx.x + k * 256;
-    if (e < ST_LY * ST_TX) plane[(e >> 6) * ST_LX + (e & 63) + 1] = r[k];
-  }
-  if (threadIdx.x < 2 * ST_LY) {
-    const int ly = threadIdx.x >> 1, side = threadIdx.x & 1;
-    plane[ly * ST_LX + (side ? ST_LX - 1 : 0)] = rh;
+  for (int k = 0; k < ST_NS; ++k) {
+    const T val = (keep >> k) & 1u ? v[k] : T(0);
+    plane[sl[k].lds] = val;
+    if (GHOSTS) st_buf_store<T, 0>(val, xr, goff[k]);
   }
 }
 
-// One launch, two kinds of workgroup.  The first nst workgroups are stencil
-// tiles; the bc_grid after them run the BC plan's row tiles (ghost
-// materialisation: they write only covered ghost cells, which the stencil
-// never reads, since it takes those values through the BC from the source
-// data cells).  bc_grid = 0 leaves x untouched.  Workgroups are dealt to the
-// 8 XCDs round-robin; stencil tiles are renumbered so that each XCD gets a
-// contiguous run of them (neighbouring tiles share halo rows in its L2).
-template <typename T, bool FUSED, int V>
-__global__ __launch_bounds__(256) void k_stencil27(const T* __restrict__ x, T* __restrict__ yout, StDesc st,
-                                                   PlanDesc d, const RowTile* __restrict__ bc_tiles, int bc_nt,
-                                                   int bc_grid) {
-  __shared__ T buf[2][ST_PLANE];
+// One launch of stencil tiles.  Workgroups are dealt to the 8 XCDs
+// round-robin; tiles are renumbered so that each XCD gets a contiguous run of
+// them (neighbouring tiles share halo rows in its L2).  Per-chunk buffer
+// ranges stay below 2 GiB (checked by the host).
+template <typename T, bool FUSED, bool GHOSTS>
+__global__ __launch_bounds__(256) void k_stencil27(const T* __restrict__ x, T* xg, T* __restrict__ yout,
+                                                   StDesc st) {
+  static_assert(FUSED || !GHOSTS, "ghost stores need the fused form");
+  __shared__ T buf[2][ST_LDS];
   __shared__ int64_t info[27];  // this block's direction table, read once
   const int ntx = (st.nx + ST_TX - 1) / ST_TX, nty = (st.ny + ST_TY - 1) / ST_TY, nzc = (st.nz + ST_ZC - 1) / ST_ZC;
   const int nst = ntx * nty * nzc * st.nblk;
-  if constexpr (FUSED) {
-    // halo programs the consumer accepts hold copies and zero rows only
-    if ((int)blockIdx.x >= nst) {
-      for (int t = blockIdx.x - nst; t < bc_nt; t += bc_grid) rt_tile<T, V, 1, false, 4, 0>(d, bc_tiles[t], false);
-      return;
-    }
-  }
   int bid;
   {
     const int q = nst >> 3, rem = nst & 7, xcd = blockIdx.x & 7, j = blockIdx.x >> 3;
@@ -1531,51 +1567,82 @@ __global__ __launch_bounds__(256) void k_stencil27(const T* __restrict__ x, T* _
     if (threadIdx.x < 27) info[threadIdx.x] = st.info[b * 27 + threadIdx.x];
     __syncthreads();
   }
-  T r[ST_NLOAD], rh;
-  st_fetch<T, FUSED>(x, st, info, b, z0 - 1, y0, x0, r, rh);
-  st_store<T>(buf[0], r, rh);
+  StSlot sl[ST_NS];
+#pragma unroll
+  for (int k = 0; k < ST_NS; ++k) sl[k] = st_slot(st, k, y0, x0);
+  const int64_t plane_out = (int64_t)st.ny * st.nx;
+  // y: this chunk's planes of block b; x (ghost stores): its planes z0 - 1 .. z1
+  const __amdgpu_buffer_rsrc_t yr = __builtin_amdgcn_make_buffer_rsrc(
+      yout + ((int64_t)b * st.nz + z0) * plane_out, 0, (int)((z1 - z0) * plane_out * (int64_t)sizeof(T)),
+      ST_RSRC_WORD3);
+  __amdgpu_buffer_rsrc_t xr = yr;
+  if (GHOSTS)
+    xr = __builtin_amdgcn_make_buffer_rsrc(xg + b * st.bcells + (int64_t)z0 * st.sz, 0,
+                                           (int)((z1 - z0 + 2) * st.sz * (int64_t)sizeof(T)), ST_RSRC_WORD3);
+  T A[ST_NS], B[ST_NS];
+  uint32_t ka, kb, ga[ST_NS], gb[ST_NS];
+  // plane z0 - 1 goes straight to LDS buffer 0; planes z0 and z0 + 1 go in flight
+  st_fetch<T, FUSED, GHOSTS>(x, st, info, b, z0 - 1, z0, z1, sl, A, ka, ga);
+  st_put<T, GHOSTS>(buf[0], sl, A, ka, ga, xr);
+  st_fetch<T, FUSED, GHOSTS>(x, st, info, b, z0, z0, z1, sl, A, ka, ga);
+  st_fetch<T, FUSED, GHOSTS>(x, st, info, b, min(z0 + 1, z1), z0, z1, sl, B, kb, gb);
   __syncthreads();
   T sm2[ST_RPT], sm1[ST_RPT], cm1[ST_RPT];
 #pragma unroll
   for (int q = 0; q < ST_RPT; ++q) sm2[q] = sm1[q] = cm1[q] = T(0);
-  const int64_t plane_out = (int64_t)st.ny * st.nx;
-  const int64_t yb = (int64_t)b * st.nz * plane_out;
-  for (int p = z0 - 1; p <= z1; ++p) {
+  // One step: LDS holds plane p; sum it, store y(p - 1) (STORE), put plane
+  // p + 1 from the set S into the other LDS buffer (PUT), then reuse S for
+  // plane p + 3 (clamped to z1: a spare load keeps the instruction count fixed).
+  auto step = [&](int p, T(&S)[ST_NS], uint32_t& kS, uint32_t(&gS)[ST_NS], auto store_c, auto put_c) {
+    constexpr bool STORE = decltype(store_c)::value, PUT = decltype(put_c)::value;
     const int cur = (p - z0 + 1) & 1;
-    if (p + 1 <= z1) st_fetch<T, FUSED>(x, st, info, b, p + 1, y0, x0, r, rh);
-    // separable 3x3 sums of plane p for this thread's rows (LDS rows
-    // RPT*ty .. RPT*ty + RPT + 1)
     T hsum[ST_RPT + 2];
 #pragma unroll
     for (int q = 0; q < ST_RPT + 2; ++q) {
       const T* row = &buf[cur][(ST_RPT * ty + q) * ST_LX + tx];
       hsum[q] = (row[0] + row[1]) + row[2];
     }
-    T sn[ST_RPT], cn[ST_RPT];
+    T sn[ST_RPT], cn[ST_RPT], yv[ST_RPT];
 #pragma unroll
     for (int q = 0; q < ST_RPT; ++q) {
       sn[q] = (hsum[q] + hsum[q + 1]) + hsum[q + 2];
       cn[q] = buf[cur][(ST_RPT * ty + q + 1) * ST_LX + tx + 1];
-    }
-    if (p >= z0 + 1) {
-      const int zo = p - 1;
-#pragma unroll
-      for (int q = 0; q < ST_RPT; ++q) {
-        const int yy = y0 + ST_RPT * ty + q, xx = x0 + tx;
-        if (yy < st.ny && xx < st.nx)
-          __builtin_nontemporal_store(T(27) * cm1[q] - ((sm2[q] + sm1[q]) + sn[q]),
-                                      &yout[yb + (int64_t)zo * plane_out + (int64_t)yy * st.nx + xx]);
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < ST_RPT; ++q) {
+      yv[q] = T(27) * cm1[q] - ((sm2[q] + sm1[q]) + sn[q]);
       sm2[q] = sm1[q];
       sm1[q] = sn[q];
       cm1[q] = cn[q];
     }
-    if (p + 1 <= z1) st_store<T>(buf[cur ^ 1], r, rh);
-    __syncthreads();
+    if constexpr (PUT) st_put<T, GHOSTS>(buf[cur ^ 1], sl, S, kS, gS, xr);
+    if constexpr (STORE) {
+#pragma unroll
+      for (int q = 0; q < ST_RPT; ++q) {
+        const int yy = y0 + ST_RPT * ty + q, xx = x0 + tx;
+        const uint32_t off = yy < st.ny && xx < st.nx
+                                 ? (uint32_t)(((int64_t)(p - 1 - z0) * plane_out + (int64_t)yy * st.nx + xx) *
+                                              (int64_t)sizeof(T))
+                                 : ST_OOB;
+        st_buf_store<T, 2>(yv[q], yr, off);  // non-temporal
+      }
+    }
+    if constexpr (PUT) {
+      __syncthreads();
+      st_fetch<T, FUSED, GHOSTS>(x, st, info, b, min(p + 3, z1), z0, z1, sl, S, kS, gS);
+    }
+  };
+  using Y = std::true_type;
+  using N = std::false_type;
+  step(z0 - 1, A, ka, ga, N{}, Y{});  // plane z0 from A
+  step(z0, B, kb, gb, N{}, Y{});      // plane z0 + 1 from B
+  int p = z0 + 1;
+  for (; p + 1 <= z1 - 1; p += 2) {
+    step(p, A, ka, ga, Y{}, Y{});
+    step(p + 1, B, kb, gb, Y{}, Y{});
   }
+  if (p <= z1 - 1) {
+    step(p, A, ka, ga, Y{}, Y{});
+    ++p;
+  }
+  step(p, A, ka, ga, Y{}, N{});  // p == z1: the last output plane z1 - 1
 }
 
 // ---- consumer of the BC's ghosts (stencil of offsets and weights) --------------------
@@ -1957,7 +2024,7 @@ void device_upload_plan(Plan& p) {
     p.d_dr_scratch = sc;
   }
   device_upload_tiles(p);
-  if (p.st_ok) {
+  if (p.st_fused) {
     void* si = nullptr;
     HIP_CHECK(hipMalloc(&si, p.st_info.size() * sizeof(int64_t)));
     p.d_st_dev = si;
@@ -2429,7 +2496,9 @@ void device_adjoint_noalloc(const Plan& p, void* grad, void* stream) {
 }
 
 void device_stencil27(Plan& p, const void* x, void* y, void* stream, bool fused, void* xghost) {
-  if (!p.st_ok || !p.d_st_info) fail(HBC_EUNSUPPORTED, p.st_reason.empty() ? "plan not usable by the 27-point consumer" : p.st_reason);
+  if (!p.st_ok) fail(HBC_EUNSUPPORTED, p.st_reason.empty() ? "plan not usable by the 27-point consumer" : p.st_reason);
+  if (fused && (!p.st_fused || !p.d_st_info))
+    fail(HBC_EUNSUPPORTED, p.st_fused_reason.empty() ? "plan not usable by the fused 27-point consumer" : p.st_fused_reason);
   StDesc st;
   st.nblk = p.st_nblocks;
   st.nz = (int32_t)p.st_n[0];
@@ -2442,34 +2511,28 @@ void device_stencil27(Plan& p, const void* x, void* y, void* stream, bool fused,
   const int ntx = (st.nx + ST_TX - 1) / ST_TX, nty = (st.ny + ST_TY - 1) / ST_TY, nzc = (st.nz + ST_ZC - 1) / ST_ZC;
   const int64_t grid = (int64_t)ntx * nty * nzc * st.nblk;
   if (grid >= (int64_t(1) << 31)) fail(HBC_EUNSUPPORTED, "grid too large for the 27-point consumer");
+  // each workgroup's x and y ranges are buffer resources addressed in 32 bits
+  const int64_t esz = p.dtype == HBC_F64 ? 8 : 4;
+  if ((int64_t)(ST_ZC + 2) * st.sz * esz >= (int64_t)ST_OOB || (int64_t)ST_ZC * st.ny * st.nx * esz >= (int64_t)ST_OOB)
+    fail(HBC_EUNSUPPORTED, "blocks too large for the 27-point consumer (32-plane chunks of 2 GiB or more)");
   hipStream_t s = S(stream);
-  // ghost materialisation rides in the same launch as extra workgroups
-  const int bc_nt = xghost ? (int)p.host.rtiles.size() : 0;
-  const int bc_grid = bc_nt == 0 ? 0 : (p.tune.persistent > 0 ? std::min(p.tune.persistent, bc_nt) : bc_nt);
-  if ((int64_t)grid + bc_grid >= (int64_t(1) << 31)) fail(HBC_EUNSUPPORTED, "grid too large for the 27-point consumer");
-  const PlanDesc d = make_desc(p, xghost);
-  const dim3 g((unsigned)(grid + bc_grid)), blk(256);
-  if (p.dtype == HBC_F64) {
-    const double* xd = static_cast<const double*>(x);
-    double* yd = static_cast<double*>(y);
+  const dim3 g((unsigned)grid), blk(256);
+  if (grid == 0) return;
+  auto go = [&](auto tag) {
+    using T = decltype(tag);
+    const T* xt = static_cast<const T*>(x);
+    T* yt = static_cast<T*>(y);
     if (!fused)
-      hipLaunchKernelGGL((k_stencil27<double, false, 1>), g, blk, 0, s, xd, yd, st, d, p.d_rtiles, 0, 0);
-    else if (p.vec >= 2)
-      hipLaunchKernelGGL((k_stencil27<double, true, 2>), g, blk, 0, s, xd, yd, st, d, p.d_rtiles, bc_nt, bc_grid);
+      hipLaunchKernelGGL((k_stencil27<T, false, false>), g, blk, 0, s, xt, nullptr, yt, st);
+    else if (xghost)
+      hipLaunchKernelGGL((k_stencil27<T, true, true>), g, blk, 0, s, xt, static_cast<T*>(xghost), yt, st);
     else
-      hipLaunchKernelGGL((k_stencil27<double, true, 1>), g, blk, 0, s, xd, yd, st, d, p.d_rtiles, bc_nt, bc_grid);
-  } else {
-    const float* xf = static_cast<const float*>(x);
-    float* yf = static_cast<float*>(y);
-    if (!fused)
-      hipLaunchKernelGGL((k_stencil27<float, false, 1>), g, blk, 0, s, xf, yf, st, d, p.d_rtiles, 0, 0);
-    else if (p.vec == 4)
-      hipLaunchKernelGGL((k_stencil27<float, true, 4>), g, blk, 0, s, xf, yf, st, d, p.d_rtiles, bc_nt, bc_grid);
-    else if (p.vec == 2)
-      hipLaunchKernelGGL((k_stencil27<float, true, 2>), g, blk, 0, s, xf, yf, st, d, p.d_rtiles, bc_nt, bc_grid);
-    else
-      hipLaunchKernelGGL((k_stencil27<float, true, 1>), g, blk, 0, s, xf, yf, st, d, p.d_rtiles, bc_nt, bc_grid);
-  }
+      hipLaunchKernelGGL((k_stencil27<T, true, false>), g, blk, 0, s, xt, nullptr, yt, st);
+  };
+  if (p.dtype == HBC_F64)
+    go(double{});
+  else
+    go(float{});
   HIP_CHECK(hipGetLastError());
 }
 

@@ -1210,12 +1210,11 @@ void build_csc(Plan& plan) {
 // the fused kernel is allowed only when each of a block's 26 ghost regions is
 // one translated copy of a neighbouring block (or zero, or left uncovered).
 void compute_stencil_info(Plan& p) {
-  p.st_ok = false;
+  p.st_ok = p.st_fused = false;
   const Grid& g = p.grid;
-  auto no = [&](const char* why) { p.st_reason = why; };
+  auto no = [&](const char* why) { p.st_reason = p.st_fused_reason = why; };
   if (g.nd != 4) return no("the 27-point consumer needs a Cartesian block grid (block, z, y, x)");
   if (p.layout.inner != 1) return no("the 27-point consumer needs inner == 1");
-  if (p.stats.rows_data > 0) return no("the 27-point consumer does not take data rows");
   const Block& B0 = g.blocks[0];
   int64_t n[3];
   for (int d = 0; d < 3; ++d) n[d] = B0.data.extent(d + 1);
@@ -1227,11 +1226,17 @@ void compute_stencil_info(Plan& p) {
         return no("the 27-point consumer needs equal blocks with a one-cell halo");
   }
   const int nb = (int)g.blocks.size();
+  for (int d = 0; d < 3; ++d) p.st_n[d] = n[d];
+  p.st_nblocks = nb;
+  p.st_ok = true;  // the unfused form reads the ghosts x holds
+  auto no_fused = [&](const char* why) { p.st_fused_reason = why; };
+  if (p.stats.rows_data > 0) return no_fused("the fused 27-point consumer does not take data rows");
   std::vector<int64_t> info((size_t)nb * 27, -3);
   for (int b = 0; b < nb; ++b) info[(size_t)b * 27 + 13] = b;
   std::vector<int64_t> firsts(nb);
   for (int b = 0; b < nb; ++b) firsts[b] = g.blocks[b].first_cell;
   const HostTables& T = p.host;
+  std::vector<int64_t> rows_in((size_t)nb * 27, 0);  // covered rows per block and direction
   bool ok = true;
   for (size_t si = 0; si < T.segs.size() && ok; ++si) {
     const DevSeg& sg = T.segs[si];
@@ -1263,31 +1268,40 @@ void compute_stencil_info(Plan& p) {
         }
         if (!match) {
           ok = false;
-          no("a halo copy is not a translation by one block");
+          no_fused("a halo copy is not a translation by one block");
           return;
         }
         v = ob;
       } else {
         ok = false;
-        no("the fused consumer supports copy and zero rows only");
+        no_fused("the fused consumer supports copy and zero rows only");
         return;
       }
+      ++rows_in[(size_t)b * 27 + di];
       int64_t& slot = info[(size_t)b * 27 + di];
       if (slot == -3) {
         slot = v;
       } else if (slot != v) {
         ok = false;
-        no("one ghost region mixes BC kinds or source blocks");
+        no_fused("one ghost region mixes BC kinds or source blocks");
       }
     });
   }
   if (!ok) return;
+  // the fused form reads a whole region through the BC: every cell of a
+  // covered region must have its row
+  for (int b = 0; b < nb; ++b)
+    for (int di = 0; di < 27; ++di) {
+      if (di == 13 || info[(size_t)b * 27 + di] == -3) continue;
+      const int dd[3] = {di / 9 - 1, di / 3 % 3 - 1, di % 3 - 1};
+      int64_t cells = 1;
+      for (int d = 0; d < 3; ++d) cells *= dd[d] == 0 ? n[d] : 1;
+      if (rows_in[(size_t)b * 27 + di] != cells) return no_fused("a ghost region of the 27-point consumer is only partly covered");
+    }
   for (int64_t& v : info)
     if (v == -3) v = -2;
   p.st_info.swap(info);
-  for (int d = 0; d < 3; ++d) p.st_n[d] = n[d];
-  p.st_nblocks = nb;
-  p.st_ok = true;
+  p.st_fused = true;
 }
 
 // ---- host evaluation of compiled rows (tests without a GPU) --------------------------------

@@ -248,6 +248,71 @@ def test_hpcg_bc_and_stencil(nb, n):
         assert (d <= tol).all(), float((d / np.maximum(bound, 1e-300)).max())
 
 
+FACE7 = [(0, 0, 0, 0), (0, 1, 0, 0), (0, -1, 0, 0), (0, 0, 1, 0), (0, 0, -1, 0), (0, 0, 0, 1), (0, 0, 0, -1)]
+
+
+@pytest.mark.parametrize("nb,n", [(2, 24), (3, 9)])
+def test_hpcg_fused_with_uncovered_regions(nb, n):
+    """A plan that drops the edge and corner rows (a 7-point consumer
+    footprint): the fused form reads those regions from x itself and neither
+    form writes them.  Fused (with and without ghost stores) equals BC apply +
+    stencil bit for bit, in y and in x."""
+    x = synthinputs.uniform((nb * n,) * 3, seed=5)
+    g, blocks, full = hpcg_field(nb, n, x)
+    want = np.concatenate([b.reshape(-1) for b in blocks])
+    W = n + 2
+    c = np.arange(W)
+    on = ((c == 0) | (c == W - 1)).astype(int)
+    cnt = on[:, None, None] + on[None, :, None] + on[None, None, :]
+    edge = np.broadcast_to(cnt >= 2, (nb ** 3, W, W, W)).reshape(-1)
+    pre = full.copy()
+    pre[edge] = want[edge]  # edge / corner ghosts hold the halo values; face ghosts stay NaN
+    hg = hb.Grid.cartesian([nb] * 3, [n] * 3, 1)
+    prog = hb.Program(hg)
+    prog.cart_add_halo([nb] * 3, [n] * 3, 1)
+    prog.set_consumer(FACE7)
+    plan = hb.Plan(prog, inner=1)
+    assert plan.stats()["rows_dead"] > 0
+    ny = nb ** 3 * n ** 3
+    xa = torch.from_numpy(pre.copy()).cuda()
+    ya = torch.empty(ny, dtype=torch.float64, device="cuda")
+    hb.apply(plan, xa)
+    hb.stencil27(plan, xa, ya)
+    xf = torch.from_numpy(pre.copy()).cuda()
+    yf = torch.empty_like(ya)
+    hb.fused_stencil27(plan, xf, yf)
+    xr = torch.from_numpy(pre.copy()).cuda()
+    yr = torch.empty_like(ya)
+    hb.fused_stencil27(plan, xr, yr, write_ghosts=False)
+    torch.cuda.synchronize()
+    assert np.array_equal(xa.cpu().numpy(), want)  # faces from the BC, edges as they were
+    assert np.array_equal(xf.cpu().numpy(), want)
+    assert np.array_equal(xr.cpu().numpy(), pre, equal_nan=True)
+    assert torch.equal(yf, ya) and torch.equal(yr, ya)
+    yref = np.concatenate([ohpcg.stencil27(b).reshape(-1) for b in blocks])
+    bound = np.concatenate([ohpcg.abs_row_sum(b).reshape(-1) for b in blocks])
+    assert (np.abs(ya.cpu().numpy() - yref) <= 64 * 2.0 ** -53 * bound).all()
+
+
+def test_hpcg_partly_covered_region_refuses_the_fused_form():
+    """One ghost region covered for half its cells: the fused form would read
+    the other half through the BC, so it is refused; the unfused form runs."""
+    n = 8
+    hg = hb.Grid.cartesian([1, 1, 1], [n] * 3, 1)
+    prog = hb.Program(hg)
+    prog.add_map([(0, 1), (0, n), (0, n // 2), (-1, 0)], np.eye(4, dtype=np.int64), [0, 0, 0, n])
+    plan = hb.Plan(prog, inner=1)
+    xt = torch.zeros(hg.cells, dtype=torch.float64, device="cuda")
+    y = torch.empty(n ** 3, dtype=torch.float64, device="cuda")
+    hb.stencil27(plan, xt, y)
+    torch.cuda.synchronize()
+    assert torch.equal(y, torch.zeros_like(y))
+    for wg in (True, False):
+        with pytest.raises(hb.HbcError) as e:
+            hb.fused_stencil27(plan, xt, y, write_ghosts=wg)
+        assert e.value.code == hb.EUNSUPPORTED and "partly covered" in str(e.value)
+
+
 def test_hpcg_closed_form_on_ones():
     nb, n = 2, 16
     x = np.ones((nb * n,) * 3)
