@@ -142,7 +142,9 @@ typedef struct {
   int64_t window_runs;      /* runs of those rows (at most rows_per_tile rows each) */
 } hbc_stats;
 
-/* Launch shape of the apply kernels (chosen by the plan, changed by tuning). */
+/* Launch shape of the apply kernels (chosen by the plan, changed by tuning).
+ * The point-major adjoint's LDS kernel has a fixed shape of its own (256
+ * threads, about 4 lanes per row); the other adjoint kernels follow this one. */
 typedef struct {
   int32_t block;            /* threads per workgroup: 64, 128, 192 or 256 */
   int32_t lanes_per_row;    /* power of two; lanes that share one row */

@@ -269,7 +269,8 @@ inline int rows_per_batch(int lanes_per_row) { return lanes_per_row >= 128 ? 2 :
 // tiles, and the tile whose decrement empties it zeroes the row and restores
 // the counter for the next call.  Covered ghost rows no source reads are
 // zeroed by extra workgroups of the same launch.
-constexpr int ADJ_LDS_ROWS = 64;
+constexpr int ADJ_LDS_ROWS = 64;  // 32..160 measured: 64 is fastest at C768 x 32
+constexpr int ADJ_LDS_BLOCK = 256;  // threads of the LDS adjoint's workgroups
 constexpr int ADJ_LDS_BYTES = 40 * 1024;
 constexpr int ADJ_ZERO_ROWS = 64;  // rows per zeroing workgroup
 // Reader counters the allocation-free adjoint keeps in its static device

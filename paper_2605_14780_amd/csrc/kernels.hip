@@ -1334,14 +1334,14 @@ __global__ __launch_bounds__(256) void k_adjoint_lds(PlanDesc d, AdjDesc a, AdjL
     }
   }
   __syncthreads();  // every load of this tile's ghost rows has returned
-  if ((int)threadIdx.x < nu) {
-    const int c = q.uctr[tl.first_u + threadIdx.x];
+  for (int u = threadIdx.x; u < nu; u += blockDim.x) {
+    const int c = q.uctr[tl.first_u + u];
     int z = 1;
     if (c >= 0) {
       z = atomicSub(&q.ctr[c], 1) == 1 ? 1 : 0;
       if (z) atomicExch(&q.ctr[c], q.ctrinit[c]);
     }
-    zflag[threadIdx.x] = z;
+    zflag[u] = z;
   }
   __syncthreads();
   for (int e = threadIdx.x; e < nu * nvec; e += blockDim.x) {
@@ -2359,18 +2359,35 @@ void device_apply(const Plan& p, void* field, void* stream, bool zero_only) {
   }
 }
 
+// The LDS adjoint's own launch shape, whatever the forward's tuning: 256
+// threads and few lanes per row, so that each row group walks few sources
+// (its sources run one after another, a load then a store each).  Measured
+// at C768 x 32 (rows of 8 and 16 vectors): 4 lanes per row beat 1, 2, 8 and
+// 16 in FP64 and FP32.  Rows of fewer vectors take one lane per vector;
+// longer rows a quarter of their vectors, at most 16 lanes (not measured).
+template <int V>
+static int adjoint_lds_lanes(const Plan& p) {
+  const int64_t nvec = p.layout.inner / V;
+  const int64_t want = nvec < 4 ? nvec : std::min<int64_t>(16, std::max<int64_t>(4, nvec / 4));
+  int shift = 0;
+  while ((int64_t(1) << shift) < want) ++shift;
+  return shift;
+}
+
 template <typename T, int V>
-static void launch_adjoint_lds(const Plan& p, const PlanDesc& d, const AdjDesc& a, hipStream_t st, int32_t* ctr) {
+static void launch_adjoint_lds(const Plan& p, const PlanDesc& d0, const AdjDesc& a, hipStream_t st, int32_t* ctr) {
   const AdjLdsHost& A = p.host.adj_lds;
+  PlanDesc d = d0;
+  d.lpr_shift = adjoint_lds_lanes<V>(p);
   AdjLdsDesc q{p.d_al_tiles, p.d_al_ucell, p.d_al_uctr, p.d_al_ctrinit, ctr ? ctr : p.d_al_ctr, p.d_al_slot,
                p.d_al_zero, (int32_t)A.tiles.size(), (int32_t)A.zero_rows.size()};
   const int grid = q.ntiles + (q.nzero + ADJ_ZERO_ROWS - 1) / ADJ_ZERO_ROWS;
   if (grid == 0) return;
   const size_t lds = (size_t)A.brows * p.layout.inner * sizeof(T);
   if (d.nt)
-    HBC_LAUNCH((k_adjoint_lds<T, V, true>), dim3(grid), dim3(p.tune.block), lds, st, d, a, q);
+    HBC_LAUNCH((k_adjoint_lds<T, V, true>), dim3(grid), dim3(ADJ_LDS_BLOCK), lds, st, d, a, q);
   else
-    HBC_LAUNCH((k_adjoint_lds<T, V, false>), dim3(grid), dim3(p.tune.block), lds, st, d, a, q);
+    HBC_LAUNCH((k_adjoint_lds<T, V, false>), dim3(grid), dim3(ADJ_LDS_BLOCK), lds, st, d, a, q);
   HIP_CHECK(hipGetLastError());
 }
 

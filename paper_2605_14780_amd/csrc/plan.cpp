@@ -1070,9 +1070,9 @@ static void build_adj_lds(Plan& plan) {
   for (int64_t k = 0; k < nsrc; ++k) maxc = std::max<int64_t>(maxc, C.cnt[k]);
   if (maxc > C.aw || maxc > brows || brows < 1) return;  // the CSR-walking kernel serves such plans
   A.brows = (int32_t)brows;
-  // sources per tile: about 4 per row group of the launch shape
-  const int64_t groups = std::max<int64_t>(1, plan.tune.block / plan.tune.lanes_per_row);
-  const int64_t smax = std::max<int64_t>(1, std::min<int64_t>(4 * groups, 256));
+  // sources per tile: at most 256 (about 4 per row group of the adjoint's
+  // launch shape); the ghost-row limit is the one that binds in practice
+  const int64_t smax = 256;
   A.slot.assign((size_t)nsrc * C.aw, 0);
   std::unordered_map<int64_t, int32_t> local;
   std::unordered_map<int64_t, int32_t> readers;  // ghost -> reader tiles
