@@ -1427,8 +1427,8 @@ constexpr int ST_LX = ST_TX + 2, ST_LY = ST_TY + 2, ST_PLANE = ST_LX * ST_LY;
 constexpr int ST_NLOAD = (ST_LY * ST_TX + 255) / 256;  // interior columns of the TY + 2 rows
 constexpr int ST_NS = ST_NLOAD + 1;                     // + one value of the two halo columns
 constexpr int ST_LDS = ST_PLANE + 256;                  // + one slot per thread for values with no place
-constexpr uint32_t ST_OOB = 0x80000000u;                // buffer offset past every range (ranges < 2 GiB)
-constexpr int32_t ST_RSRC_WORD3 = 0x00020000;           // raw buffer, 32-bit data format
+constexpr uint32_t BUF_OOB = 0x80000000u;                // buffer offset past every range (ranges < 2 GiB)
+constexpr int32_t BUF_RSRC_WORD3 = 0x00020000;           // raw buffer, 32-bit data format
 static_assert(ST_TY % 4 == 0, "tile rows must split over 4 wavefronts");
 
 // One value a thread fetches per plane: column (y, xx) of the block's halo box.
@@ -1485,7 +1485,7 @@ __device__ __forceinline__ void st_buf_store(T v, __amdgpu_buffer_rsrc_t r, uint
 
 // Issue the loads of plane z into one register set.  keep: bit k set where
 // value k is used as loaded (a valid position that is not a zero row).
-// goff: byte offsets of the ghost stores in the chunk's x resource (ST_OOB: none).
+// goff: byte offsets of the ghost stores in the chunk's x resource (BUF_OOB: none).
 template <typename T, bool FUSED, bool GHOSTS>
 __device__ __forceinline__ void st_fetch(const T* __restrict__ x, const StDesc& st, const int64_t* info, int b,
                                          int z, int z0, int z1, const StSlot (&sl)[ST_NS], T (&v)[ST_NS],
@@ -1518,7 +1518,7 @@ __device__ __forceinline__ void st_fetch(const T* __restrict__ x, const StDesc& 
       const bool g = sl[k].own && ghost && covered && zown;
       goff[k] = g ? (uint32_t)(((int64_t)(z + 1 - z0) * st.sz + (int64_t)(sl[k].y + 1) * st.sy + (sl[k].xx + 1)) *
                                (int64_t)sizeof(T))
-                  : ST_OOB;
+                  : BUF_OOB;
     }
   }
 }
@@ -1574,11 +1574,11 @@ __global__ __launch_bounds__(256) void k_stencil27(const T* __restrict__ x, T* x
   // y: this chunk's planes of block b; x (ghost stores): its planes z0 - 1 .. z1
   const __amdgpu_buffer_rsrc_t yr = __builtin_amdgcn_make_buffer_rsrc(
       yout + ((int64_t)b * st.nz + z0) * plane_out, 0, (int)((z1 - z0) * plane_out * (int64_t)sizeof(T)),
-      ST_RSRC_WORD3);
+      BUF_RSRC_WORD3);
   __amdgpu_buffer_rsrc_t xr = yr;
   if (GHOSTS)
     xr = __builtin_amdgcn_make_buffer_rsrc(xg + b * st.bcells + (int64_t)z0 * st.sz, 0,
-                                           (int)((z1 - z0 + 2) * st.sz * (int64_t)sizeof(T)), ST_RSRC_WORD3);
+                                           (int)((z1 - z0 + 2) * st.sz * (int64_t)sizeof(T)), BUF_RSRC_WORD3);
   T A[ST_NS], B[ST_NS];
   uint32_t ka, kb, ga[ST_NS], gb[ST_NS];
   // plane z0 - 1 goes straight to LDS buffer 0; planes z0 and z0 + 1 go in flight
@@ -1620,7 +1620,7 @@ __global__ __launch_bounds__(256) void k_stencil27(const T* __restrict__ x, T* x
         const uint32_t off = yy < st.ny && xx < st.nx
                                  ? (uint32_t)(((int64_t)(p - 1 - z0) * plane_out + (int64_t)yy * st.nx + xx) *
                                               (int64_t)sizeof(T))
-                                 : ST_OOB;
+                                 : BUF_OOB;
         st_buf_store<T, 2>(yv[q], yr, off);  // non-temporal
       }
     }
@@ -2530,7 +2530,7 @@ void device_stencil27(Plan& p, const void* x, void* y, void* stream, bool fused,
   if (grid >= (int64_t(1) << 31)) fail(HBC_EUNSUPPORTED, "grid too large for the 27-point consumer");
   // each workgroup's x and y ranges are buffer resources addressed in 32 bits
   const int64_t esz = p.dtype == HBC_F64 ? 8 : 4;
-  if ((int64_t)(ST_ZC + 2) * st.sz * esz >= (int64_t)ST_OOB || (int64_t)ST_ZC * st.ny * st.nx * esz >= (int64_t)ST_OOB)
+  if ((int64_t)(ST_ZC + 2) * st.sz * esz >= (int64_t)BUF_OOB || (int64_t)ST_ZC * st.ny * st.nx * esz >= (int64_t)BUF_OOB)
     fail(HBC_EUNSUPPORTED, "blocks too large for the 27-point consumer (32-plane chunks of 2 GiB or more)");
   hipStream_t s = S(stream);
   const dim3 g((unsigned)grid), blk(256);
