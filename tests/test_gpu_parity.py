@@ -294,6 +294,65 @@ def test_hpcg_fused_with_uncovered_regions(nb, n):
     assert (np.abs(ya.cpu().numpy() - yref) <= 64 * 2.0 ** -53 * bound).all()
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("nb,n,periodic", [((2, 1, 3), (70, 9, 37), 0), ((1, 2, 2), (5, 17, 130), 5)])
+def test_hpcg_noncubic_blocks(nb, n, periodic, dtype):
+    """Blocks of unequal extents: z chunks with a 6-plane tail, partial x and
+    y tiles, an x tile two values wide; zero padding or periodic wrap per
+    dimension.  The fused forms equal BC apply + stencil bit for bit (y and
+    x's ghosts), and y matches a plain numpy 27-point operator on the padded
+    global field within 64 roundings of the absolute row sum."""
+    tdt, dt, eps = (torch.float64, hb.F64, 2.0 ** -53) if dtype == "f64" else (torch.float32, hb.F32, 2.0 ** -24)
+    N = [nb[d] * n[d] for d in range(3)]
+    g = np.random.default_rng(11).standard_normal(N)
+    if dtype == "f32":
+        g = g.astype(np.float32).astype(np.float64)
+    W = [n[d] + 2 for d in range(3)]
+    full = np.full((nb[0] * nb[1] * nb[2], W[0], W[1], W[2]), np.nan)
+    blocks = []
+    for bz in range(nb[0]):
+        for by in range(nb[1]):
+            for bx in range(nb[2]):
+                sl = tuple(slice(c * n[d], (c + 1) * n[d]) for d, c in enumerate((bz, by, bx)))
+                full[(bz * nb[1] + by) * nb[2] + bx, 1:-1, 1:-1, 1:-1] = g[sl]
+                blocks.append(sl)
+    pad = g
+    for d in range(3):
+        widths = [(1, 1) if i == d else (0, 0) for i in range(3)]
+        pad = np.pad(pad, widths, mode="wrap" if periodic >> d & 1 else "constant")
+    box = np.zeros(N)
+    abox = np.zeros(N)
+    for dz in range(3):
+        for dy in range(3):
+            for dx in range(3):
+                v = pad[dz:dz + N[0], dy:dy + N[1], dx:dx + N[2]]
+                box += v
+                abox += np.abs(v)
+    yref_g = 27 * g - box
+    bound_g = 26 * np.abs(g) + (abox - np.abs(g))
+    yref = np.concatenate([yref_g[sl].reshape(-1) for sl in blocks])
+    bound = np.concatenate([bound_g[sl].reshape(-1) for sl in blocks])
+    hg = hb.Grid.cartesian(list(nb), list(n), 1)
+    prog = hb.Program(hg)
+    prog.cart_add_halo(list(nb), list(n), 1, periodic)
+    plan = hb.Plan(prog, inner=1, dtype=dt)
+    src = torch.from_numpy(full.reshape(-1)).to(tdt).cuda()
+    ny = int(np.prod(N))
+    xa, ya = src.clone(), torch.empty(ny, dtype=tdt, device="cuda")
+    hb.apply(plan, xa)
+    hb.stencil27(plan, xa, ya)
+    xf, yf = src.clone(), torch.empty_like(ya)
+    hb.fused_stencil27(plan, xf, yf)
+    xr, yr = src.clone(), torch.empty_like(ya)
+    hb.fused_stencil27(plan, xr, yr, write_ghosts=False)
+    torch.cuda.synchronize()
+    assert torch.equal(yf, ya) and torch.equal(yr, ya)
+    assert np.array_equal(xf.cpu().numpy(), xa.cpu().numpy(), equal_nan=True)
+    assert np.array_equal(xr.cpu().numpy(), src.cpu().numpy(), equal_nan=True)
+    d = np.abs(ya.cpu().numpy().astype(np.float64) - yref)
+    assert (d <= 64 * eps * bound).all(), float((d / np.maximum(bound, 1e-300)).max())
+
+
 def test_hpcg_partly_covered_region_refuses_the_fused_form():
     """One ghost region covered for half its cells: the fused form would read
     the other half through the BC, so it is refused; the unfused form runs."""
