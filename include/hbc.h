@@ -150,6 +150,9 @@ typedef struct {
   int32_t lanes_per_row;    /* power of two; lanes that share one row */
   int32_t rows_per_tile;    /* rows per work tile (sliding-window rows: rows per run, at most 16) */
   int32_t persistent;       /* 0: one workgroup per tile; >0: that many workgroups loop over tiles */
+  int32_t window_order;     /* sliding-window rows: 0 pipelined (each row's store issued while later
+                               rows' sources still arrive), 1 ordered (sources, then the rows in turn);
+                               both give the same bits */
 } hbc_tune;
 
 /* ---- errors ---------------------------------------------------------------- */

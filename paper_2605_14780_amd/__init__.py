@@ -62,7 +62,7 @@ class StatsT(C.Structure):
 
 class TuneT(C.Structure):
     _fields_ = [("block", C.c_int32), ("lanes_per_row", C.c_int32), ("rows_per_tile", C.c_int32),
-                ("persistent", C.c_int32)]
+                ("persistent", C.c_int32), ("window_order", C.c_int32)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

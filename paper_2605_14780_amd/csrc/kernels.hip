@@ -118,6 +118,39 @@ __device__ __forceinline__ void stv(T* p, const Pack<T, V>& r) {
   }
 }
 
+// Raw buffer accesses: a store at an offset past the resource's range is
+// dropped by the hardware, so a lane that stores nothing can still issue the
+// instruction (ranges stay below 2 GiB, so BUF_OOB is past every one).
+constexpr uint32_t BUF_OOB = 0x80000000u;
+constexpr int32_t BUF_RSRC_WORD3 = 0x00020000;  // raw buffer, 32-bit data format
+
+// Store of one pack through a buffer resource (dropped where off is out of range).
+template <typename T, int V, bool NT>
+__device__ __forceinline__ void stv_buf(const Pack<T, V>& p, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+  constexpr int AUX = NT ? 2 : 0;  // non-temporal
+  constexpr int BYTES = (int)sizeof(T) * V;
+  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  if constexpr (BYTES == 16) {
+    typedef T tv __attribute__((ext_vector_type(V)));
+    tv v;
+#pragma unroll
+    for (int i = 0; i < V; ++i) v[i] = p.v[i];
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, off, 0, AUX);
+  } else if constexpr (BYTES == 8 && V == 1) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, p.v[0]), r, off, 0, AUX);
+  } else if constexpr (BYTES == 8) {
+    typedef T tv __attribute__((ext_vector_type(V)));
+    tv v;
+#pragma unroll
+    for (int i = 0; i < V; ++i) v[i] = p.v[i];
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, AUX);
+  } else {
+    static_assert(BYTES == 4, "pack of 4, 8 or 16 bytes");
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, p.v[0]), r, off, 0, AUX);
+  }
+}
+
 // Source inner slot of output slot l under rotation code `rot` (see rot_code):
 // component a of the vector takes sign_a * component p(a) of the source.
 template <typename T>
@@ -564,22 +597,12 @@ __device__ __forceinline__ double rdl(double v, int k) {
 // order, then the component sign, then b), so both give the same bits.
 // Workgroups past the window items write the plan's zero rows (ztiles), when
 // those are all its other rows.
+// Ordered form: the rows' destinations and weights, then the run's source
+// rows, then the rows one after another.  The autotuner picks it where it is
+// faster (at some run lengths it is, in FP32).
 template <typename T, int V, bool NT, int RM>
-__global__ __launch_bounds__(256) void k_apply_win(PlanDesc d, const WinRun* __restrict__ runs, int nitems,
-                                                   int nslices, int zero_only, const RowTile* __restrict__ ztiles,
-                                                   int nz) {
-  const int nwin = (nitems + 3) >> 2;
-  if ((int)blockIdx.x >= nwin) {
-    for (int t = (int)blockIdx.x - nwin; t < nz; t += (int)gridDim.x - nwin) zero_row_tile<T>(d, ztiles[t]);
-    return;
-  }
-  // workgroups are dealt to the 8 XCDs round-robin: give each XCD a
-  // contiguous range of runs (neighbouring runs share three cells)
-  int b = (int)blockIdx.x;
-  {
-    const int q = nwin >> 3, rem = nwin & 7, x = b & 7, jx = b >> 3;
-    b = x * q + min(x, rem) + jx;
-  }
+__device__ __forceinline__ void win_ordered(const PlanDesc& d, const WinRun* __restrict__ runs, int nitems,
+                                            int nslices, int zero_only, int b) {
   const int lane = (int)threadIdx.x & 63;
   const int item = b * 4 + ((int)threadIdx.x >> 6);
   if (item >= nitems) return;
@@ -638,6 +661,118 @@ __global__ __launch_bounds__(256) void k_apply_win(PlanDesc d, const WinRun* __r
       if (ok) stv<T, V, NT>(f + (int64_t)rdl(my_dst, r) * d.cs + l, y);
     }
   }
+}
+
+// Pipelined form: scalar run descriptor; the rows' destinations and weights
+// and the run's source rows in flight together; without b, every store
+// issued (see below) so that each row waits only for its own source rows.
+template <typename T, int V, bool NT, int RM>
+__device__ __forceinline__ void win_pipelined(const PlanDesc& d, const WinRun* __restrict__ runs, int nitems,
+                                              int nslices, int zero_only, int b) {
+  const int lane = (int)threadIdx.x & 63;
+  // the wave's item is the same in every lane: the run descriptor comes
+  // through scalar loads
+  const int item = __builtin_amdgcn_readfirstlane(b * 4 + ((int)threadIdx.x >> 6));
+  if (item >= nitems) return;
+  const int ri = item / nslices, slc = item - ri * nslices;
+  const WinRun rn = runs[ri];
+  T* __restrict__ f = static_cast<T*>(d.field);
+  const int64_t nvec = d.inner / V;
+  const int64_t vi = (int64_t)slc * 64 + lane;
+  const bool ok = vi < nvec;
+  const int64_t l = (ok ? vi : 0) * V;  // lanes past the row's end repeat vector 0 and store nothing
+  T sign = T(1);
+  const int64_t sl = rot_slot<T>(d, rn.rot, l, sign);
+  const int R = rn.nrows;
+  // lane r holds row r's destination and weights (lanes past the run repeat
+  // its last row; rows are read back with readlane)
+  const int mr = min(lane, R - 1);
+  if (zero_only) {
+    const int my_dst = d.row_dst[rn.row_begin + mr];
+    Pack<T, V> z;
+#pragma unroll
+    for (int i = 0; i < V; ++i) z.v[i] = T(0);
+#pragma unroll
+    for (int r = 0; r < RM; ++r)
+      if (r < R && ok) stv<T, V, NT>(f + (int64_t)rdl(my_dst, r) * d.cs + l, z);
+    return;
+  }
+  // the rows' destinations and weights, then the run's source rows, all in
+  // flight together.  Every load is issued whatever R (spare slots re-read
+  // the run's last source row) and, without b, every store too (through a
+  // buffer range of its one destination row, with an out-of-range offset
+  // where nothing is stored): loads and stores retire in issue order, and
+  // guarded ones would make each row's store wait for the one before it.
+  const int my_dst = d.row_dst[rn.row_begin + mr];
+  T my_w[4];
+  {
+    const T* wp = static_cast<const T*>(d.ell_val) + rn.tab + 4 * mr;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) my_w[m] = wp[m];
+  }
+  const int64_t step = (int64_t)rn.dl * d.cs;
+  const T* x0 = f + (int64_t)rn.src0 * d.cs + sl;
+  Pack<T, V> x[RM + 3];
+#pragma unroll
+  for (int j = 0; j < RM + 3; ++j) x[j] = ldv<T, V>(x0 + (int64_t)min(j, R + 2) * step);
+  auto row_value = [&](int r) {
+    const T c0 = rdl(my_w[0], r), c1 = rdl(my_w[1], r), c2 = rdl(my_w[2], r), c3 = rdl(my_w[3], r);
+    Pack<T, V> y;
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      T a = c0 * x[r].v[i];
+      a = fma(c1, x[r + 1].v[i], a);
+      a = fma(c2, x[r + 2].v[i], a);
+      a = fma(c3, x[r + 3].v[i], a);
+      y.v[i] = sign * a;
+    }
+    return y;
+  };
+  if (!rn.has_b) {
+    const uint32_t off = ok ? (uint32_t)(l * (int64_t)sizeof(T)) : BUF_OOB;
+    const int row_bytes = (int)(d.inner * (int64_t)sizeof(T));  // < 2 GiB (checked by the host)
+#pragma unroll
+    for (int r = 0; r < RM; ++r) {
+      const Pack<T, V> y = row_value(r);
+      const __amdgpu_buffer_rsrc_t dr = __builtin_amdgcn_make_buffer_rsrc(
+          f + (int64_t)rdl(my_dst, min(r, R - 1)) * d.cs, 0, row_bytes, BUF_RSRC_WORD3);
+      stv_buf<T, V, NT>(y, dr, r < R ? off : BUF_OOB);
+    }
+    return;
+  }
+  const T* __restrict__ bt = static_cast<const T*>(d.bval) + rn.brow;
+#pragma unroll
+  for (int r = 0; r < RM; ++r) {
+    if (r < R) {
+      Pack<T, V> y = row_value(r);
+      const T* bp = bt + (int64_t)r * rn.b_inner;
+#pragma unroll
+      for (int i = 0; i < V; ++i) y.v[i] = y.v[i] + (rn.b_inner == 1 ? bp[0] : bp[l + i]);
+      if (ok) stv<T, V, NT>(f + (int64_t)rdl(my_dst, r) * d.cs + l, y);
+    }
+  }
+}
+
+template <typename T, int V, bool NT, int RM, bool ORD>
+__global__ __launch_bounds__(256) void k_apply_win(PlanDesc d, const WinRun* __restrict__ runs, int nitems,
+                                                   int nslices, int zero_only, const RowTile* __restrict__ ztiles,
+                                                   int nz) {
+  const int nwin = (nitems + 3) >> 2;
+  if ((int)blockIdx.x >= nwin) {
+    for (int t = (int)blockIdx.x - nwin; t < nz; t += (int)gridDim.x - nwin) zero_row_tile<T>(d, ztiles[t]);
+    return;
+  }
+  // workgroups are dealt to the 8 XCDs round-robin: give each XCD a
+  // contiguous range of runs (neighbouring runs share three cells)
+  int b = (int)blockIdx.x;
+  {
+    const int q = nwin >> 3, rem = nwin & 7, x = b & 7, jx = b >> 3;
+    b = x * q + min(x, rem) + jx;
+  }
+  if constexpr (ORD)
+    win_ordered<T, V, NT, RM>(d, runs, nitems, nslices, zero_only, b);
+  else
+    win_pipelined<T, V, NT, RM>(d, runs, nitems, nslices, zero_only, b);
 }
 
 // One entry of a wide tile: its weight and the LDS offset (in values) of its
@@ -1427,8 +1562,6 @@ constexpr int ST_LX = ST_TX + 2, ST_LY = ST_TY + 2, ST_PLANE = ST_LX * ST_LY;
 constexpr int ST_NLOAD = (ST_LY * ST_TX + 255) / 256;  // interior columns of the TY + 2 rows
 constexpr int ST_NS = ST_NLOAD + 1;                     // + one value of the two halo columns
 constexpr int ST_LDS = ST_PLANE + 256;                  // + one slot per thread for values with no place
-constexpr uint32_t BUF_OOB = 0x80000000u;                // buffer offset past every range (ranges < 2 GiB)
-constexpr int32_t BUF_RSRC_WORD3 = 0x00020000;           // raw buffer, 32-bit data format
 static_assert(ST_TY % 4 == 0, "tile rows must split over 4 wavefronts");
 
 // One value a thread fetches per plane: column (y, xx) of the block's halo box.
@@ -2228,22 +2361,38 @@ static void launch_win(const Plan& p, const PlanDesc& d, hipStream_t st, bool ze
   const dim3 g((unsigned)(nwin + nz)), b(256);
   const int z = zero_only ? 1 : 0;
   const int rm = p.host.win_maxr;  // longest run: the smallest instance that holds it
-#define HBC_WIN(RM)                                                                                               \
+#define HBC_WIN_O(RM, O)                                                                                          \
   do {                                                                                                              \
     if (d.nt)                                                                                                       \
-      HBC_LAUNCH((k_apply_win<T, V, true, RM>), g, b, 0, st, d, p.d_wruns, (int)nitems, (int)nsl, z,         \
+      HBC_LAUNCH((k_apply_win<T, V, true, RM, O>), g, b, 0, st, d, p.d_wruns, (int)nitems, (int)nsl, z,      \
                          p.d_rtiles, nz);                                                                          \
     else                                                                                                            \
-      HBC_LAUNCH((k_apply_win<T, V, false, RM>), g, b, 0, st, d, p.d_wruns, (int)nitems, (int)nsl, z,        \
+      HBC_LAUNCH((k_apply_win<T, V, false, RM, O>), g, b, 0, st, d, p.d_wruns, (int)nitems, (int)nsl, z,     \
                          p.d_rtiles, nz);                                                                          \
   } while (0)
+#define HBC_WIN(RM)                  \
+  do {                               \
+    if (p.tune.window_order)         \
+      HBC_WIN_O(RM, true);           \
+    else                             \
+      HBC_WIN_O(RM, false);          \
+  } while (0)
+  // one instance per run length the autotuner tries: every load slot of a
+  // full run is used (a shorter run re-reads its last source row)
   if (rm <= 4)
     HBC_WIN(4);
+  else if (rm <= 6)
+    HBC_WIN(6);
   else if (rm <= 8)
     HBC_WIN(8);
+  else if (rm <= 10)
+    HBC_WIN(10);
+  else if (rm <= 12)
+    HBC_WIN(12);
   else
     HBC_WIN(16);
 #undef HBC_WIN
+#undef HBC_WIN_O
   HIP_CHECK(hipGetLastError());
 }
 
@@ -3075,8 +3224,9 @@ double device_plan_autotune(Plan& p, void* const* fields, int nfields, const cha
       hbc_tune t{};
       double ms = 0;
       if (std::sscanf(line.c_str() + line.find("\"block\""),
-                      "\"block\": %d, \"lanes_per_row\": %d, \"rows_per_tile\": %d, \"persistent\": %d, \"ms\": %lf",
-                      &t.block, &t.lanes_per_row, &t.rows_per_tile, &t.persistent, &ms) == 5) {
+                      "\"block\": %d, \"lanes_per_row\": %d, \"rows_per_tile\": %d, \"persistent\": %d, "
+                      "\"window_order\": %d, \"ms\": %lf",
+                      &t.block, &t.lanes_per_row, &t.rows_per_tile, &t.persistent, &t.window_order, &ms) == 6) {
         build_tiles(p, t);
         device_upload_tiles(p);
         return device_time_apply(p, fields, nfields, reps, stream);
@@ -3090,12 +3240,14 @@ double device_plan_autotune(Plan& p, void* const* fields, int nfields, const cha
   std::vector<hbc_tune> cand;
   if (p.stats.rows_window > 0) {
     // window plans: the run length (a run's three extra cells against the
-    // number of wavefronts in flight)
-    for (int r : {4, 6, 8, 10, 12, 16}) {
-      hbc_tune t = def;
-      t.rows_per_tile = r;
-      cand.push_back(t);
-    }
+    // number of wavefronts in flight) and the order of loads and stores
+    for (int r : {4, 6, 8, 10, 12, 16})
+      for (int o : {0, 1}) {
+        hbc_tune t = def;
+        t.rows_per_tile = r;
+        t.window_order = o;
+        cand.push_back(t);
+      }
   } else {
     for (int bl : {128, 256})
       for (int lf : {1, 2}) {
@@ -3124,7 +3276,7 @@ double device_plan_autotune(Plan& p, void* const* fields, int nfields, const cha
     std::ofstream out(cache_path, std::ios::app);
     out << "{\"key\": \"" << key << "\", \"block\": " << best.block << ", \"lanes_per_row\": " << best.lanes_per_row
         << ", \"rows_per_tile\": " << best.rows_per_tile << ", \"persistent\": " << best.persistent
-        << ", \"ms\": " << best_ms << "}\n";
+        << ", \"window_order\": " << best.window_order << ", \"ms\": " << best_ms << "}\n";
   }
   return best_ms;
 }

@@ -756,6 +756,7 @@ bool windows_possible(const Plan& plan) {
   const int64_t es = plan.dtype == HBC_F64 ? 8 : 4;
   if (L.order != HBC_POINT_MAJOR || (plan.flags & HBC_PLAN_NO_WINDOWS) || plan.stats.rows_data > 0) return false;
   if (plan.vec * es != 16 || L.inner * es < WIN_MIN_BYTES) return false;
+  if (L.inner * es >= (int64_t(1) << 31)) return false;  // a row is one 32-bit buffer range
   for (const DevSeg& sg : plan.host.segs)
     if (sg.kind == SEG_ELL && sg.width == 4 && !(sg.flags & SEGF_ELL_PADDED) && sg.nrows > 0) return true;
   return false;
@@ -765,6 +766,7 @@ hbc_tune default_tune(const Plan& plan) {
   hbc_tune t{};
   t.block = 256;
   t.persistent = 0;
+  t.window_order = 0;
   const int64_t rows = std::max<int64_t>(1, plan.stats.rows_covered);
   if (plan.layout.order == HBC_POINT_MAJOR) {
     // 16 bytes per lane (vec elements, unroll times): a row group covers a whole row
@@ -1000,6 +1002,7 @@ void build_tiles(Plan& plan, const hbc_tune& t) {
     fail(HBC_EINVAL, "lanes_per_row must be a power of two <= block");
   if (t.rows_per_tile < 1) fail(HBC_EINVAL, "rows_per_tile must be >= 1");
   if (t.persistent < 0) fail(HBC_EINVAL, "persistent must be >= 0");
+  if (t.window_order != 0 && t.window_order != 1) fail(HBC_EINVAL, "window_order must be 0 or 1");
   std::vector<DevTile> tiles;
   for (size_t s = 0; s < plan.host.segs.size(); ++s) {
     const DevSeg& sg = plan.host.segs[s];

@@ -4,7 +4,7 @@ wavefront walking a run of rows along the neighbour's grid line).
 Its sum is the general row path's, so the bar is bit identity with a plan of
 the same program built with windows=False (the general row kernel), for FP64
 and FP32, with and without the component rotation and b, for run lengths from
-1 to 64 rows and rows of 512 bytes to 2 KiB; the general row path itself is
+1 to 64 rows, both orders of loads and stores, and rows of 512 bytes to 2 KiB; the general row path itself is
 checked against the oracle elsewhere.  Also: a graph captured before a change
 of the launch shape is refused, not replayed over freed tables.
 """
@@ -66,12 +66,13 @@ def test_window_kernel_bitwise_general_path(N, h, nf, nl, dtype, vector, with_b)
     want = x.clone()
     hb.apply(pr, want)
     for R in (1, 5, 16, 64):
-        pw.tune = dict(pw.tune, rows_per_tile=R)
-        got = x.clone()
-        hb.apply(pw, got)
-        torch.cuda.synchronize()
-        assert torch.isfinite(got).all(), R
-        assert torch.equal(got, want), R
+        for order in (0, 1):  # pipelined and ordered loads and stores
+            pw.tune = dict(pw.tune, rows_per_tile=R, window_order=order)
+            got = x.clone()
+            hb.apply(pw, got)
+            torch.cuda.synchronize()
+            assert torch.isfinite(got).all(), (R, order)
+            assert torch.equal(got, want), (R, order)
 
 
 def test_window_adjoint_and_graph_after_tuning():
