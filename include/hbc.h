@@ -330,7 +330,8 @@ int hbc_plan_get_tune(const hbc_plan* plan, hbc_tune* out);
 int hbc_plan_set_tune(hbc_plan* plan, const hbc_tune* t);
 
 /* Try candidate launch shapes (workgroup size, lanes per row, rows per tile,
- * persistent workgroups), timing HIP-graph applies cycled over the `nfields`
+ * persistent workgroups; for plans with sliding-window rows the run length and
+ * the order of loads and stores), timing HIP-graph applies cycled over the `nfields`
  * device fields (`nelem` values each; their ghost values are overwritten,
  * data cells are not), and keep the fastest.  With cache_path (JSON lines
  * keyed by device, dtype, layout and the plan's sizes) a stored choice is
