@@ -137,7 +137,7 @@ typedef struct {
   int64_t rows_narrow;      /* CSR rows of >= 8 entries and < 32 bytes served by the entry-splitting kernel */
   int64_t rows_window;      /* 4-entry rows on four consecutive points of a grid line, each row's window at
                                the previous row's or one point further (Sec. III-B interpolation rows of a
-                               face-edge strip), served by the window kernel: point-major, rows of >= 512
+                               face-edge strip), served by the window kernel: point-major, rows of >= 256
                                bytes in whole 16-byte vectors; each wavefront loads a run's cells once */
   int64_t window_runs;      /* runs of those rows (at most rows_per_tile rows each) */
 } hbc_stats;

@@ -226,7 +226,13 @@ struct alignas(16) NarrowTile {
 // the cells src0 + (r + m) * dl, m < 4, so a run of R rows reads R + 3
 // distinct cells.  One wavefront takes a run and a slice of 64 16-byte
 // vectors of the inner values and loads each of the run's cells once.
-constexpr int WIN_MAXR = 16, WIN_MIN_BYTES = 512, WIN_DEFAULT_ROWS = 8;
+// rows of 256 bytes and up: the window kernel beats the row kernel from there
+// (C768 x 32 FP64: 7.4 against 8.6 us); at 128 bytes a wavefront's slice is
+// mostly idle lanes and it loses (FP32: 6.7 against 4.8 us)
+constexpr int WIN_MAXR = 16, WIN_MIN_BYTES = 256, WIN_DEFAULT_ROWS = 8;
+// segments with b: from 512 bytes (C768 x 32 FP64 with b on every strip row:
+// 12.4 us windowed at 256 bytes against 10.7 us with the row kernel)
+constexpr int WIN_MIN_BYTES_B = 512;
 struct alignas(16) WinRun {
   int32_t src0, dl, nrows, nsrc;
   int64_t row_begin;  // first row in the per-row tables (row_dst)
@@ -329,6 +335,7 @@ struct HostTables {
   std::vector<char> seg_win;
   std::vector<WinRun> wruns;
   int32_t win_maxr = 0;  // longest run
+  bool win_has_b = false;  // a run with b values (the window launch picks its instance by it)
   // data rows: destination cells, CSR over data cells (absolute pointers)
   std::vector<int32_t> dr_cell;
   std::vector<int64_t> dr_ptr;

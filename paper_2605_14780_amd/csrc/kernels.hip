@@ -663,10 +663,10 @@ __device__ __forceinline__ void win_ordered(const PlanDesc& d, const WinRun* __r
   }
 }
 
-// Pipelined form: scalar run descriptor; the rows' destinations and weights
-// and the run's source rows in flight together; without b, every store
-// issued (see below) so that each row waits only for its own source rows.
-template <typename T, int V, bool NT, int RM>
+// Pipelined form: scalar run descriptor; the rows' destinations and weights,
+// the run's source rows and its b values in flight together; every store
+// issued (see below) so that each row waits only for its own loads.
+template <typename T, int V, bool NT, int RM, bool HB>
 __device__ __forceinline__ void win_pipelined(const PlanDesc& d, const WinRun* __restrict__ runs, int nitems,
                                               int nslices, int zero_only, int b) {
   const int lane = (int)threadIdx.x & 63;
@@ -699,10 +699,10 @@ __device__ __forceinline__ void win_pipelined(const PlanDesc& d, const WinRun* _
   }
   // the rows' destinations and weights, then the run's source rows, all in
   // flight together.  Every load is issued whatever R (spare slots re-read
-  // the run's last source row) and, without b, every store too (through a
-  // buffer range of its one destination row, with an out-of-range offset
-  // where nothing is stored): loads and stores retire in issue order, and
-  // guarded ones would make each row's store wait for the one before it.
+  // the run's last source row) and every store too (through a buffer range
+  // of its one destination row, with an out-of-range offset where nothing is
+  // stored): loads and stores retire in issue order, and guarded ones would
+  // make each row's store wait for the one before it.
   const int my_dst = d.row_dst[rn.row_begin + mr];
   T my_w[4];
   {
@@ -728,32 +728,42 @@ __device__ __forceinline__ void win_pipelined(const PlanDesc& d, const WinRun* _
     }
     return y;
   };
-  if (!rn.has_b) {
-    const uint32_t off = ok ? (uint32_t)(l * (int64_t)sizeof(T)) : BUF_OOB;
-    const int row_bytes = (int)(d.inner * (int64_t)sizeof(T));  // < 2 GiB (checked by the host)
+  // b values of the run's rows, issued with the sources (a row past the run
+  // re-reads the run's last one); one value per row is broadcast
+  // (HB: the plan has runs with b; instances without it keep no registers for b)
+  Pack<T, V> bv[HB ? RM : 1];
+  if (HB && rn.has_b) {
+    const T* __restrict__ bt = static_cast<const T*>(d.bval) + rn.brow;
 #pragma unroll
     for (int r = 0; r < RM; ++r) {
-      const Pack<T, V> y = row_value(r);
-      const __amdgpu_buffer_rsrc_t dr = __builtin_amdgcn_make_buffer_rsrc(
-          f + (int64_t)rdl(my_dst, min(r, R - 1)) * d.cs, 0, row_bytes, BUF_RSRC_WORD3);
-      stv_buf<T, V, NT>(y, dr, r < R ? off : BUF_OOB);
+      const T* bp = bt + (int64_t)min(r, R - 1) * rn.b_inner;
+      if (rn.b_inner == 1) {
+        const T b0 = bp[0];
+#pragma unroll
+        for (int i = 0; i < V; ++i) bv[r].v[i] = b0;
+      } else {
+        bv[r] = ldv<T, V>(bp + l);
+      }
     }
-    return;
   }
-  const T* __restrict__ bt = static_cast<const T*>(d.bval) + rn.brow;
+  const uint32_t off = ok ? (uint32_t)(l * (int64_t)sizeof(T)) : BUF_OOB;
+  const int row_bytes = (int)(d.inner * (int64_t)sizeof(T));  // < 2 GiB (checked by the host)
 #pragma unroll
   for (int r = 0; r < RM; ++r) {
-    if (r < R) {
-      Pack<T, V> y = row_value(r);
-      const T* bp = bt + (int64_t)r * rn.b_inner;
+    Pack<T, V> y = row_value(r);
+    if constexpr (HB) {
+      if (rn.has_b) {
 #pragma unroll
-      for (int i = 0; i < V; ++i) y.v[i] = y.v[i] + (rn.b_inner == 1 ? bp[0] : bp[l + i]);
-      if (ok) stv<T, V, NT>(f + (int64_t)rdl(my_dst, r) * d.cs + l, y);
+        for (int i = 0; i < V; ++i) y.v[i] = y.v[i] + bv[r].v[i];
+      }
     }
+    const __amdgpu_buffer_rsrc_t dr = __builtin_amdgcn_make_buffer_rsrc(
+        f + (int64_t)rdl(my_dst, min(r, R - 1)) * d.cs, 0, row_bytes, BUF_RSRC_WORD3);
+    stv_buf<T, V, NT>(y, dr, r < R ? off : BUF_OOB);
   }
 }
 
-template <typename T, int V, bool NT, int RM, bool ORD>
+template <typename T, int V, bool NT, int RM, bool ORD, bool HB>
 __global__ __launch_bounds__(256) void k_apply_win(PlanDesc d, const WinRun* __restrict__ runs, int nitems,
                                                    int nslices, int zero_only, const RowTile* __restrict__ ztiles,
                                                    int nz) {
@@ -772,7 +782,7 @@ __global__ __launch_bounds__(256) void k_apply_win(PlanDesc d, const WinRun* __r
   if constexpr (ORD)
     win_ordered<T, V, NT, RM>(d, runs, nitems, nslices, zero_only, b);
   else
-    win_pipelined<T, V, NT, RM>(d, runs, nitems, nslices, zero_only, b);
+    win_pipelined<T, V, NT, RM, HB>(d, runs, nitems, nslices, zero_only, b);
 }
 
 // One entry of a wide tile: its weight and the LDS offset (in values) of its
@@ -2361,21 +2371,23 @@ static void launch_win(const Plan& p, const PlanDesc& d, hipStream_t st, bool ze
   const dim3 g((unsigned)(nwin + nz)), b(256);
   const int z = zero_only ? 1 : 0;
   const int rm = p.host.win_maxr;  // longest run: the smallest instance that holds it
-#define HBC_WIN_O(RM, O)                                                                                          \
+#define HBC_WIN_O(RM, O, HB)                                                                                      \
   do {                                                                                                              \
     if (d.nt)                                                                                                       \
-      HBC_LAUNCH((k_apply_win<T, V, true, RM, O>), g, b, 0, st, d, p.d_wruns, (int)nitems, (int)nsl, z,      \
+      HBC_LAUNCH((k_apply_win<T, V, true, RM, O, HB>), g, b, 0, st, d, p.d_wruns, (int)nitems, (int)nsl, z,  \
                          p.d_rtiles, nz);                                                                          \
     else                                                                                                            \
-      HBC_LAUNCH((k_apply_win<T, V, false, RM, O>), g, b, 0, st, d, p.d_wruns, (int)nitems, (int)nsl, z,     \
+      HBC_LAUNCH((k_apply_win<T, V, false, RM, O, HB>), g, b, 0, st, d, p.d_wruns, (int)nitems, (int)nsl, z, \
                          p.d_rtiles, nz);                                                                          \
   } while (0)
-#define HBC_WIN(RM)                  \
-  do {                               \
-    if (p.tune.window_order)         \
-      HBC_WIN_O(RM, true);           \
-    else                             \
-      HBC_WIN_O(RM, false);          \
+#define HBC_WIN(RM)                         \
+  do {                                      \
+    if (p.tune.window_order)                \
+      HBC_WIN_O(RM, true, false);           \
+    else if (p.host.win_has_b)              \
+      HBC_WIN_O(RM, false, true);           \
+    else                                    \
+      HBC_WIN_O(RM, false, false);          \
   } while (0)
   // one instance per run length the autotuner tries: every load slot of a
   // full run is used (a shorter run re-reads its last source row)

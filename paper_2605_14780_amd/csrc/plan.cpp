@@ -748,9 +748,19 @@ static int64_t pow2_ceil(int64_t v) {
   return p;
 }
 
-// Whether build_windows can take a segment of the plan (its per-segment
-// checks aside): point-major, whole 16-byte vectors, rows of >= WIN_MIN_BYTES,
-// a 4-wide ELL segment without padding.
+// Whether a segment can take sliding windows, its column pattern aside: a
+// 4-wide ELL segment without padding; with b values only from WIN_MIN_BYTES_B
+// per row (the b loads of a run cost more than the window saves on shorter
+// rows).
+static bool win_seg_shape(const Plan& plan, const DevSeg& sg) {
+  const int64_t es = plan.dtype == HBC_F64 ? 8 : 4;
+  if (sg.kind != SEG_ELL || sg.width != 4 || (sg.flags & SEGF_ELL_PADDED) || sg.nrows == 0) return false;
+  return !(sg.has_b && plan.layout.inner * es < WIN_MIN_BYTES_B);
+}
+
+// Whether build_windows can take a segment of the plan (its column patterns
+// aside): point-major, whole 16-byte vectors, rows of >= WIN_MIN_BYTES, a
+// segment of the window shape.
 bool windows_possible(const Plan& plan) {
   const Layout& L = plan.layout;
   const int64_t es = plan.dtype == HBC_F64 ? 8 : 4;
@@ -758,7 +768,7 @@ bool windows_possible(const Plan& plan) {
   if (plan.vec * es != 16 || L.inner * es < WIN_MIN_BYTES) return false;
   if (L.inner * es >= (int64_t(1) << 31)) return false;  // a row is one 32-bit buffer range
   for (const DevSeg& sg : plan.host.segs)
-    if (sg.kind == SEG_ELL && sg.width == 4 && !(sg.flags & SEGF_ELL_PADDED) && sg.nrows > 0) return true;
+    if (win_seg_shape(plan, sg)) return true;
   return false;
 }
 
@@ -950,12 +960,13 @@ static void build_windows(Plan& plan, int rmax) {
   T.seg_win.assign(T.segs.size(), 0);
   T.wruns.clear();
   T.win_maxr = 0;
+  T.win_has_b = false;
   plan.stats.rows_window = plan.stats.window_runs = 0;
   if (!windows_possible(plan)) return;
   rmax = std::max(1, std::min(rmax, WIN_MAXR));
   for (size_t si = 0; si < T.segs.size(); ++si) {
     const DevSeg& sg = T.segs[si];
-    if (sg.kind != SEG_ELL || sg.width != 4 || (sg.flags & SEGF_ELL_PADDED) || sg.nrows == 0) continue;
+    if (!win_seg_shape(plan, sg)) continue;
     if (T.seg_wide.size() == T.segs.size() && T.seg_wide[si]) continue;
     const int32_t* c = T.ell_col.data() + sg.tab;
     auto dl_of = [&](int64_t r) { return (int64_t)c[4 * r + 1] - c[4 * r]; };
@@ -989,6 +1000,7 @@ static void build_windows(Plan& plan, int rmax) {
       w.b_inner = sg.b_inner;
       T.wruns.push_back(w);
       T.win_maxr = std::max<int32_t>(T.win_maxr, (int32_t)n);
+      T.win_has_b = T.win_has_b || sg.has_b;
       r0 += n;
     }
     plan.stats.rows_window += sg.nrows;

@@ -316,6 +316,44 @@ def test_narrow_row_selection(inner, dtype, order, narrow):
     assert st["rows_wide"] == 0
 
 
+@pytest.mark.parametrize("inner,dtype,order,with_b,windowed", [
+    (32, "f64", hb.POINT_MAJOR, False, True),    # 256-byte rows: windows
+    (64, "f32", hb.POINT_MAJOR, False, True),
+    (16, "f64", hb.POINT_MAJOR, False, False),   # 128 bytes: the row kernel
+    (32, "f64", hb.POINT_MAJOR, True, False),    # b on every strip: windows from 512 bytes only
+    (64, "f64", hb.POINT_MAJOR, True, True),
+    (64, "f64", hb.PLANE_MAJOR, False, False),
+])
+def test_window_row_selection(inner, dtype, order, with_b, windowed):
+    """Interpolation rows of the face-edge strips take the window kernel in
+    point-major plans of >= 256-byte rows (>= 512 with b values).  The
+    default launch shape follows: runs of WIN_DEFAULT_ROWS rows where windows
+    are taken, else the row kernel's own tile (a plan whose window-shaped rows
+    all fall under the b threshold keeps the row tiles of a plan built
+    without windows)."""
+    N, h = 24, 3
+    base, w = closed_form_weights(N, h)
+    g = hb.Grid.cubed_sphere(N, h)
+    p = hb.Program(g)
+    p.cs_add(N, h, hb.CS_LAGRANGE, vector=False, base=base, w=w)
+    if with_b:
+        for f in range(6):
+            for side in (ocs.LEFT, ocs.RIGHT, ocs.BOTTOM, ocs.TOP):
+                p.add_vector(ocs.side_box(f, side, N, h), np.full((N * h, 1), 0.25), ninner=1)
+    dt = hb.F64 if dtype == "f64" else hb.F32
+    plan = hb.Plan(p, inner=inner, dtype=dt, order=order, host_only=True)
+    st = plan.stats()
+    ref = hb.Plan(p, inner=inner, dtype=dt, order=order, host_only=True, windows=False)
+    assert ref.stats()["rows_window"] == 0
+    if windowed:
+        assert st["rows_window"] == st["rows_ell"] == 24 * h * N
+        assert st["window_runs"] >= 24 * h * -(-N // 8)
+        assert plan.tune["rows_per_tile"] == 8
+    else:
+        assert st["rows_window"] == 0 and st["window_runs"] == 0
+        assert plan.tune == ref.tune
+
+
 def test_smoke_entry_is_importable_and_shapes_consistent():
     """smoke() needs a GPU; here only its module imports and its field layout
     matches the oracle grid (cells face by face, inner trailing)."""

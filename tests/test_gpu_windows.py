@@ -4,7 +4,7 @@ wavefront walking a run of rows along the neighbour's grid line).
 Its sum is the general row path's, so the bar is bit identity with a plan of
 the same program built with windows=False (the general row kernel), for FP64
 and FP32, with and without the component rotation and b, for run lengths from
-1 to 64 rows, both orders of loads and stores, and rows of 512 bytes to 2 KiB; the general row path itself is
+1 to 64 rows, both orders of loads and stores, and rows of 256 bytes to 2 KiB; the general row path itself is
 checked against the oracle elsewhere.  Also: a graph captured before a change
 of the launch shape is refused, not replayed over freed tables.
 """
@@ -47,6 +47,8 @@ def field(N, h, nf, nl, tdt, seed):
 
 
 @pytest.mark.parametrize("N,h,nf,nl,dtype,vector,with_b", [
+    (48, 3, 1, 32, "f64", False, False),   # 256-byte rows, the shortest that take windows (without b)
+    (40, 3, 4, 16, "f32", True, False),    # 256-byte FP32 rows
     (48, 3, 4, 16, "f64", True, False),    # 512-byte rows
     (48, 3, 4, 16, "f64", True, True),
     (48, 2, 1, 128, "f32", False, True),   # 512-byte FP32 rows
@@ -73,6 +75,25 @@ def test_window_kernel_bitwise_general_path(N, h, nf, nl, dtype, vector, with_b)
             torch.cuda.synchronize()
             assert torch.isfinite(got).all(), (R, order)
             assert torch.equal(got, want), (R, order)
+
+
+def test_window_rows_with_b_from_512_bytes():
+    """Segments with b take windows from 512-byte rows, the others from 256:
+    at 256 bytes a plan with b on some strips windows only the others, and
+    still gives the general path's bits."""
+    N, h, nf, nl = 48, 3, 1, 32
+    grid, pw, pr = cs_pair(N, h, nf, nl, hb.F64, False, True)
+    st = pw.stats()
+    assert 0 < st["rows_window"] < st["rows_ell"]
+    x = field(N, h, nf, nl, torch.float64, seed=3)
+    want, got = x.clone(), x.clone()
+    hb.apply(pr, want)
+    hb.apply(pw, got)
+    torch.cuda.synchronize()
+    assert torch.equal(got, want)
+    grid, pw2, _ = cs_pair(N, h, 4, 16, hb.F64, True, True)  # 512-byte rows: every strip
+    st2 = pw2.stats()
+    assert st2["rows_window"] == st2["rows_ell"] > 0
 
 
 def test_window_adjoint_and_graph_after_tuning():
