@@ -430,7 +430,11 @@ int hbc_consumer_create(const hbc_plan* plan, int32_t noffsets, const int64_t* o
                         hbc_consumer** out);
 /* y: device, y_nelem = data cells x inner values (block by block, each block's
  * data box row-major, inner values contiguous per cell); x: the plan's field
- * (x_nelem = cells x inner).  Sums in offset order (first product, then FMAs).
+ * (x_nelem = cells x inner).  Sums in offset order (first product, then FMAs),
+ * except where the offsets lie on at most 3 lines along the last dimension
+ * (equal in the others), each within +-1 along it, without repeats: then line
+ * by line (lines in order of first appearance, each in ascending last
+ * coordinate), in both forms.
  * fused = 0: every read from x, ghosts as stored (run hbc_apply first).
  * fused = 1: reads of covered ghosts go through the BC: each cell whose
  * stencil reaches ghosts has one row composed at creation, entries (source

@@ -50,6 +50,58 @@ void box_tiles(const Grid& g, int b, const Box& bx, const Box& data, int64_t yba
   }
 }
 
+// Lines of the offsets: offsets equal in all but the last dimension.  When
+// they lie on at most CONS_MAXLINES lines, each within +-1 along the last
+// dimension and without repeats, the structured walk keeps a ring of each
+// line's last three points (one new load per line and cell), and the
+// offsets are reordered line by line (lines in order of first appearance,
+// each in ascending last coordinate): the order of every sum, in both forms.
+// Returns the offsets per line (empty: the general walk).
+std::vector<int> find_lines(int nd, ConsumerHost& C) {
+  const int noff = C.noff;
+  std::vector<std::vector<int>> lines;
+  for (int o = 0; o < noff; ++o) {
+    const int64_t p = C.off[(size_t)o * nd + nd - 1];
+    if (p < -1 || p > 1) return {};
+    size_t l = 0;
+    for (; l < lines.size(); ++l) {
+      const int f = lines[l][0];
+      bool same = true;
+      for (int d = 0; d + 1 < nd; ++d) same = same && C.off[(size_t)f * nd + d] == C.off[(size_t)o * nd + d];
+      if (same) break;
+    }
+    if (l == lines.size()) {
+      if (lines.size() == (size_t)CONS_MAXLINES) return {};
+      lines.emplace_back();
+    }
+    for (int q : lines[l])
+      if (C.off[(size_t)q * nd + nd - 1] == p) return {};  // a repeated offset
+    lines[l].push_back(o);
+  }
+  std::vector<int64_t> off;
+  std::vector<double> w;
+  std::vector<int> len;
+  C.line_w.assign(lines.size() * 3, 0.0);
+  C.line_mask = 0;
+  for (size_t l = 0; l < lines.size(); ++l) {
+    std::vector<int>& L = lines[l];
+    std::sort(L.begin(), L.end(), [&](int a, int b) { return C.off[(size_t)a * nd + nd - 1] < C.off[(size_t)b * nd + nd - 1]; });
+    const int64_t pmax = C.off[(size_t)L.back() * nd + nd - 1];
+    for (int o : L) {
+      off.insert(off.end(), C.off.begin() + (size_t)o * nd, C.off.begin() + (size_t)(o + 1) * nd);
+      w.push_back(C.w[o]);
+      const int s = (int)(C.off[(size_t)o * nd + nd - 1] - pmax + 2);
+      C.line_w[l * 3 + s] = C.w[o];
+      C.line_mask |= 1 << (3 * l + s);
+    }
+    len.push_back((int)L.size());
+  }
+  C.off.swap(off);
+  C.w.swap(w);
+  C.nlines = (int)lines.size();
+  return len;
+}
+
 }  // namespace
 
 void compile_consumer(const Plan& plan, int noff, const int64_t* offsets, const double* weights, ConsumerHost& C) {
@@ -68,6 +120,7 @@ void compile_consumer(const Plan& plan, int noff, const int64_t* offsets, const 
       C.off[(size_t)o * nd + d] = v / g.step[d];
     }
   C.w.assign(weights, weights + noff);
+  const std::vector<int> line_len = find_lines(nd, C);
   // every read of every data cell stays inside its block's full box
   C.delta.resize(g.blocks.size() * (size_t)noff);
   for (size_t b = 0; b < g.blocks.size(); ++b) {
@@ -83,6 +136,13 @@ void compile_consumer(const Plan& plan, int noff, const int64_t* offsets, const 
       C.delta[b * noff + o] = (int32_t)dl;
     }
   }
+  // each line's last point: its last offset (the lines' offsets are consecutive)
+  C.line_delta.resize(g.blocks.size() * (size_t)C.nlines);
+  for (size_t b = 0, o = 0; b < g.blocks.size(); ++b, o = 0)
+    for (int l = 0; l < C.nlines; ++l) {
+      o += (size_t)line_len[l];
+      C.line_delta[b * C.nlines + l] = C.delta[b * noff + o - 1];
+    }
   const int lpr = std::max(1, plan.tune.lanes_per_row), groups = std::max(1, 256 / lpr);
   C.tile_cells = groups * CONS_CELLS;
   C.tile_rows = groups;  // one boundary row per row group

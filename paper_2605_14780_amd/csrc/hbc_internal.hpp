@@ -463,11 +463,20 @@ struct alignas(16) CTile {
 constexpr int CONS_RB = 2;      // cells (or boundary rows) per batch of a row group
 constexpr int CONS_CELLS = 16;  // cells of a structured tile per row group
 constexpr int CONS_MAXOFF = 64; // offsets at most
+constexpr int CONS_MAXLINES = 3; // lines of the line walk at most
 struct ConsumerHost {
   int noff = 0;
-  std::vector<int64_t> off;        // noff x nd, lattice steps
+  std::vector<int64_t> off;        // noff x nd, lattice steps (line by line when nlines > 0)
   std::vector<double> w;           // noff
   std::vector<int32_t> delta;      // nblocks x noff cell deltas
+  // line walk of the structured tiles: the offsets lie on nlines lines along
+  // the last dimension (equal in the others), each within +-1 along it; a
+  // row group keeps the last three points of each line in registers.  0: the
+  // general walk.
+  int nlines = 0;
+  std::vector<int32_t> line_delta; // nblocks x nlines: cell delta of each line's last point
+  std::vector<double> line_w;      // nlines x 3: weight of ring slot s (the line's last point - 2 + s)
+  int32_t line_mask = 0;           // bit 3 l + s: slot s of line l is an offset
   std::vector<CTile> tiles_all;    // every data cell (unfused: ghosts read from the field)
   std::vector<CTile> tiles_int;    // cells whose reads are all data cells (fused)
   std::vector<int32_t> brow_y;     // boundary rows (fused): output row

@@ -1812,13 +1812,86 @@ struct ConsDesc {
   int32_t nbrow;  // boundary rows (0: unfused)
   int32_t tile_rows;  // boundary rows per tile
   void* y;
+  const int32_t* line_delta;  // line walk: per block, cell delta of each line's last point
+  const void* line_w;         // lines x 3 ring-slot weights
+  int32_t line_mask;          // bit 3 l + s: slot s of line l is an offset
 };
 
-// PIPE: at most 8 offsets and one pass of a row group per cell (the
-// pipelined walk); else the offsets go 8 at a time, a batch of cells at once.
-// The boundary rows' tiles come first in the grid (they then overlap the
+// Line walk of a structured tile (NL lines, see ConsumerHost): slot s of
+// line l's ring holds the point k + line_delta[l] - 2 + s of cell k.  A row
+// group walks its cells in chunks of CONS_CELLS steps; every step issues the
+// next cell's new point of each line before the current cell's sum and
+// store, and every load and store is issued whatever the chunk's length
+// (loads clamped to the chunk's last cell, stores past it dropped through
+// the output range), so that each wait is for the current cell's points only.
+template <typename T, int V, bool NT, int NL>
+__device__ __forceinline__ void cons_lines(const PlanDesc& d, const ConsDesc& c, const CTile& t, int kb, int ke,
+                                           int lane) {
+  constexpr int NS = CONS_CELLS;
+  const T* __restrict__ x = static_cast<const T*>(d.field);
+  const int64_t l = (int64_t)lane * V;
+  const int32_t* __restrict__ ld = c.line_delta + (int64_t)t.blk * NL;
+  const T* __restrict__ lw = static_cast<const T*>(c.line_w);
+  int32_t dl[NL], s0[NL];
+  T w[NL][3];
+  bool on[NL][3];
+#pragma unroll
+  for (int q = 0; q < NL; ++q) {
+    dl[q] = ld[q];
+    const int m3 = (c.line_mask >> (3 * q)) & 7;
+    s0[q] = (m3 & 1) ? 0 : ((m3 & 2) ? 1 : 2);  // the line's first slot (slots before it are never read)
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      w[q][u] = lw[3 * q + u];
+      on[q][u] = (m3 >> u) & 1;
+    }
+  }
+  const T* __restrict__ xb = x + (int64_t)t.cell0 * d.cs + l;
+  const int row_bytes = (int)(d.inner * (int64_t)sizeof(T));
+  for (int k0 = kb; k0 < ke; k0 += NS) {
+    const int last = min(ke, k0 + NS) - 1;
+    Pack<T, V> R[NL][3];
+#pragma unroll
+    for (int q = 0; q < NL; ++q)
+#pragma unroll
+      for (int u = 0; u < 3; ++u) R[q][u] = ldv<T, V>(xb + (int64_t)(k0 + dl[q] - 2 + max(u, s0[q])) * d.cs);
+    // the chunk's output rows: one buffer range (NS rows of < 4 KiB each at most)
+    T* yc = static_cast<T*>(c.y) + (int64_t)(t.y0 + k0) * d.inner;
+    const __amdgpu_buffer_rsrc_t yr =
+        __builtin_amdgcn_make_buffer_rsrc(yc, 0, (last - k0 + 1) * row_bytes, BUF_RSRC_WORD3);
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      const int kn = min(k0 + j + 1, last);
+      Pack<T, V> nx[NL];
+#pragma unroll
+      for (int q = 0; q < NL; ++q) nx[q] = ldv<T, V>(xb + (int64_t)(kn + dl[q]) * d.cs);
+      Pack<T, V> acc;
+#pragma unroll
+      for (int i = 0; i < V; ++i) acc.v[i] = T(-0.0);  // fma(w, x, -0) = w * x: the first term is a product
+#pragma unroll
+      for (int q = 0; q < NL; ++q)
+#pragma unroll
+        for (int u = 0; u < 3; ++u)
+#pragma unroll
+          for (int i = 0; i < V; ++i) acc.v[i] = on[q][u] ? fma(w[q][u], R[q][u].v[i], acc.v[i]) : acc.v[i];
+      const uint32_t off = (uint32_t)((int64_t)j * d.inner + l) * (uint32_t)sizeof(T);
+      stv_buf<T, V, NT>(acc, yr, k0 + j <= last ? off : BUF_OOB);
+#pragma unroll
+      for (int q = 0; q < NL; ++q) {
+        R[q][0] = R[q][1];
+        R[q][1] = R[q][2];
+        R[q][2] = nx[q];
+      }
+    }
+  }
+}
+
+// WALK of the structured tiles: 0, the offsets 8 at a time over a batch of
+// cells; 1, the pipelined walk (at most 8 offsets, one pass of a row group
+// per cell); 10 + NL, the line walk of NL lines (one pass per cell).  The
+// boundary rows' tiles come first in the grid (they then overlap the
 // structured tiles instead of trailing them).
-template <typename T, int V, bool NT, bool PIPE>
+template <typename T, int V, bool NT, int WALK>
 __global__ __launch_bounds__(256) void k_consumer(PlanDesc d, ConsDesc c) {
   constexpr int RB = CONS_RB, EC = 8;
   const int lpr = 1 << d.lpr_shift;
@@ -1843,7 +1916,10 @@ __global__ __launch_bounds__(256) void k_consumer(PlanDesc d, ConsDesc c) {
     // a row group walks a contiguous part of the tile's run
     const int cpg = (t.n + ngroups - 1) / ngroups;
     const int kb = grp * cpg, ke = min(t.n, kb + cpg);
-    if constexpr (PIPE) {
+    if constexpr (WALK > 10) {
+      if (lane < nvec && kb < ke) cons_lines<T, V, NT, WALK - 10>(d, c, t, kb, ke, lane);
+      return;
+    } else if constexpr (WALK == 1) {
       // one pass per cell: the next cell's reads issued before the current
       // cell's store (two register sets, A and B)
       if (lane >= nvec) return;
@@ -2735,6 +2811,8 @@ struct ConsDev {
   const int8_t* brot = nullptr;
   const int32_t* bconst_row = nullptr;
   const void* bconst = nullptr;
+  const int32_t* line_delta = nullptr;
+  const void* line_w = nullptr;
 };
 
 void* device_consumer_upload(const Plan& p, const ConsumerHost& C) {
@@ -2742,7 +2820,7 @@ void* device_consumer_upload(const Plan& p, const ConsumerHost& C) {
   const size_t o_dl = pk.vec(C.delta), o_w = pk.reals(C.w, p.dtype), o_ta = pk.vec(C.tiles_all),
                o_ti = pk.vec(C.tiles_int), o_by = pk.vec(C.brow_y), o_bp = pk.vec(C.bptr), o_bc = pk.vec(C.bcol),
                o_bw = pk.reals(C.bw, p.dtype), o_br = pk.vec(C.brot), o_bk = pk.vec(C.bconst_row),
-               o_bv = pk.reals(C.bconst, p.dtype);
+               o_bv = pk.reals(C.bconst, p.dtype), o_ld = pk.vec(C.line_delta), o_lw = pk.reals(C.line_w, p.dtype);
   auto* cd = new ConsDev;
   void* dev = nullptr;
   const hipError_t e = hipMalloc(&dev, pk.buf.size());
@@ -2769,6 +2847,8 @@ void* device_consumer_upload(const Plan& p, const ConsumerHost& C) {
   cd->brot = reinterpret_cast<const int8_t*>(b + o_br);
   cd->bconst_row = reinterpret_cast<const int32_t*>(b + o_bk);
   cd->bconst = b + o_bv;
+  cd->line_delta = reinterpret_cast<const int32_t*>(b + o_ld);
+  cd->line_w = b + o_lw;
   return cd;
 }
 
@@ -2779,17 +2859,31 @@ void device_consumer_free(void* h) {
   delete cd;
 }
 
-template <typename T, int V>
-static void launch_consumer(bool nt, dim3 g, dim3 b, hipStream_t st, const PlanDesc& d, const ConsDesc& c) {
-  const bool pipe = c.noff <= 8 && d.inner / V <= (int64_t(1) << d.lpr_shift);
-  if (nt && pipe)
-    hipLaunchKernelGGL((k_consumer<T, V, true, true>), g, b, 0, st, d, c);
-  else if (nt)
-    hipLaunchKernelGGL((k_consumer<T, V, true, false>), g, b, 0, st, d, c);
-  else if (pipe)
-    hipLaunchKernelGGL((k_consumer<T, V, false, true>), g, b, 0, st, d, c);
+template <typename T, int V, int WALK>
+static void launch_consumer_walk(bool nt, dim3 g, dim3 b, hipStream_t st, const PlanDesc& d, const ConsDesc& c) {
+  if (nt)
+    hipLaunchKernelGGL((k_consumer<T, V, true, WALK>), g, b, 0, st, d, c);
   else
-    hipLaunchKernelGGL((k_consumer<T, V, false, false>), g, b, 0, st, d, c);
+    hipLaunchKernelGGL((k_consumer<T, V, false, WALK>), g, b, 0, st, d, c);
+}
+
+template <typename T, int V>
+static void launch_consumer(bool nt, int nlines, dim3 g, dim3 b, hipStream_t st, const PlanDesc& d,
+                            const ConsDesc& c) {
+  // one pass of a row group per cell: the line walk, else the pipelined walk
+  // for at most 8 offsets
+  const bool one_pass = d.inner / V <= (int64_t(1) << d.lpr_shift);
+  static_assert(CONS_MAXLINES == 3, "one line-walk instance per line count");
+  if (one_pass && nlines == 1)
+    launch_consumer_walk<T, V, 11>(nt, g, b, st, d, c);
+  else if (one_pass && nlines == 2)
+    launch_consumer_walk<T, V, 12>(nt, g, b, st, d, c);
+  else if (one_pass && nlines == 3)
+    launch_consumer_walk<T, V, 13>(nt, g, b, st, d, c);
+  else if (one_pass && c.noff <= 8)
+    launch_consumer_walk<T, V, 1>(nt, g, b, st, d, c);
+  else
+    launch_consumer_walk<T, V, 0>(nt, g, b, st, d, c);
 }
 
 void device_consumer_apply(const Plan& p, const ConsumerHost& C, void* h, const void* x, void* y, bool fused,
@@ -2812,6 +2906,9 @@ void device_consumer_apply(const Plan& p, const ConsumerHost& C, void* h, const 
   c.nbrow = fused ? (int32_t)C.brow_y.size() : 0;
   c.tile_rows = std::max(1, C.tile_rows);
   c.y = y;
+  c.line_delta = cd->line_delta;
+  c.line_w = cd->line_w;
+  c.line_mask = C.line_mask;
   const int64_t nbt = (c.nbrow + c.tile_rows - 1) / c.tile_rows;
   const int64_t grid = (int64_t)c.ntiles + nbt;
   if (grid >= (int64_t(1) << 31)) fail(HBC_EUNSUPPORTED, "consumer grid too large");
@@ -2820,16 +2917,16 @@ void device_consumer_apply(const Plan& p, const ConsumerHost& C, void* h, const 
   hipStream_t st = S(stream);
   if (p.dtype == HBC_F64) {
     if (p.vec >= 2)
-      launch_consumer<double, 2>(d.nt != 0, g, blk, st, d, c);
+      launch_consumer<double, 2>(d.nt != 0, C.nlines, g, blk, st, d, c);
     else
-      launch_consumer<double, 1>(d.nt != 0, g, blk, st, d, c);
+      launch_consumer<double, 1>(d.nt != 0, C.nlines, g, blk, st, d, c);
   } else {
     if (p.vec == 4)
-      launch_consumer<float, 4>(d.nt != 0, g, blk, st, d, c);
+      launch_consumer<float, 4>(d.nt != 0, C.nlines, g, blk, st, d, c);
     else if (p.vec == 2)
-      launch_consumer<float, 2>(d.nt != 0, g, blk, st, d, c);
+      launch_consumer<float, 2>(d.nt != 0, C.nlines, g, blk, st, d, c);
     else
-      launch_consumer<float, 1>(d.nt != 0, g, blk, st, d, c);
+      launch_consumer<float, 1>(d.nt != 0, C.nlines, g, blk, st, d, c);
   }
   HIP_CHECK(hipGetLastError());
 }

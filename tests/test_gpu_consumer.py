@@ -31,6 +31,15 @@ CROSS = [(0, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]
 CROSS_W = [-4.0, 1.0, 1.0, 1.0, 1.0]
 SKEW = [(0, 2, -1), (0, 0, 0), (0, -1, 0), (0, 0, 2), (0, -2, -2), (0, 1, 1)]
 SKEW_W = [0.25, -1.5, 2.0, 0.75, -0.5, 1.0]
+# stencils of the line walk (offsets on <= 3 lines along the last dimension,
+# each within +-1 along it): one line; two lines, one with a hole and one
+# reaching only 0 and +1; the full 9-point box
+LINE1 = [(0, 0, -1), (0, 0, 0), (0, 0, 1)]
+LINE1_W = [1.0, -2.0, 1.0]
+LINES2 = [(0, 1, 1), (0, 0, -1), (0, 1, 0), (0, 0, 1)]
+LINES2_W = [0.5, -1.25, 2.0, 0.75]
+BOX9 = [(0, a, b) for a in (-1, 0, 1) for b in (1, 0, -1)]
+BOX9_W = [0.3, -0.7, 1.1, 0.9, -8.0, 0.6, -0.2, 1.3, 0.45]
 
 
 def magnitude_bound(op, u, offs, w, vec):
@@ -65,6 +74,10 @@ def make(plan, offs, w, ndata):
     (48, 3, 4, 16, CROSS, CROSS_W, "f64"),   # 512-byte rows
     (48, 3, 4, 16, SKEW, SKEW_W, "f32"),
     (24, 2, 1, 3, CROSS, CROSS_W, "f64"),
+    (24, 3, 4, 4, LINE1, LINE1_W, "f64"),
+    (20, 3, 4, 4, LINES2, LINES2_W, "f32"),
+    (48, 3, 4, 16, BOX9, BOX9_W, "f64"),
+    (17, 2, 1, 3, BOX9, BOX9_W, "f32"),
 ])
 def test_consumer_oracle_weights_fused_and_unfused(N, h, nf, nl, offs, w, dtype):
     I = nf * nl
@@ -109,6 +122,34 @@ def test_consumer_library_weights_fused_equals_unfused(N, h, nl):
     scale = np.abs(full[og.data_cells]).max(axis=0)
     assert (np.abs(yf - yu) <= 1e-13 * 8 * scale).all()
     assert np.array_equal(np.nan_to_num(xf.cpu().numpy(), nan=7.0), np.nan_to_num(full, nan=7.0))
+
+
+@pytest.mark.parametrize("offs,w", [(CROSS, CROSS_W), (BOX9, BOX9_W)])
+def test_consumer_walk_longer_than_a_chunk(offs, w):
+    """A launch shape set after the consumer was compiled gives each row group
+    more cells than one chunk of the line walk (one row group per tile here):
+    the walk goes on chunk by chunk with the same sums, bit for bit."""
+    N, h, nf, nl = 40, 3, 4, 16
+    I = nf * nl
+    vec = (2 * nl, nl, nl)
+    grid, prog = oracle_weights_program(hb, N, h, True)
+    plan = hb.Plan(prog, inner=I, vec=vec)
+    og = ocs.grid(N, h)
+    full = cs_full_field(N, h, nf, nl, seed=5, noise=1e-3)
+    cons = make(plan, offs, w, og.ndata)
+    want = [run(cons, plan, full, torch.float64, f)[0] for f in (True, False)]
+    t = plan.tune
+    assert 256 // t["lanes_per_row"] > 1
+    t["lanes_per_row"] = 256
+    plan.tune = t
+    got = [run(cons, plan, full, torch.float64, f)[0] for f in (True, False)]
+    for a, b in zip(want, got):
+        assert np.array_equal(a, b)
+    op = assemble(og, ocs.subs(N, h, "lagrange", vector=True))
+    ref = stencil_after_bc(op, full, offs, w, vec)
+    bound = 1e-13 * magnitude_bound(op, full, offs, w, vec)
+    for y in got:
+        assert (np.abs(y - ref) <= bound).all()
 
 
 def test_consumer_footprint_plan():
