@@ -145,7 +145,7 @@ void compile_consumer(const Plan& plan, int noff, const int64_t* offsets, const 
     }
   const int lpr = std::max(1, plan.tune.lanes_per_row), groups = std::max(1, 256 / lpr);
   C.tile_cells = groups * CONS_CELLS;
-  C.tile_rows = groups;  // one boundary row per row group
+  C.tile_rows = groups * CONS_BROWS;
   // covered ghost rows: cell -> row of the plan's device order
   const HostTables& T = plan.host;
   std::unordered_map<int32_t, int64_t> row_of;
