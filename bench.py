@@ -27,6 +27,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import subprocess
 import sys
 import tempfile
@@ -43,10 +44,16 @@ def log(msg):
 
 
 def kernel_source_hash():
+    """Hash of the sources the apply kernels and their tables are built from,
+    with comments and whitespace left out (an edited comment keeps committed
+    counters valid; any change to the code voids them)."""
     h = hashlib.sha256()
-    for f in ("kernels.hip", "plan.cpp"):
-        with open(os.path.join(ROOT, "paper_2605_14780_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    for f in ("kernels.hip", "plan.cpp", "hbc_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2605_14780_amd", "csrc", f)) as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

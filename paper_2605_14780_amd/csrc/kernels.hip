@@ -1789,12 +1789,13 @@ __global__ __launch_bounds__(256) void k_stencil27(const T* __restrict__ x, T* x
 }
 
 // ---- consumer of the BC's ghosts (stencil of offsets and weights) --------------------
-// Structured tiles: a run of cells along the last dimension; each row group
-// takes CONS_RB cells, issues all their reads (EC offsets at a time) and sums
-// them in offset order (first product, then FMAs).  Boundary rows (fused
-// form): the stencil composed with the BC rows of the ghosts it reaches, as
-// entries (cell, weight, component rotation) summed in order, plus the
-// composed b.  The output y holds the data cells block by block, each block's
+// Structured tiles: a run of cells along the last dimension, which each row
+// group walks in one of three ways (the line walk, the pipelined walk, or
+// batches of CONS_RB cells with the offsets EC at a time; see k_consumer),
+// every sum in the consumer's offset order (first product, then FMAs).
+// Boundary rows (fused form): the stencil composed with the BC rows of the
+// ghosts it reaches, as entries (cell, weight, component rotation) summed in
+// order, plus the composed b.  The output y holds the data cells block by block, each block's
 // data box row-major, inner values point-major.
 struct ConsDesc {
   const int32_t* delta;  // per block: noff cell deltas
