@@ -152,6 +152,38 @@ def test_consumer_walk_longer_than_a_chunk(offs, w):
         assert (np.abs(y - ref) <= bound).all()
 
 
+@pytest.mark.parametrize("off", [(0, 0, 0), (0, 0, 1), (0, -1, 0), (0, 1, -1), (0, 1, 2)])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_consumer_unit_shift_is_exact(off, dtype):
+    """A consumer of one offset with weight 1 copies the field after the BC,
+    shifted by that offset, and both forms give its bits exactly: a composed
+    boundary row is its ghost's BC row with the weights times 1 (the sign
+    folded into each weight negates each partial sum exactly), in the
+    apply's order, plus b.  Offsets with a last coordinate within +-1 take the
+    line walk, (0, 1, 2) the pipelined walk.  (A consistency check between
+    the apply and the consumer; both are checked against the oracle
+    elsewhere.)"""
+    N, h, nf, nl = 20, 3, 4, 4
+    I = nf * nl
+    vec = (2 * nl, nl, nl)
+    W = N + 2 * h
+    rng = np.random.default_rng(11)
+    b = [(ocs.side_box(2, ocs.LEFT, N, h), rng.standard_normal((h * N, I)))]
+    grid, prog = oracle_weights_program(hb, N, h, True, b=b)
+    dt, tdt = (hb.F64, torch.float64) if dtype == "f64" else (hb.F32, torch.float32)
+    plan = hb.Plan(prog, inner=I, vec=vec, dtype=dt)
+    og = ocs.grid(N, h)
+    full = cs_full_field(N, h, nf, nl, seed=9, noise=1e-3)
+    cons = make(plan, [off], [1.0], og.ndata)
+    yu, xa = run(cons, plan, full, tdt, False)
+    yf, _ = run(cons, plan, full, tdt, True)
+    xa = xa.cpu().numpy().astype(np.float64).reshape(6, W, W, I)
+    want = xa[:, h + off[1]:h + off[1] + N, h + off[2]:h + off[2] + N].reshape(-1, I)
+    assert np.isfinite(want).all()
+    assert np.array_equal(yu, want)
+    assert np.array_equal(yf, want)
+
+
 def test_consumer_footprint_plan():
     """A plan compiled with the consumer's own footprint (only the ghosts the
     stencil reads) gives the same fused and unfused results as the full plan."""
