@@ -325,7 +325,9 @@ __device__ __forceinline__ void run_tile_pm(const PlanDesc& d, const DevSeg& s, 
 // bit 0 the 4-wide Lagrange rows, bit 1 general ELL/CSR rows.  Paths of
 // absent kinds are compiled out (their registers would lower the occupancy of
 // every other kind).
-constexpr int KM_ELL4 = 1, KM_GENERAL = 2, KM_UNAL = 4;
+// KM_SEQFB: Lagrange row batches whose windows do not slide go row by row
+// (see the ELL path).
+constexpr int KM_ELL4 = 1, KM_GENERAL = 2, KM_UNAL = 4, KM_SEQFB = 8;
 template <typename T, int V, int U, bool NT, int RB, int KM>
 __device__ __forceinline__ void rt_tile(const PlanDesc& d, const RowTile& tl, bool zero_only) {
   const int lpr = 1 << d.lpr_shift;
@@ -442,6 +444,33 @@ __device__ __forceinline__ void rt_tile(const PlanDesc& d, const RowTile& tl, bo
                 a = fma(wt[q][3], w[q + 3][u].v[i], a);
                 y[q][u].v[i] = sign[u] * a;
               }
+        } else if constexpr ((KM & KM_SEQFB) != 0) {
+          // the windows do not slide (a run restarts inside the batch, or the
+          // group's rows end before the batch does): row by row, so that this
+          // path holds one row's sources rather than the batch's, and the
+          // kernel (whose registers are those of its largest path) keeps more
+          // waves resident
+#pragma unroll
+          for (int q = 0; q < RB; ++q) {
+            Pack<T, V> x[4][U];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+              const T* src = f + (int64_t)c[q][m] * d.cs;
+#pragma unroll
+              for (int u = 0; u < U; ++u) x[m][u] = ldv<T, V, UA>(src + sl[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+              for (int i = 0; i < V; ++i) {
+                T a = wt[q][0] * x[0][u].v[i];
+                a = fma(wt[q][1], x[1][u].v[i], a);
+                a = fma(wt[q][2], x[2][u].v[i], a);
+                a = fma(wt[q][3], x[3][u].v[i], a);
+                y[q][u].v[i] = sign[u] * a;
+              }
+            __builtin_amdgcn_sched_barrier(0);  // keep the next row's loads after this row's sum
+          }
         } else {
           Pack<T, V> x[RB][4][U];
 #pragma unroll
@@ -2351,25 +2380,29 @@ template <typename T, int V, int U, int KX = 0>
 static void launch_rows_vu(const PlanDesc& d, hipStream_t st, int grid, int blk, const RowTile* tiles, int nt, int z,
                            const DataDesc& dd) {
   const bool rb2 = rows_per_batch(1 << d.lpr_shift) == 2;
+  // FP64 rows take the row-by-row fallback of non-sliding Lagrange batches
+  // (C768 x 32 with b: 9.5-9.7 against 10.6-10.8 us); FP32 rows keep the
+  // batched one (7.1 against 6.5 us: their groups often hold one row)
+  constexpr int KS = sizeof(T) == 8 ? KM_SEQFB : 0;
   const dim3 g(grid + dd.grid), b(blk);
   if (d.general) {
     if (d.nt && rb2)
-      HBC_LAUNCH((k_apply_rows<T, V, U, true, 2, 3 | KX>), g, b, 0, st, d, tiles, nt, z, dd);
+      HBC_LAUNCH((k_apply_rows<T, V, U, true, 2, 3 | KX | KS>), g, b, 0, st, d, tiles, nt, z, dd);
     else if (d.nt)
-      HBC_LAUNCH((k_apply_rows<T, V, U, true, 4, 3 | KX>), g, b, 0, st, d, tiles, nt, z, dd);
+      HBC_LAUNCH((k_apply_rows<T, V, U, true, 4, 3 | KX | KS>), g, b, 0, st, d, tiles, nt, z, dd);
     else if (rb2)
-      HBC_LAUNCH((k_apply_rows<T, V, U, false, 2, 3 | KX>), g, b, 0, st, d, tiles, nt, z, dd);
+      HBC_LAUNCH((k_apply_rows<T, V, U, false, 2, 3 | KX | KS>), g, b, 0, st, d, tiles, nt, z, dd);
     else
-      HBC_LAUNCH((k_apply_rows<T, V, U, false, 4, 3 | KX>), g, b, 0, st, d, tiles, nt, z, dd);
+      HBC_LAUNCH((k_apply_rows<T, V, U, false, 4, 3 | KX | KS>), g, b, 0, st, d, tiles, nt, z, dd);
   } else {
     if (d.nt && rb2)
-      HBC_LAUNCH((k_apply_rows<T, V, U, true, 2, 1 | KX>), g, b, 0, st, d, tiles, nt, z, dd);
+      HBC_LAUNCH((k_apply_rows<T, V, U, true, 2, 1 | KX | KS>), g, b, 0, st, d, tiles, nt, z, dd);
     else if (d.nt)
-      HBC_LAUNCH((k_apply_rows<T, V, U, true, 4, 1 | KX>), g, b, 0, st, d, tiles, nt, z, dd);
+      HBC_LAUNCH((k_apply_rows<T, V, U, true, 4, 1 | KX | KS>), g, b, 0, st, d, tiles, nt, z, dd);
     else if (rb2)
-      HBC_LAUNCH((k_apply_rows<T, V, U, false, 2, 1 | KX>), g, b, 0, st, d, tiles, nt, z, dd);
+      HBC_LAUNCH((k_apply_rows<T, V, U, false, 2, 1 | KX | KS>), g, b, 0, st, d, tiles, nt, z, dd);
     else
-      HBC_LAUNCH((k_apply_rows<T, V, U, false, 4, 1 | KX>), g, b, 0, st, d, tiles, nt, z, dd);
+      HBC_LAUNCH((k_apply_rows<T, V, U, false, 4, 1 | KX | KS>), g, b, 0, st, d, tiles, nt, z, dd);
   }
 }
 
@@ -3217,14 +3250,14 @@ void device_batch_apply(Batch* b, void* stream) {
   const dim3 g(grid), blk(b->tune.block);
   if (b->dtype == HBC_F64) {
     if (gen)
-      hipLaunchKernelGGL((k_batch<double, 3>), g, blk, 0, S(stream), b->d_descs, b->d_tiles, nt);
+      hipLaunchKernelGGL((k_batch<double, 3 | KM_SEQFB>), g, blk, 0, S(stream), b->d_descs, b->d_tiles, nt);
     else
-      hipLaunchKernelGGL((k_batch<double, 1>), g, blk, 0, S(stream), b->d_descs, b->d_tiles, nt);
+      hipLaunchKernelGGL((k_batch<double, 1 | KM_SEQFB>), g, blk, 0, S(stream), b->d_descs, b->d_tiles, nt);
   } else {
     if (gen)
-      hipLaunchKernelGGL((k_batch<float, 3>), g, blk, 0, S(stream), b->d_descs, b->d_tiles, nt);
+      hipLaunchKernelGGL((k_batch<float, 3 | KM_SEQFB>), g, blk, 0, S(stream), b->d_descs, b->d_tiles, nt);
     else
-      hipLaunchKernelGGL((k_batch<float, 1>), g, blk, 0, S(stream), b->d_descs, b->d_tiles, nt);
+      hipLaunchKernelGGL((k_batch<float, 1 | KM_SEQFB>), g, blk, 0, S(stream), b->d_descs, b->d_tiles, nt);
   }
   HIP_CHECK(hipGetLastError());
 }
