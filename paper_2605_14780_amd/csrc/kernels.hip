@@ -452,23 +452,29 @@ __device__ __forceinline__ void rt_tile(const PlanDesc& d, const RowTile& tl, bo
           // waves resident
 #pragma unroll
           for (int q = 0; q < RB; ++q) {
-            Pack<T, V> x[4][U];
+            if (q > 0 && rr[q] == rr[q - 1]) {
+              // past the group's last row (clamped to it): its value, no loads
 #pragma unroll
-            for (int m = 0; m < 4; ++m) {
-              const T* src = f + (int64_t)c[q][m] * d.cs;
+              for (int u = 0; u < U; ++u) y[q][u] = y[q - 1][u];
+            } else {
+              Pack<T, V> x[4][U];
 #pragma unroll
-              for (int u = 0; u < U; ++u) x[m][u] = ldv<T, V, UA>(src + sl[u]);
-            }
+              for (int m = 0; m < 4; ++m) {
+                const T* src = f + (int64_t)c[q][m] * d.cs;
 #pragma unroll
-            for (int u = 0; u < U; ++u)
-#pragma unroll
-              for (int i = 0; i < V; ++i) {
-                T a = wt[q][0] * x[0][u].v[i];
-                a = fma(wt[q][1], x[1][u].v[i], a);
-                a = fma(wt[q][2], x[2][u].v[i], a);
-                a = fma(wt[q][3], x[3][u].v[i], a);
-                y[q][u].v[i] = sign[u] * a;
+                for (int u = 0; u < U; ++u) x[m][u] = ldv<T, V, UA>(src + sl[u]);
               }
+#pragma unroll
+              for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int i = 0; i < V; ++i) {
+                  T a = wt[q][0] * x[0][u].v[i];
+                  a = fma(wt[q][1], x[1][u].v[i], a);
+                  a = fma(wt[q][2], x[2][u].v[i], a);
+                  a = fma(wt[q][3], x[3][u].v[i], a);
+                  y[q][u].v[i] = sign[u] * a;
+                }
+            }
             __builtin_amdgcn_sched_barrier(0);  // keep the next row's loads after this row's sum
           }
         } else {
