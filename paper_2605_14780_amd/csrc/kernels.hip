@@ -2387,8 +2387,8 @@ static void launch_rows_vu(const PlanDesc& d, hipStream_t st, int grid, int blk,
                            const DataDesc& dd) {
   const bool rb2 = rows_per_batch(1 << d.lpr_shift) == 2;
   // FP64 rows take the row-by-row fallback of non-sliding Lagrange batches
-  // (C768 x 32 with b: 9.5-9.7 against 10.6-10.8 us); FP32 rows keep the
-  // batched one (7.1 against 6.5 us: their groups often hold one row)
+  // (C768 x 32 with b: 9.5-9.9 against 10.6-10.8 us); FP32 rows keep the
+  // batched one (measured: 7.1-7.4 against 6.5-6.6 us row by row)
   constexpr int KS = sizeof(T) == 8 ? KM_SEQFB : 0;
   const dim3 g(grid + dd.grid), b(blk);
   if (d.general) {
