@@ -13,8 +13,15 @@
 * C384 wide interpolation rows (16..25 entries, LDS-staged kernel): sampled
   rows against the oracle's;
 * the 64-grid FP32 batch in its autotuned graph launch: bit identity with
-  plain applies and sampled rows against the oracle's.
+  plain applies and sampled rows against the oracle's;
+* the radius-1 cross consumer on the full C384 x 256 field (plan compiled
+  with the cross's footprint, the default launch shape the bench times),
+  fused and unfused: sampled data cells (every cell along two faces' edges,
+  whose stencils reach ghosts, and random interior cells) against the
+  oracle's stencil over its BC.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -372,3 +379,65 @@ def test_batch_64_grids_full_size(tmp_path):
             got = out[(f * W + (j + h)) * W + (i + h)].cpu().numpy().astype(np.float64)
             assert (np.abs(got - ref) <= 8 * 2.0 ** -24 * (np.abs(w) @ np.abs(X))).all(), (k, f, j, i)
             checked += 1
+
+
+def test_c384_cross_consumer_sampled():
+    """The cross consumer (weights -4, 1, 1, 1, 1, the line walk) on the full
+    C384 x 256 FP64 field ((u, v) rotated), with the oracle's own columns and
+    weights in the BC program so that the plain arithmetic bound applies:
+    every sampled cell within 1e-13 of sum_o |w_o| T[c + o], T = |u| on data
+    cells and sum |A| |u| on ghosts, fused (composed boundary rows) and
+    unfused (stored ghosts)."""
+    from helpers import cs_full_field
+    N, h, nf, nl = 384, 3, 4, 64
+    I = nf * nl
+    vec = (2 * nl, nl, nl)
+    W = N + 2 * h
+    cross = [(0, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]
+    wts = [-4.0, 1.0, 1.0, 1.0, 1.0]
+    grid, prog = oracle_weights_program(hb, N, h, True)
+    prog.set_consumer(cross)
+    plan = hb.Plan(prog, inner=I, vec=vec, dtype=hb.F64)
+    cons = hb.Consumer(plan, cross, wts)
+    assert cons.stats()["boundary_rows"] > 0
+    full = cs_full_field(N, h, nf, nl, seed=2, noise=1e-3)
+    ndata = 6 * N * N
+    ys = {}
+    for fused in (True, False):
+        x = torch.from_numpy(full).cuda()
+        if not fused:
+            hb.apply(plan, x)
+        y = torch.full((ndata * I,), float("nan"), dtype=torch.float64, device="cuda")
+        cons.apply(x, y, fused=fused)
+        torch.cuda.synchronize()
+        ys[fused] = y.view(ndata, I).cpu().numpy()
+        del x, y
+    og = ocs.grid(N, h)
+    op = assemble(og, ocs.subs(N, h, "lagrange", vector=True))
+    up = o_apply(op, full, vec).reshape(6, W, W, I)
+    aop = dataclasses.replace(op, parts={k: abs(A) for k, A in op.parts.items()}, b=None)
+    T = np.abs(o_apply(aop, np.abs(full), vec)).reshape(6, W, W, I)
+    # every cell along the edges of faces 0 and 4 (j = 0, N - 1) and faces 2
+    # and 5 (i = 0, N - 1), then random interior cells
+    ii = np.arange(N)
+    f_, i_, j_ = [], [], []
+    for f in (0, 4):
+        for j in (0, N - 1):
+            f_.append(np.full(N, f)), i_.append(ii), j_.append(np.full(N, j))
+    for f in (2, 5):
+        for i in (0, N - 1):
+            f_.append(np.full(N, f)), i_.append(np.full(N, i)), j_.append(ii)
+    rng = np.random.default_rng(7)
+    f_.append(rng.integers(0, 6, 1000)), i_.append(rng.integers(1, N - 1, 1000)), j_.append(rng.integers(1, N - 1, 1000))
+    f, i, j = (np.concatenate(a) for a in (f_, i_, j_))
+    ref = np.zeros((len(f), I))
+    bound = np.zeros((len(f), I))
+    for (_, di, dj), w in zip(cross, wts):
+        ref += w * up[f, h + i + di, h + j + dj]
+        bound += abs(w) * T[f, h + i + di, h + j + dj]
+    rows = f * N * N + i * N + j
+    for fused, y in ys.items():
+        got = y[rows]
+        assert np.isfinite(got).all(), fused
+        ratio = np.abs(got - ref) / np.maximum(1e-13 * bound, 1e-300)
+        assert ratio.max() <= 1.0, (fused, float(ratio.max()))
