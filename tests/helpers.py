@@ -1,6 +1,8 @@
 """Shared helpers of the GPU parity tests (build inputs, run both sides, compare)."""
 from __future__ import annotations
 
+import dataclasses
+
 import math
 
 import numpy as np
@@ -179,3 +181,18 @@ def normwise_error(got_g, ref_g, data):
     """max over inner slots of max|got - ref| / max|data| (per slot)."""
     scale = np.abs(data).max(axis=0)
     return float((np.abs(got_g - ref_g).max(axis=0) / np.where(scale > 0, scale, 1.0)).max())
+
+
+def magnitude_operator(op):
+    """The oracle operator with |A|, |b| and every component rotation's signs
+    dropped (a plain permutation of the two components), so that applying it
+    to |u| gives sum |a| |x| + |b| for every ghost value, read through the
+    same permutation as the value itself.  (Applying |A| with the signed
+    rotation would give a negative partial sum for a negated component,
+    which |b| then partly cancels.)"""
+    parts, rows = {}, {}
+    for k, A in op.parts.items():
+        ak = None if k is None else tuple(abs(int(v)) for v in k)
+        parts[ak] = parts[ak] + abs(A) if ak in parts else abs(A)
+        rows[ak] = rows[ak] | op.part_rows[k] if ak in rows else op.part_rows[k].copy()
+    return dataclasses.replace(op, parts=parts, part_rows=rows, b=None if op.b is None else np.abs(op.b))

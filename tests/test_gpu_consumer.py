@@ -7,14 +7,13 @@ programs that carry the oracle's own weights, both must lie within
 1e-13 (FP64) or 16 FP32 roundings of sum_o |w_o| T[c + o], where T is |u| on
 data cells and sum |A| |x| + |b| on ghosts (the magnitudes the sums add).
 """
-import dataclasses
 import itertools
 
 import numpy as np
 import pytest
 
 import synthinputs
-from helpers import cs_full_field, gpu_available, oracle_weights_program
+from helpers import cs_full_field, gpu_available, magnitude_operator, oracle_weights_program
 from oracle import VectorSub, apply as o_apply, assemble
 from oracle import cubed_sphere as ocs
 from oracle import hpcg as ohpcg
@@ -44,9 +43,7 @@ BOX9_W = [0.3, -0.7, 1.1, 0.9, -8.0, 0.6, -0.2, 1.3, 0.45]
 
 def magnitude_bound(op, u, offs, w, vec):
     """sum_o |w_o| T[c + o]: T = |u| on data cells, |A| |x| + |b| on covered ghosts."""
-    aop = dataclasses.replace(op, parts={k: abs(A) for k, A in op.parts.items()},
-                              b=None if op.b is None else np.abs(op.b))
-    T = np.abs(o_apply(aop, np.abs(u), vec))
+    T = o_apply(magnitude_operator(op), np.abs(u), vec)
     empty = assemble(op.grid, [])
     return stencil_after_bc(empty, T, offs, [abs(v) for v in w])
 

@@ -1,0 +1,152 @@
+"""Seeded random BC programs on small multi-block grids, every cell against the oracle.
+
+Each case draws a grid of 1-3 blocks (a leading block coordinate and a 2-D
+box with a halo of 1-3 cells), fills every ghost strip and corner of every
+block with one randomly chosen basic sub-matrix (Sec. IV-A-3, Tables II/III):
+
+* a periodic copy or a mirror from the block's own data region, or a copy
+  from another block's data region, with a random weight and, for vector
+  layouts, a random component rotation;
+* zero rows;
+* ELL rows of width 1-6 or CSR rows of 0-12 entries reading random data
+  cells of any block, with random weights (and rotation);
+* nothing (the ghosts stay as they are),
+
+adds a sub-vector b (one value per row, or one per inner slot, the same
+width throughout a program) to some of the boxes, and compiles the program
+for a random layout: inner extent, point- or plane-major, FP64 or FP32,
+sliding windows allowed or not.  The oracle assembles the same sub-matrices and sub-vectors from their
+definitions.  Data cells and uncovered ghosts must come back unchanged, and
+every covered ghost value must lie within 32 roundings of
+sum |A| |x| + |b| (taken through the row's component rotation) of the
+oracle's value.
+"""
+import numpy as np
+import pytest
+
+from helpers import gpu_available, magnitude_operator
+from oracle import MapSub, RowsSub, VectorSub, ZeroSub, apply as o_apply, assemble
+from oracle.grid import Grid as OGrid
+
+pytestmark = pytest.mark.gpu
+
+if gpu_available():
+    import torch
+
+    import paper_2605_14780_amd as hb
+
+ROTS = [(1, 0, 0, 1), (0, 1, 1, 0), (-1, 0, 0, 1), (1, 0, 0, -1), (-1, 0, 0, -1), (0, -1, 1, 0), (0, 1, -1, 0),
+        (0, -1, -1, 0)]
+KINDS = ["periodic", "mirror", "other", "zero", "ell", "csr", "none"]
+
+
+def draw_case(seed):
+    rng = np.random.default_rng(seed)
+    nb = int(rng.integers(1, 4))
+    h = int(rng.integers(1, 4))
+    n = [int(rng.integers(max(h, 4), 20)), int(rng.integers(max(h, 4), 24))]
+    lo, hi = [0, -h, -h], [nb, n[0] + h, n[1] + h]
+    g = hb.Grid(lo, hi)
+    og = OGrid(lo, hi)
+    for k in range(nb):
+        full = [(k, k + 1), (-h, n[0] + h), (-h, n[1] + h)]
+        data = [(k, k + 1), (0, n[0]), (0, n[1])]
+        g.add_block(full, data)
+        og.add_block(full, data)
+    I = int(rng.choice([1, 2, 3, 4, 5, 8, 12, 16, 31, 32, 64, 96]))
+    vec = (0, I // 2, I // 2) if I % 2 == 0 and rng.random() < 0.5 else None
+    order = int(rng.integers(0, 2))
+    dtype = "f64" if rng.random() < 0.5 else "f32"
+    windows = bool(rng.random() < 0.7)
+    nin = 1 if rng.random() < 0.5 else I  # b values per row (one width for the whole program)
+    W0, W1 = n[0] + 2 * h, n[1] + 2 * h
+
+    def cell(k, x, y):  # the library's linear cell index (blocks in order, full boxes row-major)
+        return (k * W0 + (x + h)) * W1 + (y + h)
+
+    prog = hb.Program(g)
+    subs = []
+    # the ghost region of a block: 4 strips and 4 corners
+    spans = [[(-h, 0), (0, n[d]), (n[d], n[d] + h)] for d in range(2)]
+    for k in range(nb):
+        for sx in range(3):
+            for sy in range(3):
+                if sx == 1 and sy == 1:
+                    continue
+                rows = [(k, k + 1), spans[0][sx], spans[1][sy]]
+                box_cells = [(k, x, y) for x in range(*rows[1]) for y in range(*rows[2])]
+                kind = str(rng.choice(KINDS))
+                if kind == "other" and nb == 1:
+                    kind = "periodic"
+                rot = ROTS[int(rng.integers(0, 8))] if vec is not None and rng.random() < 0.4 else None
+                if kind in ("periodic", "mirror", "other"):
+                    M = np.eye(3, dtype=np.int64)
+                    off = np.zeros(3, dtype=np.int64)
+                    if kind == "other":
+                        off[0] = int(rng.choice([j for j in range(nb) if j != k])) - k
+                    for d, s in ((1, sx), (2, sy)):
+                        nd = n[d - 1]
+                        if s == 1:
+                            continue
+                        if kind == "mirror":  # reflect about the block's face
+                            M[d, d] = -1
+                            off[d] = -1 if s == 0 else 2 * nd - 1
+                        else:  # wrap into the data region
+                            off[d] = nd if s == 0 else -nd
+                    w = float(rng.choice([1.0, rng.standard_normal()]))
+                    prog.add_map(rows, M, off, weight=w, rot=rot)
+                    subs.append(MapSub(rows, lambda c, M=M, off=off: tuple(int(v) for v in M @ np.array(c) + off),
+                                       w, rot))
+                elif kind == "zero":
+                    prog.add_zero(rows)
+                    subs.append(ZeroSub(rows))
+                elif kind in ("ell", "csr"):
+                    width = int(rng.integers(1, 7))
+                    ents, cols, vals, ptr = {}, [], [], [0]
+                    for c in box_cells:
+                        m = width if kind == "ell" else int(rng.integers(0, 13))
+                        e = []
+                        for _ in range(m):
+                            kk = int(rng.integers(0, nb))
+                            x, y = int(rng.integers(0, n[0])), int(rng.integers(0, n[1]))
+                            wv = float(rng.standard_normal())
+                            e.append(((kk, x, y), wv))
+                            cols.append(cell(kk, x, y))
+                            vals.append(wv)
+                        ptr.append(len(cols))
+                        ents[c] = e
+                    if kind == "ell":
+                        prog.add_ell(rows, width, cols, vals, rot=rot)
+                    else:
+                        prog.add_csr(rows, ptr, cols, vals, rot=rot)
+                    subs.append(RowsSub(rows, lambda c, ents=ents: ents[tuple(c)], rot))
+                if rng.random() < 0.4:
+                    b = rng.standard_normal((len(box_cells), nin))
+                    prog.add_vector(rows, b, ninner=nin)
+                    subs.append(VectorSub(rows, b if nin > 1 else b[:, 0]))
+    return g, og, prog, subs, I, vec, order, dtype, windows, rng
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_program_matches_oracle(seed):
+    g, og, prog, subs, I, vec, order, dtype, windows, rng = draw_case(seed)
+    dt, npdt, eps = (hb.F64, np.float64, 2.0 ** -53) if dtype == "f64" else (hb.F32, np.float32, 2.0 ** -24)
+    plan = hb.Plan(prog, inner=I, order=order, vec=vec, dtype=dt, windows=windows)
+    op = assemble(og, subs)
+    u = rng.standard_normal((og.ncells, I)).astype(npdt).astype(np.float64)  # inputs as the GPU holds them
+    arr = u if order == 0 else np.ascontiguousarray(u.T)
+    t = torch.from_numpy(np.ascontiguousarray(arr.astype(npdt))).cuda()
+    hb.apply(plan, t)
+    torch.cuda.synchronize()
+    got = t.cpu().numpy().astype(np.float64)
+    got = got if order == 0 else np.ascontiguousarray(got.T)
+    ref = o_apply(op, u, vec)
+    D, G = og.data_cells, og.ghost_cells
+    assert np.array_equal(got[D], u[D])
+    cov = G[op.covered]
+    assert np.array_equal(got[G[~op.covered]], u[G[~op.covered]])
+    mag = o_apply(magnitude_operator(op), np.abs(u), vec)[cov]  # sum |A| |x| + |b| per value
+    err = np.abs(got[cov] - ref[cov])
+    bad = np.argwhere(err > 32 * eps * mag)
+    assert bad.size == 0, (seed, I, vec, order, dtype, windows, bad[:3].tolist(),
+                           [og.coord_of_cell(int(cov[r])) for r, _ in bad[:3]])

@@ -177,3 +177,25 @@ def test_vjp_dot_product_identity():
     lhs = float(np.sum(Fu * w))
     rhs = float(np.sum(u * vjp(op, w, vec)))
     assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1.0)
+
+
+def test_magnitude_operator_drops_rotation_signs():
+    """The bound helper of the GPU tests: for a negated copy with a component
+    rotation that flips a sign, plus b, applying it to |u| gives
+    |w| |u[mapped cell, permuted slot]| + |b| per value (no cancellation
+    between the negated part and b)."""
+    from helpers import magnitude_operator
+    g = Grid([0, -1], [1, 4])
+    g.add_block([(0, 1), (-1, 4)], [(0, 1), (0, 3)])
+    rows = [(0, 1), (-1, 0)]
+    rot = (0, -1, 1, 0)  # slot pairs swapped, one of them negated
+    b = np.array([[0.5, -0.25, 2.0, -1.0]])
+    op = assemble(g, [MapSub(rows, lambda c: (c[0], 2), weight=-3.0, rot=rot), VectorSub(rows, b)])
+    vec = (0, 2, 2)  # components at slots {0, 1} and {2, 3}
+    u = np.arange(1.0, 21.0).reshape(5, 4) * np.array([1, -1, 1, -1])
+    mag = apply(magnitude_operator(op), np.abs(u), vec)
+    src = np.abs(u[3])  # cell (0, 2): the mapped data cell
+    want = 3.0 * src[[2, 3, 0, 1]] + np.abs(b[0])
+    assert np.array_equal(mag[0], want)
+    val = apply(op, u, vec)[0]
+    assert (np.abs(val) <= mag[0]).all()
