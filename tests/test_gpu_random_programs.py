@@ -1,4 +1,4 @@
-"""Seeded random BC programs on small multi-block grids, every cell against the oracle.
+"""Seeded random BC programs on small multi-block grids, every cell against the oracle (forward and adjoint).
 
 Each case draws a grid of 1-3 blocks (a leading block coordinate and a 2-D
 box with a halo of 1-3 cells), fills every ghost strip and corner of every
@@ -150,3 +150,35 @@ def test_random_program_matches_oracle(seed):
     bad = np.argwhere(err > 32 * eps * mag)
     assert bad.size == 0, (seed, I, vec, order, dtype, windows, bad[:3].tolist(),
                            [og.coord_of_cell(int(cov[r])) for r, _ in bad[:3]])
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_program_adjoint_matches_oracle(seed):
+    """The adjoint of the same random programs against the oracle's VJP
+    (data cells gain A^T of the covered ghosts' values, covered ghosts
+    become 0, uncovered ghosts keep theirs): every value within
+    (entries of its column + 4) roundings of |ybar| + |A|^T |ybar| (through
+    the rotations' permutations)."""
+    from oracle import vjp
+    g, og, prog, subs, I, vec, order, dtype, windows, rng = draw_case(seed)
+    dt, npdt, eps = (hb.F64, np.float64, 2.0 ** -53) if dtype == "f64" else (hb.F32, np.float32, 2.0 ** -24)
+    plan = hb.Plan(prog, inner=I, order=order, vec=vec, dtype=dt, windows=windows)
+    op = assemble(og, subs)
+    yb = rng.standard_normal((og.ncells, I)).astype(npdt).astype(np.float64)
+    arr = yb if order == 0 else np.ascontiguousarray(yb.T)
+    t = torch.from_numpy(np.ascontiguousarray(arr.astype(npdt))).cuda()
+    hb.apply_adjoint(plan, t)
+    torch.cuda.synchronize()
+    got = t.cpu().numpy().astype(np.float64)
+    got = got if order == 0 else np.ascontiguousarray(got.T)
+    ref = vjp(op, yb, vec)
+    D, G = og.data_cells, og.ghost_cells
+    assert (got[G[op.covered]] == 0).all()
+    assert np.array_equal(got[G[~op.covered]], yb[G[~op.covered]])
+    mag = vjp(magnitude_operator(op), np.abs(yb), vec)[D]
+    cnt = 0
+    for A in op.parts.values():
+        cnt = cnt + np.diff(A.tocsc().indptr)  # entries per source (column)
+    err = np.abs(got[D] - ref[D])
+    bad = np.argwhere(err > (np.asarray(cnt)[:, None] + 4) * eps * mag)
+    assert bad.size == 0, (seed, I, vec, order, dtype, bad[:3].tolist())
