@@ -1,4 +1,5 @@
-"""Seeded random BC programs on small multi-block grids, every cell against the oracle (forward and adjoint).
+"""Seeded random BC programs on small multi-block grids, every cell against
+the oracle: forward, adjoint, and random consumer stencils read after them.
 
 Each case draws a grid of 1-3 blocks (a leading block coordinate and a 2-D
 box with a halo of 1-3 cells), fills every ghost strip and corner of every
@@ -182,3 +183,42 @@ def test_random_program_adjoint_matches_oracle(seed):
     err = np.abs(got[D] - ref[D])
     bad = np.argwhere(err > (np.asarray(cnt)[:, None] + 4) * eps * mag)
     assert bad.size == 0, (seed, I, vec, order, dtype, bad[:3].tolist())
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_random_consumer_matches_oracle(seed):
+    """A random stencil (1-9 offsets within the halo, repeats allowed, random
+    weights) read after the same random programs (point-major), fused and
+    unfused, against the oracle's stencil over its BC: every value within 64
+    roundings of sum_o |w_o| T[c + o] (T = |u| on data cells and uncovered
+    ghosts, sum |A| |x| + |b| on covered ones).  Uncovered ghosts are read as
+    stored by both."""
+    from oracle.consumer import stencil_after_bc
+    g, og, prog, subs, I, vec, _, dtype, windows, rng = draw_case(1000 + seed)
+    h = -og.blocks[0].full[1][0]
+    noff = int(rng.integers(1, 10))
+    offs = [(0, int(rng.integers(-h, h + 1)), int(rng.integers(-h, h + 1))) for _ in range(noff)]
+    if rng.random() < 0.5:  # a stencil on lines of the last dimension (the line walk)
+        offs = [(0, o[1], max(-1, min(1, o[2]))) for o in offs]
+    wts = [float(v) for v in rng.standard_normal(noff)]
+    dt, npdt, tdt, eps = ((hb.F64, np.float64, torch.float64, 2.0 ** -53) if dtype == "f64"
+                          else (hb.F32, np.float32, torch.float32, 2.0 ** -24))
+    plan = hb.Plan(prog, inner=I, vec=vec, dtype=dt, windows=windows)
+    cons = hb.Consumer(plan, offs, wts)
+    op = assemble(og, subs)
+    u = rng.standard_normal((og.ncells, I)).astype(npdt).astype(np.float64)
+    ndata = len(og.data_cells)
+    ref = stencil_after_bc(op, u, offs, wts, vec)
+    T = o_apply(magnitude_operator(op), np.abs(u), vec)
+    bound = 64 * eps * stencil_after_bc(assemble(og, []), T, offs, [abs(v) for v in wts])
+    for fused in (False, True):
+        x = torch.from_numpy(u.astype(npdt)).cuda()
+        if not fused:
+            hb.apply(plan, x)
+        y = torch.full((ndata * I,), float("nan"), dtype=tdt, device="cuda")
+        cons.apply(x, y, fused=fused)
+        torch.cuda.synchronize()
+        got = y.view(ndata, I).cpu().numpy().astype(np.float64)
+        assert np.isfinite(got).all(), fused
+        bad = np.argwhere(np.abs(got - ref) > bound)
+        assert bad.size == 0, (seed, fused, offs, I, vec, dtype, bad[:3].tolist())
