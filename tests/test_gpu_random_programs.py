@@ -1,5 +1,6 @@
 """Seeded random BC programs on small multi-block grids, every cell against
-the oracle: forward, adjoint, and random consumer stencils read after them.
+the oracle: forward, adjoint, random consumer stencils read after them, and
+a batch of them.
 
 Each case draws a grid of 1-3 blocks (a leading block coordinate and a 2-D
 box with a halo of 1-3 cells), fills every ghost strip and corner of every
@@ -41,7 +42,7 @@ ROTS = [(1, 0, 0, 1), (0, 1, 1, 0), (-1, 0, 0, 1), (1, 0, 0, -1), (-1, 0, 0, -1)
 KINDS = ["periodic", "mirror", "other", "zero", "ell", "csr", "none"]
 
 
-def draw_case(seed):
+def draw_case(seed, force_dtype=None, force_order=None):
     rng = np.random.default_rng(seed)
     nb = int(rng.integers(1, 4))
     h = int(rng.integers(1, 4))
@@ -58,6 +59,8 @@ def draw_case(seed):
     vec = (0, I // 2, I // 2) if I % 2 == 0 and rng.random() < 0.5 else None
     order = int(rng.integers(0, 2))
     dtype = "f64" if rng.random() < 0.5 else "f32"
+    order = order if force_order is None else force_order
+    dtype = dtype if force_dtype is None else force_dtype
     windows = bool(rng.random() < 0.7)
     nin = 1 if rng.random() < 0.5 else I  # b values per row (one width for the whole program)
     W0, W1 = n[0] + 2 * h, n[1] + 2 * h
@@ -222,3 +225,55 @@ def test_random_consumer_matches_oracle(seed):
         assert np.isfinite(got).all(), fused
         bad = np.argwhere(np.abs(got - ref) > bound)
         assert bad.size == 0, (seed, fused, offs, I, vec, dtype, bad[:3].tolist())
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_random_programs_in_one_batch(dtype):
+    """Six random programs (point-major, one dtype) applied as one batch: the
+    general-row instance of the batch kernel (ELL of other widths, CSR rows,
+    maps, zero rows, b).  Every launch shape gives the same bits; they equal
+    the plan's plain apply (except where the plain apply sends CSR rows of
+    >= 8 entries and < 32 bytes to the entry-splitting kernel, whose sum is
+    ordered differently), and the oracle within the forward test's bound."""
+    dt, npdt, tdt, eps = ((hb.F64, np.float64, torch.float64, 2.0 ** -53) if dtype == "f64"
+                          else (hb.F32, np.float32, torch.float32, 2.0 ** -24))
+    cases = [draw_case(3000 + k, force_dtype=dtype, force_order=0) for k in range(6)]
+    plans, inputs, ops, vecs = [], [], [], []
+    for (g, og, prog, subs, I, vec, _, _, windows, rng) in cases:
+        plans.append(hb.Plan(prog, inner=I, vec=vec, dtype=dt, windows=windows))
+        u = rng.standard_normal((og.ncells, I)).astype(npdt)
+        inputs.append(torch.from_numpy(u).cuda())
+        ops.append((og, assemble(og, subs), u.astype(np.float64)))
+        vecs.append(vec)
+    want = []
+    for plan, x in zip(plans, inputs):
+        y = x.clone()
+        hb.apply(plan, y)
+        want.append(y)
+    same_order = [p.stats()["rows_narrow"] == 0 for p in plans]
+    assert any(same_order) and not all(same_order)
+    batch = hb.Batch(plans)
+    fields = [x.clone() for x in inputs]
+    batch.bind(fields)
+    first = None
+    for tune in [None, dict(block=128, lanes_per_row=32, rows_per_tile=0, persistent=0),
+                 dict(block=256, lanes_per_row=0, rows_per_tile=4096, persistent=300),
+                 dict(block=64, lanes_per_row=0, rows_per_tile=64, persistent=0)]:
+        if tune is not None:
+            batch.tune = tune
+        for f, x in zip(fields, inputs):
+            f.copy_(x)
+        batch.apply()
+        torch.cuda.synchronize()
+        if first is None:
+            first = [f.clone() for f in fields]
+        for k, (f, w, f0) in enumerate(zip(fields, want, first)):
+            assert torch.equal(f, f0), (k, tune)
+            if same_order[k]:
+                assert torch.equal(f, w), (k, tune)
+    for f, (og, op, u), vec in zip(fields, ops, vecs):
+        got = f.cpu().numpy().astype(np.float64)
+        ref = o_apply(op, u, vec)
+        cov = og.ghost_cells[op.covered]
+        mag = o_apply(magnitude_operator(op), np.abs(u), vec)[cov]
+        assert (np.abs(got[cov] - ref[cov]) <= 32 * eps * mag).all()
