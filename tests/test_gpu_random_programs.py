@@ -1,6 +1,6 @@
 """Seeded random BC programs on small multi-block grids, every cell against
-the oracle: forward, adjoint, random consumer stencils read after them, and
-a batch of them.
+the oracle: forward, adjoint, new b values on the compiled plans, random
+consumer stencils read after them, and a batch of them.
 
 Each case draws a grid of 1-3 blocks (a leading block coordinate and a 2-D
 box with a halo of 1-3 cells), fills every ghost strip and corner of every
@@ -70,6 +70,7 @@ def draw_case(seed, force_dtype=None, force_order=None):
 
     prog = hb.Program(g)
     subs = []
+    vectors = []  # (sub-vector id, index in subs, values shape)
     # the ghost region of a block: 4 strips and 4 corners
     spans = [[(-h, 0), (0, n[d]), (n[d], n[d] + h)] for d in range(2)]
     for k in range(nb):
@@ -126,14 +127,15 @@ def draw_case(seed, force_dtype=None, force_order=None):
                     subs.append(RowsSub(rows, lambda c, ents=ents: ents[tuple(c)], rot))
                 if rng.random() < 0.4:
                     b = rng.standard_normal((len(box_cells), nin))
-                    prog.add_vector(rows, b, ninner=nin)
+                    sid = prog.add_vector(rows, b, ninner=nin)
                     subs.append(VectorSub(rows, b if nin > 1 else b[:, 0]))
-    return g, og, prog, subs, I, vec, order, dtype, windows, rng
+                    vectors.append((sid, len(subs) - 1, b.shape))
+    return g, og, prog, subs, I, vec, order, dtype, windows, rng, vectors
 
 
 @pytest.mark.parametrize("seed", range(24))
 def test_random_program_matches_oracle(seed):
-    g, og, prog, subs, I, vec, order, dtype, windows, rng = draw_case(seed)
+    g, og, prog, subs, I, vec, order, dtype, windows, rng, vectors = draw_case(seed)
     dt, npdt, eps = (hb.F64, np.float64, 2.0 ** -53) if dtype == "f64" else (hb.F32, np.float32, 2.0 ** -24)
     plan = hb.Plan(prog, inner=I, order=order, vec=vec, dtype=dt, windows=windows)
     op = assemble(og, subs)
@@ -164,7 +166,7 @@ def test_random_program_adjoint_matches_oracle(seed):
     (entries of its column + 4) roundings of |ybar| + |A|^T |ybar| (through
     the rotations' permutations)."""
     from oracle import vjp
-    g, og, prog, subs, I, vec, order, dtype, windows, rng = draw_case(seed)
+    g, og, prog, subs, I, vec, order, dtype, windows, rng, vectors = draw_case(seed)
     dt, npdt, eps = (hb.F64, np.float64, 2.0 ** -53) if dtype == "f64" else (hb.F32, np.float32, 2.0 ** -24)
     plan = hb.Plan(prog, inner=I, order=order, vec=vec, dtype=dt, windows=windows)
     op = assemble(og, subs)
@@ -197,7 +199,7 @@ def test_random_consumer_matches_oracle(seed):
     ghosts, sum |A| |x| + |b| on covered ones).  Uncovered ghosts are read as
     stored by both."""
     from oracle.consumer import stencil_after_bc
-    g, og, prog, subs, I, vec, _, dtype, windows, rng = draw_case(1000 + seed)
+    g, og, prog, subs, I, vec, _, dtype, windows, rng, _ = draw_case(1000 + seed)
     h = -og.blocks[0].full[1][0]
     noff = int(rng.integers(1, 10))
     offs = [(0, int(rng.integers(-h, h + 1)), int(rng.integers(-h, h + 1))) for _ in range(noff)]
@@ -239,7 +241,7 @@ def test_random_programs_in_one_batch(dtype):
                           else (hb.F32, np.float32, torch.float32, 2.0 ** -24))
     cases = [draw_case(3000 + k, force_dtype=dtype, force_order=0) for k in range(6)]
     plans, inputs, ops, vecs = [], [], [], []
-    for (g, og, prog, subs, I, vec, _, _, windows, rng) in cases:
+    for (g, og, prog, subs, I, vec, _, _, windows, rng, _) in cases:
         plans.append(hb.Plan(prog, inner=I, vec=vec, dtype=dt, windows=windows))
         u = rng.standard_normal((og.ncells, I)).astype(npdt)
         inputs.append(torch.from_numpy(u).cuda())
@@ -277,3 +279,33 @@ def test_random_programs_in_one_batch(dtype):
         cov = og.ghost_cells[op.covered]
         mag = o_apply(magnitude_operator(op), np.abs(u), vec)[cov]
         assert (np.abs(got[cov] - ref[cov]) <= 32 * eps * mag).all()
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_program_new_b_values(seed):
+    """New values for every sub-vector of a compiled random program
+    (set_vector, Sec. III-B's affine part changing between applies): the next
+    apply equals the oracle's operator assembled with the new values, within
+    the forward test's bound."""
+    g, og, prog, subs, I, vec, order, dtype, windows, rng, vectors = draw_case(seed)
+    if not vectors:
+        pytest.skip("this draw has no sub-vector")
+    dt, npdt, eps = (hb.F64, np.float64, 2.0 ** -53) if dtype == "f64" else (hb.F32, np.float32, 2.0 ** -24)
+    plan = hb.Plan(prog, inner=I, order=order, vec=vec, dtype=dt, windows=windows)
+    subs = list(subs)
+    for sid, k, shape in vectors:
+        nb = rng.standard_normal(shape)
+        plan.set_vector(sid, nb)
+        subs[k] = VectorSub(subs[k].rows, nb if shape[1] > 1 else nb[:, 0])
+    op = assemble(og, subs)
+    u = rng.standard_normal((og.ncells, I)).astype(npdt).astype(np.float64)
+    arr = u if order == 0 else np.ascontiguousarray(u.T)
+    t = torch.from_numpy(np.ascontiguousarray(arr.astype(npdt))).cuda()
+    hb.apply(plan, t)
+    torch.cuda.synchronize()
+    got = t.cpu().numpy().astype(np.float64)
+    got = got if order == 0 else np.ascontiguousarray(got.T)
+    ref = o_apply(op, u, vec)
+    cov = og.ghost_cells[op.covered]
+    mag = o_apply(magnitude_operator(op), np.abs(u), vec)[cov]
+    assert (np.abs(got[cov] - ref[cov]) <= 32 * eps * mag).all()
