@@ -1,6 +1,7 @@
 """Seeded random BC programs on small multi-block grids, every cell against
 the oracle: forward, adjoint, new b values on the compiled plans, random
-consumer stencils read after them, and a batch of them.
+consumer stencils read after them, and a batch of them; and HIP-graph
+replays of their forward and adjoint against the eager calls.
 
 Each case draws a grid of 1-3 blocks (a leading block coordinate and a 2-D
 box with a halo of 1-3 cells), fills every ghost strip and corner of every
@@ -309,3 +310,31 @@ def test_random_program_new_b_values(seed):
     cov = og.ghost_cells[op.covered]
     mag = o_apply(magnitude_operator(op), np.abs(u), vec)[cov]
     assert (np.abs(got[cov] - ref[cov]) <= 32 * eps * mag).all()
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_program_graph_replays(seed):
+    """Forward and adjoint of random programs captured in HIP graphs: three
+    replays, with eager copies and synchronisations between them, each equal
+    bit for bit to the eager call (the adjoint's reader counters are
+    restored by every call, so a replay starts from the same state)."""
+    g, og, prog, subs, I, vec, order, dtype, windows, rng, _ = draw_case(5000 + seed)
+    dt, npdt = (hb.F64, np.float64) if dtype == "f64" else (hb.F32, np.float32)
+    plan = hb.Plan(prog, inner=I, order=order, vec=vec, dtype=dt, windows=windows)
+    u = rng.standard_normal((og.ncells, I)).astype(npdt)
+    arr = u if order == 0 else np.ascontiguousarray(u.T)
+    src = torch.from_numpy(np.ascontiguousarray(arr)).cuda()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        for op_kind, eager in ((hb.OP_APPLY, hb.apply), (hb.OP_ADJOINT, hb.apply_adjoint)):
+            want = src.clone()
+            eager(plan, want, stream=s.cuda_stream)
+            x = src.clone()
+            graph = hb.ApplyGraph(plan, [x], 1, stream=s.cuda_stream, op=op_kind)
+            for rep in range(3):
+                x.copy_(src)
+                torch.cuda.synchronize()
+                graph.launch(stream=s.cuda_stream)
+                torch.cuda.synchronize()
+                assert torch.equal(x, want), (op_kind, rep)
+            del graph
