@@ -1891,7 +1891,8 @@ __device__ __forceinline__ void cons_lines(const PlanDesc& d, const ConsDesc& c,
     for (int q = 0; q < NL; ++q)
 #pragma unroll
       for (int u = 0; u < 3; ++u) R[q][u] = ldv<T, V>(xb + (int64_t)(k0 + dl[q] - 2 + max(u, s0[q])) * d.cs);
-    // the chunk's output rows: one buffer range (NS rows of < 4 KiB each at most)
+    // the chunk's output rows: one buffer range (NS rows of at most 4 KiB each: a
+    // one-pass row group covers at most 256 lanes of 16 bytes)
     T* yc = static_cast<T*>(c.y) + (int64_t)(t.y0 + k0) * d.inner;
     const __amdgpu_buffer_rsrc_t yr =
         __builtin_amdgcn_make_buffer_rsrc(yc, 0, (last - k0 + 1) * row_bytes, BUF_RSRC_WORD3);
