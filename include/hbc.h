@@ -424,7 +424,9 @@ int hbc_fused_stencil27(const hbc_plan* plan, void* x, int64_t x_nelem, void* y,
  * stay in its block's full region (HBC_EINVAL).  Point-major plans without
  * data rows (HBC_EUNSUPPORTED otherwise).  The consumer keeps a pointer to the
  * plan, which must outlive it; it reads the plan's rows as compiled at
- * creation (later new sub-vector values need a new consumer). */
+ * creation (later new sub-vector values need a new consumer).  On a plan
+ * created HBC_PLAN_HOST_ONLY the consumer is compiled on the host only:
+ * hbc_consumer_stats works, hbc_consumer_apply returns HBC_EINVAL. */
 typedef struct hbc_consumer hbc_consumer;
 int hbc_consumer_create(const hbc_plan* plan, int32_t noffsets, const int64_t* offsets, const double* weights,
                         hbc_consumer** out);

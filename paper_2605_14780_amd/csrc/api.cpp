@@ -706,12 +706,13 @@ int hbc_consumer_create(const hbc_plan* plan, int32_t noffsets, const int64_t* o
                         hbc_consumer** out) {
   hbc_consumer* c = nullptr;
   const int rc = guard([&] {
-    check_device_plan(plan);
+    need(plan != nullptr, "NULL plan");
     need(offsets && weights && out, "NULL argument");
     c = new hbc_consumer;
     c->plan = plan;
     compile_consumer(plan->p, noffsets, offsets, weights, c->host);
-    c->dev = device_consumer_upload(plan->p, c->host);
+    // a host-only plan's consumer is compiled (stats) but never uploaded
+    if (!(plan->p.flags & HBC_PLAN_HOST_ONLY)) c->dev = device_consumer_upload(plan->p, c->host);
     *out = c;
     c = nullptr;
   });
@@ -726,6 +727,7 @@ int hbc_consumer_apply(const hbc_consumer* c, const void* x, int64_t x_nelem, vo
                        int32_t fused, void* stream) {
   return guard([&] {
     need(c != nullptr, "NULL consumer");
+    check_device_plan(c->plan);
     check_field(x);
     check_field(y);
     check_size(c->plan, x_nelem);

@@ -111,6 +111,36 @@ static void scenario(Buffers& B) {
     // device calls on a host-only plan are refused without touching a device
     double dummy[2];
     EXPECT(hbc_apply(pl, dummy, 2, nullptr), HBC_EINVAL);
+    // consumers compiled on the host-only plan: the cross and the 9-point box
+    // (the line walk's order), a skewed stencil (the general order); applies
+    // refused, an offset reaching past the halo refused
+    {
+      const int64_t cross[15] = {0, 0, 0, 0, 1, 0, 0, -1, 0, 0, 0, 1, 0, 0, -1};
+      const int64_t skew[12] = {0, 2, -1, 0, 0, 0, 0, -1, 2, 0, -3, 3};
+      int64_t box9[27];
+      double w9[9];
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+          box9[3 * (3 * a + b)] = 0, box9[3 * (3 * a + b) + 1] = a - 1, box9[3 * (3 * a + b) + 2] = 1 - b;
+          w9[3 * a + b] = 0.5 * (a + 1) - b;
+        }
+      const double wc[5] = {-4, 1, 1, 1, 1}, ws[4] = {0.25, -1.5, 2.0, 0.75};
+      const int64_t far[3] = {0, 4, 0};
+      int64_t nbr = 0, nbe = 0;
+      hbc_consumer* cs = nullptr;
+      CALL(hbc_consumer_create(pl, 5, cross, wc, &cs));
+      const int st1 = hbc_consumer_stats(cs, &nbr, &nbe);
+      const int ap1 = hbc_consumer_apply(cs, dummy, 2, dummy, 2, 1, nullptr);
+      hbc_consumer_destroy(cs);
+      CALL(st1);
+      EXPECT(ap1, HBC_EINVAL);
+      CALL(hbc_consumer_create(pl, 9, box9, w9, &cs));
+      hbc_consumer_destroy(cs);
+      CALL(hbc_consumer_create(pl, 4, skew, ws, &cs));
+      hbc_consumer_destroy(cs);
+      cs = nullptr;
+      EXPECT(hbc_consumer_create(pl, 1, far, wc, &cs), HBC_EINVAL);
+    }
     EXPECT(hbc_plan_create(nullptr, &lay, HBC_F64, HBC_PLAN_HOST_ONLY, &plf), HBC_EINVAL);
     hbc_layout bad{0, HBC_POINT_MAJOR, 0, 0, 0};
     EXPECT(hbc_plan_create(p, &bad, HBC_F64, HBC_PLAN_HOST_ONLY, &plf), HBC_EINVAL);
@@ -121,6 +151,12 @@ static void scenario(Buffers& B) {
     CALL(hbc_program_set_consumer(pf, 5, cross));
     hbc_layout lay2{I, HBC_PLANE_MAJOR, 2, 4, 2};
     CALL(hbc_plan_create(pf, &lay2, HBC_F32, HBC_PLAN_HOST_ONLY, &plf));
+    {
+      hbc_consumer* cp = nullptr;
+      EXPECT(hbc_consumer_create(plf, 5, cross, nullptr, &cp), HBC_EINVAL);  // no weights
+      const double wc[5] = {-4, 1, 1, 1, 1};
+      EXPECT(hbc_consumer_create(plf, 5, cross, wc, &cp), HBC_EUNSUPPORTED);  // plane-major
+    }
     // Cartesian blocks with a one-cell halo, one periodic direction
     const int32_t nb[3] = {2, 2, 2};
     const int64_t n[3] = {4, 4, 5};

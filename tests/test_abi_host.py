@@ -585,3 +585,28 @@ def test_binding_checks_host_array_lengths():
     gs.add_block([(0, 1), (0, 20, 2)], [(0, 1), (4, 16, 2)])
     ps = hb.Program(gs)
     assert ps.box_rows([(0, 1), (0, 4)]) == 2
+
+
+@pytest.mark.parametrize("N,h", [(6, 1), (12, 3), (20, 2)])
+def test_consumer_compiled_on_a_host_only_plan(N, h):
+    """A consumer of a host-only cubed-sphere Lagrange plan is compiled on the
+    host (applies need a device plan).  Its composed boundary rows in closed
+    form: the cells next to a face edge, 4N - 4 per face; for the cross, 8
+    entries on an edge (4 data reads, one ghost's 4 Lagrange entries) and 11
+    at a corner cell (two ghosts); for the 9-point box, 6 data reads plus 3
+    ghosts on an edge (18), and at a corner 4 data reads, 4 edge ghosts and
+    the zero corner ghost (20)."""
+    base, w = closed_form_weights(N, h)
+    g = hb.Grid.cubed_sphere(N, h)
+    p = hb.Program(g)
+    p.cs_add(N, h, hb.CS_LAGRANGE, vector=False, base=base, w=w)
+    plan = hb.Plan(p, inner=4, host_only=True)
+    cross = [(0, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]
+    box9 = [(0, a, b) for a in (-1, 0, 1) for b in (-1, 0, 1)]
+    for offs, edge, corner in ((cross, 8, 11), (box9, 18, 20)):
+        st = hb.Consumer(plan, offs, [1.0] * len(offs)).stats()
+        assert st["boundary_rows"] == 6 * (4 * N - 4)
+        assert st["boundary_entries"] == 6 * ((4 * N - 8) * edge + 4 * corner)
+    c = hb.Consumer(plan, cross, [1.0] * 5)
+    # an apply is refused (host-only plan) before any pointer is read
+    assert hb.lib().hbc_consumer_apply(c._h, None, 0, None, 0, 1, None) == hb.EINVAL
