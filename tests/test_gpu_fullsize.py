@@ -14,6 +14,8 @@
   rows against the oracle's;
 * the 64-grid FP32 batch in its autotuned graph launch: bit identity with
   plain applies and sampled rows against the oracle's;
+* a field beyond 4 GiB (C384 x 768 FP64): window kernel, row kernel and
+  adjoint on sampled rows and cells at the plain bound;
 * the radius-1 cross consumer on the full C384 x 256 field (plan compiled
   with the cross's footprint, the default launch shape the bench times),
   fused and unfused: sampled data cells (every cell along two faces' edges,
@@ -439,3 +441,71 @@ def test_c384_cross_consumer_sampled():
         assert np.isfinite(got).all(), fused
         ratio = np.abs(got - ref) / np.maximum(1e-13 * bound, 1e-300)
         assert ratio.max() <= 1.0, (fused, float(ratio.max()))
+
+
+def test_c384_field_beyond_4_gib():
+    """A field of more than 4 GiB (C384, halo 3, 768 FP64 values per cell:
+    5.6 GB), so that cell offsets need 64 bits: the window kernel and the row
+    kernel (a plan built without windows) on the program carrying the
+    oracle's own weights; 3000 sampled ghost rows, all 768 values, within
+    the plain bound 1e-13 * max(|ref|, sum |w x|) of the oracle's rows; and
+    the adjoint on the same field, 3000 sampled data cells that some ghost
+    reads against ybar + A^T ybar from the oracle's columns (bound: (entries
+    + 2) roundings of |ybar| + |A|^T |ybar|)."""
+    N, h, I = 384, 3, 768
+    grid, prog = oracle_weights_program(hb, N, h, False)
+    og = ocs.grid(N, h)
+    assert og.ncells * I * 8 > 4 * 2 ** 30
+    rng = np.random.default_rng(11)
+    full = rng.standard_normal((og.ncells, I))
+    op = assemble(og, ocs.subs(N, h, "lagrange"))
+    A = sum(op.parts.values()).tocsr()
+    G = og.ghost_cells
+    pick = rng.choice(np.nonzero(op.covered)[0], 3000, replace=False)
+    ref = np.zeros((len(pick), I))
+    mag = np.zeros((len(pick), I))
+    for k, r in enumerate(pick):
+        cols = og.data_cells[A.indices[A.indptr[r]:A.indptr[r + 1]]]
+        w = A.data[A.indptr[r]:A.indptr[r + 1]]
+        ref[k] = w @ full[cols]
+        mag[k] = np.abs(w) @ np.abs(full[cols])
+    cells = torch.from_numpy(G[pick]).cuda()
+    src = torch.from_numpy(full).cuda()
+    del full
+    for windows in (True, False):
+        plan = hb.Plan(prog, inner=I, dtype=hb.F64, windows=windows)
+        st = plan.stats()
+        assert (st["rows_window"] > 0) == windows
+        x = src.clone()
+        hb.apply(plan, x)
+        torch.cuda.synchronize()
+        got = x[cells].cpu().numpy()
+        del x
+        bound = 1e-13 * np.maximum(np.abs(ref), mag)
+        assert (np.abs(got - ref) <= bound).all(), (windows, float((np.abs(got - ref) / bound).max()))
+    # the adjoint: src as ybar (random, so every covered ghost carries a value)
+    yb = src.cpu().numpy()
+    Acsc = A.tocsc()
+    read = np.nonzero(np.diff(Acsc.indptr))[0]  # data columns some ghost reads
+    dpick = rng.choice(read, 3000, replace=False)
+    aref = np.zeros((len(dpick), I))
+    amag = np.zeros((len(dpick), I))
+    cnt = np.diff(Acsc.indptr)[dpick]
+    for k, j in enumerate(dpick):
+        rows = Acsc.indices[Acsc.indptr[j]:Acsc.indptr[j + 1]]
+        w = Acsc.data[Acsc.indptr[j]:Acsc.indptr[j + 1]]
+        c = og.data_cells[j]
+        aref[k] = yb[c] + w @ yb[G[rows]]
+        amag[k] = np.abs(yb[c]) + np.abs(w) @ np.abs(yb[G[rows]])
+    del yb
+    dcells = torch.from_numpy(og.data_cells[dpick]).cuda()
+    for windows in (True, False):
+        plan = hb.Plan(prog, inner=I, dtype=hb.F64, windows=windows)
+        y = src.clone()
+        hb.apply_adjoint(plan, y)
+        torch.cuda.synchronize()
+        assert (y[cells] == 0).all()
+        got = y[dcells].cpu().numpy()
+        del y
+        bound = (cnt[:, None] + 2) * U64 * amag
+        assert (np.abs(got - aref) <= bound).all(), (windows, float((np.abs(got - aref) / bound).max()))
