@@ -299,3 +299,45 @@ def test_plan_autotune_is_value_neutral(tmp_path):
     hb.apply(plan, got)
     torch.cuda.synchronize()
     assert torch.equal(got, want)
+
+
+def test_batch_with_empty_plans():
+    """Plans without rows (an empty program) inside a batch contribute no
+    tiles: the other plans' fields equal their plain applies bit for bit and
+    the empty plans' fields stay as they were, eagerly and through a graph;
+    a batch of empty plans alone is a no-op."""
+    def empty_plan(N, I):
+        g = hb.Grid.cubed_sphere(N, 2)
+        return hb.Plan(hb.Program(g), inner=I), g.cells * I
+    e1, n1 = empty_plan(8, 4)
+    e2, n2 = empty_plan(6, 4)
+    grid, full_plan, _ = cs_plan(12, 2, 1, 4)
+    assert e1.stats()["rows_covered"] == 0
+    rng = np.random.default_rng(3)
+    xs = [torch.from_numpy(rng.standard_normal(n)).cuda() for n in (n1, grid.cells * 4, n2)]
+    want = [x.clone() for x in xs]
+    hb.apply(full_plan, want[1])
+    batch = hb.Batch([e1, full_plan, e2])
+    fields = [x.clone() for x in xs]
+    batch.bind(fields)
+    batch.apply()
+    torch.cuda.synchronize()
+    for f, w in zip(fields, want):
+        assert torch.equal(f, w)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        batch.graph_capture(s.cuda_stream)
+        for rep in range(2):
+            for f, x in zip(fields, xs):
+                f.copy_(x)
+            torch.cuda.synchronize()
+            batch.graph_launch(s.cuda_stream)
+            torch.cuda.synchronize()
+            for f, w in zip(fields, want):
+                assert torch.equal(f, w), rep
+    only = hb.Batch([e1, e2])
+    f2 = [xs[0].clone(), xs[2].clone()]
+    only.bind(f2)
+    only.apply()
+    torch.cuda.synchronize()
+    assert torch.equal(f2[0], xs[0]) and torch.equal(f2[1], xs[2])
