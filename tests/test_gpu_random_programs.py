@@ -43,11 +43,14 @@ ROTS = [(1, 0, 0, 1), (0, 1, 1, 0), (-1, 0, 0, 1), (1, 0, 0, -1), (-1, 0, 0, -1)
 KINDS = ["periodic", "mirror", "other", "zero", "ell", "csr", "none"]
 
 
-def draw_case(seed, force_dtype=None, force_order=None):
+def draw_case(seed, force_dtype=None, force_order=None, force_shape=None):
+    """One random case; force_shape = (halo, n0, n1) fixes the block shape."""
     rng = np.random.default_rng(seed)
     nb = int(rng.integers(1, 4))
     h = int(rng.integers(1, 4))
     n = [int(rng.integers(max(h, 4), 20)), int(rng.integers(max(h, 4), 24))]
+    if force_shape is not None:
+        h, n = force_shape[0], list(force_shape[1:])
     lo, hi = [0, -h, -h], [nb, n[0] + h, n[1] + h]
     g = hb.Grid(lo, hi)
     og = OGrid(lo, hi)
@@ -338,3 +341,40 @@ def test_random_program_graph_replays(seed):
                 torch.cuda.synchronize()
                 assert torch.equal(x, want), (op_kind, rep)
             del graph
+
+
+@pytest.mark.parametrize("shape", [(1, 5, 1), (1, 3, 2), (2, 2, 3), (1, 1, 1)])
+def test_random_consumer_on_thin_blocks(shape):
+    """Blocks of 1-3 data cells along a dimension (runs of one or two cells,
+    every stencil reaching the halo): random programs and the cross and
+    9-point box (the line walk) and a stencil with a repeated offset (the
+    general walk), fused and unfused, against the oracle."""
+    from oracle.consumer import stencil_after_bc
+    h = shape[0]
+    stencils = [[(0, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)],
+                [(0, a, b) for a in (-1, 0, 1) for b in (-1, 0, 1)],
+                [(0, h, -h), (0, 0, 0), (0, -h, h), (0, 0, 0)]]  # a repeated offset: the general walk
+    for k, offs in enumerate(stencils):
+        g, og, prog, subs, I, vec, _, dtype, windows, rng, _ = draw_case(7000 + 10 * k + sum(shape), force_order=0,
+                                                                         force_shape=shape)
+        wts = [float(v) for v in rng.standard_normal(len(offs))]
+        dt, npdt, tdt, eps = ((hb.F64, np.float64, torch.float64, 2.0 ** -53) if dtype == "f64"
+                              else (hb.F32, np.float32, torch.float32, 2.0 ** -24))
+        plan = hb.Plan(prog, inner=I, vec=vec, dtype=dt, windows=windows)
+        cons = hb.Consumer(plan, offs, wts)
+        op = assemble(og, subs)
+        u = rng.standard_normal((og.ncells, I)).astype(npdt).astype(np.float64)
+        ndata = len(og.data_cells)
+        ref = stencil_after_bc(op, u, offs, wts, vec)
+        T = o_apply(magnitude_operator(op), np.abs(u), vec)
+        bound = 64 * eps * stencil_after_bc(assemble(og, []), T, offs, [abs(v) for v in wts])
+        for fused in (False, True):
+            x = torch.from_numpy(u.astype(npdt)).cuda()
+            if not fused:
+                hb.apply(plan, x)
+            y = torch.full((ndata * I,), float("nan"), dtype=tdt, device="cuda")
+            cons.apply(x, y, fused=fused)
+            torch.cuda.synchronize()
+            got = y.view(ndata, I).cpu().numpy().astype(np.float64)
+            assert np.isfinite(got).all(), (shape, k, fused)
+            assert (np.abs(got - ref) <= bound).all(), (shape, k, fused)
