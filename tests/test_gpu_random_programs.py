@@ -378,3 +378,41 @@ def test_random_consumer_on_thin_blocks(shape):
             got = y.view(ndata, I).cpu().numpy().astype(np.float64)
             assert np.isfinite(got).all(), (shape, k, fused)
             assert (np.abs(got - ref) <= bound).all(), (shape, k, fused)
+
+
+@pytest.mark.parametrize("shape", [(1, 5, 1), (1, 3, 2), (2, 2, 3), (1, 1, 1), (3, 3, 3)])
+@pytest.mark.parametrize("k", range(3))
+def test_random_program_thin_blocks(shape, k):
+    """Random programs on blocks of 1-3 data cells along a dimension (strips
+    of one or two rows, runs of one row), random layouts: forward and
+    adjoint against the oracle, every cell."""
+    from oracle import vjp
+    g, og, prog, subs, I, vec, order, dtype, windows, rng, _ = draw_case(8000 + 7 * k + sum(shape),
+                                                                         force_shape=shape)
+    dt, npdt, eps = (hb.F64, np.float64, 2.0 ** -53) if dtype == "f64" else (hb.F32, np.float32, 2.0 ** -24)
+    plan = hb.Plan(prog, inner=I, order=order, vec=vec, dtype=dt, windows=windows)
+    op = assemble(og, subs)
+    u = rng.standard_normal((og.ncells, I)).astype(npdt).astype(np.float64)
+    D, G = og.data_cells, og.ghost_cells
+    cov = G[op.covered]
+    for adjoint in (False, True):
+        arr = u if order == 0 else np.ascontiguousarray(u.T)
+        t = torch.from_numpy(np.ascontiguousarray(arr.astype(npdt))).cuda()
+        (hb.apply_adjoint if adjoint else hb.apply)(plan, t)
+        torch.cuda.synchronize()
+        got = t.cpu().numpy().astype(np.float64)
+        got = got if order == 0 else np.ascontiguousarray(got.T)
+        if not adjoint:
+            ref = o_apply(op, u, vec)
+            mag = o_apply(magnitude_operator(op), np.abs(u), vec)
+            assert np.array_equal(got[D], u[D])
+            assert (np.abs(got[cov] - ref[cov]) <= 32 * eps * mag[cov]).all(), (shape, k)
+        else:
+            ref = vjp(op, u, vec)
+            mag = vjp(magnitude_operator(op), np.abs(u), vec)
+            cnt = 0
+            for A in op.parts.values():
+                cnt = cnt + np.diff(A.tocsc().indptr)
+            assert (got[cov] == 0).all()
+            assert (np.abs(got[D] - ref[D]) <= (np.asarray(cnt)[:, None] + 4) * eps * mag[D]).all(), (shape, k)
+        assert np.array_equal(got[G[~op.covered]], u[G[~op.covered]])
