@@ -744,7 +744,7 @@ __device__ __forceinline__ void win_pipelined(const PlanDesc& d, const WinRun* _
   // picks among them), FP32 11.2 against 11.8 us; priority 1 or 3, dropped
   // after the loads or before the stores, all give the same.  The same
   // bracket around the loads of the row, consumer, adjoint and wide-row
-  // kernels gains nothing.
+  // kernels gains nothing, and the 27-point march loses with it.
   __builtin_amdgcn_s_setprio(3);
   const int my_dst = d.row_dst[rn.row_begin + mr];
   T my_w[4];
