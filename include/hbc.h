@@ -334,8 +334,9 @@ int hbc_plan_set_tune(hbc_plan* plan, const hbc_tune* t);
  * the order of loads and stores), timing HIP-graph applies cycled over the `nfields`
  * device fields (`nelem` values each; their ghost values are overwritten,
  * data cells are not), and keep the fastest.  With cache_path (JSON lines
- * keyed by device, dtype, layout and the plan's sizes) a stored choice is
- * reused.  *ms receives the chosen shape's time per apply.  Results do not
+ * keyed by device, dtype, layout, the plan's sizes and the generation of the
+ * library's kernels) a stored choice is reused; one stored by a build whose
+ * kernels time differently is not.  *ms receives the chosen shape's time per apply.  Results do not
  * depend on the shape (Sec. V-C: specialise once, run many). */
 int hbc_plan_autotune(hbc_plan* plan, void* const* fields, int64_t nelem, int32_t nfields, const char* cache_path,
                       void* stream, double* ms);

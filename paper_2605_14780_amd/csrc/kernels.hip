@@ -3314,13 +3314,20 @@ void device_batch_set_tune(Batch* b, const hbc_tune& t) {
 
 void device_batch_stats(const Batch* b, hbc_stats* out) { *out = b->stats; }
 
+// Generation of the kernels' performance, part of every autotune cache key:
+// a choice stored by a build whose kernels time differently is not reused
+// (bumped with such changes; 2: window loads at raised priority, where runs
+// of 4 turned from the fastest to among the slowest).
+constexpr int TUNE_CACHE_GEN = 2;
+
 static std::string batch_key(const Batch* b) {
   int dev = 0;
   hipDeviceProp_t prop;
   HIP_CHECK(hipGetDevice(&dev));
   HIP_CHECK(hipGetDeviceProperties(&prop, dev));
   std::ostringstream k;
-  k << prop.gcnArchName << "|" << (b->dtype == HBC_F64 ? "f64" : "f32") << "|point|" << b->plans.size() << "|"
+  k << prop.gcnArchName << "|g" << TUNE_CACHE_GEN << "|" << (b->dtype == HBC_F64 ? "f64" : "f32") << "|point|"
+    << b->plans.size() << "|"
     << b->stats.ghost_values << "|" << b->stats.rows_covered;
   std::string s = k.str();
   for (char& c : s)
@@ -3353,13 +3360,14 @@ static double time_batch(Batch* b, hipStream_t s, int reps) {
 }
 
 // ---- plan autotuner ------------------------------------------------------------------------
+
 static std::string plan_key(const Plan& p) {
   int dev = 0;
   hipDeviceProp_t prop;
   HIP_CHECK(hipGetDevice(&dev));
   HIP_CHECK(hipGetDeviceProperties(&prop, dev));
   std::ostringstream k;
-  k << prop.gcnArchName << "|plan|" << (p.dtype == HBC_F64 ? "f64" : "f32") << "|"
+  k << prop.gcnArchName << "|g" << TUNE_CACHE_GEN << "|plan|" << (p.dtype == HBC_F64 ? "f64" : "f32") << "|"
     << (p.layout.order == HBC_POINT_MAJOR ? "point" : "plane") << "|" << p.layout.inner << "|" << p.vec << "|"
     << p.stats.rows_covered << "|" << p.stats.segments << "|" << p.stats.nnz << "|" << p.stats.rows_data << "|w"
     << (windows_possible(p) ? 1 : 0);
