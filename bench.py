@@ -57,8 +57,9 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(name):
-    """HBM bytes per launch from committed counter runs, if taken on the current kernel source."""
+def traffic_from_profile(name, kernel):
+    """HBM bytes per launch of `kernel` from committed counter runs, if they were taken on that
+    kernel (the launch shape the autotuner chose in this run) and on the current kernel source."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
@@ -68,7 +69,7 @@ def traffic_from_profile(name):
         return None
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return rec.get("kernels", {}).get(kernel, {}).get("hbm_bytes_per_launch")
 
 
 class Timer:
@@ -973,7 +974,8 @@ def main():
                                "point-major FP64, cache-rotated over independent fields", "N": 384, "halo": 3,
                    "inner": 256, "ghost_values_per_apply": st["ghost_values"], "copies": args.copies},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile("apply_c384_f64_pmc.json"),
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic_from_profile("apply_c384_f64_pmc.json", kern[0]) if len(kern) == 1 else None,
                      "alg_bytes_per_launch": st["alg_bytes"], "kernel": kern[0],
                      **({"kernels": kern} if len(kern) > 1 else {})},
         "cpu_baseline": {"value": allc["cells_per_s"], "unit": "ghost cells/s", "cores": allc["workers"],

@@ -3360,7 +3360,6 @@ static double time_batch(Batch* b, hipStream_t s, int reps) {
 }
 
 // ---- plan autotuner ------------------------------------------------------------------------
-
 static std::string plan_key(const Plan& p) {
   int dev = 0;
   hipDeviceProp_t prop;
