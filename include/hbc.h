@@ -336,8 +336,9 @@ int hbc_plan_set_tune(hbc_plan* plan, const hbc_tune* t);
  * data cells are not), and keep the fastest.  With cache_path (JSON lines
  * keyed by device, dtype, layout, the plan's sizes and the generation of the
  * library's kernels) a stored choice is reused; one stored by a build whose
- * kernels time differently is not.  *ms receives the chosen shape's time per apply.  Results do not
- * depend on the shape (Sec. V-C: specialise once, run many). */
+ * kernels time differently is not.  *ms receives the chosen shape's time
+ * per apply.  Results do not depend on the shape (Sec. V-C: specialise once,
+ * run many). */
 int hbc_plan_autotune(hbc_plan* plan, void* const* fields, int64_t nelem, int32_t nfields, const char* cache_path,
                       void* stream, double* ms);
 
