@@ -889,9 +889,17 @@ __global__ __launch_bounds__(256) void k_apply_wide(PlanDesc d, const WideTile* 
     zero_row_tile<T>(d, ztiles[blockIdx.x - nwide]);
     return;
   }
+  // workgroups are dealt to the 8 XCDs round-robin: give each XCD a
+  // contiguous range of (tile, slice group) items, so that neighbouring
+  // tiles, which share source cells, meet in one L2
+  int b = (int)blockIdx.x;
+  {
+    const int q = nwide >> 3, rem = nwide & 7, x = b & 7, jx = b >> 3;
+    b = x * q + min(x, rem) + jx;
+  }
   const int runs = (nslices + spw - 1) / spw;
-  const WideTile tl = tiles[blockIdx.x / runs];
-  const int s0 = (blockIdx.x % runs) * spw;
+  const WideTile tl = tiles[b / runs];
+  const int s0 = (b % runs) * spw;
   const int s1 = min(nslices, s0 + spw);
   T* __restrict__ f = static_cast<T*>(d.field);
   typedef T vt __attribute__((ext_vector_type(V)));
