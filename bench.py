@@ -13,8 +13,12 @@ K applies cycling over `--copies` independent fields, so the touched data
 (about 115 MB per apply) is not served from the 256 MB Infinity Cache.
 
 The other workloads run after the headline and are reported under "extras":
-C48 single-field latency, the C384 workload in FP32, the HPCG-shaped 256^3
-BC + 27-point operator (BC only, unfused, fused), 64 batched grids of uneven
+C48 single-field latency, the C384 workload in FP32 and on the plane-major
+layout (autotuned), a device copy of the headline's bytes, the C384 plan
+trimmed to a radius-1 cross consumer's footprint and that consumer (unfused
+and fused with the BC), wide quadrature rows (C384 and C90 (h, u, v)),
+block-edge averaging on an Np = 385 grid, the HPCG-shaped 256^3 BC +
+27-point operator (BC only, unfused, fused), 64 batched grids of uneven
 sizes in FP32 (persistent launch vs 64 plain launches, autotuned), and the
 C768 forward / adjoint in FP64 and FP32.  The CPU oracle is timed on the
 host and every GPU result is checked against it in the same run.
