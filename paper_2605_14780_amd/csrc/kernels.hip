@@ -1503,7 +1503,14 @@ __global__ __launch_bounds__(256) void k_adjoint_lds(PlanDesc d, AdjDesc a, AdjL
     }
     return;
   }
-  const AdjLdsTile tl = q.tiles[blockIdx.x];
+  // workgroups are dealt to the 8 XCDs round-robin: give each XCD a
+  // contiguous range of tiles (neighbouring tiles read shared ghost rows)
+  int bt = (int)blockIdx.x;
+  {
+    const int nq = q.ntiles >> 3, rem = q.ntiles & 7, x = bt & 7, jx = bt >> 3;
+    bt = x * nq + min(x, rem) + jx;
+  }
+  const AdjLdsTile tl = q.tiles[bt];
   const int nu = tl.nu;
   // staging: SG vector loads of ghost rows in flight per thread, then their
   // LDS stores (row u of the tile at u * inner)
